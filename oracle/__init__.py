@@ -1,0 +1,172 @@
+"""FP64 CPU oracle for EM-ADMM and NLEM (ctypes shim over em_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg may use this package; the product path never
+does.  It shares no code with the GPU library.
+
+Parity pins: every function here is checked in ``tests/test_oracle_pins.py``
+against closed forms, optimality conditions and brute force (see each
+test's docstring for the passage it follows).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "em_oracle.c")
+_LIB = os.path.join(_HERE, "libemoracle.so")
+
+CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
+INIT_GIVEN, INIT_MAXW = 0, 1
+
+
+def build(force: bool = True) -> str:
+    """Compile em_oracle.c with gcc -O2 (no fast-math) and OpenMP."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        dp, fp, i64p, i32p = (C.POINTER(C.c_double), C.POINTER(C.c_float),
+                              C.POINTER(C.c_int64), C.POINTER(C.c_int32))
+        lib.oracle_prox.argtypes = [C.c_int64, dp, dp, C.c_double, dp]
+        lib.oracle_prox.restype = None
+        lib.oracle_em_solve.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, C.c_double,
+                                        C.c_double, dp, dp, dp, C.c_int64, C.c_double,
+                                        i64p, dp, dp]
+        lib.oracle_em_solve.restype = C.c_int
+        lib.oracle_em_batch.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p,
+                                        C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
+                                        C.c_double, C.c_int, dp, i32p, i32p, dp, dp, C.c_int]
+        lib.oracle_em_batch.restype = C.c_int
+        lib.oracle_nlem.argtypes = [C.c_int64, C.c_int64, fp, C.c_int64, C.c_int64, C.c_double,
+                                    C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
+                                    C.c_double, C.c_int64, i64p, dp, dp, dp, i32p, i32p, dp, dp,
+                                    C.c_int]
+        lib.oracle_nlem.restype = C.c_int
+        lib.oracle_max_threads.argtypes = []
+        lib.oracle_max_threads.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(arr, ctype):
+    if arr is None:
+        return None
+    return arr.ctypes.data_as(C.POINTER(ctype))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def prox(v, u, lam: float) -> np.ndarray:
+    """Closed-form prox Psi_lambda(v, u) of lambda * ||x - u|| (equation closed-form)."""
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+    out = np.empty_like(v)
+    _load().oracle_prox(v.size, _p(v, C.c_double), _p(u, C.c_double), float(lam),
+                        _p(out, C.c_double))
+    return out
+
+
+def em_solve(a, w, mu: float, lo: float, hi: float, z0, y0=None, max_iter: int = 100,
+             tol: float = 0.0) -> dict:
+    """One instance of Algorithm 1 in FP64; returns z, y, x, iters, residuals, flags."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    assert w.size == n
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    assert z.size == d
+    y = np.zeros((n, d)) if y0 is None else np.array(y0, dtype=np.float64).reshape(n, d).copy()
+    x = np.zeros((n, d))
+    it = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    f = _load().oracle_em_solve(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                float(lo), float(hi), _p(z, C.c_double), _p(y, C.c_double),
+                                _p(x, C.c_double), int(max_iter), float(tol), C.byref(it),
+                                C.byref(rp), C.byref(rd))
+    return dict(z=z, y=y, x=x, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f))
+
+
+def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW, z0=None,
+             max_iter_each=None, nthreads: int = 0) -> dict:
+    """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
+    z_size, lo, hi).  Returns z (float64, concatenated), iters, flags, residuals."""
+    inst = batch.inst
+    B = int(inst.shape[0])
+    a = np.ascontiguousarray(batch.a, dtype=np.float32)
+    w = np.ascontiguousarray(batch.w, dtype=np.float32)
+    a_off = np.ascontiguousarray(inst["a_off"], dtype=np.int64)
+    w_off = np.ascontiguousarray(inst["w_off"], dtype=np.int64)
+    z_off = np.ascontiguousarray(inst["z_off"], dtype=np.int64)
+    n = np.ascontiguousarray(inst["n"], dtype=np.int32)
+    d = np.ascontiguousarray(inst["d"], dtype=np.int32)
+    z = np.zeros(batch.z_size, dtype=np.float64) if z0 is None else np.array(z0, np.float64).copy()
+    iters = np.zeros(B, np.int32)
+    flags = np.zeros(B, np.int32)
+    rp = np.zeros(B)
+    rd = np.zeros(B)
+    mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
+    _load().oracle_em_batch(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
+                            _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
+                            _p(d, C.c_int32), float(mu), float(batch.lo), float(batch.hi),
+                            int(max_iter), _p(mie, C.c_int32), float(tol), int(init),
+                            _p(z, C.c_double), _p(iters, C.c_int32), _p(flags, C.c_int32),
+                            _p(rp, C.c_double), _p(rd, C.c_double), int(nthreads))
+    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd)
+
+
+def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: float,
+         mu: float, max_iter: int, tol: float, pix=None, max_iter_each=None,
+         want_z: bool = False, want_weights: bool = False, nthreads: int = 0) -> dict:
+    """NLEM on the float32 image ``img`` (H x W) for the pixels ``pix`` (linear
+    indices; None = all).  Returns out (float64), iters, flags, residuals and
+    optionally the full patches z and the window weights."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = img.shape
+    d = (2 * patch_radius + 1) ** 2
+    nmax = (2 * window_radius + 1) ** 2
+    pixa = None if pix is None else np.ascontiguousarray(pix, dtype=np.int64)
+    npix = H * W if pixa is None else int(pixa.size)
+    out = np.zeros(npix)
+    zf = np.zeros((npix, d)) if want_z else None
+    wo = np.zeros((npix, nmax)) if want_weights else None
+    iters = np.zeros(npix, np.int32)
+    flags = np.zeros(npix, np.int32)
+    rp = np.zeros(npix)
+    rd = np.zeros(npix)
+    mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
+    _load().oracle_nlem(H, W, _p(img, C.c_float), int(patch_radius), int(window_radius),
+                        float(h), float(lo), float(hi), float(mu), int(max_iter),
+                        _p(mie, C.c_int32), float(tol), npix, _p(pixa, C.c_int64),
+                        _p(out, C.c_double), _p(zf, C.c_double), _p(wo, C.c_double),
+                        _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
+                        _p(rd, C.c_double), int(nthreads))
+    res = dict(out=out, iters=iters, flags=flags, r_pri=rp, r_dual=rd)
+    if want_z:
+        res["z"] = zf
+    if want_weights:
+        res["weights"] = wo
+    return res

@@ -1,0 +1,332 @@
+/*
+ * FP64 CPU oracle for the box-constrained Euclidean median solved by
+ * EM-ADMM, and for the Non-Local Euclidean Medians (NLEM) denoiser.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg use it.  It shares no code, header or constant with the
+ * GPU library.
+ *
+ * Source: K. N. Chaudhury and K. R. Ramakrishnan, "A new ADMM algorithm for
+ * the Euclidean median and its application to robust patch regression"
+ * (arXiv:1501.03879).
+ *
+ * Everything is IEEE binary64 with round-to-nearest, no fast-math, points
+ * summed sequentially k = 1..n exactly in the order Algorithm 1 gives.
+ * Readings where the paper is silent (stopping rule, tolerance scale, border
+ * handling, flags) are stated next to the code that implements them.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_CONVERGED 1
+#define OR_MAXITER 2
+#define OR_EMPTY 4
+#define OR_BAD_INPUT 8
+
+#define OR_INIT_GIVEN 0
+#define OR_INIT_MAXW 1
+
+/*
+ * Proximal map of f(x) = lambda * ||x - u||_2, equation (closed-form):
+ *   Psi_lambda(v, u) = v - min(lambda, ||v - u||) (v - u) / ||v - u||.
+ * When ||v - u|| <= lambda the minimum picks ||v - u|| and the result is u
+ * exactly; this also covers v = u, where the printed quotient is 0/0.
+ */
+void oracle_prox(int64_t d, const double *v, const double *u, double lambda, double *out)
+{
+    double nu2 = 0.0;
+    for (int64_t j = 0; j < d; ++j) {
+        double t = v[j] - u[j];
+        nu2 += t * t;
+    }
+    double nu = sqrt(nu2);
+    if (nu <= lambda) {
+        for (int64_t j = 0; j < d; ++j) out[j] = u[j];
+    } else {
+        for (int64_t j = 0; j < d; ++j) out[j] = v[j] - lambda * (v[j] - u[j]) / nu;
+    }
+}
+
+/* Coordinate-wise projection onto the box [lo, hi]^d (Section 3). */
+static double clamp_box(double x, double lo, double hi)
+{
+    if (x < lo) return lo;
+    if (x > hi) return hi;
+    return x;
+}
+
+/*
+ * Scale D of the relative stopping tolerance: the box width hi - lo when it
+ * is finite and positive, otherwise max(1, max_k ||a_k||_inf).
+ */
+static double tol_scale(int64_t n, int64_t d, const double *a, double lo, double hi)
+{
+    if (isfinite(lo) && isfinite(hi) && hi > lo) return hi - lo;
+    double m = 1.0;
+    for (int64_t i = 0; i < n * d; ++i) {
+        double t = fabs(a[i]);
+        if (t > m) m = t;
+    }
+    return m;
+}
+
+/*
+ * One instance of Algorithm 1 (EM-ADMM) in its printed form, with unscaled
+ * multipliers y_k and penalty mu:
+ *   loop:  r = 0
+ *          for k: x_k = Psi_{w_k/mu}(z - y_k/mu, a_k);  r += x_k + y_k/mu
+ *          z = P_C(r / N)                       (N = n, the points present)
+ *          for k: y_k += mu (x_k - z)
+ * The loop stops after max_iter iterations, or earlier when tol > 0 and both
+ *   r_pri  = sqrt(sum_k ||x_k - z||^2 / (n d))
+ *   r_dual = sqrt(||z - z_prev||^2 / d)
+ * are <= tol * D (the paper leaves the criterion open; this is the primal and
+ * dual residual pair of the ADMM literature, checked every iteration).
+ *
+ * a: n*d points (point-major), w: n weights, z: d values in/out (the initial
+ * z is used unprojected), y: n*d multipliers in/out (NULL means start from
+ * zero and discard), x_out: n*d last local variables (NULL to skip).
+ * Returns the flag word; *iters, *r_pri, *r_dual receive the iteration count
+ * and the residuals of the last iteration run (0 when none ran).
+ * n = 0: z is left as given (EMPTY).  A negative or non-finite weight, or a
+ * non-finite point or initial z: z is set to NaN (BAD_INPUT).
+ */
+int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
+                    double mu, double lo, double hi, double *z, double *y,
+                    double *x_out, int64_t max_iter, double tol,
+                    int64_t *iters, double *r_pri, double *r_dual)
+{
+    *iters = 0;
+    *r_pri = 0.0;
+    *r_dual = 0.0;
+    if (n == 0) return OR_EMPTY;
+    int bad = 0;
+    for (int64_t k = 0; k < n; ++k)
+        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!isfinite(a[i])) bad = 1;
+    for (int64_t j = 0; j < d; ++j)
+        if (!isfinite(z[j])) bad = 1;
+    if (bad) {
+        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
+        return OR_BAD_INPUT;
+    }
+    double D = tol_scale(n, d, a, lo, hi);
+
+    double *ybuf = y ? y : (double *)calloc((size_t)(n * d), sizeof(double));
+    double *x = (double *)malloc((size_t)(n * d) * sizeof(double));
+    double *v = (double *)malloc((size_t)d * sizeof(double));
+    double *r = (double *)malloc((size_t)d * sizeof(double));
+    double *zprev = (double *)malloc((size_t)d * sizeof(double));
+
+    int flags = OR_MAXITER;
+    for (int64_t t = 1; t <= max_iter; ++t) {
+        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            const double *ak = a + k * d;
+            double *yk = ybuf + k * d;
+            double *xk = x + k * d;
+            double lambda = w[k] / mu;                    /* lambda = w_k / mu */
+            for (int64_t j = 0; j < d; ++j) v[j] = z[j] - yk[j] / mu;   /* v = z - y_k / mu */
+            oracle_prox(d, v, ak, lambda, xk);
+            for (int64_t j = 0; j < d; ++j) r[j] += xk[j] + yk[j] / mu;
+        }
+        for (int64_t j = 0; j < d; ++j) {
+            zprev[j] = z[j];
+            z[j] = clamp_box(r[j] / (double)n, lo, hi);
+        }
+        for (int64_t k = 0; k < n; ++k)
+            for (int64_t j = 0; j < d; ++j)
+                ybuf[k * d + j] += mu * (x[k * d + j] - z[j]);
+
+        double sp = 0.0, sd = 0.0;
+        for (int64_t k = 0; k < n; ++k)
+            for (int64_t j = 0; j < d; ++j) {
+                double e = x[k * d + j] - z[j];
+                sp += e * e;
+            }
+        for (int64_t j = 0; j < d; ++j) {
+            double e = z[j] - zprev[j];
+            sd += e * e;
+        }
+        *r_pri = sqrt(sp / (double)(n * d));
+        *r_dual = sqrt(sd / (double)d);
+        *iters = t;
+        if (tol > 0.0 && *r_pri <= tol * D && *r_dual <= tol * D) {
+            flags = OR_CONVERGED;
+            break;
+        }
+    }
+    if (x_out) memcpy(x_out, x, (size_t)(n * d) * sizeof(double));
+    if (!y) free(ybuf);
+    free(x);
+    free(v);
+    free(r);
+    free(zprev);
+    return flags;
+}
+
+static void set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/*
+ * A batch of independent instances (the points and weights are the float32
+ * buffers the GPU reads, widened to binary64 here).  Instance b has n[b]
+ * points of dimension d[b] at a + a_off[b], weights at w + w_off[b] and its
+ * result at z + z_off[b].  init = GIVEN uses z as the initial value; init =
+ * MAXW starts from the point of largest weight (lowest index on ties).
+ * max_iter_each (nullable) overrides max_iter per instance.
+ */
+int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_off,
+                    const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
+                    const int32_t *d_arr, double mu, double lo, double hi,
+                    int64_t max_iter, const int32_t *max_iter_each, double tol, int init,
+                    double *z, int32_t *iters, int32_t *flags, double *r_pri,
+                    double *r_dual, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = 0; b < B; ++b) {
+        int64_t n = n_arr[b], d = d_arr[b];
+        double *ab = (double *)malloc((size_t)(n * d + 1) * sizeof(double));
+        double *wb = (double *)malloc((size_t)(n + 1) * sizeof(double));
+        for (int64_t i = 0; i < n * d; ++i) ab[i] = (double)a[a_off[b] + i];
+        for (int64_t k = 0; k < n; ++k) wb[k] = (double)w[w_off[b] + k];
+        double *zb = z + z_off[b];
+        if (init == OR_INIT_MAXW && n > 0) {
+            int64_t best = 0;
+            for (int64_t k = 1; k < n; ++k)
+                if (wb[k] > wb[best]) best = k;
+            for (int64_t j = 0; j < d; ++j) zb[j] = ab[best * d + j];
+        }
+        int64_t it = 0;
+        double rp = 0.0, rd = 0.0;
+        int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
+        int f = oracle_em_solve(n, d, ab, wb, mu, lo, hi, zb, NULL, NULL, mi, tol, &it, &rp, &rd);
+        if (iters) iters[b] = (int32_t)it;
+        if (flags) flags[b] = f;
+        if (r_pri) r_pri[b] = rp;
+        if (r_dual) r_dual[b] = rd;
+        free(ab);
+        free(wb);
+    }
+    return 0;
+}
+
+/* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */
+static int64_t reflect(int64_t i, int64_t N)
+{
+    if (i < 0) return -i - 1;
+    if (i >= N) return 2 * N - i - 1;
+    return i;
+}
+
+/*
+ * Patch P_i of Section 3: the (2pr+1) x (2pr+1) square of the noisy image
+ * centred at pixel (iy, ix), row-major, pixels outside the image taken by
+ * symmetric reflection.
+ */
+static void extract_patch(const float *img, int64_t H, int64_t W, int64_t pr,
+                          int64_t iy, int64_t ix, double *P)
+{
+    int64_t side = 2 * pr + 1;
+    for (int64_t dy = -pr; dy <= pr; ++dy)
+        for (int64_t dx = -pr; dx <= pr; ++dx)
+            P[(dy + pr) * side + (dx + pr)] =
+                (double)img[reflect(iy + dy, H) * W + reflect(ix + dx, W)];
+}
+
+/*
+ * NLEM (Section 3): for each requested pixel i, the points are the patches
+ * P_j of every pixel j of the (2wr+1) x (2wr+1) search window centred at i
+ * that lies inside the image (the window is truncated at borders, j = i
+ * included, row-major order), the weights are w_ij = exp(-||P_i - P_j||^2 /
+ * h^2) (not normalised), the box is [lo, hi]^d, the initial z is the noisy
+ * patch P_i (unprojected) and y starts at zero.  The denoised pixel is the
+ * centre coordinate of the returned patch, z[(d - 1) / 2].
+ *
+ * pix: npix linear pixel indices (NULL: all H*W pixels in order).
+ * max_iter_each (nullable): per requested pixel iteration cap.
+ * out: npix denoised values; zfull (nullable): npix*d patches;
+ * weights_out (nullable): npix * (2wr+1)^2 weights in window order, slots of
+ * points outside the image set to -1.
+ */
+int oracle_nlem(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
+                double h, double lo, double hi, double mu, int64_t max_iter,
+                const int32_t *max_iter_each, double tol, int64_t npix,
+                const int64_t *pix, double *out, double *zfull, double *weights_out,
+                int32_t *iters, int32_t *flags, double *r_pri, double *r_dual,
+                int nthreads)
+{
+    int64_t side = 2 * pr + 1, d = side * side;
+    int64_t wside = 2 * wr + 1, nmax = wside * wside;
+    set_threads(nthreads);
+    if (!pix) npix = H * W;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < npix; ++q) {
+        int64_t i = pix ? pix[q] : q;
+        int64_t iy = i / W, ix = i % W;
+        double *a = (double *)malloc((size_t)(nmax * d) * sizeof(double));
+        double *wk = (double *)malloc((size_t)nmax * sizeof(double));
+        double *z = (double *)malloc((size_t)d * sizeof(double));
+        double *Pi = (double *)malloc((size_t)d * sizeof(double));
+        extract_patch(img, H, W, pr, iy, ix, Pi);
+        int64_t n = 0;
+        for (int64_t dy = -wr; dy <= wr; ++dy)
+            for (int64_t dx = -wr; dx <= wr; ++dx) {
+                int64_t jy = iy + dy, jx = ix + dx;
+                int64_t slot = (dy + wr) * wside + (dx + wr);
+                if (jy < 0 || jy >= H || jx < 0 || jx >= W) {
+                    if (weights_out) weights_out[q * nmax + slot] = -1.0;
+                    continue;
+                }
+                double *Pj = a + n * d;
+                extract_patch(img, H, W, pr, jy, jx, Pj);
+                double dist2 = 0.0;
+                for (int64_t c = 0; c < d; ++c) {
+                    double t = Pi[c] - Pj[c];
+                    dist2 += t * t;
+                }
+                wk[n] = exp(-dist2 / (h * h));
+                if (weights_out) weights_out[q * nmax + slot] = wk[n];
+                ++n;
+            }
+        memcpy(z, Pi, (size_t)d * sizeof(double));
+        int64_t it = 0;
+        double rp = 0.0, rd = 0.0;
+        int64_t mi = max_iter_each ? max_iter_each[q] : max_iter;
+        int f = oracle_em_solve(n, d, a, wk, mu, lo, hi, z, NULL, NULL, mi, tol, &it, &rp, &rd);
+        out[q] = z[(d - 1) / 2];
+        if (zfull) memcpy(zfull + q * d, z, (size_t)d * sizeof(double));
+        if (iters) iters[q] = (int32_t)it;
+        if (flags) flags[q] = f;
+        if (r_pri) r_pri[q] = rp;
+        if (r_dual) r_dual[q] = rd;
+        free(a);
+        free(wk);
+        free(z);
+        free(Pi);
+    }
+    return 0;
+}
