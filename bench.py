@@ -1,0 +1,216 @@
+"""Benchmark: Non-Local Euclidean Medians on one MI355X.
+
+One step = nlem_denoise over the whole 256 x 256 synthetic image (sigma 20,
+patch 7x7 so d = 49, window 21x21 so n <= 441, h = 10 sigma, box [0, 255],
+mu = 1e-3, primal/dual residual 1e-4 relative to 255 or 200 iterations):
+staging, weights, per-pixel EM-ADMM and the centre-pixel output all run in
+the library's kernels.  Every pixel is one EM solve.
+
+Reported: EM solves/s (= pixels/s) of the batched persistent kernel, the
+roofline of that kernel on the FP32 FLOP model (6 flop per point-coordinate
+per iteration plus 3 per point-coordinate for the weights), and the FP64
+oracle timed on this host's cores on a bounded pixel sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--plain N]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "EM solves/sec & Mpixel/s at n=441,d=49, residual 1e-4 (batched FP32 vs plain)"
+FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 vector peak (packed FP32)
+FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
+    ap.add_argument("--plain", type=int, default=0,
+                    help="also time the plain one-instance-per-launch path on N pixels")
+    return ap.parse_args()
+
+
+def window_sizes(H, W, R):
+    import numpy as np
+    y = np.arange(H)
+    x = np.arange(W)
+    ny = np.minimum(y + R, H - 1) - np.maximum(y - R, 0) + 1
+    nx = np.minimum(x + R, W - 1) - np.maximum(x - R, 0) + 1
+    return (ny[:, None] * nx[None, :]).reshape(-1)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: each pixel's solve is independent, so the "
+              "image would be split by rows across GPUs with no exchange; "
+              "multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1501_03879_amd as emx
+    import synth
+
+    wl = synth.nlem_256()
+    im = wl.images[0]
+    H, W = im.noisy.shape
+    pr, wr = im.patch_radius, im.window_radius
+    d = (2 * pr + 1) ** 2
+    dev = torch.device("cuda:0")
+    img = torch.from_numpy(im.noisy).to(dev)
+    out = torch.empty_like(img)
+    stats = torch.zeros((H * W, 4), dtype=torch.int32, device=dev)
+    hd = emx.handle(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        hd.nlem_denoise(img, out, stats, patch_radius=pr, window_radius=wr, h=im.h, lo=wl.lo,
+                        hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    hd.sync()
+
+    it, fl, rp, rd = emx.stats_view(stats)
+    iters = it.cpu().numpy().astype(np.int64)
+    flags = fl.cpu().numpy()
+    n = window_sizes(H, W, wr).astype(np.int64)
+    elem_iters = float(np.sum(n * d * iters))
+    flops = 6.0 * elem_iters + 3.0 * float(np.sum(n * d))
+    tflops = flops / (ms * 1e-3) / 1e12
+    solves_per_s = H * W / (ms * 1e-3)
+
+    res = {
+        "metric": METRIC,
+        "value": solves_per_s,
+        "unit": "EM solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"nlem {H}x{W} sigma=20 patch 7x7 (d={d}) window 21x21 (n<=441) "
+                               f"h=200 box [0,255] mu={wl.mu} tol={wl.tol} max_iter={wl.max_iter}",
+                   "pixels": H * W, "patch_radius": pr, "window_radius": wr},
+        "mpixel_per_s": solves_per_s / 1e6,
+        "mean_iters": float(iters.mean()),
+        "converged_fraction": float(np.mean(flags == 1)),
+        "elem_iters_per_s": elem_iters / (ms * 1e-3),
+        "host_wall_s": wall,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
+                     "frac_nonpacked_fma_peak": tflops / FP32_NONPACKED_TFLOPS,
+                     "flops_per_launch": flops, "traffic": None},
+    }
+
+    if args.plain > 0:
+        res["plain"] = plain_rate(args.plain, im, wl, dev, hd)
+        res["speedup_vs_plain"] = solves_per_s / res["plain"]["solves_per_s"]
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(im, wl, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+def plain_rate(npix, im, wl, dev, hd):
+    """The plain path (em_solve_plain: one kernel launch per pixel, iterates in
+    device memory) on the first `npix` interior pixels' materialised patches
+    and NLM weights (built on the host in float64, stored as float32)."""
+    import numpy as np
+    import torch
+
+    import paper_1501_03879_amd as emx
+    import synth
+    img = im.noisy.astype(np.float64)
+    H, W = img.shape
+    P = np.pad(img, 3, mode="symmetric")
+    pts, ws = [], []
+    rng = np.random.default_rng(1)
+    for _ in range(npix):
+        iy, ix = rng.integers(10, H - 10), rng.integers(10, W - 10)
+        a = np.array([P[y:y + 7, x:x + 7].reshape(-1) for y in range(iy - 10, iy + 11)
+                      for x in range(ix - 10, ix + 11)])
+        c = P[iy:iy + 7, ix:ix + 7].reshape(-1)
+        pts.append(a.astype(np.float32))
+        ws.append(np.exp(-np.sum((a - c) ** 2, axis=1) / im.h ** 2).astype(np.float32))
+    b = synth.pointsets.pack_instances(pts, ws, 0.0, 255.0)
+    a = torch.from_numpy(b.a).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    inst = emx.instances_tensor(b.inst, dev)
+    z = torch.zeros(b.z_size, device=dev)
+    st = torch.zeros((b.B, 4), dtype=torch.int32, device=dev)
+    kw = dict(lo=0.0, hi=255.0, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
+    hd.em_solve_plain(a, w, inst, b.inst, z, st, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hd.em_solve_plain(a, w, inst, b.inst, z, st, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hd.em_solve_batch(a, w, inst, z, st, **kw)
+    torch.cuda.synchronize()
+    dtb = time.perf_counter() - t0
+    return {"solves_per_s": b.B / dt, "instances": b.B, "batched_same_instances_solves_per_s": b.B / dtb,
+            "note": "n=441 d=49 interior pixels, materialised patches, init = largest weight (the centre)"}
+
+
+def cpu_baseline(im, wl, target_s):
+    """The FP64 oracle on a bounded pixel sample, all host threads."""
+    import numpy as np
+
+    import oracle
+    H, W = im.noisy.shape
+    rng = np.random.default_rng(0)
+    order = rng.permutation(H * W)
+    threads = oracle.max_threads()
+    npix = 512
+    done = 0
+    total_t = 0.0
+    while True:
+        pix = order[done:done + npix]
+        t0 = time.perf_counter()
+        oracle.nlem(im.noisy, im.patch_radius, im.window_radius, im.h, wl.lo, wl.hi, wl.mu,
+                    wl.max_iter, wl.tol, pix=pix, nthreads=threads)
+        total_t += time.perf_counter() - t0
+        done += len(pix)
+        if total_t >= target_s or done >= H * W:
+            break
+        rate = done / total_t
+        npix = int(min(H * W - done, max(512, rate * (target_s - total_t))))
+    return {"value": done / total_t, "unit": "EM solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} random pixels of the 256x256 image ({done / (H * W):.1%}), "
+                      f"FP64, {total_t:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * emx.h - C ABI of the MI355X (gfx950) box-constrained Euclidean-median
+ * library.
+ *
+ * Method: K. N. Chaudhury and K. R. Ramakrishnan, "A new ADMM algorithm for
+ * the Euclidean median and its application to robust patch regression"
+ * (arXiv:1501.03879).  The library computes, for many independent instances,
+ *
+ *     min over z in C = [lo, hi]^d of  sum_k w_k ||z - a_k||_2        (EM)
+ *
+ * by the variable-splitting ADMM of Section 2 (Algorithm 1, EM-ADMM): local
+ * copies x_k updated by the closed-form prox of w_k/mu ||. - a_k|| (block
+ * soft-thresholding, equation (closed-form)), the global z by the box
+ * projection of the unweighted mean of x_k + y_k/mu (equation (updatez)),
+ * and the multipliers by y_k += mu (x_k - z) (equation (updatey)).  The
+ * penalty mu is called rho in this interface.  nlem_denoise applies it to
+ * every pixel of an image as in Section 3 (Non-Local Euclidean Medians).
+ *
+ * Conventions shared by every call:
+ *  - All array arguments are DEVICE pointers owned by the caller.  They must
+ *    stay valid until the work queued on `stream` has finished.  The library
+ *    never frees or retains them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every compute call only queues work on it and returns; kernel faults
+ *    surface from em_sync or from the caller's own synchronisation.
+ *  - Argument errors are detected on the host before anything is queued and
+ *    return EM_ERR_INVALID_ARG (nothing is written).  Problems inside one
+ *    instance (no points, a bad weight or point) are reported per instance in
+ *    em_stats_t.flags, never as a call error.
+ *  - Starting point: y_k = 0 (Section 3) and z as documented per call; the
+ *    starting z is used as given (Algorithm 1 does not project it).
+ *  - Stopping (the paper leaves the criterion open): after iteration t,
+ *        r_pri  = sqrt( sum_k ||x_k - z||^2 / (n d) )
+ *        r_dual = sqrt( ||z^t - z^{t-1}||^2 / d ),
+ *    stop when both are <= tol * D, where D = hi - lo for a finite box and
+ *    max(1, max_k ||a_k||_inf) otherwise.  The primal residual is only
+ *    evaluated on iterations that follow one with r_dual <= 4 tol D (and on
+ *    the last allowed iteration), so a solve may end one iteration later
+ *    than a solver that evaluates both every iteration.  tol = 0 runs
+ *    exactly max_iter iterations; max_iter = 0 returns the starting z.
+ *  - Arithmetic is FP32 (image storage may be FP16, widened on load).
+ */
+#ifndef EMX_H
+#define EMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EM_OK = 0,
+    EM_ERR_INVALID_ARG = -1,   /* bad pointer, size, parameter or handle */
+    EM_ERR_UNSUPPORTED = -2,   /* valid request outside the compiled limits */
+    EM_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed */
+    EM_ERR_HIP = -4            /* a HIP runtime call failed */
+} em_status_t;
+
+/* em_stats_t.flags bits */
+enum {
+    EM_CONVERGED = 1, /* stopped by the residual test */
+    EM_MAXITER = 2,   /* stopped after max_iter iterations */
+    EM_EMPTY = 4,     /* n = 0: z left as given */
+    EM_BAD_INPUT = 8  /* negative/non-finite weight or non-finite point: z set to NaN */
+};
+
+/* Starting value of z for em_solve_batch / em_solve_plain. */
+typedef enum {
+    EM_INIT_GIVEN = 0, /* the caller's z (in/out) */
+    EM_INIT_MAXW = 1   /* the point of largest weight, lowest index on ties */
+} em_init_t;
+
+/* Limits of this build. */
+#define EM_MAX_D 64            /* largest dimension d per instance */
+#define EM_MAX_N 512           /* largest point count n per instance */
+#define EM_MAX_PATCH_RADIUS 3  /* nlem: patch side 2r+1 <= 7 (d <= 49) */
+#define EM_MAX_WINDOW_RADIUS 10/* nlem: window side 2R+1 <= 21 (n <= 441) */
+
+/*
+ * One instance of a batch, in device memory (32 bytes).  Points a_k are
+ * n x d float32 values, point-major, starting at a[a_off]; weights w_k are n
+ * float32 at w[w_off]; z (d float32) lives at z[z_off].
+ */
+typedef struct {
+    int64_t a_off;
+    int64_t w_off;
+    int64_t z_off;
+    int32_t n;
+    int32_t d;
+} em_instance_t;
+
+/* Per-instance (or per-pixel) result record, in device memory (16 bytes). */
+typedef struct {
+    int32_t iters;  /* iterations run */
+    int32_t flags;  /* EM_* bits */
+    float r_pri;    /* residuals of the last iteration (NaN if not evaluated, 0 if none ran) */
+    float r_dual;
+} em_stats_t;
+
+typedef struct em_context *em_handle_t;
+
+/*
+ * Create a handle bound to HIP device `device` (it becomes current for the
+ * calling thread).  The handle owns a small device workspace (work-queue
+ * counters, instance class lists) that grows on demand and is released by
+ * em_destroy.  One handle per host thread; a handle is not thread-safe, and
+ * concurrent calls on one handle from different streams race on its
+ * workspace.
+ * Errors: INVALID_ARG for a NULL out-pointer or a bad device index;
+ * OUT_OF_MEMORY; HIP.
+ */
+em_status_t em_create(em_handle_t *handle, int device);
+
+/* Release a handle after synchronising its device.  NULL is accepted. */
+em_status_t em_destroy(em_handle_t handle);
+
+/*
+ * em_solve_batch - solve B independent instances of (EM) with one persistent
+ * kernel per shape class (Algorithm 1; the z-update mean is over the n points
+ * of the instance, equation (updatez) with N = n).
+ *   a, w, inst, z, stats: device pointers (stats may be NULL);
+ *   inst[B] describes the instances (n in [0, EM_MAX_N], d in [1, EM_MAX_D]);
+ *   lo <= hi (either may be infinite; lo = -inf and hi = +inf give the
+ *   unconstrained median); rho > 0 finite is the penalty mu; max_iter >= 0;
+ *   tol >= 0; init is an em_init_t.
+ * Instances must not overlap in z.  n = 0 leaves z unchanged (EMPTY).
+ * Errors: INVALID_ARG (NULL handle, NULL pointers with B > 0, B < 0, rho <= 0
+ * or not finite, max_iter < 0, tol < 0 or NaN, lo > hi or NaN, bad init);
+ * UNSUPPORTED when an instance exceeds the limits is NOT detected on the host
+ * (the descriptors are device data): such instances get flags = EM_BAD_INPUT
+ * and z = NaN.  HIP on launch failure.
+ */
+em_status_t em_solve_batch(em_handle_t handle, void *stream, int64_t B,
+                           const float *a, const float *w, const em_instance_t *inst,
+                           float lo, float hi, float rho, int32_t max_iter, float tol,
+                           int32_t init, float *z, em_stats_t *stats);
+
+/*
+ * em_solve_plain - the same computation as em_solve_batch with one kernel
+ * launch per instance and the iterates kept in device memory: the simple
+ * one-instance-per-launch baseline the batched solver is measured against.
+ * Same arguments and errors; it additionally needs the descriptors on the
+ * host, so `inst_host` (host memory, B entries, identical to `inst`) is
+ * required.
+ */
+em_status_t em_solve_plain(em_handle_t handle, void *stream, int64_t B,
+                           const float *a, const float *w, const em_instance_t *inst,
+                           const em_instance_t *inst_host,
+                           float lo, float hi, float rho, int32_t max_iter, float tol,
+                           int32_t init, float *z, em_stats_t *stats);
+
+/*
+ * nlem_denoise - Non-Local Euclidean Medians (Section 3): for every pixel i of
+ * the H x W image (row-major, FP32, or FP16 when img_is_f16 != 0):
+ *   points  a_j = P_j, the (2r+1)^2 patch around pixel j (row-major; pixels
+ *           beyond the image border by symmetric reflection, x[-1] = x[0]),
+ *           for every pixel j of the (2R+1)^2 search window around i that is
+ *           inside the image (the window is truncated at borders; j = i is
+ *           included);
+ *   weights w_ij = exp(-||P_i - P_j||^2 / h^2)  (not normalised, w_ii = 1);
+ *   box     [lo, hi]^d (finite), z starts at the noisy patch P_i;
+ *   output  out[i] = the centre coordinate of the solution patch
+ *           (equation (L1regression) and the text after it).
+ * r = patch_radius in [0, EM_MAX_PATCH_RADIUS], R = window_radius in
+ * [0, EM_MAX_WINDOW_RADIUS], both < min(H, W); h_param > 0.
+ * stats: NULL or H*W records.  `out` must not alias `img`.
+ * Errors: INVALID_ARG (NULL handle/img/out, H or W < 1, radii out of range,
+ * h_param <= 0, lo/hi not finite or lo > hi, rho <= 0, max_iter < 0,
+ * tol < 0); UNSUPPORTED (radii above the compiled limits); HIP.
+ */
+em_status_t nlem_denoise(em_handle_t handle, void *stream, const void *img, int32_t img_is_f16,
+                         int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                         float h_param, float lo, float hi, float rho, int32_t max_iter,
+                         float tol, float *out, em_stats_t *stats);
+
+/* One image of an nlem_denoise_multi call (host memory; pointers are device). */
+typedef struct {
+    const void *img;       /* H x W, FP32 or FP16 (per img_is_f16) */
+    float *out;            /* H x W */
+    em_stats_t *stats;     /* NULL or H*W */
+    int32_t H, W;
+    int32_t patch_radius, window_radius;
+    float h_param;
+    int32_t img_is_f16;
+} nlem_image_t;
+
+/*
+ * nlem_denoise_multi - nlem_denoise for `count` images of different sizes and
+ * radii, queued as one captured HIP graph (one persistent launch per shape
+ * class, the classes running concurrently).  The graph is cached on the
+ * handle and re-launched when the same image list (pointers, sizes, radii)
+ * and parameters are passed again.  Per-image rules and errors as for
+ * nlem_denoise; `images` is host memory with `count` entries.
+ */
+em_status_t nlem_denoise_multi(em_handle_t handle, void *stream, int32_t count,
+                               const nlem_image_t *images, float lo, float hi, float rho,
+                               int32_t max_iter, float tol);
+
+/* Wait for the stream and report any asynchronous HIP error as EM_ERR_HIP. */
+em_status_t em_sync(em_handle_t handle, void *stream);
+
+/* Static description of a status code. */
+const char *em_status_string(em_status_t status);
+
+/* Text of the last error recorded on the handle ("" if none). */
+const char *em_last_error(em_handle_t handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMX_H */

@@ -1,0 +1,201 @@
+"""Python binding of libemx (box-constrained Euclidean median by EM-ADMM on
+MI355X / gfx950).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+of ``libemx.so`` (see ``include/emx.h`` for the C ABI).  PyTorch supplies
+device memory and the current stream.  Importing this module does not load
+the library; the first call does, and raises ``RuntimeError`` if the library
+was not built (there is no CPU fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libemx.so")
+
+EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
+CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
+INIT_GIVEN, INIT_MAXW = 0, 1
+MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10
+
+# the 16-byte per-instance / per-pixel result record (em_stats_t)
+STATS_FIELDS = ("iters", "flags", "r_pri", "r_dual")
+
+
+class EmxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class NlemImage(C.Structure):
+    _fields_ = [("img", C.c_void_p), ("out", C.c_void_p), ("stats", C.c_void_p),
+                ("H", C.c_int32), ("W", C.c_int32), ("patch_radius", C.c_int32),
+                ("window_radius", C.c_int32), ("h_param", C.c_float), ("img_is_f16", C.c_int32)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library():
+    """Load libemx.so (built by ``build()``); raises if it is missing."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not found: build the HIP library first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        lib = C.CDLL(LIB_PATH)
+        vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
+        lib.em_create.argtypes = [C.POINTER(vp), C.c_int]
+        lib.em_create.restype = C.c_int
+        lib.em_destroy.argtypes = [vp]
+        lib.em_destroy.restype = C.c_int
+        lib.em_solve_batch.argtypes = [vp, vp, i64, vp, vp, vp, f32, f32, f32, i32, f32, i32, vp, vp]
+        lib.em_solve_batch.restype = C.c_int
+        lib.em_solve_plain.argtypes = [vp, vp, i64, vp, vp, vp, vp, f32, f32, f32, i32, f32, i32, vp, vp]
+        lib.em_solve_plain.restype = C.c_int
+        lib.nlem_denoise.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, f32, f32, i32, f32,
+                                     vp, vp]
+        lib.nlem_denoise.restype = C.c_int
+        lib.nlem_denoise_multi.argtypes = [vp, vp, i32, C.POINTER(NlemImage), f32, f32, f32, i32, f32]
+        lib.nlem_denoise_multi.restype = C.c_int
+        lib.em_sync.argtypes = [vp, vp]
+        lib.em_sync.restype = C.c_int
+        lib.em_status_string.argtypes = [C.c_int]
+        lib.em_status_string.restype = C.c_char_p
+        lib.em_last_error.argtypes = [vp]
+        lib.em_last_error.restype = C.c_char_p
+        _lib = lib
+        return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Handle:
+    """An em_handle_t bound to one device (see em_create)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.em_create(C.byref(h), int(device))
+        if st != EM_OK:
+            raise EmxError(st, f"em_create(device={device}) failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.em_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != EM_OK:
+            msg = self.lib.em_last_error(self.h).decode()
+            raise EmxError(st, f"{what}: {self.lib.em_status_string(st).decode()} {msg}")
+
+    # -- calls ----------------------------------------------------------------
+
+    def em_solve_batch(self, a, w, inst, z, stats=None, *, lo, hi, rho, max_iter, tol,
+                       init=INIT_MAXW, stream=None):
+        """a, w: float32 device tensors; inst: device tensor of em_instance_t
+        (B x 32 bytes, e.g. an int64 tensor of shape [B, 4]); z: float32 device
+        tensor (in/out); stats: None or an int32/float32 device tensor of
+        B x 4 words."""
+        B = int(inst.numel() * inst.element_size() // 32)
+        st = self.lib.em_solve_batch(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
+                                     float(lo), float(hi), float(rho), int(max_iter), float(tol),
+                                     int(init), _ptr(z), _ptr(stats))
+        self._check(st, "em_solve_batch")
+
+    def em_solve_plain(self, a, w, inst, inst_host, z, stats=None, *, lo, hi, rho, max_iter, tol,
+                       init=INIT_MAXW, stream=None):
+        """As em_solve_batch, one launch per instance; inst_host is the same
+        descriptor array in host memory (numpy array or CPU tensor)."""
+        B = int(inst.numel() * inst.element_size() // 32)
+        hp = inst_host.ctypes.data if hasattr(inst_host, "ctypes") else inst_host.data_ptr()
+        st = self.lib.em_solve_plain(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
+                                     C.c_void_p(hp), float(lo), float(hi), float(rho),
+                                     int(max_iter), float(tol), int(init), _ptr(z), _ptr(stats))
+        self._check(st, "em_solve_plain")
+
+    def nlem_denoise(self, img, out, stats=None, *, patch_radius, window_radius, h, lo=0.0,
+                     hi=255.0, rho=1e-3, max_iter=200, tol=1e-4, stream=None):
+        """img: H x W float32 or float16 device tensor; out: H x W float32."""
+        import torch
+        H, W = int(img.shape[0]), int(img.shape[1])
+        is16 = 1 if img.dtype == torch.float16 else 0
+        st = self.lib.nlem_denoise(self.h, _stream(stream), _ptr(img), is16, H, W,
+                                   int(patch_radius), int(window_radius), float(h), float(lo),
+                                   float(hi), float(rho), int(max_iter), float(tol), _ptr(out),
+                                   _ptr(stats))
+        self._check(st, "nlem_denoise")
+
+    def nlem_denoise_multi(self, items, *, lo=0.0, hi=255.0, rho=1e-3, max_iter=200, tol=1e-4,
+                           stream=None):
+        """items: list of dicts with img, out, stats (optional), patch_radius,
+        window_radius, h."""
+        import torch
+        arr = (NlemImage * len(items))()
+        for k, it in enumerate(items):
+            img = it["img"]
+            arr[k] = NlemImage(img.data_ptr(), it["out"].data_ptr(),
+                               it["stats"].data_ptr() if it.get("stats") is not None else None,
+                               int(img.shape[0]), int(img.shape[1]), int(it["patch_radius"]),
+                               int(it["window_radius"]), float(it["h"]),
+                               1 if img.dtype == torch.float16 else 0)
+        self._keep = (arr, items)  # descriptors must outlive graph (re)creation
+        st = self.lib.nlem_denoise_multi(self.h, _stream(stream), len(items), arr, float(lo),
+                                         float(hi), float(rho), int(max_iter), float(tol))
+        self._check(st, "nlem_denoise_multi")
+
+    def sync(self, stream=None):
+        self._check(self.lib.em_sync(self.h, _stream(stream)), "em_sync")
+
+
+_handles = {}
+
+
+def handle(device: int = 0) -> Handle:
+    """A process-wide handle per device."""
+    h = _handles.get(device)
+    if h is None:
+        h = _handles[device] = Handle(device)
+    return h
+
+
+def stats_view(stats):
+    """Split a B x 4 int32 stats tensor into (iters, flags, r_pri, r_dual)."""
+    import torch
+    s = stats.view(torch.int32).reshape(-1, 4)
+    return s[:, 0], s[:, 1], s[:, 2].view(torch.float32), s[:, 3].view(torch.float32)
+
+
+def instances_tensor(inst_np, device="cuda"):
+    """Upload a numpy em_instance_t array (synth.pointsets.INSTANCE_DTYPE) as a
+    [B, 4] int64 device tensor with the same bytes."""
+    import numpy as np
+    import torch
+    raw = np.ascontiguousarray(inst_np).view(np.int64).reshape(-1, 4)
+    return torch.from_numpy(raw.copy()).to(device)

@@ -1,0 +1,137 @@
+// Device helpers shared by the EM-ADMM kernels (gfx950, wave64).
+//
+// Cross-lane sums use the CDNA4 lane-swap instructions
+//   v_permlane32_swap_b32 X, Y : X <- [X.lo32, Y.lo32], Y <- [X.hi32, Y.hi32]
+//   v_permlane16_swap_b32 X, Y : X <- [X.r0, Y.r0, X.r2, Y.r2], Y <- [X.r1, Y.r1, X.r3, Y.r3]
+// (r = 16-lane row) followed by DPP butterflies inside a row.  Summation
+// order is fixed, so every result is bit-reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace emx {
+
+__device__ __forceinline__ float swap32_sum(float x, float y) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_sum(float x, float y) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+// Sum over the 16 lanes of each row; every lane of the row receives it.
+__device__ __forceinline__ float row_sum16(float x) {
+    x += dpp<0xB1>(x);   // quad_perm [1,0,3,2]: lane ^ 1
+    x += dpp<0x4E>(x);   // quad_perm [2,3,0,1]: lane ^ 2
+    x += dpp<0x141>(x);  // row_half_mirror: pairs the two quads of each half-row
+    x += dpp<0x140>(x);  // row_mirror: pairs the two half-rows
+    return x;
+}
+
+// Sum over all 64 lanes; every lane receives it.
+__device__ __forceinline__ float wave_sum(float x) {
+    x = swap32_sum(x, x);
+    x = swap16_sum(x, x);
+    return row_sum16(x);
+}
+
+__device__ __forceinline__ float row_max16(float x) {
+    x = fmaxf(x, dpp<0xB1>(x));
+    x = fmaxf(x, dpp<0x4E>(x));
+    x = fmaxf(x, dpp<0x141>(x));
+    x = fmaxf(x, dpp<0x140>(x));
+    return x;
+}
+
+__device__ __forceinline__ float wave_max(float x) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+    auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    x = fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
+    return row_max16(x);
+}
+
+// Reduce-scatter of V per-lane values over the 64 lanes of a wave.
+//
+// After the call, for slot j < H2 and row r = lane / 16, out[j] holds (on all
+// 16 lanes of row r) the wave-wide sum of input coordinate
+//     rs_coord<V>(r, j) = j + (r & 1) * H2 + (r >> 1) * H1,
+// valid when rs_valid<V>(r, j); other (row, slot) pairs hold 0.
+// Cost: H1 + H2 swaps and adds, then 4 DPP adds per output slot.
+template <int V>
+struct RS {
+    static constexpr int H1 = (V + 1) / 2;
+    static constexpr int H2 = (H1 + 1) / 2;
+    static __host__ __device__ constexpr bool valid(int r, int j) {
+        return (j + (r & 1) * H2 < H1) && (j + (r & 1) * H2 + (r >> 1) * H1 < V);
+    }
+    static __host__ __device__ constexpr int coord(int r, int j) {
+        return j + (r & 1) * H2 + (r >> 1) * H1;
+    }
+    // inverse map: coordinate c -> row and slot
+    static __host__ __device__ constexpr int row_of(int c) {
+        return (c < H1) ? (c < H2 ? 0 : 1) : ((c - H1) < H2 ? 2 : 3);
+    }
+    static __host__ __device__ constexpr int slot_of(int c) {
+        return (c < H1) ? (c < H2 ? c : c - H2) : ((c - H1) < H2 ? c - H1 : c - H1 - H2);
+    }
+};
+
+template <int V>
+__device__ __forceinline__ void reduce_scatter(const float (&x)[V], float (&out)[RS<V>::H2]) {
+    constexpr int H1 = RS<V>::H1, H2 = RS<V>::H2;
+    float t[H1];
+#pragma unroll
+    for (int j = 0; j < H1; ++j) t[j] = swap32_sum(x[j], (j + H1 < V) ? x[j + H1] : 0.0f);
+#pragma unroll
+    for (int j = 0; j < H2; ++j) out[j] = swap16_sum(t[j], (j + H2 < H1) ? t[j + H2] : 0.0f);
+#pragma unroll
+    for (int j = 0; j < H2; ++j) out[j] = row_sum16(out[j]);
+}
+
+// Reads a wave-uniform float held by lane `lane` of a VGPR into an SGPR.
+__device__ __forceinline__ float readlane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ float readfirstlane(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Marks a wave-uniform condition as such, so the compiler branches on it
+// with scalar branches instead of exec masks (which would keep both sides'
+// register state alive).
+__device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfirstlane((int)b) != 0; }
+
+// Shrink factor of the block soft-threshold (closed-form prox of
+// lambda ||x - a||): x = v - s (v - a) with s = min(lambda, nu) / nu and
+// nu = ||v - a||.  s = 1 (x = a) whenever nu <= lambda, which also covers
+// nu = 0; lambda < 0 marks an absent point and gives s = 0.
+__device__ __forceinline__ float shrink(float nu2, float lambda) {
+    float s = (nu2 > lambda * lambda) ? lambda * __builtin_amdgcn_rsqf(nu2) : 1.0f;
+    return lambda < 0.0f ? 0.0f : s;
+}
+
+__device__ __forceinline__ float clampf(float x, float lo, float hi) {
+    return fminf(fmaxf(x, lo), hi);
+}
+
+// Symmetric (edge-repeating) reflection into [0, N), then clamped so that
+// positions the solver never reads still address valid memory.
+__device__ __forceinline__ int reflect_idx(int i, int N) {
+    i = (i < 0) ? (-i - 1) : i;
+    i = (i >= N) ? (2 * N - i - 1) : i;
+    return min(max(i, 0), N - 1);
+}
+
+}  // namespace emx

@@ -1,0 +1,472 @@
+// Host runtime of the C ABI declared in include/emx.h: argument validation,
+// handle-owned workspace, persistent-grid sizing and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "emx_internal.hpp"
+#include "nlem_table.hpp"
+
+namespace emx {
+
+// batch_kernel.hip
+em_status_t batch_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
+                        const float *w, const em_instance_t *inst, float lo, float hi, float rho,
+                        int32_t max_iter, float tol, int32_t init, float *z, em_stats_t *stats);
+em_status_t plain_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
+                        const float *w, const em_instance_t *inst, const em_instance_t *inst_host,
+                        float lo, float hi, float rho, int32_t max_iter, float tol, int32_t init,
+                        float *z, em_stats_t *stats);
+
+__global__ void reset_counters_kernel(unsigned int *c, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0u;
+}
+}  // namespace emx
+
+using namespace emx;
+
+struct MultiGraph {
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct em_context {
+    int device = 0;
+    int num_cus = 0;
+    unsigned int *counters = nullptr;  // kNumCounters work-queue heads
+    int num_counters = 0;
+    std::string last_error;
+    std::map<const void *, int> occupancy;
+    MultiGraph multi;
+    // batch workspace (grown on demand)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    // plain-path workspace
+    void *plain_ws = nullptr;
+    size_t plain_ws_bytes = 0;
+};
+
+static em_status_t fail(em_context *ctx, em_status_t st, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+static em_status_t hip_fail(em_context *ctx, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, EM_ERR_HIP, m);
+}
+
+#define EMX_HIP(ctx, call)                                  \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+    } while (0)
+
+namespace emx {
+
+int blocks_per_cu(em_context *ctx, const void *fn, int threads) {
+    auto it = ctx->occupancy.find(fn);
+    if (it != ctx->occupancy.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess || nb < 1) nb = 1;
+    ctx->occupancy[fn] = nb;
+    return nb;
+}
+
+int ctx_num_cus(em_context *ctx) { return ctx->num_cus; }
+int ctx_device(em_context *ctx) { return ctx->device; }
+
+em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg) { return fail(ctx, st, msg); }
+
+em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what) { return hip_fail(ctx, e, what); }
+
+// Work-queue heads: a fixed pool owned by the handle.
+unsigned int *ctx_counters(em_context *ctx, int n) {
+    if (n > ctx->num_counters) return nullptr;
+    return ctx->counters;
+}
+
+em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, int n) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3((n + 255) / 256), dim3(256), 0, s, c, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(ctx, e, "reset_counters launch");
+    return EM_OK;
+}
+
+// Device workspace of at least `bytes` (grown by reallocation; previous
+// contents are not preserved).  Synchronises the device before freeing.
+void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
+    *st = EM_OK;
+    if (bytes <= ctx->ws_bytes) return ctx->ws;
+    if (ctx->ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t cap = bytes + bytes / 4 + 4096;
+    if (hipMalloc(&ctx->ws, cap) != hipSuccess) {
+        ctx->ws = nullptr;
+        *st = fail(ctx, EM_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+        return nullptr;
+    }
+    ctx->ws_bytes = cap;
+    return ctx->ws;
+}
+
+void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
+    *st = EM_OK;
+    if (bytes <= ctx->plain_ws_bytes) return ctx->plain_ws;
+    if (ctx->plain_ws) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->plain_ws);
+        ctx->plain_ws = nullptr;
+        ctx->plain_ws_bytes = 0;
+    }
+    size_t cap = bytes + 4096;
+    if (hipMalloc(&ctx->plain_ws, cap) != hipSuccess) {
+        ctx->plain_ws = nullptr;
+        *st = fail(ctx, EM_ERR_OUT_OF_MEMORY, "plain workspace allocation failed");
+        return nullptr;
+    }
+    ctx->plain_ws_bytes = cap;
+    return ctx->plain_ws;
+}
+
+}  // namespace emx
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+
+static constexpr int kNumCounters = 256;
+
+extern "C" em_status_t em_create(em_handle_t *handle, int device) {
+    if (!handle) return EM_ERR_INVALID_ARG;
+    *handle = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return EM_ERR_HIP;
+    if (device < 0 || device >= ndev) return EM_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return EM_ERR_HIP;
+    em_context *ctx = new (std::nothrow) em_context();
+    if (!ctx) return EM_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete ctx;
+        return EM_ERR_HIP;
+    }
+    ctx->num_cus = prop.multiProcessorCount;
+    if (hipMalloc(&ctx->counters, kNumCounters * sizeof(unsigned int)) != hipSuccess) {
+        delete ctx;
+        return EM_ERR_OUT_OF_MEMORY;
+    }
+    if (hipMemset(ctx->counters, 0, kNumCounters * sizeof(unsigned int)) != hipSuccess) {
+        (void)hipFree(ctx->counters);
+        delete ctx;
+        return EM_ERR_HIP;
+    }
+    ctx->num_counters = kNumCounters;
+    *handle = ctx;
+    return EM_OK;
+}
+
+extern "C" em_status_t em_destroy(em_handle_t h) {
+    if (!h) return EM_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    if (h->multi.exec) (void)hipGraphExecDestroy(h->multi.exec);
+    if (h->multi.graph) (void)hipGraphDestroy(h->multi.graph);
+    if (h->counters) (void)hipFree(h->counters);
+    if (h->ws) (void)hipFree(h->ws);
+    if (h->plain_ws) (void)hipFree(h->plain_ws);
+    delete h;
+    return EM_OK;
+}
+
+extern "C" const char *em_status_string(em_status_t s) {
+    switch (s) {
+        case EM_OK: return "EM_OK";
+        case EM_ERR_INVALID_ARG: return "EM_ERR_INVALID_ARG";
+        case EM_ERR_UNSUPPORTED: return "EM_ERR_UNSUPPORTED";
+        case EM_ERR_OUT_OF_MEMORY: return "EM_ERR_OUT_OF_MEMORY";
+        case EM_ERR_HIP: return "EM_ERR_HIP";
+    }
+    return "EM_ERR_UNKNOWN";
+}
+
+extern "C" const char *em_last_error(em_handle_t h) { return h ? h->last_error.c_str() : ""; }
+
+extern "C" em_status_t em_sync(em_handle_t h, void *stream) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "asynchronous error");
+    return EM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// NLEM
+// ---------------------------------------------------------------------------
+
+static int points_per_lane(int R) { return ((2 * R + 1) * (2 * R + 1) + 63) / 64; }
+
+// Kernel for a shape: the default coordinate-wave count, or EMX_NLEM_WC when
+// that variant is compiled (a tuning override).
+static NlemKernelInfo select_nlem_kernel(int pr, int m) {
+    const char *env = getenv("EMX_NLEM_WC");
+    if (env && *env) {
+        NlemKernelInfo k = nlem_kernel(pr, m, atoi(env));
+        if (k.fn) return k;
+    }
+    return nlem_kernel(pr, m, nlem_default_wc(pr, m));
+}
+
+static em_status_t check_solver_params(em_context *ctx, float lo, float hi, float rho,
+                                       int32_t max_iter, float tol) {
+    if (!(rho > 0.0f) || !std::isfinite(rho)) return fail(ctx, EM_ERR_INVALID_ARG, "rho must be finite and > 0");
+    if (max_iter < 0) return fail(ctx, EM_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (!(tol >= 0.0f)) return fail(ctx, EM_ERR_INVALID_ARG, "tol must be >= 0 (not NaN)");
+    if (std::isnan(lo) || std::isnan(hi) || lo > hi) return fail(ctx, EM_ERR_INVALID_ARG, "need lo <= hi");
+    return EM_OK;
+}
+
+static em_status_t check_image(em_context *ctx, const nlem_image_t &im) {
+    if (!im.img || !im.out) return fail(ctx, EM_ERR_INVALID_ARG, "img and out must be non-NULL");
+    if (im.H < 1 || im.W < 1) return fail(ctx, EM_ERR_INVALID_ARG, "H and W must be >= 1");
+    if (im.patch_radius < 0 || im.window_radius < 0)
+        return fail(ctx, EM_ERR_INVALID_ARG, "radii must be >= 0");
+    if (!(im.h_param > 0.0f) || !std::isfinite(im.h_param))
+        return fail(ctx, EM_ERR_INVALID_ARG, "h must be finite and > 0");
+    if (im.patch_radius > EM_MAX_PATCH_RADIUS || im.window_radius > EM_MAX_WINDOW_RADIUS)
+        return fail(ctx, EM_ERR_UNSUPPORTED, "patch or window radius above the compiled limits");
+    if (im.patch_radius >= im.H || im.patch_radius >= im.W)
+        return fail(ctx, EM_ERR_INVALID_ARG, "patch radius must be < min(H, W)");
+    if ((int64_t)im.H * im.W >= (int64_t)1 << 31) return fail(ctx, EM_ERR_UNSUPPORTED, "image too large");
+    if ((const void *)im.out == im.img) return fail(ctx, EM_ERR_INVALID_ARG, "out must not alias img");
+    return EM_OK;
+}
+
+static NlemImageDesc make_desc(const nlem_image_t &im) {
+    NlemImageDesc d{};
+    d.img = im.img;
+    d.out = im.out;
+    d.stats = im.stats;
+    d.H = im.H;
+    d.W = im.W;
+    d.R = im.window_radius;
+    d.is_f16 = im.img_is_f16 ? 1 : 0;
+    const double h = im.h_param;
+    d.k_h = (float)(1.4426950408889634 / (h * h));
+    return d;
+}
+
+static void fill_common(NlemLaunch &L, float lo, float hi, float rho, int32_t max_iter, float tol) {
+    L.max_iter = max_iter;
+    L.inv_mu = 1.0f / rho;
+    L.lo = lo;
+    L.hi = hi;
+    L.tau = tol * (hi - lo);
+    L.tau_arm = 4.0f * L.tau;
+}
+
+struct NlemGroup {
+    int pr, m;
+    std::vector<int> images;
+};
+
+static std::vector<NlemGroup> group_images(int32_t count, const nlem_image_t *images) {
+    std::vector<NlemGroup> groups;
+    for (int i = 0; i < count; ++i) {
+        const int pr = images[i].patch_radius, m = points_per_lane(images[i].window_radius);
+        NlemGroup *g = nullptr;
+        for (auto &x : groups)
+            if (x.pr == pr && x.m == m && (int)x.images.size() < kMaxImagesPerLaunch) g = &x;
+        if (!g) {
+            groups.push_back(NlemGroup{pr, m, {}});
+            g = &groups.back();
+        }
+        g->images.push_back(i);
+    }
+    return groups;
+}
+
+static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, float lo, float hi,
+                              float rho, int32_t max_iter, float tol, unsigned int *counter) {
+    NlemLaunch L;
+    memset(&L, 0, sizeof(L));
+    fill_common(L, lo, hi, rho, max_iter, tol);
+    L.count = (int)g.images.size();
+    L.prefix[0] = 0;
+    for (int k = 0; k < L.count; ++k) {
+        const nlem_image_t &im = images[g.images[k]];
+        L.img[k] = make_desc(im);
+        L.prefix[k + 1] = L.prefix[k] + (int64_t)im.H * im.W;
+    }
+    L.counter = counter;
+    return L;
+}
+
+extern "C" em_status_t nlem_denoise(em_handle_t h, void *stream, const void *img, int32_t img_is_f16,
+                                    int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                                    float h_param, float lo, float hi, float rho, int32_t max_iter,
+                                    float tol, float *out, em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    nlem_image_t im{img, out, stats, H, W, patch_radius, window_radius, h_param, img_is_f16};
+    em_status_t st = check_image(h, im);
+    if (st != EM_OK) return st;
+    st = check_solver_params(h, lo, hi, rho, max_iter, tol);
+    if (st != EM_OK) return st;
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(h, EM_ERR_INVALID_ARG, "nlem needs a finite box");
+    EMX_HIP(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto groups = group_images(1, &im);
+    const NlemGroup &g = groups[0];
+    NlemKernelInfo k = select_nlem_kernel(g.pr, g.m);
+    NlemLaunch L = make_launch(g, &im, lo, hi, rho, max_iter, tol, h->counters);
+    st = ctx_reset_counters(h, s, h->counters, 1);
+    if (st != EM_OK) return st;
+    const int64_t total = L.prefix[L.count];
+    const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+    void *args[] = {&L};
+    EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
+    return EM_OK;
+}
+
+static bool same_key(const std::vector<char> &a, const std::vector<char> &b) {
+    return a.size() == b.size() && memcmp(a.data(), b.data(), a.size()) == 0;
+}
+
+extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t count,
+                                          const nlem_image_t *images, float lo, float hi, float rho,
+                                          int32_t max_iter, float tol) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (count < 0 || (count > 0 && !images)) return fail(h, EM_ERR_INVALID_ARG, "bad image list");
+    for (int i = 0; i < count; ++i) {
+        em_status_t st = check_image(h, images[i]);
+        if (st != EM_OK) return st;
+    }
+    em_status_t st = check_solver_params(h, lo, hi, rho, max_iter, tol);
+    if (st != EM_OK) return st;
+    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(h, EM_ERR_INVALID_ARG, "nlem needs a finite box");
+    if (count == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    std::vector<char> key(sizeof(nlem_image_t) * count + 5 * sizeof(float));
+    memcpy(key.data(), images, sizeof(nlem_image_t) * count);
+    float params[5] = {lo, hi, rho, (float)max_iter, tol};
+    memcpy(key.data() + sizeof(nlem_image_t) * count, params, sizeof(params));
+
+    if (!h->multi.exec || !same_key(key, h->multi.key)) {
+        if (h->multi.exec) (void)hipGraphExecDestroy(h->multi.exec);
+        if (h->multi.graph) (void)hipGraphDestroy(h->multi.graph);
+        h->multi.exec = nullptr;
+        h->multi.graph = nullptr;
+        auto groups = group_images(count, images);
+        if ((int)groups.size() > h->num_counters) return fail(h, EM_ERR_UNSUPPORTED, "too many shape groups");
+        hipGraph_t graph;
+        EMX_HIP(h, hipGraphCreate(&graph, 0));
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const NlemGroup &g = groups[gi];
+            NlemKernelInfo k = select_nlem_kernel(g.pr, g.m);
+            unsigned int *counter = h->counters + gi;
+            NlemLaunch L = make_launch(g, images, lo, hi, rho, max_iter, tol, counter);
+            // node 1: zero this group's work-queue head (a kernel, not a memset node)
+            hipKernelNodeParams rp{};
+            int one = 1;
+            void *rargs[] = {&counter, &one};
+            rp.func = reinterpret_cast<void *>(&reset_counters_kernel);
+            rp.gridDim = dim3(1);
+            rp.blockDim = dim3(64);
+            rp.sharedMemBytes = 0;
+            rp.kernelParams = rargs;
+            rp.extra = nullptr;
+            hipGraphNode_t rnode, knode;
+            hipError_t e = hipGraphAddKernelNode(&rnode, graph, nullptr, 0, &rp);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(h, e, "hipGraphAddKernelNode(reset)");
+            }
+            const int64_t total = L.prefix[L.count];
+            const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+            hipKernelNodeParams kp{};
+            void *kargs[] = {&L};
+            kp.func = const_cast<void *>(k.fn);
+            kp.gridDim = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, cap)));
+            kp.blockDim = dim3(k.threads);
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = kargs;
+            kp.extra = nullptr;
+            e = hipGraphAddKernelNode(&knode, graph, &rnode, 1, &kp);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(h, e, "hipGraphAddKernelNode(nlem)");
+            }
+        }
+        hipGraphExec_t exec;
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(h, e, "hipGraphInstantiate");
+        }
+        h->multi.graph = graph;
+        h->multi.exec = exec;
+        h->multi.key = key;
+    }
+    EMX_HIP(h, hipGraphLaunch(h->multi.exec, s));
+    return EM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch and plain
+// ---------------------------------------------------------------------------
+
+static em_status_t check_batch_args(em_context *h, int64_t B, const float *a, const float *w,
+                                    const em_instance_t *inst, float *z, float lo, float hi,
+                                    float rho, int32_t max_iter, float tol, int32_t init) {
+    if (B < 0) return fail(h, EM_ERR_INVALID_ARG, "B must be >= 0");
+    if (B > 0 && (!a || !w || !inst || !z)) return fail(h, EM_ERR_INVALID_ARG, "NULL array with B > 0");
+    if (B >= ((int64_t)1 << 31)) return fail(h, EM_ERR_UNSUPPORTED, "B too large");
+    if (init != EM_INIT_GIVEN && init != EM_INIT_MAXW) return fail(h, EM_ERR_INVALID_ARG, "bad init");
+    return check_solver_params(h, lo, hi, rho, max_iter, tol);
+}
+
+extern "C" em_status_t em_solve_batch(em_handle_t h, void *stream, int64_t B, const float *a,
+                                      const float *w, const em_instance_t *inst, float lo, float hi,
+                                      float rho, int32_t max_iter, float tol, int32_t init, float *z,
+                                      em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    em_status_t st = check_batch_args(h, B, a, w, inst, z, lo, hi, rho, max_iter, tol, init);
+    if (st != EM_OK) return st;
+    if (B == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return batch_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, lo, hi, rho, max_iter, tol,
+                       init, z, stats);
+}
+
+extern "C" em_status_t em_solve_plain(em_handle_t h, void *stream, int64_t B, const float *a,
+                                      const float *w, const em_instance_t *inst,
+                                      const em_instance_t *inst_host, float lo, float hi, float rho,
+                                      int32_t max_iter, float tol, int32_t init, float *z,
+                                      em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    em_status_t st = check_batch_args(h, B, a, w, inst, z, lo, hi, rho, max_iter, tol, init);
+    if (st != EM_OK) return st;
+    if (B > 0 && !inst_host) return fail(h, EM_ERR_INVALID_ARG, "inst_host is required");
+    if (B == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return plain_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, inst_host, lo, hi, rho,
+                       max_iter, tol, init, z, stats);
+}

@@ -1,0 +1,54 @@
+// Structures shared by the host runtime and the kernels (not part of the ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/emx.h"
+
+namespace emx {
+
+constexpr int kMaxImagesPerLaunch = 16;
+
+// One image of a denoising launch (passed by value inside the kernel arguments).
+struct NlemImageDesc {
+    const void *img;      // H x W, FP32 or FP16
+    float *out;           // H x W
+    em_stats_t *stats;    // nullable, H x W
+    int32_t H, W;
+    int32_t R;            // window radius
+    int32_t is_f16;
+    float k_h;            // log2(e) / h^2: w = exp2(-dist^2 * k_h)
+    int32_t pad_;
+};
+
+struct NlemLaunch {
+    NlemImageDesc img[kMaxImagesPerLaunch];
+    int64_t prefix[kMaxImagesPerLaunch + 1];  // pixel prefix sums
+    int32_t count;
+    int32_t max_iter;
+    float inv_mu;
+    float lo, hi;
+    float tau;       // tol * (hi - lo); 0 = fixed iteration count
+    float tau_arm;   // primal residual evaluated after an iteration with r_dual <= tau_arm
+    unsigned int *counter;  // work-queue head, zeroed before the launch
+};
+
+// Batch solve: a shape class of instances (listed in `list`).
+struct BatchLaunch {
+    const float *a;
+    const float *w;
+    const em_instance_t *inst;
+    const int32_t *list;       // instance ids of this class
+    const unsigned int *list_count;
+    unsigned int *counter;     // work-queue head, zeroed before the launch
+    float *z;
+    em_stats_t *stats;
+    float lo, hi, inv_mu_unused;
+    float mu;
+    float tol;
+    float arm;                 // factor on tol*D for arming the primal residual
+    int32_t max_iter;
+    int32_t init;
+};
+
+}  // namespace emx

@@ -1,0 +1,422 @@
+// Non-Local Euclidean Medians on gfx950: one persistent kernel that solves,
+// for every pixel, the box-constrained Euclidean median of the patches of its
+// search window with NLM weights (Section 3 of arXiv:1501.03879) by EM-ADMM
+// (Algorithm 1).
+//
+// Mapping
+//  * A workgroup of WC waves owns one pixel at a time (work queue, early
+//    exit per pixel).  It stages the (2(R+r)+1)^2 image tile around the pixel
+//    (symmetric reflection at the borders) into LDS once; every point a_j is
+//    then read from that tile, never materialised.
+//  * Wave w owns a fixed slice of the d = (2r+1)^2 patch coordinates; lane l
+//    owns window positions p = l + 64 q, q < M.  Per point and slice it keeps
+//    one state value g = e - a in registers for the whole solve, where e is
+//    the prox displacement s (v - a) of the last iteration.
+//  * Per iteration (exactly Algorithm 1, rewritten with the scaled multiplier
+//    u_k = y_k / mu; c = 2 z^t - z^{t-1}):
+//      delta = g + c = v_k - a_k             (v_k = z - u_k)
+//      nu^2  = ||delta||^2                    (slices summed through LDS)
+//      s     = min(lambda, nu) / nu           (closed-form prox, lambda = w/mu)
+//      E    += s delta  (= sum_k e_k),  g = s delta - a
+//      z'    = clamp(z - E / n, lo, hi)       (the unweighted mean of x_k + u_k)
+//    so x_k = v_k - e_k and u_k' = z - z' - e_k are implicit.  The first
+//    iteration's nu^2 equals ||P_i - P_j||^2 (z starts at P_i, u = 0), which
+//    gives the NLM weights w_j = exp(-nu^2 / h^2) without a separate pass.
+//  * Sums over points: in-lane, then a permlane/DPP reduce-scatter across the
+//    wave; z, c live in a reduced layout (16 lanes per coordinate) and c is
+//    broadcast to SGPRs for the next pass.
+#pragma once
+
+#include <float.h>
+#include <hip/hip_fp16.h>
+
+#include "em_device.hpp"
+#include "emx_internal.hpp"
+
+namespace emx {
+
+// Slices with at most this many point values per lane keep the points in
+// registers (read from the LDS tile once per pixel).
+constexpr int kKeepPointsInRegs = 64;
+
+template <int M>
+constexpr int rmax_for() {
+    int r = 0;
+    while ((2 * (r + 1) + 1) * (2 * (r + 1) + 1) <= 64 * M) ++r;
+    return r;
+}
+
+template <int PR, int M, int WC>
+struct NlemShape {
+    static constexpr int PS = 2 * PR + 1;
+    static constexpr int D = PS * PS;
+    static constexpr int RMAX = rmax_for<M>();
+    static constexpr int WSM = 2 * RMAX + 1;
+    static constexpr int TW = 2 * (RMAX + PR) + 1;
+    // Pitch: consecutive window rows start 32 floats apart modulo 32 banks
+    // after a full row of WSM points, so 32 consecutive lanes hit 32 banks.
+    static constexpr int P = WSM + 32;
+    static constexpr int TILE = TW * P;
+    static constexpr int DS = (D + WC - 1) / WC;
+    static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
+};
+
+template <int PR, int M, int WC, int SW>
+__device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, float *xn, float *xs,
+                                          float *zpE, float *cvec, unsigned int *item_s) {
+    using S = NlemShape<PR, M, WC>;
+    constexpr int J0 = SW * S::DS;
+    constexpr int NJ = (S::D - J0 < S::DS) ? (S::D - J0) : S::DS;
+    using RSx = RS<NJ>;
+    constexpr int H2 = RSx::H2;
+    constexpr int JC = (S::D - 1) / 2;  // centre coordinate
+
+    const int lane = threadIdx.x & 63;
+    const int row = lane >> 4;
+    // per-wave: z^{t-1}, then E^t, [slot][row]; strided by the largest slice
+    float *zp_s = zpE + SW * 2 * RS<S::DS>::H2 * 4;
+    float *Ep_s = zp_s + H2 * 4;
+    float *cv = cvec + SW * S::DS;        // per-wave: c = 2 z^t - z^{t-1} of the slice
+    // points stay in registers when they fit (the compiler hoists the tile reads)
+    constexpr bool kKeep = M * NJ <= kKeepPointsInRegs;
+    // tile offset of slice coordinate jj within a patch (folded after unrolling)
+    auto poff = [](int jj) { return ((J0 + jj) / S::PS) * S::P + ((J0 + jj) % S::PS); };
+
+    for (;;) {
+        if (threadIdx.x == 0) *item_s = atomicAdd(L.counter, 1u);
+        __syncthreads();
+        const int64_t item = (int64_t)(unsigned int)uniform_int((int)*item_s);
+        if (item >= L.prefix[L.count]) break;
+        int b = 0;
+        while (b + 1 < L.count && item >= L.prefix[b + 1]) ++b;
+        const NlemImageDesc I = L.img[b];
+        const int pix = (int)(item - L.prefix[b]);
+        const int H = I.H, W = I.W, R = I.R;
+        const int iy = pix / W, ix = pix - (pix / W) * W;
+        const int WSr = 2 * R + 1;
+        const int TWr = 2 * (R + PR) + 1;
+
+        // ---- a1: stage the tile (rows iy-R-r .. iy+R+r), reflected at borders
+        for (int idx = threadIdx.x; idx < TWr * TWr; idx += 64 * WC) {
+            const int ty = idx / TWr, tx = idx - (idx / TWr) * TWr;
+            const int gy = reflect_idx(iy - R - PR + ty, H);
+            const int gx = reflect_idx(ix - R - PR + tx, W);
+            float v;
+            if (I.is_f16)
+                v = __half2float(reinterpret_cast<const __half *>(I.img)[(int64_t)gy * W + gx]);
+            else
+                v = reinterpret_cast<const float *>(I.img)[(int64_t)gy * W + gx];
+            tile[ty * S::P + tx] = v;
+        }
+        __syncthreads();
+
+        // ---- points owned by this lane: window slot p -> tile offset of its patch
+        const int y0 = max(iy - R, 0), y1 = min(iy + R, H - 1);
+        const int x0 = max(ix - R, 0), x1 = min(ix + R, W - 1);
+        const int n = (y1 - y0 + 1) * (x1 - x0 + 1);
+        const float inv_ws = 1.0f / (float)WSr;
+        int base[M];
+        float lam[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int p = lane + 64 * q;
+            const int wy = (int)(((float)p + 0.5f) * inv_ws);
+            const int wx = p - wy * WSr;
+            const int py = iy - R + wy, px = ix - R + wx;
+            const bool valid = (p < WSr * WSr) && py >= 0 && py < H && px >= 0 && px < W;
+            base[q] = valid ? (wy * S::P + wx) : 0;
+            lam[q] = valid ? 0.0f : -1.0f;
+        }
+
+        // ---- a3: z = P_i (unprojected), u = 0  (so g = -a, c = z)
+        const int cbase = R * S::P + R;
+        float zr[H2];
+#pragma unroll
+        for (int j = 0; j < H2; ++j) {
+            const int cc = J0 + RSx::coord(row, j);
+            const bool vj = RSx::valid(row, j);
+            const float zv = tile[cbase + (cc / S::PS) * S::P + (cc % S::PS)];
+            zr[j] = vj ? zv : 0.0f;
+            if (lane == 16 * row) {
+                zp_s[j * 4 + row] = zr[j];
+                Ep_s[j * 4 + row] = 0.0f;
+                if (vj) cv[RSx::coord(row, j)] = zr[j];
+            }
+        }
+        float g[M][NJ];
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) g[q][jj] = -tile[base[q] + poff(jj)];
+
+        const float inv_n = 1.0f / (float)n;
+        const float fn = (float)n;
+        const float inv_d = 1.0f / (float)S::D;
+        const float inv_nd = 1.0f / ((float)n * (float)S::D);
+        const int max_iter = L.max_iter;
+        const float tau2 = L.tau * L.tau;
+        const float arm2 = L.tau_arm * L.tau_arm;
+
+        int iters = 0, flags = EM_MAXITER;
+        float rp2 = 0.0f, rd2 = 0.0f;  // mean squares of the last evaluated iteration
+        float rd_w = 0.0f, rp_w = 0.0f;
+        bool armed_last = false, bad = false, done = false;
+        int t = 1;
+        for (; t <= max_iter; ++t) {
+            // Large slices read the points from the LDS tile every iteration;
+            // without this the compiler hoists the loop-invariant tile reads
+            // and keeps all M*NJ points live in registers.
+            if constexpr (!kKeep) asm volatile("" ::: "memory");
+            // ---- a4 (first half): delta = g + c, partial ||delta||^2
+            float nrm[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) nrm[q] = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const float cj = cv[jj];
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    g[q][jj] += cj;
+                    nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                }
+            }
+            float rd_all = rd_w, rp_all = rp_w;
+            if constexpr (WC > 1) {
+                float *X = xn + (t & 1) * WC * M * 64;
+                float *XS = xs + (t & 1) * WC * 4;
+#pragma unroll
+                for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = nrm[q];
+                if (lane == 0) {
+                    XS[SW * 4 + 0] = rd_w;
+                    XS[SW * 4 + 1] = rp_w;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
+                    nrm[q] = sum;
+                }
+                rd_all = 0.0f;
+                rp_all = 0.0f;
+#pragma unroll
+                for (int w = 0; w < WC; ++w) {
+                    rd_all += XS[w * 4 + 0];
+                    rp_all += XS[w * 4 + 1];
+                }
+                rd_all = readfirstlane(rd_all);
+                rp_all = readfirstlane(rp_all);
+            }
+            // ---- a8: stop test for iteration t-1 (all waves hold identical sums)
+            if (t > 1) {
+                rd2 = rd_all * inv_d;
+                rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                if (uniform(tau2 > 0.0f && armed_last && rp2 <= tau2 && rd2 <= tau2)) {
+                    flags = EM_CONVERGED;
+                    iters = t - 1;
+                    done = true;
+                    break;
+                }
+            }
+            // ---- a2: NLM weights from the first iteration's distances
+            if (t == 1) {
+                bool nonfinite = false;
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    if (lam[q] >= 0.0f) {
+                        nonfinite |= !(nrm[q] <= FLT_MAX);
+                        lam[q] = exp2f(-nrm[q] * I.k_h) * L.inv_mu;
+                    }
+                }
+                if (__any(nonfinite)) {
+                    bad = true;
+                    break;
+                }
+            }
+            const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
+            float s[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
+
+            // ---- a8 (armed iterations only): lane sums of ||x_k - c||^2 with
+            // x_k = v_k - e_k = a_k + (1 - s) delta, read-only on the state
+            float rp_lane = 0.0f;
+            if (armed) {
+                float rq[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) rq[q] = 0.0f;
+                float na[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(0)];
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    const float cj = cv[jj];
+                    float cur[M];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) cur[q] = na[q];
+                    if (jj + 1 < NJ) {
+#pragma unroll
+                        for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(jj + 1)];
+                    }
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const float y = fmaf(1.0f - s[q], g[q][jj], -(cur[q] + cj));
+                        rq[q] = fmaf(y, y, rq[q]);
+                    }
+                    if constexpr (!kKeep) __builtin_amdgcn_sched_barrier(0);
+                }
+                // Absent window slots need no mask: their s is 0 and their state
+                // stays g = -a, so delta and -(-a + c) round identically, y = 0.
+#pragma unroll
+                for (int q = 0; q < M; ++q) rp_lane += rq[q];
+            }
+            // keep the two passes' tile reads separate (no values carried over)
+            if constexpr (!kKeep) asm volatile("" ::: "memory");
+
+            // ---- a4 (second half) + a5 partial sums: E = sum_k s delta, g = s delta - a
+            // (tile reads pipelined one coordinate ahead)
+            float acc[NJ];
+            {
+                float na[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(0)];
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    float cur[M];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) cur[q] = na[q];
+                    if (jj + 1 < NJ) {
+#pragma unroll
+                        for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(jj + 1)];
+                    }
+                    float ac = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const float d = g[q][jj];
+                        ac = fmaf(s[q], d, ac);
+                        g[q][jj] = fmaf(s[q], d, cur[q]);
+                    }
+                    acc[jj] = ac;
+                    if constexpr (!kKeep) __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // Materialise the new state here: otherwise the updates are sunk
+            // past the reductions and delta and the points stay live meanwhile.
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) asm volatile("" : "+v"(g[q][jj]));
+            // ---- a5: reduce over the wave; a6: z-update; a7 implicit in g and c
+            float E[H2];
+            reduce_scatter<NJ>(acc, E);
+            float rdx = 0.0f, rpx = 0.0f;
+#pragma unroll
+            for (int j = 0; j < H2; ++j) {
+                const bool vj = RSx::valid(row, j);
+                const float zn = clampf(zr[j] - E[j] * inv_n, L.lo, L.hi);
+                const float dz = zn - zr[j];
+                const float zpj = zp_s[j * 4 + row];
+                if (armed) {
+                    // sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
+                    // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1}
+                    const float Epj = Ep_s[j * 4 + row];
+                    const float cz = (2.0f * zr[j] - zpj) - zn;
+                    rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
+                }
+                rdx += vj ? dz * dz : 0.0f;
+                if (lane == 16 * row) {
+                    zp_s[j * 4 + row] = zr[j];
+                    Ep_s[j * 4 + row] = E[j];
+                    if (vj) cv[RSx::coord(row, j)] = 2.0f * zn - zr[j];
+                }
+                zr[j] = vj ? zn : 0.0f;
+            }
+            rd_w = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) + (readlane(rdx, 32) + readlane(rdx, 48)));
+            if (armed) {
+                const float tot = wave_sum(rp_lane);
+                rp_w = readfirstlane(readfirstlane(tot) +
+                       ((readlane(rpx, 0) + readlane(rpx, 16)) + (readlane(rpx, 32) + readlane(rpx, 48))));
+            } else {
+                rp_w = 0.0f;
+            }
+            armed_last = armed;
+        }
+
+        if (!done && !bad) {
+            iters = max_iter;
+            if (max_iter >= 1) {
+                float rd_all = rd_w, rp_all = rp_w;
+                if constexpr (WC > 1) {
+                    float *XS = xs + (t & 1) * WC * 4;
+                    if (lane == 0) {
+                        XS[SW * 4 + 0] = rd_w;
+                        XS[SW * 4 + 1] = rp_w;
+                    }
+                    __syncthreads();
+                    rd_all = 0.0f;
+                    rp_all = 0.0f;
+#pragma unroll
+                    for (int w = 0; w < WC; ++w) {
+                        rd_all += XS[w * 4 + 0];
+                        rp_all += XS[w * 4 + 1];
+                    }
+                    rd_all = readfirstlane(rd_all);
+                    rp_all = readfirstlane(rp_all);
+                }
+                rd2 = rd_all * inv_d;
+                rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                flags = (tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
+            }
+        }
+        if (bad) {
+            flags = EM_BAD_INPUT;
+            iters = 0;
+            rp2 = 0.0f;
+            rd2 = 0.0f;
+        }
+
+        // ---- a9: the centre coordinate of the solution patch
+        if constexpr (JC >= J0 && JC < J0 + NJ) {
+            constexpr int rc = RSx::row_of(JC - J0);
+            constexpr int sc = RSx::slot_of(JC - J0);
+            if (lane == 16 * rc) I.out[pix] = bad ? __builtin_nanf("") : zr[sc];
+        }
+        if (SW == 0 && lane == 0 && I.stats != nullptr) {
+            em_stats_t st;
+            st.iters = iters;
+            st.flags = flags;
+            st.r_pri = sqrtf(rp2);
+            st.r_dual = sqrtf(rd2);
+            I.stats[pix] = st;
+        }
+    }
+}
+
+template <int PR, int M, int WC, int SW>
+__device__ __forceinline__ void nlem_dispatch(int wave, const NlemLaunch &L, float *tile, float *xn,
+                                              float *xs, float *zpE, float *cvec, unsigned int *item_s) {
+    if constexpr (SW + 1 == WC) {
+        nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, zpE, cvec, item_s);
+    } else {
+        if (wave == SW)
+            nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, zpE, cvec, item_s);
+        else
+            nlem_dispatch<PR, M, WC, SW + 1>(wave, L, tile, xn, xs, zpE, cvec, item_s);
+    }
+}
+
+template <int PR, int M, int WC>
+__global__ __launch_bounds__(64 * WC, 2) void nlem_solve_kernel(NlemLaunch L) {
+    using S = NlemShape<PR, M, WC>;
+    __shared__ float tile[S::TILE];
+    __shared__ float xn[S::XN];
+    __shared__ float xs[2 * WC * 4];
+    __shared__ float zpE[WC * 2 * RS<S::DS>::H2 * 4 + 8];
+    __shared__ float cvec[WC * S::DS];
+    __shared__ unsigned int item_s;
+    const int wave = uniform_int(threadIdx.x >> 6);
+    nlem_dispatch<PR, M, WC, 0>(wave, L, tile, xn, xs, zpE, cvec, &item_s);
+}
+
+}  // namespace emx

@@ -1,0 +1,35 @@
+// Table of compiled NLEM kernel shapes (one translation unit per patch radius).
+#pragma once
+
+namespace emx {
+
+struct NlemKernelInfo {
+    const void *fn;  // nullptr when the shape is not compiled
+    int threads;
+};
+
+// m = points per lane (1..7), wc = waves per pixel over the patch coordinates
+NlemKernelInfo nlem_kernels_pr0(int m, int wc);
+NlemKernelInfo nlem_kernels_pr1(int m, int wc);
+NlemKernelInfo nlem_kernels_pr2(int m, int wc);
+NlemKernelInfo nlem_kernels_pr3(int m, int wc);
+
+// Default coordinate-wave count per (patch radius, points per lane): the
+// smallest count whose register state fits two waves per SIMD without spills.
+inline int nlem_default_wc(int pr, int m) {
+    if (pr <= 1) return 1;
+    if (pr == 2) return (m <= 3) ? 1 : 2;
+    return (m <= 3) ? 2 : 3;
+}
+
+inline NlemKernelInfo nlem_kernel(int pr, int m, int wc) {
+    switch (pr) {
+        case 0: return nlem_kernels_pr0(m, wc);
+        case 1: return nlem_kernels_pr1(m, wc);
+        case 2: return nlem_kernels_pr2(m, wc);
+        case 3: return nlem_kernels_pr3(m, wc);
+    }
+    return NlemKernelInfo{nullptr, 0};
+}
+
+}  // namespace emx

@@ -1,0 +1,77 @@
+"""Shared helpers for the GPU parity tests (run the HIP path through the C ABI
+and the FP64 oracle on the same input bits)."""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    return torch.device("cuda:0")
+
+
+def handle():
+    import paper_1501_03879_amd as emx
+    return emx.handle(0)
+
+
+def run_nlem(img_np, pr, wr, h, mu, max_iter, tol, lo=0.0, hi=255.0, fp16=False):
+    """NLEM on the GPU; returns (out float64 [H*W], stats dict of numpy arrays)."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    t = torch.from_numpy(np.ascontiguousarray(img_np, dtype=np.float32)).to(dev)
+    if fp16:
+        t = t.half()
+    out = torch.full(t.shape, -7.0, dtype=torch.float32, device=dev)
+    stats = torch.zeros((t.numel(), 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    hd.nlem_denoise(t, out, stats, patch_radius=pr, window_radius=wr, h=h, lo=lo, hi=hi, rho=mu,
+                    max_iter=max_iter, tol=tol)
+    hd.sync()
+    it, fl, rp, rd = emx.stats_view(stats)
+    return (out.cpu().numpy().reshape(-1).astype(np.float64),
+            dict(iters=it.cpu().numpy(), flags=fl.cpu().numpy(), r_pri=rp.cpu().numpy(),
+                 r_dual=rd.cpu().numpy()))
+
+
+def run_batch(batch, mu, max_iter, tol, init, z0=None, plain=False):
+    """em_solve_batch (or em_solve_plain) on the GPU for a synth.PointSetBatch."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    a = torch.from_numpy(np.ascontiguousarray(batch.a, dtype=np.float32)).to(dev)
+    w = torch.from_numpy(np.ascontiguousarray(batch.w, dtype=np.float32)).to(dev)
+    inst = emx.instances_tensor(batch.inst, dev)
+    zsz = max(batch.z_size, 1)
+    if z0 is None:
+        z = torch.zeros(zsz, dtype=torch.float32, device=dev)
+    else:
+        z = torch.from_numpy(np.ascontiguousarray(z0, dtype=np.float32)).to(dev)
+    stats = torch.zeros((max(batch.B, 1), 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    if plain:
+        hd.em_solve_plain(a, w, inst, np.ascontiguousarray(batch.inst), z, stats, lo=batch.lo,
+                          hi=batch.hi, rho=mu, max_iter=max_iter, tol=tol, init=init)
+    else:
+        hd.em_solve_batch(a, w, inst, z, stats, lo=batch.lo, hi=batch.hi, rho=mu,
+                          max_iter=max_iter, tol=tol, init=init)
+    hd.sync()
+    it, fl, rp, rd = emx.stats_view(stats)
+    return (z.cpu().numpy().astype(np.float64),
+            dict(iters=it.cpu().numpy()[:batch.B], flags=fl.cpu().numpy()[:batch.B],
+                 r_pri=rp.cpu().numpy()[:batch.B], r_dual=rd.cpu().numpy()[:batch.B]))
+
+
+def rel_errors(got, ref, D):
+    """(max |got - ref| / D, rms |got - ref| / D) over finite reference entries."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    diff = np.abs(got - ref) / D
+    return float(diff.max()) if diff.size else 0.0, float(np.sqrt(np.mean(diff ** 2))) if diff.size else 0.0
+
+
+def report(name, emax, erms):
+    print(f"[parity] {name}: max_rel={emax:.3e} rms_rel={erms:.3e}", flush=True)

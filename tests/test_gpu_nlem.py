@@ -1,0 +1,202 @@
+"""GPU parity of nlem_denoise against the FP64 oracle (Section 3 pipeline:
+patches, truncated window, NLM weights, EM-ADMM per pixel, centre pixel).
+
+Tolerance: max |gpu - oracle| <= 1e-4 * (hi - lo) per output pixel with FP32
+image storage, 2e-3 with FP16 storage (the oracle then sees the FP32 image).
+In tolerance mode the GPU's per-pixel iteration count is fed back to the
+oracle (fixed-iteration rerun), since both sides stop on a float decision.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_errors, report, run_nlem
+
+pytestmark = pytest.mark.gpu
+D = 255.0
+
+
+def _small(seed, H, W, sigma=20.0):
+    rng = np.random.default_rng(seed)
+    return synth.add_gaussian_noise(rng, synth.piecewise_smooth_image(rng, H, W), sigma).astype(np.float32)
+
+
+def test_small_config_full_image_fixed_iterations():
+    """64x64 gradient+shapes, r=2, R=5, mu=1, exactly 50 iterations: every pixel."""
+    wl = synth.nlem_small()
+    im = wl.images[0]
+    got, st = run_nlem(im.noisy, im.patch_radius, im.window_radius, im.h, wl.mu, wl.max_iter, wl.tol)
+    ref = oracle.nlem(im.noisy, im.patch_radius, im.window_radius, im.h, 0, 255, wl.mu, wl.max_iter, 0.0)
+    emax, erms = rel_errors(got, ref["out"], D)
+    report("nlem 64x64 r2 R5 T50", emax, erms)
+    assert emax <= 1e-4
+    assert np.all(st["iters"] == 50) and np.all(st["flags"] == 2)
+
+
+@pytest.mark.parametrize("pr,wr,H,W,T", [(0, 2, 9, 11, 7), (1, 3, 13, 10, 9), (2, 7, 21, 17, 6),
+                                         (3, 4, 12, 15, 8), (3, 10, 24, 26, 5), (2, 10, 23, 30, 4),
+                                         (1, 9, 20, 22, 5), (3, 6, 17, 19, 6), (3, 8, 19, 18, 5)])
+def test_shapes_fixed_iterations(pr, wr, H, W, T):
+    """Every compiled (patch, window) class, ragged image sizes, all pixels."""
+    img = _small(pr * 100 + wr, H, W)
+    got, st = run_nlem(img, pr, wr, 10.0 * 20, 1e-3, T, 0.0)
+    ref = oracle.nlem(img, pr, wr, 200.0, 0, 255, 1e-3, T, 0.0)
+    emax, erms = rel_errors(got, ref["out"], D)
+    report(f"nlem {H}x{W} r{pr} R{wr} T{T}", emax, erms)
+    assert emax <= 1e-4
+
+
+def test_tiny_images_and_degenerate_windows():
+    """Windows larger than the image, one-row images, 2x2 images."""
+    for (H, W, pr, wr) in ((1, 7, 0, 3), (3, 5, 1, 2), (2, 2, 1, 1), (7, 4, 3, 10), (5, 9, 2, 10)):
+        img = _small(H * 31 + W, H, W)
+        got, _ = run_nlem(img, pr, wr, 150.0, 1e-2, 6, 0.0)
+        ref = oracle.nlem(img, pr, wr, 150.0, 0, 255, 1e-2, 6, 0.0)
+        emax, erms = rel_errors(got, ref["out"], D)
+        report(f"nlem tiny {H}x{W} r{pr} R{wr}", emax, erms)
+        assert emax <= 1e-4
+
+
+def test_zero_iterations_returns_noisy_image():
+    img = _small(5, 16, 16)
+    got, st = run_nlem(img, 3, 10, 200.0, 1e-3, 0, 1e-4)
+    np.testing.assert_array_equal(got, img.reshape(-1).astype(np.float64))
+    assert np.all(st["iters"] == 0)
+
+
+def test_constant_image():
+    img = np.full((20, 23), 113.0, dtype=np.float32)
+    got, st = run_nlem(img, 3, 10, 200.0, 1e-3, 50, 1e-4)
+    np.testing.assert_allclose(got, 113.0, atol=1e-3)
+    assert np.all(st["flags"] == 1)
+
+
+def test_256_tolerance_mode_sampled():
+    """The 256x256 sigma-20 image at d=49, n<=441, tol 1e-4, <=200 iterations:
+    whole image on the GPU; 1536 sampled pixels (corners, borders, interior)
+    recomputed by the oracle at the GPU's iteration counts."""
+    wl = synth.nlem_256()
+    im = wl.images[0]
+    got, st = run_nlem(im.noisy, 3, 10, im.h, wl.mu, wl.max_iter, wl.tol)
+    H, W = im.noisy.shape
+    rng = np.random.default_rng(0)
+    border = [i for i in range(H * W) if min(i // W, i % W, H - 1 - i // W, W - 1 - i % W) < 10]
+    pix = np.unique(np.concatenate([[0, W - 1, (H - 1) * W, H * W - 1],
+                                    rng.choice(border, 512, replace=False),
+                                    rng.choice(H * W, 1020, replace=False)]))
+    ref = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, 0.0, pix=pix,
+                      max_iter_each=st["iters"][pix])
+    emax, erms = rel_errors(got[pix], ref["out"], D)
+    report("nlem 256x256 tol-mode (sampled, oracle at GPU iterations)", emax, erms)
+    assert emax <= 1e-4
+    # the stop was legitimate: residuals at the GPU's count are within tol (FP32 slack 5%)
+    tau = wl.tol * D
+    ok = (ref["r_pri"] <= 1.05 * tau) & (ref["r_dual"] <= 1.05 * tau)
+    conv = st["flags"][pix] == 1
+    assert np.all(ok[conv])
+    # and not late: compare with the oracle's own stopping iteration
+    own = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, wl.tol, pix=pix)
+    diff = st["iters"][pix] - own["iters"]
+    print(f"[parity] iteration count gpu - oracle: mean {diff.mean():.3f}, "
+          f"|diff|<=1 for {np.mean(np.abs(diff) <= 1):.3f}", flush=True)
+    assert np.mean(np.abs(diff) <= 1) >= 0.95
+    assert np.mean(st["flags"] == 1) >= 0.99
+
+
+def test_fp16_storage():
+    """FP16 image storage: within 2e-3 of the FP32-image oracle, and within
+    1e-4 of the oracle fed the FP16-rounded image."""
+    wl = synth.nlem_512_mixed(fp16_storage=True)
+    img = wl.images[0].noisy[:40, :48].copy()
+    got, _ = run_nlem(img, 3, 10, 300.0, wl.mu, 20, 0.0, fp16=True)
+    ref32 = oracle.nlem(img, 3, 10, 300.0, 0, 255, wl.mu, 20, 0.0)
+    ref16 = oracle.nlem(img.astype(np.float16).astype(np.float32), 3, 10, 300.0, 0, 255, wl.mu, 20, 0.0)
+    e32, r32 = rel_errors(got, ref32["out"], D)
+    e16, r16 = rel_errors(got, ref16["out"], D)
+    report("nlem fp16 storage vs fp32-image oracle", e32, r32)
+    report("nlem fp16 storage vs fp16-image oracle", e16, r16)
+    assert e32 <= 2e-3
+    assert e16 <= 1e-4
+
+
+def test_nonfinite_pixel_flags_neighbourhood():
+    """A NaN pixel makes every window that reaches it BAD_INPUT (output NaN);
+    pixels whose windows avoid it are unaffected."""
+    img = _small(9, 30, 30)
+    img[5, 6] = np.nan
+    got, st = run_nlem(img, 1, 2, 200.0, 1e-3, 10, 0.0)
+    H, W = img.shape
+    yy, xx = np.divmod(np.arange(H * W), W)
+    touched = (np.abs(yy - 5) <= 3) & (np.abs(xx - 6) <= 3)   # R + r = 3
+    far = (np.abs(yy - 5) > 6) | (np.abs(xx - 6) > 6)
+    bad = st["flags"] == 8
+    np.testing.assert_array_equal(bad, touched)
+    assert np.all(np.isnan(got[bad]))
+    clean = img.copy()
+    clean[5, 6] = 0.0
+    ref = oracle.nlem(img, 1, 2, 200.0, 0, 255, 1e-3, 10, 0.0, pix=np.flatnonzero(far))
+    emax, _ = rel_errors(got[far], ref["out"], D)
+    assert emax <= 1e-4
+
+
+def test_multi_image_graph():
+    """Several images of different sizes and radii in one captured graph,
+    launched twice (the second launch replays the cached graph)."""
+    import torch
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    dev = gpu()
+    specs = [(31, 40, 2, 5), (25, 22, 3, 10), (40, 33, 3, 7), (18, 27, 2, 10), (33, 29, 1, 4)]
+    imgs, items = [], []
+    for k, (H, W, pr, wr) in enumerate(specs):
+        im = _small(700 + k, H, W)
+        imgs.append(im)
+        t = torch.from_numpy(im).to(dev)
+        items.append(dict(img=t, out=torch.zeros_like(t), patch_radius=pr, window_radius=wr, h=200.0,
+                          stats=torch.zeros((H * W, 4), dtype=torch.int32, device=dev)))
+    hd = handle()
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(-1.0)
+        hd.nlem_denoise_multi(items, lo=0.0, hi=255.0, rho=1e-3, max_iter=9, tol=0.0)
+        hd.sync()
+        for (H, W, pr, wr), im, it in zip(specs, imgs, items):
+            ref = oracle.nlem(im, pr, wr, 200.0, 0, 255, 1e-3, 9, 0.0)
+            emax, erms = rel_errors(it["out"].cpu().numpy().reshape(-1), ref["out"], D)
+            report(f"multi rep{rep} {H}x{W} r{pr} R{wr}", emax, erms)
+            assert emax <= 1e-4
+            assert np.all(emx.stats_view(it["stats"])[0].cpu().numpy() == 9)
+
+
+def test_invalid_arguments_rejected():
+    import torch
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    dev = gpu()
+    hd = handle()
+    img = torch.zeros((8, 8), device=dev)
+    out = torch.zeros_like(img)
+    bad = [dict(patch_radius=-1, window_radius=2, h=1.0), dict(patch_radius=1, window_radius=2, h=0.0),
+           dict(patch_radius=1, window_radius=2, h=1.0, rho=0.0),
+           dict(patch_radius=1, window_radius=2, h=1.0, max_iter=-1),
+           dict(patch_radius=1, window_radius=2, h=1.0, tol=-1.0),
+           dict(patch_radius=1, window_radius=2, h=1.0, lo=5.0, hi=1.0),
+           dict(patch_radius=1, window_radius=2, h=1.0, lo=float("-inf"), hi=1.0)]
+    for kw in bad:
+        with pytest.raises(emx.EmxError) as ei:
+            hd.nlem_denoise(img, out, None, **kw)
+        assert ei.value.status == emx.EM_ERR_INVALID_ARG
+    with pytest.raises(emx.EmxError) as ei:   # patch radius must be < min(H, W)
+        hd.nlem_denoise(torch.zeros((3, 9), device=dev), torch.zeros((3, 9), device=dev), None,
+                        patch_radius=3, window_radius=2, h=1.0)
+    assert ei.value.status == emx.EM_ERR_INVALID_ARG
+    with pytest.raises(emx.EmxError) as ei:
+        hd.nlem_denoise(torch.zeros((30, 30), device=dev), torch.zeros((30, 30), device=dev), None,
+                        patch_radius=4, window_radius=2, h=1.0)
+    assert ei.value.status == emx.EM_ERR_UNSUPPORTED
+    with pytest.raises(emx.EmxError) as ei:
+        hd.nlem_denoise(torch.zeros((30, 30), device=dev), torch.zeros((30, 30), device=dev), None,
+                        patch_radius=2, window_radius=11, h=1.0)
+    assert ei.value.status == emx.EM_ERR_UNSUPPORTED
