@@ -40,7 +40,21 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--plain", type=int, default=0,
                     help="also time the plain one-instance-per-launch path on N pixels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 512 MiB device-to-device copy (3 times): the known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = (512 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copy calibration: 3 copies of {src.numel() * 4} bytes", flush=True)
 
 
 def window_sizes(H, W, R):
@@ -54,6 +68,9 @@ def window_sizes(H, W, R):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: each pixel's solve is independent, so the "
               "image would be split by rows across GPUs with no exchange; "

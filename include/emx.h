@@ -34,7 +34,7 @@
  *        r_dual = sqrt( ||z^t - z^{t-1}||^2 / d ),
  *    stop when both are <= tol * D, where D = hi - lo for a finite box and
  *    max(1, max_k ||a_k||_inf) otherwise.  The primal residual is only
- *    evaluated on iterations that follow one with r_dual <= 4 tol D (and on
+ *    evaluated on iterations that follow one with r_dual <= tol D (and on
  *    the last allowed iteration), so a solve may end one iteration later
  *    than a solver that evaluates both every iteration.  tol = 0 runs
  *    exactly max_iter iterations; max_iter = 0 returns the starting z.

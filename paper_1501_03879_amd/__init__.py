@@ -15,7 +15,7 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libemx.so")
+LIB_PATH = os.environ.get("EMX_LIBRARY") or os.path.join(HERE, "libemx.so")
 
 EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8

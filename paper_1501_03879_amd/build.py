@@ -14,8 +14,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-LIB = os.path.join(HERE, "libemx.so")
-BUILD_DIR = os.path.join(HERE, "_build")
+LIB = os.environ.get("EMX_BUILD_OUTPUT") or os.path.join(HERE, "libemx.so")
+BUILD_DIR = os.environ.get("EMX_BUILD_DIR") or os.path.join(HERE, "_build")
 SOURCES = ["nlem_pr0.hip", "nlem_pr1.hip", "nlem_pr2.hip", "nlem_pr3.hip", "batch_kernel.hip",
            "emx_host.hip"]
 ARCH = os.environ.get("EMX_OFFLOAD_ARCH", "gfx950")
@@ -29,7 +29,8 @@ def hipcc() -> str:
 
 
 def compile_flags():
-    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    extra = os.environ.get("EMX_EXTRA_FLAGS", "").split()
+    return extra + [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
             "-Wno-unused-result", "-Wno-unused-variable",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(HERE, "..", "include")]

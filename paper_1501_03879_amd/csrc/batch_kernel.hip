@@ -124,7 +124,7 @@ struct BatchShape {
 };
 
 template <int DS, int M, int WC, int WP>
-__global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L) {
+__global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunch L) {
     using S = BatchShape<DS, M, WC, WP>;
     using RSx = RS<DS>;
     constexpr int H2 = S::H2;
@@ -133,15 +133,17 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
     __shared__ float xe[(WP > 1) ? 2 * WP * WC * H2 * 4 : 1];
     __shared__ float xs[2 * WC * WP * 4];
     __shared__ float zpE[WC * 2 * H2 * 4 * WP];
+    __shared__ float cvec[WC * WP * DS];
     __shared__ unsigned int item_s;
     __shared__ int flag_s[4];
 
     const int lane = threadIdx.x & 63;
     const int row = lane >> 4;
-    const int wave = threadIdx.x >> 6;
+    const int wave = uniform_int(threadIdx.x >> 6);
     const int cw = wave % WC, pw = wave / WC;
-    float *zp_s = zpE + wave * 2 * H2 * 4;
+    float *zp_s = zpE + wave * 2 * H2 * 4;  // per wave: z^{t-1}, E^t in the reduced layout
     float *Ep_s = zp_s + H2 * 4;
+    float *cv = cvec + wave * DS;           // per wave: c = 2 z^t - z^{t-1} of the slice
     const unsigned int cbeg = L.offsets[L.cls];
     const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
 
@@ -153,11 +155,11 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
             flag_s[2] = 0;  // the starting z is bad
         }
         __syncthreads();
-        const unsigned int it = item_s;
+        const unsigned int it = (unsigned int)uniform_int((int)item_s);
         if (it >= ccount) break;
-        const int b = L.list[cbeg + it];
+        const int b = uniform_int(L.list[cbeg + it]);
         const em_instance_t e = L.inst[b];
-        const int n = e.n, d = e.d;
+        const int n = uniform_int(e.n), d = uniform_int(e.d);
         const float *A = L.a + e.a_off;
         const float *Wt = L.w + e.w_off;
         float *Z = L.z + e.z_off;
@@ -193,14 +195,14 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
                     }
                     const float wv = vp ? Wt[p] : 0.0f;
                     bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
-                    lam[q] = vp ? wv : -1.0f;  // weight for now; lambda after init
+                    lam[q] = vp ? wv : -1.0f;  // weight for now (-1: no point); lambda below
                 }
             }
         }
         const float wamax = wave_max(amax);
         if (__any(bad_l) && lane == 0) flag_s[0] = 1;
         if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));  // non-negative floats order as ints
-        // ---- MAXW init: largest weight, lowest index on ties (all waves see all weights of their points)
+        // ---- MAXW init: largest weight, lowest index on ties
         int best = 0;
         if (L.init == EM_INIT_MAXW) {
             float wb = -1.0f;
@@ -216,28 +218,30 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
             const float wm = wave_max(wb);
             const float cand = (wb == wm) ? (float)pb : 3.0e38f;
             const float pmin = -wave_max(-cand);
-            if (WP > 1) {
-                if (lane == 0) xs[wave * 4 + 0] = wm, xs[wave * 4 + 1] = pmin;
-            } else {
-                best = (int)pmin;
-            }
-            if (WP > 1) {
+            if constexpr (WP > 1) {
+                if (lane == 0) {
+                    xs[wave * 4 + 0] = wm;
+                    xs[wave * 4 + 1] = pmin;
+                }
                 __syncthreads();
                 float bw = -1.0f, bp = 3.0e38f;
                 for (int v = 0; v < WP; ++v) {
                     const float wv = xs[(v * WC) * 4 + 0], pv = xs[(v * WC) * 4 + 1];
                     if (wv > bw || (wv == bw && pv < bp)) bw = wv, bp = pv;
                 }
-                best = (int)bp;
+                best = uniform_int((int)bp);
+            } else {
+                best = uniform_int((int)pmin);
             }
         }
         __syncthreads();
-        const bool bad = flag_s[0] != 0;
+        const bool bad = uniform(flag_s[0] != 0);
         const float Dscale = (__builtin_isfinite(L.lo) && __builtin_isfinite(L.hi) && L.hi > L.lo)
                                  ? (L.hi - L.lo)
-                                 : fmaxf(1.0f, __int_as_float(flag_s[1]));
+                                 : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
         const float tau = L.tol * Dscale;
-        const float tau_arm = L.arm * tau;
+        const float tau2 = tau * tau;
+        const float arm2 = (L.arm * tau) * (L.arm * tau);
 
         // ---- starting z in the reduced layout; c = z
         float zr[H2];
@@ -253,25 +257,23 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
             if (lane == 16 * row) {
                 zp_s[j * 4 + row] = zv;
                 Ep_s[j * 4 + row] = 0.0f;
+                if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = zv;  // 0 on padded coordinates
             }
         }
         if (__any(zbad) && lane == 0) flag_s[2] = 1;
         __syncthreads();
-        const bool bad_all = bad || (flag_s[2] != 0);
+        const bool bad_all = uniform(bad || (flag_s[2] != 0));
         __syncthreads();  // flags are reset by the next pop
 
         int iters = 0, flags = EM_MAXITER;
-        float rpri = 0.0f, rdual = 0.0f;
+        float rp2 = 0.0f, rd2 = 0.0f;
         if (bad_all) {
             flags = EM_BAD_INPUT;
         } else {
-            float cS[DS];
-#pragma unroll
-            for (int jj = 0; jj < DS; ++jj) cS[jj] = readlane(zr[RSx::slot_of(jj)], 16 * RSx::row_of(jj));
             float g[M][DS];
 #pragma unroll
             for (int q = 0; q < M; ++q) {
-                lam[q] = (lam[q] >= 0.0f) ? lam[q] * L.inv_mu : -1.0f;
+                lam[q] = (lam[q] >= 0.0f) ? lam[q] * L.inv_mu : 0.0f;
 #pragma unroll
                 for (int jj = 0; jj < DS; ++jj) g[q][jj] = na[q][jj];
             }
@@ -284,16 +286,18 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
             bool armed_last = false, done = false;
             int t = 1;
             for (; t <= max_iter; ++t) {
+                // ---- pass 1: delta = g + c, partial ||delta||^2
                 float nrm[M];
 #pragma unroll
-                for (int q = 0; q < M; ++q) {
-                    float acc = 0.0f;
+                for (int q = 0; q < M; ++q) nrm[q] = 0.0f;
 #pragma unroll
-                    for (int jj = 0; jj < DS; ++jj) {
-                        g[q][jj] += cS[jj];
-                        acc = fmaf(g[q][jj], g[q][jj], acc);
+                for (int jj = 0; jj < DS; ++jj) {
+                    const float cj = cv[jj];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        g[q][jj] += cj;
+                        nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
                     }
-                    nrm[q] = acc;
                 }
                 float rd_all = rd_w, rp_all = rp_w;
                 if constexpr (WC > 1 || WP > 1) {
@@ -312,14 +316,12 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
                         float *X = xn + (t & 1) * WC * WP * M * 64;
 #pragma unroll
                         for (int q = 0; q < M; ++q) {
-                            float s = 0.0f;
+                            float sum = 0.0f;
 #pragma unroll
-                            for (int v = 0; v < WC; ++v) s += X[((pw * WC + v) * M + q) * 64 + lane];
-                            nrm[q] = s;
+                            for (int v = 0; v < WC; ++v) sum += X[((pw * WC + v) * M + q) * 64 + lane];
+                            nrm[q] = sum;
                         }
                     }
-                    // residual partials: coordinate waves of point-wave 0 carry
-                    // the per-coordinate terms, every wave its own point terms
                     rd_all = 0.0f;
                     rp_all = 0.0f;
 #pragma unroll
@@ -327,50 +329,60 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
                         rd_all += XS[v * 4 + 0];
                         rp_all += XS[v * 4 + 1];
                     }
+                    rd_all = readfirstlane(rd_all);
+                    rp_all = readfirstlane(rp_all);
                 }
+                // ---- stop test for iteration t-1 (all waves hold identical sums)
                 if (t > 1) {
-                    rdual = sqrtf(rd_all * inv_d);
-                    rpri = sqrtf(fmaxf(rp_all, 0.0f) * inv_nd);
-                    if (tau > 0.0f && armed_last && rpri <= tau && rdual <= tau) {
+                    rd2 = rd_all * inv_d;
+                    rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                    if (uniform(tau2 > 0.0f && armed_last && rp2 <= tau2 && rd2 <= tau2)) {
                         flags = EM_CONVERGED;
                         iters = t - 1;
                         done = true;
                         break;
                     }
                 }
-                const bool armed = (t == max_iter) || (tau > 0.0f && t > 1 && rdual <= tau_arm);
+                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
                 float s[M];
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
+                // ---- armed iterations: lane sums of ||x_k - c||^2, x_k = a_k + (1 - s) delta.
+                // Absent points and padded coordinates give exactly 0 (g stays -a).
+                float rp_lane = 0.0f;
+                if (armed) {
+                    float rq[M];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rq[q] = 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj < DS; ++jj) {
+                        const float cj = cv[jj];
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            const float y = fmaf(1.0f - s[q], g[q][jj], -(na[q][jj] + cj));
+                            rq[q] = fmaf(y, y, rq[q]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rp_lane += rq[q];
+                }
+                // ---- pass 2: E = sum_k s delta, g = s delta - a
                 float acc[DS];
 #pragma unroll
-                for (int jj = 0; jj < DS; ++jj) acc[jj] = 0.0f;
-                float rp_lane = 0.0f;
-                if (!armed) {
-#pragma unroll
-                    for (int q = 0; q < M; ++q)
-#pragma unroll
-                        for (int jj = 0; jj < DS; ++jj) {
-                            const float dl = g[q][jj];
-                            acc[jj] = fmaf(s[q], dl, acc[jj]);
-                            g[q][jj] = fmaf(s[q], dl, na[q][jj]);
-                        }
-                } else {
+                for (int jj = 0; jj < DS; ++jj) {
+                    float ac = 0.0f;
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
-                        float rq = 0.0f;
-#pragma unroll
-                        for (int jj = 0; jj < DS; ++jj) {
-                            const float dl = g[q][jj];
-                            acc[jj] = fmaf(s[q], dl, acc[jj]);
-                            const float gn = fmaf(s[q], dl, na[q][jj]);
-                            g[q][jj] = gn;
-                            const float y = (dl - gn) - cS[jj];  // x_k - c^t (0 on padded coordinates)
-                            rq = fmaf(y, y, rq);
-                        }
-                        rp_lane += (lam[q] >= 0.0f) ? rq : 0.0f;
+                        const float dl = g[q][jj];
+                        ac = fmaf(s[q], dl, ac);
+                        g[q][jj] = fmaf(s[q], dl, na[q][jj]);
                     }
+                    acc[jj] = ac;
                 }
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < DS; ++jj) asm volatile("" : "+v"(g[q][jj]));
                 float E[H2];
                 reduce_scatter<DS>(acc, E);
                 if constexpr (WP > 1) {
@@ -389,41 +401,40 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
                     }
                 }
                 float rdx = 0.0f, rpx = 0.0f;
-                float cR[H2];
 #pragma unroll
                 for (int j = 0; j < H2; ++j) {
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
                     const float zn = clampf(zr[j] - E[j] * inv_n, L.lo, L.hi);
                     const float dz = zn - zr[j];
+                    const float zpj = zp_s[j * 4 + row];
                     if (armed) {
                         // x_k - z' = (x_k - c) + (c - z'), sum_k (x_k - c) = E^t - E^{t+1}
-                        const float zpj = zp_s[j * 4 + row];
                         const float Epj = Ep_s[j * 4 + row];
                         const float cz = (2.0f * zr[j] - zpj) - zn;
                         rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
                     }
                     rdx += vj ? dz * dz : 0.0f;
-                    cR[j] = vj ? (2.0f * zn - zr[j]) : 0.0f;
                     if (lane == 16 * row) {
                         zp_s[j * 4 + row] = zr[j];
                         Ep_s[j * 4 + row] = E[j];
+                        if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = vj ? (2.0f * zn - zr[j]) : 0.0f;
                     }
                     zr[j] = vj ? zn : 0.0f;
                 }
                 // per-coordinate terms are counted once, by point-wave 0
-                const float rdw = (readlane(rdx, 0) + readlane(rdx, 16)) + (readlane(rdx, 32) + readlane(rdx, 48));
+                const float rdw = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) +
+                                                (readlane(rdx, 32) + readlane(rdx, 48)));
                 rd_w = (pw == 0) ? rdw : 0.0f;
                 if (armed) {
                     const float tot = readfirstlane(wave_sum(rp_lane));
-                    const float px = (readlane(rpx, 0) + readlane(rpx, 16)) + (readlane(rpx, 32) + readlane(rpx, 48));
+                    const float px = readfirstlane((readlane(rpx, 0) + readlane(rpx, 16)) +
+                                                   (readlane(rpx, 32) + readlane(rpx, 48)));
                     rp_w = tot + ((pw == 0) ? px : 0.0f);
                 } else {
                     rp_w = 0.0f;
                 }
                 armed_last = armed;
-#pragma unroll
-                for (int jj = 0; jj < DS; ++jj) cS[jj] = readlane(cR[RSx::slot_of(jj)], 16 * RSx::row_of(jj));
             }
             if (!done) {
                 iters = max_iter;
@@ -443,10 +454,12 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
                             rd_all += XS[v * 4 + 0];
                             rp_all += XS[v * 4 + 1];
                         }
+                        rd_all = readfirstlane(rd_all);
+                        rp_all = readfirstlane(rp_all);
                     }
-                    rdual = sqrtf(rd_all * inv_d);
-                    rpri = sqrtf(fmaxf(rp_all, 0.0f) * inv_nd);
-                    flags = (tau > 0.0f && rpri <= tau && rdual <= tau) ? EM_CONVERGED : EM_MAXITER;
+                    rd2 = rd_all * inv_d;
+                    rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                    flags = (tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
                 }
             }
         }
@@ -462,8 +475,8 @@ __global__ __launch_bounds__(64 * WC * WP) void batch_solve_kernel(ClassLaunch L
             em_stats_t st;
             st.iters = bad_all ? 0 : iters;
             st.flags = flags;
-            st.r_pri = bad_all ? 0.0f : rpri;
-            st.r_dual = bad_all ? 0.0f : rdual;
+            st.r_pri = bad_all ? 0.0f : sqrtf(rp2);
+            st.r_dual = bad_all ? 0.0f : sqrtf(rd2);
             L.stats[b] = st;
         }
     }
@@ -528,7 +541,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         L.mu = rho;
         L.inv_mu = 1.0f / rho;
         L.tol = tol;
-        L.arm = 4.0f;
+        L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
         L.max_iter = max_iter;
         L.init = init;
         L.cls = c;

@@ -219,6 +219,11 @@ extern "C" em_status_t em_sync(em_handle_t h, void *stream) {
 // NLEM
 // ---------------------------------------------------------------------------
 
+// The primal residual costs three VALU operations per point coordinate, so
+// it is evaluated only on iterations that follow one whose dual residual was
+// already within kArmFactor * tol * D (both must be within tol * D to stop).
+static constexpr float kArmFactor = 1.0f;
+
 static int points_per_lane(int R) { return ((2 * R + 1) * (2 * R + 1) + 63) / 64; }
 
 // Kernel for a shape: the default coordinate-wave count, or EMX_NLEM_WC when
@@ -277,7 +282,7 @@ static void fill_common(NlemLaunch &L, float lo, float hi, float rho, int32_t ma
     L.lo = lo;
     L.hi = hi;
     L.tau = tol * (hi - lo);
-    L.tau_arm = 4.0f * L.tau;
+    L.tau_arm = kArmFactor * L.tau;
 }
 
 struct NlemGroup {

@@ -53,9 +53,14 @@ struct NlemShape {
     static constexpr int RMAX = rmax_for<M>();
     static constexpr int WSM = 2 * RMAX + 1;
     static constexpr int TW = 2 * (RMAX + PR) + 1;
-    // Pitch: consecutive window rows start 32 floats apart modulo 32 banks
-    // after a full row of WSM points, so 32 consecutive lanes hit 32 banks.
-    static constexpr int P = WSM + 32;
+    // Pitch = WSM + 32: after a full window row of WSM points the next row
+    // continues on the next bank (mod 32), so 32 consecutive lanes reading
+    // one patch coordinate of consecutive window points hit distinct banks.
+    // (WSM + 64, conflict-free mod 64 as well, timed the same on MI355X.)
+#ifndef EMX_TILE_PITCH_PAD
+#define EMX_TILE_PITCH_PAD 32
+#endif
+    static constexpr int P = WSM + EMX_TILE_PITCH_PAD;
     static constexpr int TILE = TW * P;
     static constexpr int DS = (D + WC - 1) / WC;
     static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
@@ -224,10 +229,9 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 bool nonfinite = false;
 #pragma unroll
                 for (int q = 0; q < M; ++q) {
-                    if (lam[q] >= 0.0f) {
-                        nonfinite |= !(nrm[q] <= FLT_MAX);
-                        lam[q] = exp2f(-nrm[q] * I.k_h) * L.inv_mu;
-                    }
+                    const bool valid = lam[q] >= 0.0f;   // -1 marks window slots outside the image
+                    nonfinite |= valid && !(nrm[q] <= FLT_MAX);
+                    lam[q] = valid ? exp2f(-nrm[q] * I.k_h) * L.inv_mu : 0.0f;
                 }
                 if (__any(nonfinite)) {
                     bad = true;
