@@ -47,14 +47,40 @@ def parse():
 
 
 def copy_calibration():
+    """A device copy of 512 MiB whose source was written before 2 GiB of other
+    writes (so it is not resident in the 256 MB last-level cache): the
+    known-size kernel that scales the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
     n = (512 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    flush = torch.empty(4 * n, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
     for _ in range(3):
+        flush.fill_(2.0)
         dst.copy_(src)
     torch.cuda.synchronize()
     print(f"copy calibration: 3 copies of {src.numel() * 4} bytes", flush=True)
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the NLEM kernel from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "nlem_256x256_d49_counters.md")
+    csrc = os.path.join(ROOT, "paper_1501_03879_amd", "csrc")
+    try:
+        text = open(path).read()
+        src = "".join(open(os.path.join(csrc, f)).read()
+                      for f in ("nlem_kernel.hpp", "em_device.hpp", "nlem_table.hpp", "emx_internal.hpp"))
+    except OSError:
+        return None
+    h = hashlib.sha256(src.encode()).hexdigest()[:16]
+    m_h = re.search(r"kernel_source_sha256_16: (\w+)", text)
+    m_t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_h or not m_t or m_h.group(1) != h:
+        return None
+    return float(m_t.group(1))
 
 
 def window_sizes(H, W, R):
@@ -147,7 +173,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
                      "frac_nonpacked_fma_peak": tflops / FP32_NONPACKED_TFLOPS,
-                     "flops_per_launch": flops, "traffic": None},
+                     "flops_per_launch": flops, "traffic": profiled_traffic(),
+                     "timing": "HIP events on the launch stream around the timed steps; each step "
+                               "is one reset kernel (~5 us) plus one NLEM kernel launch"},
     }
 
     if args.plain > 0:
