@@ -108,3 +108,55 @@ def make_pointset_batch(seed: int, B: int, n_lo: int = 8, n_hi: int = 512,
         pts += p
         ws += w
     return pack_instances(pts, ws, lo, hi)
+
+
+def make_pointset_batch_device(seed: int, B: int, device, n_lo: int = 8, n_hi: int = 512,
+                               d_choices=(2, 3, 16, 49, 64), outlier_prob: float = 0.2,
+                               nu: float = 1.5, scale: float = 50.0):
+    """The same distribution as make_pointset_batch, drawn on a torch device
+    with a seeded torch generator (for full-size batches that do not fit a
+    host-side draw in reasonable time).  Points of instances with equal d are
+    stored contiguously (so per-point outlier scales broadcast), while the
+    instance order is a random permutation.  Returns (a, w, inst_np,
+    z_size): a and w are float32 device tensors, inst_np the descriptors
+    (INSTANCE_DTYPE, host)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n = torch.randint(n_lo, n_hi + 1, (B,), generator=g, device=device)
+    dsel = torch.randint(0, len(d_choices), (B,), generator=g, device=device)
+    dvals = torch.tensor(d_choices, device=device)[dsel]
+    order = torch.randperm(B, generator=g, device=device)      # instance ids in storage order
+    n_h = n.cpu().numpy().astype(np.int64)
+    d_h = dvals.cpu().numpy().astype(np.int64)
+    order_h = order.cpu().numpy()
+    # storage: group by d (stable in the permuted order)
+    grp = np.argsort(d_h[order_h], kind="stable")
+    store = order_h[grp]                                        # instance ids, d-grouped
+    sizes = n_h[store] * d_h[store]
+    a_off_store = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    w_off_store = np.concatenate([[0], np.cumsum(n_h[store])[:-1]])
+    inst = np.zeros(B, dtype=INSTANCE_DTYPE)
+    inst["a_off"][store] = a_off_store
+    inst["w_off"][store] = w_off_store
+    inst["z_off"] = np.concatenate([[0], np.cumsum(d_h)[:-1]])
+    inst["n"] = n_h
+    inst["d"] = d_h
+    total_a = int(sizes.sum())
+    total_w = int(n_h.sum())
+    a = torch.empty(total_a, dtype=torch.float32, device=device)
+    w = torch.empty(total_w, dtype=torch.float32, device=device).exponential_(1.0, generator=g)
+    pos_a = 0
+    for dv in d_choices:
+        sel = store[d_h[store] == dv]
+        npts = int(n_h[sel].sum())
+        if npts == 0:
+            continue
+        blk = a[pos_a:pos_a + npts * dv].view(npts, dv)
+        blk.normal_(generator=g)
+        out = torch.rand(npts, generator=g, device=device) < outlier_prob
+        V = 2.0 * torch._standard_gamma(torch.full((npts,), nu / 2.0, device=device), generator=g)
+        mult = torch.where(out, scale / torch.sqrt(V / nu), torch.ones_like(V))
+        blk.mul_(mult[:, None])
+        pos_a += npts * dv
+    return a, w, inst, int(d_h.sum())
