@@ -97,6 +97,69 @@ __device__ __forceinline__ void reduce_scatter(const float (&x)[V], float (&out)
     for (int j = 0; j < H2; ++j) out[j] = row_sum16(out[j]);
 }
 
+// Full reduce-scatter of V <= 64 per-lane values over the 64 lanes: six
+// halving stages (lane bit 5, 4: permlane32/16 swaps; bits 3, 2, 1, 0: DPP
+// row_ror:8, row_half_mirror, quad_perm with selects).  Stage s keeps
+// K_{s+1} = ceil(K_s / 2) values per lane: lanes whose stage bit is clear keep
+// indices [0, K_{s+1}), the others [K_{s+1}, 2 K_{s+1}).  Afterwards every lane
+// holds one wave-wide total, for coordinate RSF<V>::coord(lane) when
+// RSF<V>::valid(lane); each valid coordinate is held by exactly one lane.
+template <int V>
+struct RSF {
+    static_assert(V >= 1 && V <= 64, "RSF: 1..64 values");
+    static __host__ __device__ constexpr int K(int s) {
+        int k = V;
+        for (int i = 0; i < s; ++i) k = (k + 1) / 2;
+        return k;
+    }
+    static __host__ __device__ constexpr int coord(int lane) {
+        int c = 0;
+        for (int s = 0; s < 6; ++s)
+            if (lane & (32 >> s)) c += K(s + 1);
+        return c;
+    }
+    static __host__ __device__ constexpr bool valid(int lane) {
+        // the index a lane holds after stage s must be below K_{s+1}; at
+        // every stage the upper lanes hold index + K_{s+1} of the K_s inputs
+        int idx = 0;
+        for (int s = 5; s >= 0; --s) {
+            if (lane & (32 >> s)) idx += K(s + 1);
+            if (idx >= K(s)) return false;
+        }
+        return true;
+    }
+};
+
+template <int CTRL>
+__device__ __forceinline__ float rs_dpp_stage(float lo, float hi, bool upper) {
+    const float send = upper ? lo : hi;
+    const float keep = upper ? hi : lo;
+    return keep + dpp<CTRL>(send);
+}
+
+template <int V>
+__device__ __forceinline__ float reduce_scatter_full(const float (&x)[V], int lane) {
+    using R = RSF<V>;
+    constexpr int K1 = R::K(1), K2 = R::K(2), K3 = R::K(3), K4 = R::K(4), K5 = R::K(5);
+    float a[K1];
+#pragma unroll
+    for (int i = 0; i < K1; ++i) a[i] = swap32_sum(x[i], (i + K1 < V) ? x[i + K1] : 0.0f);
+    float b[K2];
+#pragma unroll
+    for (int i = 0; i < K2; ++i) b[i] = swap16_sum(a[i], (i + K2 < K1) ? a[i + K2] : 0.0f);
+    const bool u8 = lane & 8, u4 = lane & 4, u2 = lane & 2, u1 = lane & 1;
+    float c[K3];
+#pragma unroll
+    for (int i = 0; i < K3; ++i) c[i] = rs_dpp_stage<0x128>(b[i], (i + K3 < K2) ? b[i + K3] : 0.0f, u8);  // row_ror:8
+    float d[K4];
+#pragma unroll
+    for (int i = 0; i < K4; ++i) d[i] = rs_dpp_stage<0x141>(c[i], (i + K4 < K3) ? c[i + K4] : 0.0f, u4);  // row_half_mirror
+    float e[K5];
+#pragma unroll
+    for (int i = 0; i < K5; ++i) e[i] = rs_dpp_stage<0x4E>(d[i], (i + K5 < K4) ? d[i + K5] : 0.0f, u2);   // lane ^ 2
+    return rs_dpp_stage<0xB1>(e[0], (1 < K5) ? e[1] : 0.0f, u1);                                          // lane ^ 1
+}
+
 // The second half of reduce_scatter, for callers that produced the stage-A
 // pairs t[j] = swap32_sum(x[j], x[j + H1]) themselves (streaming stage A
 // inside the loop that computes x keeps only H1 partial sums live).

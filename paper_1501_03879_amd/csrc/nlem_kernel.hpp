@@ -37,7 +37,10 @@ namespace emx {
 
 // Slices with at most this many point values per lane keep the points in
 // registers (read from the LDS tile once per pixel).
-constexpr int kKeepPointsInRegs = 64;
+#ifndef EMX_KEEP_POINTS
+#define EMX_KEEP_POINTS 64
+#endif
+constexpr int kKeepPointsInRegs = EMX_KEEP_POINTS;
 
 template <int M>
 constexpr int rmax_for() {
@@ -63,6 +66,11 @@ struct NlemShape {
     static constexpr int P = WSM + EMX_TILE_PITCH_PAD;
     static constexpr int TILE = TW * P;
     static constexpr int DS = (D + WC - 1) / WC;
+    // Row mapping: when a window row splits into whole runs of M points and the
+    // window fits 64 lanes that way (21 = 3 x 7 for R = 10), lane l owns M
+    // consecutive columns of one row, so one base address plus immediate
+    // offsets reaches all its points.  Used only for R = RMAX.
+    static constexpr bool ROWMAP = M > 1 && (WSM % M == 0) && (WSM / M) * WSM <= 64;
     static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
 };
 
@@ -78,12 +86,20 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 
     const int lane = threadIdx.x & 63;
     const int row = lane >> 4;
-    // per-wave: z^{t-1}, then E^t, [slot][row]; strided by the largest slice
-    float *zp_s = zpE + SW * 2 * RS<S::DS>::H2 * 4;
+    // per-wave: z^{t-1}, E^t and z^t in the reduced layout [slot][row];
+    // strided by the largest slice
+    float *zp_s = zpE + SW * 3 * RS<S::DS>::H2 * 4;
     float *Ep_s = zp_s + H2 * 4;
+    float *zr_s = Ep_s + H2 * 4;
     float *cv = cvec + SW * S::DS;        // per-wave: c = 2 z^t - z^{t-1} of the slice
     // points stay in registers when they fit (the compiler hoists the tile reads)
     constexpr bool kKeep = M * NJ <= kKeepPointsInRegs;
+    // software prefetch of the next coordinate's points (off when occupancy
+    // is the tighter constraint)
+#ifndef EMX_PREFETCH
+#define EMX_PREFETCH 1
+#endif
+    constexpr bool PF = EMX_PREFETCH != 0;
     // tile offset of slice coordinate jj within a patch (folded after unrolling)
     auto poff = [](int jj) { return ((J0 + jj) / S::PS) * S::P + ((J0 + jj) % S::PS); };
 
@@ -119,40 +135,54 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         const int y0 = max(iy - R, 0), y1 = min(iy + R, H - 1);
         const int x0 = max(ix - R, 0), x1 = min(ix + R, W - 1);
         const int n = (y1 - y0 + 1) * (x1 - x0 + 1);
-        const float inv_ws = 1.0f / (float)WSr;
-        int base[M];
+        int base[S::ROWMAP ? 1 : M];
         float lam[M];
+        if constexpr (S::ROWMAP) {
+            // lane owns M consecutive columns of one window row (R = RMAX here)
+            constexpr int LPR = S::WSM / M;
+            const int wy = lane / LPR, wx0 = (lane - (lane / LPR) * LPR) * M;
+            const bool rowok = lane < LPR * S::WSM && iy - R + wy >= 0 && iy - R + wy < H;
+            base[0] = rowok ? (wy * S::P + wx0) : 0;
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
-            const int p = lane + 64 * q;
-            const int wy = (int)(((float)p + 0.5f) * inv_ws);
-            const int wx = p - wy * WSr;
-            const int py = iy - R + wy, px = ix - R + wx;
-            const bool valid = (p < WSr * WSr) && py >= 0 && py < H && px >= 0 && px < W;
-            base[q] = valid ? (wy * S::P + wx) : 0;
-            lam[q] = valid ? 0.0f : -1.0f;
+            for (int q = 0; q < M; ++q) {
+                const int px = ix - R + wx0 + q;
+                lam[q] = (rowok && px >= 0 && px < W) ? 0.0f : -1.0f;
+            }
+        } else {
+            const float inv_ws = 1.0f / (float)WSr;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const int p = lane + 64 * q;
+                const int wy = (int)(((float)p + 0.5f) * inv_ws);
+                const int wx = p - wy * WSr;
+                const int py = iy - R + wy, px = ix - R + wx;
+                const bool valid = (p < WSr * WSr) && py >= 0 && py < H && px >= 0 && px < W;
+                base[q] = valid ? (wy * S::P + wx) : 0;
+                lam[q] = valid ? 0.0f : -1.0f;
+            }
         }
+        // tile offset of point slot q (its patch's top-left corner)
+        auto pbase = [&](int q) { return S::ROWMAP ? base[0] + q : base[q]; };
 
         // ---- a3: z = P_i (unprojected), u = 0  (so g = -a, c = z)
         const int cbase = R * S::P + R;
-        float zr[H2];
 #pragma unroll
         for (int j = 0; j < H2; ++j) {
             const int cc = J0 + RSx::coord(row, j);
             const bool vj = RSx::valid(row, j);
-            const float zv = tile[cbase + (cc / S::PS) * S::P + (cc % S::PS)];
-            zr[j] = vj ? zv : 0.0f;
+            const float zv = vj ? tile[cbase + (cc / S::PS) * S::P + (cc % S::PS)] : 0.0f;
             if (lane == 16 * row) {
-                zp_s[j * 4 + row] = zr[j];
+                zp_s[j * 4 + row] = zv;
                 Ep_s[j * 4 + row] = 0.0f;
-                if (vj) cv[RSx::coord(row, j)] = zr[j];
+                zr_s[j * 4 + row] = zv;
+                if (vj) cv[RSx::coord(row, j)] = zv;
             }
         }
         float g[M][NJ];
 #pragma unroll
         for (int q = 0; q < M; ++q)
 #pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) g[q][jj] = -tile[base[q] + poff(jj)];
+            for (int jj = 0; jj < NJ; ++jj) g[q][jj] = -tile[pbase(q) + poff(jj)];
 
         const float inv_n = 1.0f / (float)n;
         const float fn = (float)n;
@@ -251,17 +281,24 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int q = 0; q < M; ++q) rq[q] = 0.0f;
                 float na[M];
+                if constexpr (PF) {
 #pragma unroll
-                for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(0)];
+                    for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(0)];
+                }
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) {
                     const float cj = cv[jj];
                     float cur[M];
+                    if constexpr (PF) {
 #pragma unroll
-                    for (int q = 0; q < M; ++q) cur[q] = na[q];
-                    if (jj + 1 < NJ) {
+                        for (int q = 0; q < M; ++q) cur[q] = na[q];
+                        if (jj + 1 < NJ) {
 #pragma unroll
-                        for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(jj + 1)];
+                            for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(jj + 1)];
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < M; ++q) cur[q] = -tile[pbase(q) + poff(jj)];
                     }
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
@@ -279,20 +316,27 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             if constexpr (!kKeep) asm volatile("" ::: "memory");
 
             // ---- a4 (second half) + a5 partial sums: E = sum_k s delta, g = s delta - a
-            // (tile reads pipelined one coordinate ahead)
+            // (tile reads pipelined one coordinate ahead unless PF = 0)
             float acc[NJ];
             {
                 float na[M];
+                if constexpr (PF) {
 #pragma unroll
-                for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(0)];
+                    for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(0)];
+                }
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) {
                     float cur[M];
+                    if constexpr (PF) {
 #pragma unroll
-                    for (int q = 0; q < M; ++q) cur[q] = na[q];
-                    if (jj + 1 < NJ) {
+                        for (int q = 0; q < M; ++q) cur[q] = na[q];
+                        if (jj + 1 < NJ) {
 #pragma unroll
-                        for (int q = 0; q < M; ++q) na[q] = -tile[base[q] + poff(jj + 1)];
+                            for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(jj + 1)];
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < M; ++q) cur[q] = -tile[pbase(q) + poff(jj)];
                     }
                     float ac = 0.0f;
 #pragma unroll
@@ -318,23 +362,24 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
             for (int j = 0; j < H2; ++j) {
                 const bool vj = RSx::valid(row, j);
-                const float zn = clampf(zr[j] - E[j] * inv_n, L.lo, L.hi);
-                const float dz = zn - zr[j];
+                const float zrj = zr_s[j * 4 + row];
+                const float zn = clampf(zrj - E[j] * inv_n, L.lo, L.hi);
+                const float dz = zn - zrj;
                 const float zpj = zp_s[j * 4 + row];
                 if (armed) {
                     // sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
                     // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1}
                     const float Epj = Ep_s[j * 4 + row];
-                    const float cz = (2.0f * zr[j] - zpj) - zn;
+                    const float cz = (2.0f * zrj - zpj) - zn;
                     rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
                 }
                 rdx += vj ? dz * dz : 0.0f;
                 if (lane == 16 * row) {
-                    zp_s[j * 4 + row] = zr[j];
+                    zp_s[j * 4 + row] = zrj;
                     Ep_s[j * 4 + row] = E[j];
-                    if (vj) cv[RSx::coord(row, j)] = 2.0f * zn - zr[j];
+                    zr_s[j * 4 + row] = vj ? zn : 0.0f;
+                    if (vj) cv[RSx::coord(row, j)] = 2.0f * zn - zrj;
                 }
-                zr[j] = vj ? zn : 0.0f;
             }
             rd_w = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) + (readlane(rdx, 32) + readlane(rdx, 48)));
             if (armed) {
@@ -384,7 +429,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         if constexpr (JC >= J0 && JC < J0 + NJ) {
             constexpr int rc = RSx::row_of(JC - J0);
             constexpr int sc = RSx::slot_of(JC - J0);
-            if (lane == 16 * rc) I.out[pix] = bad ? __builtin_nanf("") : zr[sc];
+            if (lane == 16 * rc) I.out[pix] = bad ? __builtin_nanf("") : zr_s[sc * 4 + rc];
         }
         if (SW == 0 && lane == 0 && I.stats != nullptr) {
             em_stats_t st;
@@ -411,12 +456,15 @@ __device__ __forceinline__ void nlem_dispatch(int wave, const NlemLaunch &L, flo
 }
 
 template <int PR, int M, int WC>
-__global__ __launch_bounds__(64 * WC, 2) void nlem_solve_kernel(NlemLaunch L) {
+#ifndef EMX_NLEM_MIN_WAVES
+#define EMX_NLEM_MIN_WAVES 2
+#endif
+__global__ __launch_bounds__(64 * WC, EMX_NLEM_MIN_WAVES) void nlem_solve_kernel(NlemLaunch L) {
     using S = NlemShape<PR, M, WC>;
     __shared__ float tile[S::TILE];
     __shared__ float xn[S::XN];
     __shared__ float xs[2 * WC * 4];
-    __shared__ float zpE[WC * 2 * RS<S::DS>::H2 * 4 + 8];
+    __shared__ float zpE[WC * 3 * RS<S::DS>::H2 * 4 + 8];
     __shared__ float cvec[WC * S::DS];
     __shared__ unsigned int item_s;
     const int wave = uniform_int(threadIdx.x >> 6);
