@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 // ---- pass 1: delta = g + c, partial ||delta||^2
                 float nrm[M];
 #pragma unroll
-                for (int q = 0; q < M; ++q) nrm[q] = 0.0f;
+                for (int q = 0; q < M; ++q) nrm[q] = kNu2Floor;
 #pragma unroll
                 for (int jj = 0; jj < DS; ++jj) {
                     const float cj = cv[jj];
@@ -316,9 +316,9 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         float *X = xn + (t & 1) * WC * WP * M * 64;
 #pragma unroll
                         for (int q = 0; q < M; ++q) {
-                            float sum = 0.0f;
+                            float sum = X[(pw * WC * M + q) * 64 + lane];
 #pragma unroll
-                            for (int v = 0; v < WC; ++v) sum += X[((pw * WC + v) * M + q) * 64 + lane];
+                            for (int v = 1; v < WC; ++v) sum += X[((pw * WC + v) * M + q) * 64 + lane];
                             nrm[q] = sum;
                         }
                     }

@@ -128,6 +128,19 @@ struct RSF {
         }
         return true;
     }
+    // bit l set when lane l holds a coordinate
+    static __host__ __device__ constexpr uint64_t mask() {
+        uint64_t m = 0;
+        for (int l = 0; l < 64; ++l)
+            if (valid(l)) m |= (uint64_t)1 << l;
+        return m;
+    }
+    // the lane that holds coordinate c
+    static __host__ __device__ constexpr int lane_of(int c) {
+        for (int l = 0; l < 64; ++l)
+            if (valid(l) && coord(l) == c) return l;
+        return -1;
+    }
 };
 
 template <int CTRL>
@@ -204,10 +217,12 @@ __device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfi
 // Shrink factor of the block soft-threshold (closed-form prox of
 // lambda ||x - a||): x = v - s (v - a) with s = min(lambda, nu) / nu and
 // nu = ||v - a||, i.e. s = min(1, lambda / nu).  s = 1 (x = a) whenever
-// nu <= lambda, including nu = 0 (the guard keeps rsq finite); lambda = 0
-// gives s = 0 (x = v).  lambda >= 0.
+// nu <= lambda; lambda = 0 gives s = 0 (x = v).  lambda >= 0.  Callers start
+// their sums of squares at kNu2Floor, so nu2 > 0 and rsq stays finite
+// (nu = 0 then gives s = 1 for lambda > 0, as the exact formula's limit).
+constexpr float kNu2Floor = 1e-30f;
 __device__ __forceinline__ float shrink(float nu2, float lambda) {
-    return fminf(1.0f, lambda * __builtin_amdgcn_rsqf(fmaxf(nu2, 1e-30f)));
+    return fminf(1.0f, lambda * __builtin_amdgcn_rsqf(nu2));
 }
 
 __device__ __forceinline__ float clampf(float x, float lo, float hi) {

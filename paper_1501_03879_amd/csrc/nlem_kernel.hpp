@@ -22,9 +22,10 @@
 //    so x_k = v_k - e_k and u_k' = z - z' - e_k are implicit.  The first
 //    iteration's nu^2 equals ||P_i - P_j||^2 (z starts at P_i, u = 0), which
 //    gives the NLM weights w_j = exp(-nu^2 / h^2) without a separate pass.
-//  * Sums over points: in-lane, then a permlane/DPP reduce-scatter across the
-//    wave; z, c live in a reduced layout (16 lanes per coordinate) and c is
-//    broadcast to SGPRs for the next pass.
+//  * Sums over points: in-lane, then a full permlane/DPP reduce-scatter across
+//    the wave, after which one lane per slice coordinate holds E and keeps
+//    z^t, z^{t-1}, E^t of that coordinate in registers; c is broadcast to the
+//    other lanes through LDS for the next pass.
 #pragma once
 
 #include <float.h>
@@ -76,22 +77,22 @@ struct NlemShape {
 
 template <int PR, int M, int WC, int SW>
 __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, float *xn, float *xs,
-                                          float *zpE, float *cvec, unsigned int *item_s) {
+                                          float *cvec, unsigned int *item_s) {
     using S = NlemShape<PR, M, WC>;
     constexpr int J0 = SW * S::DS;
     constexpr int NJ = (S::D - J0 < S::DS) ? (S::D - J0) : S::DS;
-    using RSx = RS<NJ>;
-    constexpr int H2 = RSx::H2;
+    using RSx = RSF<NJ>;
     constexpr int JC = (S::D - 1) / 2;  // centre coordinate
 
     const int lane = threadIdx.x & 63;
-    const int row = lane >> 4;
-    // per-wave: z^{t-1}, E^t and z^t in the reduced layout [slot][row];
-    // strided by the largest slice
-    float *zp_s = zpE + SW * 3 * RS<S::DS>::H2 * 4;
-    float *Ep_s = zp_s + H2 * 4;
-    float *zr_s = Ep_s + H2 * 4;
-    float *cv = cvec + SW * S::DS;        // per-wave: c = 2 z^t - z^{t-1} of the slice
+    // after the reduce-scatter this lane owns slice coordinate myc (if myv)
+    const bool myv = (RSx::mask() >> lane) & 1;
+    const int myc = RSx::coord(lane);
+    const int myoff = myv ? ((J0 + myc) / S::PS) * S::P + ((J0 + myc) % S::PS) : 0;
+    // per-wave c = 2 z^t - z^{t-1} of the slice, [0, NJ); lanes that own no
+    // coordinate write to a private slot in [64, 128) instead
+    float *cv = cvec + SW * 128;
+    const int cidx = myv ? myc : 64 + lane;
     // points stay in registers when they fit (the compiler hoists the tile reads)
     constexpr bool kKeep = M * NJ <= kKeepPointsInRegs;
     // software prefetch of the next coordinate's points (off when occupancy
@@ -164,20 +165,13 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         // tile offset of point slot q (its patch's top-left corner)
         auto pbase = [&](int q) { return S::ROWMAP ? base[0] + q : base[q]; };
 
-        // ---- a3: z = P_i (unprojected), u = 0  (so g = -a, c = z)
-        const int cbase = R * S::P + R;
-#pragma unroll
-        for (int j = 0; j < H2; ++j) {
-            const int cc = J0 + RSx::coord(row, j);
-            const bool vj = RSx::valid(row, j);
-            const float zv = vj ? tile[cbase + (cc / S::PS) * S::P + (cc % S::PS)] : 0.0f;
-            if (lane == 16 * row) {
-                zp_s[j * 4 + row] = zv;
-                Ep_s[j * 4 + row] = 0.0f;
-                zr_s[j * 4 + row] = zv;
-                if (vj) cv[RSx::coord(row, j)] = zv;
-            }
-        }
+        // ---- a3: z = P_i (unprojected), u = 0  (so g = -a, c = z).  Lanes
+        // without a coordinate hold z = clamp(0) and E = 0, a fixed point of
+        // the z-update, so they need no masking below.
+        float zr = myv ? tile[R * S::P + R + myoff] : clampf(0.0f, L.lo, L.hi);  // z^t
+        float zp = zr;                                                      // z^{t-1}
+        float Ep = 0.0f;                                                    // E^t
+        cv[cidx] = zr;
         float g[M][NJ];
 #pragma unroll
         for (int q = 0; q < M; ++q)
@@ -205,7 +199,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             // ---- a4 (first half): delta = g + c, partial ||delta||^2
             float nrm[M];
 #pragma unroll
-            for (int q = 0; q < M; ++q) nrm[q] = 0.0f;
+            for (int q = 0; q < M; ++q) nrm[q] = kNu2Floor;
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) {
                 const float cj = cv[jj];
@@ -228,9 +222,9 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 __syncthreads();
 #pragma unroll
                 for (int q = 0; q < M; ++q) {
-                    float sum = 0.0f;
+                    float sum = X[q * 64 + lane];
 #pragma unroll
-                    for (int w = 0; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
+                    for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
                     nrm[q] = sum;
                 }
                 rd_all = 0.0f;
@@ -356,39 +350,23 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) asm volatile("" : "+v"(g[q][jj]));
             // ---- a5: reduce over the wave; a6: z-update; a7 implicit in g and c
-            float E[H2];
-            reduce_scatter<NJ>(acc, E);
-            float rdx = 0.0f, rpx = 0.0f;
-#pragma unroll
-            for (int j = 0; j < H2; ++j) {
-                const bool vj = RSx::valid(row, j);
-                const float zrj = zr_s[j * 4 + row];
-                const float zn = clampf(zrj - E[j] * inv_n, L.lo, L.hi);
-                const float dz = zn - zrj;
-                const float zpj = zp_s[j * 4 + row];
-                if (armed) {
-                    // sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
-                    // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1}
-                    const float Epj = Ep_s[j * 4 + row];
-                    const float cz = (2.0f * zrj - zpj) - zn;
-                    rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
-                }
-                rdx += vj ? dz * dz : 0.0f;
-                if (lane == 16 * row) {
-                    zp_s[j * 4 + row] = zrj;
-                    Ep_s[j * 4 + row] = E[j];
-                    zr_s[j * 4 + row] = vj ? zn : 0.0f;
-                    if (vj) cv[RSx::coord(row, j)] = 2.0f * zn - zrj;
-                }
-            }
-            rd_w = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) + (readlane(rdx, 32) + readlane(rdx, 48)));
+            const float Ev = reduce_scatter_full<NJ>(acc, lane);
+            const float zn = clampf(fmaf(-Ev, inv_n, zr), L.lo, L.hi);
+            const float dz = zn - zr;
+            cv[cidx] = zn + dz;
+            rd_w = readfirstlane(wave_sum(dz * dz));
             if (armed) {
-                const float tot = wave_sum(rp_lane);
-                rp_w = readfirstlane(readfirstlane(tot) +
-                       ((readlane(rpx, 0) + readlane(rpx, 16)) + (readlane(rpx, 32) + readlane(rpx, 48))));
+                // sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
+                // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1}
+                const float cz = (2.0f * zr - zp) - zn;
+                const float rpx = cz * fmaf(fn, cz, 2.0f * (Ep - Ev));
+                rp_w = readfirstlane(wave_sum(rp_lane + rpx));
             } else {
                 rp_w = 0.0f;
             }
+            zp = zr;
+            zr = zn;
+            Ep = Ev;
             armed_last = armed;
         }
 
@@ -427,9 +405,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 
         // ---- a9: the centre coordinate of the solution patch
         if constexpr (JC >= J0 && JC < J0 + NJ) {
-            constexpr int rc = RSx::row_of(JC - J0);
-            constexpr int sc = RSx::slot_of(JC - J0);
-            if (lane == 16 * rc) I.out[pix] = bad ? __builtin_nanf("") : zr_s[sc * 4 + rc];
+            constexpr int lc = RSx::lane_of(JC - J0);
+            if (lane == lc) I.out[pix] = bad ? __builtin_nanf("") : zr;
         }
         if (SW == 0 && lane == 0 && I.stats != nullptr) {
             em_stats_t st;
@@ -444,14 +421,14 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 
 template <int PR, int M, int WC, int SW>
 __device__ __forceinline__ void nlem_dispatch(int wave, const NlemLaunch &L, float *tile, float *xn,
-                                              float *xs, float *zpE, float *cvec, unsigned int *item_s) {
+                                              float *xs, float *cvec, unsigned int *item_s) {
     if constexpr (SW + 1 == WC) {
-        nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, zpE, cvec, item_s);
+        nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, cvec, item_s);
     } else {
         if (wave == SW)
-            nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, zpE, cvec, item_s);
+            nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, cvec, item_s);
         else
-            nlem_dispatch<PR, M, WC, SW + 1>(wave, L, tile, xn, xs, zpE, cvec, item_s);
+            nlem_dispatch<PR, M, WC, SW + 1>(wave, L, tile, xn, xs, cvec, item_s);
     }
 }
 
@@ -464,11 +441,10 @@ __global__ __launch_bounds__(64 * WC, EMX_NLEM_MIN_WAVES) void nlem_solve_kernel
     __shared__ float tile[S::TILE];
     __shared__ float xn[S::XN];
     __shared__ float xs[2 * WC * 4];
-    __shared__ float zpE[WC * 3 * RS<S::DS>::H2 * 4 + 8];
-    __shared__ float cvec[WC * S::DS];
+    __shared__ float cvec[WC * 128];
     __shared__ unsigned int item_s;
     const int wave = uniform_int(threadIdx.x >> 6);
-    nlem_dispatch<PR, M, WC, 0>(wave, L, tile, xn, xs, zpE, cvec, &item_s);
+    nlem_dispatch<PR, M, WC, 0>(wave, L, tile, xn, xs, cvec, &item_s);
 }
 
 }  // namespace emx
