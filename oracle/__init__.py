@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for EM-ADMM and NLEM (ctypes shim over em_oracle.c).
+"""FP64 CPU oracle for EM-ADMM, IRLS on the smooth surrogate, NLEM and NLM
+(ctypes shim over em_oracle.c).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
 benchmark's CPU-baseline leg may use this package; the product path never
@@ -23,6 +24,8 @@ _LIB = os.path.join(_HERE, "libemoracle.so")
 
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW = 0, 1
+SOLVER_ADMM, SOLVER_IRLS = 0, 1
+NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +64,18 @@ def _load():
                                     C.c_double, C.c_int64, i64p, dp, dp, dp, i32p, i32p, dp, dp,
                                     C.c_int]
         lib.oracle_nlem.restype = C.c_int
+        lib.oracle_nlem_ex.argtypes = [C.c_int64, C.c_int64, fp, C.c_int64, C.c_int64,
+                                       C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                       C.c_double, C.c_double, C.c_int64, i32p, C.c_double,
+                                       C.c_int64, i64p, dp, dp, dp, i32p, i32p, dp, dp, C.c_int]
+        lib.oracle_nlem_ex.restype = C.c_int
+        lib.oracle_irls_solve.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, C.c_double,
+                                          C.c_double, dp, C.c_int64, C.c_double, i64p, dp, dp]
+        lib.oracle_irls_solve.restype = C.c_int
+        lib.oracle_em_objective.argtypes = [C.c_int64, C.c_int64, dp, dp, dp]
+        lib.oracle_em_objective.restype = C.c_double
+        lib.oracle_surrogate_objective.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp]
+        lib.oracle_surrogate_objective.restype = C.c_double
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = C.c_int
         _lib = lib
@@ -140,10 +155,13 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
 
 def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: float,
          mu: float, max_iter: int, tol: float, pix=None, max_iter_each=None,
-         want_z: bool = False, want_weights: bool = False, nthreads: int = 0) -> dict:
+         want_z: bool = False, want_weights: bool = False, nthreads: int = 0,
+         solver: int = SOLVER_ADMM, init: int = NLEM_INIT_NOISY, eps: float = 1e-6) -> dict:
     """NLEM on the float32 image ``img`` (H x W) for the pixels ``pix`` (linear
-    indices; None = all).  Returns out (float64), iters, flags, residuals and
-    optionally the full patches z and the window weights."""
+    indices; None = all).  solver: SOLVER_ADMM (Algorithm 1, penalty mu) or
+    SOLVER_IRLS (surrogate with eps); init: the noisy patch or the NLM patch.
+    Returns out (float64), iters, flags, residuals and optionally the full
+    patches z and the window weights."""
     img = np.ascontiguousarray(img, dtype=np.float32)
     H, W = img.shape
     d = (2 * patch_radius + 1) ** 2
@@ -158,15 +176,67 @@ def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: fl
     rp = np.zeros(npix)
     rd = np.zeros(npix)
     mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
-    _load().oracle_nlem(H, W, _p(img, C.c_float), int(patch_radius), int(window_radius),
-                        float(h), float(lo), float(hi), float(mu), int(max_iter),
-                        _p(mie, C.c_int32), float(tol), npix, _p(pixa, C.c_int64),
-                        _p(out, C.c_double), _p(zf, C.c_double), _p(wo, C.c_double),
-                        _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
-                        _p(rd, C.c_double), int(nthreads))
+    _load().oracle_nlem_ex(H, W, _p(img, C.c_float), int(patch_radius), int(window_radius),
+                           float(h), float(lo), float(hi), int(solver), int(init), float(mu),
+                           float(eps), int(max_iter), _p(mie, C.c_int32), float(tol), npix,
+                           _p(pixa, C.c_int64), _p(out, C.c_double), _p(zf, C.c_double),
+                           _p(wo, C.c_double), _p(iters, C.c_int32), _p(flags, C.c_int32),
+                           _p(rp, C.c_double), _p(rd, C.c_double), int(nthreads))
     res = dict(out=out, iters=iters, flags=flags, r_pri=rp, r_dual=rd)
     if want_z:
         res["z"] = zf
     if want_weights:
         res["weights"] = wo
     return res
+
+
+def nlm(img, patch_radius: int, window_radius: int, h: float, pix=None, want_z: bool = False,
+        nthreads: int = 0) -> dict:
+    """Non-Local Means: per pixel the weighted mean sum_j w_ij P_j / sum_j w_ij of
+    the window's patches (the NLEM weights); ``out`` is its centre pixel."""
+    return nlem(img, patch_radius, window_radius, h, 0.0, 1.0, 1.0, 0, 0.0, pix=pix,
+                want_z=want_z, nthreads=nthreads, init=NLEM_INIT_NLM)
+
+
+def irls_solve(a, w, eps: float, lo: float, hi: float, z0, max_iter: int = 100,
+               tol: float = 0.0) -> dict:
+    """IRLS (majorise-minimise) on the surrogate sum_k w_k (||z - a_k||^2 + eps)^(1/2)
+    over the box, in FP64; returns z, iters, r_dual, flags."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    assert w.size == n and z.size == d
+    it = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    f = _load().oracle_irls_solve(n, d, _p(a, C.c_double), _p(w, C.c_double), float(eps),
+                                  float(lo), float(hi), _p(z, C.c_double), int(max_iter),
+                                  float(tol), C.byref(it), C.byref(rp), C.byref(rd))
+    return dict(z=z, iters=int(it.value), r_dual=rd.value, flags=int(f))
+
+
+def em_objective(a, w, z) -> float:
+    """sum_k w_k ||z - a_k|| (the objective of (EM))."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1)
+    return float(_load().oracle_em_objective(n, d, _p(a, C.c_double), _p(w, C.c_double),
+                                             _p(z, C.c_double)))
+
+
+def surrogate_objective(a, w, eps: float, z) -> float:
+    """sum_k w_k (||z - a_k||^2 + eps)^(1/2), equation (EM_surrogate)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.ascontiguousarray(z, dtype=np.float64).reshape(-1)
+    return float(_load().oracle_surrogate_objective(n, d, _p(a, C.c_double), _p(w, C.c_double),
+                                                    float(eps), _p(z, C.c_double)))

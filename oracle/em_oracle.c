@@ -1,6 +1,8 @@
 /*
  * FP64 CPU oracle for the box-constrained Euclidean median solved by
- * EM-ADMM, and for the Non-Local Euclidean Medians (NLEM) denoiser.
+ * EM-ADMM, the IRLS method for its smooth surrogate, and the Non-Local
+ * Euclidean Medians (NLEM) denoiser with the Non-Local Means estimate it is
+ * compared with and optionally started from.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
  * call this file; only the test suite, the smoke check and the benchmark's
@@ -172,6 +174,116 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
     return flags;
 }
 
+/*
+ * Objective of (EM) at z: sum_k w_k ||z - a_k||_2.
+ */
+double oracle_em_objective(int64_t n, int64_t d, const double *a, const double *w, const double *z)
+{
+    double f = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double q = 0.0;
+        for (int64_t j = 0; j < d; ++j) {
+            double t = z[j] - a[k * d + j];
+            q += t * t;
+        }
+        f += w[k] * sqrt(q);
+    }
+    return f;
+}
+
+/*
+ * The smooth surrogate of (EM) that the IRLS method of the paper's reference
+ * [Chaudhury2012] minimises, equation (EM_surrogate):
+ *   sum_k w_k (||z - a_k||^2 + eps)^(1/2),  eps > 0.
+ */
+double oracle_surrogate_objective(int64_t n, int64_t d, const double *a, const double *w,
+                                  double eps, const double *z)
+{
+    double f = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        double q = 0.0;
+        for (int64_t j = 0; j < d; ++j) {
+            double t = z[j] - a[k * d + j];
+            q += t * t;
+        }
+        f += w[k] * sqrt(q + eps);
+    }
+    return f;
+}
+
+/*
+ * IRLS for the surrogate (EM_surrogate) over the box C = [lo, hi]^d.  The
+ * paper names the method but does not print its steps; they follow from
+ * majorise-minimise: sqrt is concave, so at the current iterate z^t
+ *   (q + eps)^(1/2) <= (q_t + eps)^(1/2) + (q - q_t) / (2 (q_t + eps)^(1/2)),
+ * q = ||z - a_k||^2, with equality at z = z^t.  The majoriser is, up to a
+ * constant, sum_k omega_k ||z - a_k||^2 / 2 with
+ *   omega_k = w_k / (||z^t - a_k||^2 + eps)^(1/2),
+ * an isotropic quadratic centred at the omega-weighted mean, so its minimiser
+ * over the box is that mean projected coordinate-wise onto C:
+ *   z^{t+1} = P_C( sum_k omega_k a_k / sum_k omega_k ).
+ * Every step therefore decreases the surrogate (unless z^t is its minimiser).
+ * Stopping: after iteration t, r_dual = sqrt(||z^{t+1} - z^t||^2 / d) <= tol D
+ * with D as for EM-ADMM (there is no primal residual; *r_pri is set to 0).
+ * All weights zero: every z minimises the surrogate; z is left as given and
+ * the solve reports CONVERGED after one iteration.
+ * Flags, init and the n = 0 / bad-input rules are those of oracle_em_solve.
+ */
+int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                      double lo, double hi, double *z, int64_t max_iter, double tol,
+                      int64_t *iters, double *r_pri, double *r_dual)
+{
+    *iters = 0;
+    *r_pri = 0.0;
+    *r_dual = 0.0;
+    if (n == 0) return OR_EMPTY;
+    int bad = !(eps > 0.0);
+    for (int64_t k = 0; k < n; ++k)
+        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!isfinite(a[i])) bad = 1;
+    for (int64_t j = 0; j < d; ++j)
+        if (!isfinite(z[j])) bad = 1;
+    if (bad) {
+        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
+        return OR_BAD_INPUT;
+    }
+    double D = tol_scale(n, d, a, lo, hi);
+    double *num = (double *)malloc((size_t)d * sizeof(double));
+    int flags = OR_MAXITER;
+    for (int64_t t = 1; t <= max_iter; ++t) {
+        double den = 0.0;
+        for (int64_t j = 0; j < d; ++j) num[j] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double q = 0.0;
+            for (int64_t j = 0; j < d; ++j) {
+                double e = z[j] - a[k * d + j];
+                q += e * e;
+            }
+            double om = w[k] / sqrt(q + eps);
+            den += om;
+            for (int64_t j = 0; j < d; ++j) num[j] += om * a[k * d + j];
+        }
+        double sd = 0.0;
+        if (den > 0.0) {
+            for (int64_t j = 0; j < d; ++j) {
+                double zn = clamp_box(num[j] / den, lo, hi);
+                double e = zn - z[j];
+                sd += e * e;
+                z[j] = zn;
+            }
+        }
+        *r_dual = sqrt(sd / (double)d);
+        *iters = t;
+        if (den == 0.0 || (tol > 0.0 && *r_dual <= tol * D)) {
+            flags = OR_CONVERGED;
+            break;
+        }
+    }
+    free(num);
+    return flags;
+}
+
 static void set_threads(int nthreads)
 {
 #ifdef _OPENMP
@@ -262,9 +374,14 @@ static void extract_patch(const float *img, int64_t H, int64_t W, int64_t pr,
  * P_j of every pixel j of the (2wr+1) x (2wr+1) search window centred at i
  * that lies inside the image (the window is truncated at borders, j = i
  * included, row-major order), the weights are w_ij = exp(-||P_i - P_j||^2 /
- * h^2) (not normalised), the box is [lo, hi]^d, the initial z is the noisy
- * patch P_i (unprojected) and y starts at zero.  The denoised pixel is the
- * centre coordinate of the returned patch, z[(d - 1) / 2].
+ * h^2) (not normalised), the box is [lo, hi]^d and y starts at zero.  The
+ * denoised pixel is the centre coordinate of the returned patch, z[(d - 1) / 2].
+ *
+ * solver: 0 = EM-ADMM (Algorithm 1, penalty mu), 1 = IRLS on the surrogate
+ * (EM_surrogate) with parameter eps (oracle_irls_solve).
+ * init: 0 = the noisy patch P_i (unprojected), 1 = the NLM patch
+ * sum_j w_ij P_j / sum_j w_ij (the two starting points Section 3 compares).
+ * With init = 1 and max_iter = 0 the output is the Non-Local Means estimate.
  *
  * pix: npix linear pixel indices (NULL: all H*W pixels in order).
  * max_iter_each (nullable): per requested pixel iteration cap.
@@ -272,12 +389,12 @@ static void extract_patch(const float *img, int64_t H, int64_t W, int64_t pr,
  * weights_out (nullable): npix * (2wr+1)^2 weights in window order, slots of
  * points outside the image set to -1.
  */
-int oracle_nlem(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
-                double h, double lo, double hi, double mu, int64_t max_iter,
-                const int32_t *max_iter_each, double tol, int64_t npix,
-                const int64_t *pix, double *out, double *zfull, double *weights_out,
-                int32_t *iters, int32_t *flags, double *r_pri, double *r_dual,
-                int nthreads)
+int oracle_nlem_ex(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
+                   double h, double lo, double hi, int solver, int init, double mu,
+                   double eps, int64_t max_iter, const int32_t *max_iter_each, double tol,
+                   int64_t npix, const int64_t *pix, double *out, double *zfull,
+                   double *weights_out, int32_t *iters, int32_t *flags, double *r_pri,
+                   double *r_dual, int nthreads)
 {
     int64_t side = 2 * pr + 1, d = side * side;
     int64_t wside = 2 * wr + 1, nmax = wside * wside;
@@ -312,11 +429,24 @@ int oracle_nlem(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
                 if (weights_out) weights_out[q * nmax + slot] = wk[n];
                 ++n;
             }
-        memcpy(z, Pi, (size_t)d * sizeof(double));
+        if (init == 1) {
+            /* NLM patch: the weighted mean of the window's patches */
+            double ws = 0.0;
+            for (int64_t k = 0; k < n; ++k) ws += wk[k];
+            for (int64_t c = 0; c < d; ++c) {
+                double acc = 0.0;
+                for (int64_t k = 0; k < n; ++k) acc += wk[k] * a[k * d + c];
+                z[c] = acc / ws;
+            }
+        } else {
+            memcpy(z, Pi, (size_t)d * sizeof(double));
+        }
         int64_t it = 0;
         double rp = 0.0, rd = 0.0;
         int64_t mi = max_iter_each ? max_iter_each[q] : max_iter;
-        int f = oracle_em_solve(n, d, a, wk, mu, lo, hi, z, NULL, NULL, mi, tol, &it, &rp, &rd);
+        int f = (solver == 1)
+                    ? oracle_irls_solve(n, d, a, wk, eps, lo, hi, z, mi, tol, &it, &rp, &rd)
+                    : oracle_em_solve(n, d, a, wk, mu, lo, hi, z, NULL, NULL, mi, tol, &it, &rp, &rd);
         out[q] = z[(d - 1) / 2];
         if (zfull) memcpy(zfull + q * d, z, (size_t)d * sizeof(double));
         if (iters) iters[q] = (int32_t)it;
@@ -329,4 +459,17 @@ int oracle_nlem(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
         free(Pi);
     }
     return 0;
+}
+
+/* NLEM with EM-ADMM started from the noisy patch (oracle_nlem_ex, solver 0, init 0). */
+int oracle_nlem(int64_t H, int64_t W, const float *img, int64_t pr, int64_t wr,
+                double h, double lo, double hi, double mu, int64_t max_iter,
+                const int32_t *max_iter_each, double tol, int64_t npix,
+                const int64_t *pix, double *out, double *zfull, double *weights_out,
+                int32_t *iters, int32_t *flags, double *r_pri, double *r_dual,
+                int nthreads)
+{
+    return oracle_nlem_ex(H, W, img, pr, wr, h, lo, hi, 0, 0, mu, 1.0, max_iter, max_iter_each,
+                          tol, npix, pix, out, zfull, weights_out, iters, flags, r_pri, r_dual,
+                          nthreads);
 }

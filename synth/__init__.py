@@ -13,6 +13,7 @@ from .images import (  # noqa: F401
     piecewise_smooth_image,
     add_gaussian_noise,
     add_impulses,
+    psnr,
 )
 from .pointsets import PointSetBatch, make_pointset_batch  # noqa: F401
 from .configs import (  # noqa: F401

@@ -100,3 +100,11 @@ def add_impulses(rng: np.random.Generator, img: np.ndarray, prob: float,
     out[hit & salt] = hi
     out[hit & ~salt] = lo
     return out
+
+
+def psnr(estimate: np.ndarray, clean: np.ndarray, peak: float = 255.0) -> float:
+    """Peak signal-to-noise ratio 10 log10(peak^2 / MSE) in dB (the quality
+    measure of the paper's denoising table); an evaluation metric, not part of
+    any denoiser."""
+    err = np.asarray(estimate, np.float64) - np.asarray(clean, np.float64)
+    return float(10.0 * np.log10(peak * peak / np.mean(err * err)))
