@@ -197,6 +197,63 @@ em_status_t nlem_denoise_multi(em_handle_t handle, void *stream, int32_t count,
                                const nlem_image_t *images, float lo, float hi, float rho,
                                int32_t max_iter, float tol);
 
+/* Solver of nlem_denoise_ex. */
+typedef enum {
+    NLEM_SOLVER_ADMM = 0, /* EM-ADMM (Algorithm 1) on (EM), penalty rho */
+    NLEM_SOLVER_IRLS = 1  /* IRLS on the smooth surrogate (EM_surrogate), parameter eps */
+} nlem_solver_t;
+
+/* Starting patch z^0 of nlem_denoise_ex (the two options of Section 3). */
+typedef enum {
+    NLEM_INIT_NOISY = 0, /* the noisy patch P_i */
+    NLEM_INIT_NLM = 1    /* the Non-Local Means patch sum_j w_ij P_j / sum_j w_ij */
+} nlem_init_t;
+
+/* Options of nlem_denoise_ex (host memory). */
+typedef struct {
+    int32_t solver;   /* nlem_solver_t */
+    int32_t init;     /* nlem_init_t */
+    float lo, hi;     /* the box [lo, hi]^d, finite, lo <= hi */
+    float rho;        /* ADMM penalty mu, finite > 0 (ignored by IRLS) */
+    float eps;        /* IRLS surrogate parameter, finite > 0 (ignored by ADMM) */
+    int32_t max_iter; /* >= 0 */
+    float tol;        /* >= 0 */
+} nlem_options_t;
+
+/*
+ * nlem_denoise_ex - nlem_denoise for `count` images (one persistent launch per
+ * shape group, no graph) with a choice of solver and starting patch.
+ *   ADMM: exactly nlem_denoise, started from opt->init's patch.
+ *   IRLS: the iteratively reweighted least-squares method for the smooth
+ *     surrogate sum_j w_ij (||P - P_j||^2 + eps)^(1/2) that Section 1 cites
+ *     and Table 1 compares (the paper does not print its steps; they are the
+ *     majorise-minimise steps of that surrogate over the box):
+ *       omega_j = w_ij / (||z - P_j||^2 + eps)^(1/2),
+ *       z'      = P_C( sum_j omega_j P_j / sum_j omega_j ),
+ *     stopped when r_dual = sqrt(||z' - z||^2 / d) <= tol (hi - lo) (checked
+ *     one iteration late, as the ADMM primal residual) or after max_iter
+ *     iterations; stats report r_pri = 0.  eps is in squared intensity units
+ *     (the paper uses 1e-6 with intensities in [0, 255]).
+ *   init = NLEM_INIT_NLM with max_iter = 0 returns the NLM estimate.
+ * Weights, window, border and output rules as for nlem_denoise; `images` and
+ * `opt` are host memory.
+ * Errors: INVALID_ARG (NULL handle/options, bad image list or image, bad
+ * solver/init, eps <= 0 for IRLS, parameter errors of nlem_denoise);
+ * UNSUPPORTED (radii above the limits); HIP.
+ */
+em_status_t nlem_denoise_ex(em_handle_t handle, void *stream, int32_t count,
+                            const nlem_image_t *images, const nlem_options_t *opt);
+
+/*
+ * nlm_denoise - the Non-Local Means estimate that Table 1 compares NLEM with:
+ * out[i] = sum_j w_ij g_j / sum_j w_ij over the same truncated search window
+ * and weights as nlem_denoise (g_j the noisy pixel j, the centre of P_j).
+ * Arguments and errors as for nlem_denoise (no solver parameters, no stats).
+ */
+em_status_t nlm_denoise(em_handle_t handle, void *stream, const void *img, int32_t img_is_f16,
+                        int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                        float h_param, float *out);
+
 /* Wait for the stream and report any asynchronous HIP error as EM_ERR_HIP. */
 em_status_t em_sync(em_handle_t handle, void *stream);
 

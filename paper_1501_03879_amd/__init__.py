@@ -20,6 +20,8 @@ LIB_PATH = os.environ.get("EMX_LIBRARY") or os.path.join(HERE, "libemx.so")
 EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW = 0, 1
+SOLVER_ADMM, SOLVER_IRLS = 0, 1
+NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10
 
 # the 16-byte per-instance / per-pixel result record (em_stats_t)
@@ -36,6 +38,11 @@ class NlemImage(C.Structure):
     _fields_ = [("img", C.c_void_p), ("out", C.c_void_p), ("stats", C.c_void_p),
                 ("H", C.c_int32), ("W", C.c_int32), ("patch_radius", C.c_int32),
                 ("window_radius", C.c_int32), ("h_param", C.c_float), ("img_is_f16", C.c_int32)]
+
+
+class NlemOptions(C.Structure):
+    _fields_ = [("solver", C.c_int32), ("init", C.c_int32), ("lo", C.c_float), ("hi", C.c_float),
+                ("rho", C.c_float), ("eps", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_float)]
 
 
 _lib = None
@@ -66,6 +73,10 @@ def load_library():
         lib.nlem_denoise.restype = C.c_int
         lib.nlem_denoise_multi.argtypes = [vp, vp, i32, C.POINTER(NlemImage), f32, f32, f32, i32, f32]
         lib.nlem_denoise_multi.restype = C.c_int
+        lib.nlem_denoise_ex.argtypes = [vp, vp, i32, C.POINTER(NlemImage), C.POINTER(NlemOptions)]
+        lib.nlem_denoise_ex.restype = C.c_int
+        lib.nlm_denoise.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, vp]
+        lib.nlm_denoise.restype = C.c_int
         lib.em_sync.argtypes = [vp, vp]
         lib.em_sync.restype = C.c_int
         lib.em_status_string.argtypes = [C.c_int]
@@ -156,22 +167,46 @@ class Handle:
                            stream=None):
         """items: list of dicts with img, out, stats (optional), patch_radius,
         window_radius, h."""
-        import torch
-        arr = (NlemImage * len(items))()
-        for k, it in enumerate(items):
-            img = it["img"]
-            arr[k] = NlemImage(img.data_ptr(), it["out"].data_ptr(),
-                               it["stats"].data_ptr() if it.get("stats") is not None else None,
-                               int(img.shape[0]), int(img.shape[1]), int(it["patch_radius"]),
-                               int(it["window_radius"]), float(it["h"]),
-                               1 if img.dtype == torch.float16 else 0)
+        arr = _image_array(items)
         self._keep = (arr, items)  # descriptors must outlive graph (re)creation
         st = self.lib.nlem_denoise_multi(self.h, _stream(stream), len(items), arr, float(lo),
                                          float(hi), float(rho), int(max_iter), float(tol))
         self._check(st, "nlem_denoise_multi")
 
+    def nlem_denoise_ex(self, items, *, solver=SOLVER_ADMM, init=NLEM_INIT_NOISY, lo=0.0, hi=255.0,
+                        rho=1e-3, eps=1e-6, max_iter=200, tol=1e-4, stream=None):
+        """items: list of dicts with img, out, stats (optional), patch_radius,
+        window_radius, h (as nlem_denoise_multi)."""
+        arr = _image_array(items)
+        opt = NlemOptions(int(solver), int(init), float(lo), float(hi), float(rho), float(eps),
+                          int(max_iter), float(tol))
+        st = self.lib.nlem_denoise_ex(self.h, _stream(stream), len(items), arr, C.byref(opt))
+        self._check(st, "nlem_denoise_ex")
+
+    def nlm_denoise(self, img, out, *, patch_radius, window_radius, h, stream=None):
+        """Non-Local Means: img H x W float32/float16, out H x W float32."""
+        import torch
+        H, W = int(img.shape[0]), int(img.shape[1])
+        is16 = 1 if img.dtype == torch.float16 else 0
+        st = self.lib.nlm_denoise(self.h, _stream(stream), _ptr(img), is16, H, W, int(patch_radius),
+                                  int(window_radius), float(h), _ptr(out))
+        self._check(st, "nlm_denoise")
+
     def sync(self, stream=None):
         self._check(self.lib.em_sync(self.h, _stream(stream)), "em_sync")
+
+
+def _image_array(items):
+    import torch
+    arr = (NlemImage * len(items))()
+    for k, it in enumerate(items):
+        img = it["img"]
+        arr[k] = NlemImage(img.data_ptr(), it["out"].data_ptr(),
+                           it["stats"].data_ptr() if it.get("stats") is not None else None,
+                           int(img.shape[0]), int(img.shape[1]), int(it["patch_radius"]),
+                           int(it["window_radius"]), float(it["h"]),
+                           1 if img.dtype == torch.float16 else 0)
+    return arr
 
 
 _handles = {}

@@ -228,13 +228,13 @@ static int points_per_lane(int R) { return ((2 * R + 1) * (2 * R + 1) + 63) / 64
 
 // Kernel for a shape: the default coordinate-wave count, or EMX_NLEM_WC when
 // that variant is compiled (a tuning override).
-static NlemKernelInfo select_nlem_kernel(int pr, int m) {
+static NlemKernelInfo select_nlem_kernel(int pr, int m, int solver) {
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
-        NlemKernelInfo k = nlem_kernel(pr, m, atoi(env));
+        NlemKernelInfo k = nlem_kernel(pr, m, atoi(env), solver);
         if (k.fn) return k;
     }
-    return nlem_kernel(pr, m, nlem_default_wc(pr, m));
+    return nlem_kernel(pr, m, nlem_default_wc(pr, m), solver);
 }
 
 static em_status_t check_solver_params(em_context *ctx, float lo, float hi, float rho,
@@ -276,13 +276,42 @@ static NlemImageDesc make_desc(const nlem_image_t &im) {
     return d;
 }
 
-static void fill_common(NlemLaunch &L, float lo, float hi, float rho, int32_t max_iter, float tol) {
-    L.max_iter = max_iter;
-    L.inv_mu = 1.0f / rho;
-    L.lo = lo;
-    L.hi = hi;
-    L.tau = tol * (hi - lo);
+static void fill_common(NlemLaunch &L, const nlem_options_t &o) {
+    L.max_iter = o.max_iter;
+    L.inv_mu = (o.solver == NLEM_SOLVER_ADMM) ? 1.0f / o.rho : 0.0f;
+    L.lo = o.lo;
+    L.hi = o.hi;
+    L.tau = o.tol * (o.hi - o.lo);
     L.tau_arm = kArmFactor * L.tau;
+    L.init_nlm = (o.init == NLEM_INIT_NLM) ? 1 : 0;
+    L.eps = o.eps;
+}
+
+static nlem_options_t admm_options(float lo, float hi, float rho, int32_t max_iter, float tol) {
+    nlem_options_t o{};
+    o.solver = NLEM_SOLVER_ADMM;
+    o.init = NLEM_INIT_NOISY;
+    o.lo = lo;
+    o.hi = hi;
+    o.rho = rho;
+    o.eps = 1e-6f;
+    o.max_iter = max_iter;
+    o.tol = tol;
+    return o;
+}
+
+static em_status_t check_options(em_context *ctx, const nlem_options_t *o) {
+    if (!o) return fail(ctx, EM_ERR_INVALID_ARG, "options must be non-NULL");
+    if (o->solver != NLEM_SOLVER_ADMM && o->solver != NLEM_SOLVER_IRLS)
+        return fail(ctx, EM_ERR_INVALID_ARG, "bad solver");
+    if (o->init != NLEM_INIT_NOISY && o->init != NLEM_INIT_NLM) return fail(ctx, EM_ERR_INVALID_ARG, "bad init");
+    if (o->solver == NLEM_SOLVER_IRLS && (!(o->eps > 0.0f) || !std::isfinite(o->eps)))
+        return fail(ctx, EM_ERR_INVALID_ARG, "eps must be finite and > 0");
+    const float rho = (o->solver == NLEM_SOLVER_ADMM) ? o->rho : 1.0f;
+    em_status_t st = check_solver_params(ctx, o->lo, o->hi, rho, o->max_iter, o->tol);
+    if (st != EM_OK) return st;
+    if (!std::isfinite(o->lo) || !std::isfinite(o->hi)) return fail(ctx, EM_ERR_INVALID_ARG, "nlem needs a finite box");
+    return EM_OK;
 }
 
 struct NlemGroup {
@@ -306,11 +335,11 @@ static std::vector<NlemGroup> group_images(int32_t count, const nlem_image_t *im
     return groups;
 }
 
-static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, float lo, float hi,
-                              float rho, int32_t max_iter, float tol, unsigned int *counter) {
+static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, const nlem_options_t &o,
+                              unsigned int *counter) {
     NlemLaunch L;
     memset(&L, 0, sizeof(L));
-    fill_common(L, lo, hi, rho, max_iter, tol);
+    fill_common(L, o);
     L.count = (int)g.images.size();
     L.prefix[0] = 0;
     for (int k = 0; k < L.count; ++k) {
@@ -322,6 +351,28 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, fl
     return L;
 }
 
+// Queue one persistent launch per (patch radius, points per lane) group of
+// the images, each after a reset of its work-queue head.
+static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const nlem_image_t *images,
+                            const nlem_options_t &o) {
+    auto groups = group_images(count, images);
+    if ((int)groups.size() > h->num_counters) return fail(h, EM_ERR_UNSUPPORTED, "too many shape groups");
+    em_status_t st = ctx_reset_counters(h, s, h->counters, (int)groups.size());
+    if (st != EM_OK) return st;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const NlemGroup &g = groups[gi];
+        NlemKernelInfo k = select_nlem_kernel(g.pr, g.m, o.solver);
+        if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
+        NlemLaunch L = make_launch(g, images, o, h->counters + gi);
+        const int64_t total = L.prefix[L.count];
+        const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+        void *args[] = {&L};
+        EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
+    }
+    return EM_OK;
+}
+
 extern "C" em_status_t nlem_denoise(em_handle_t h, void *stream, const void *img, int32_t img_is_f16,
                                     int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
                                     float h_param, float lo, float hi, float rho, int32_t max_iter,
@@ -330,23 +381,40 @@ extern "C" em_status_t nlem_denoise(em_handle_t h, void *stream, const void *img
     nlem_image_t im{img, out, stats, H, W, patch_radius, window_radius, h_param, img_is_f16};
     em_status_t st = check_image(h, im);
     if (st != EM_OK) return st;
-    st = check_solver_params(h, lo, hi, rho, max_iter, tol);
+    const nlem_options_t o = admm_options(lo, hi, rho, max_iter, tol);
+    st = check_options(h, &o);
     if (st != EM_OK) return st;
-    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(h, EM_ERR_INVALID_ARG, "nlem needs a finite box");
     EMX_HIP(h, hipSetDevice(h->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    auto groups = group_images(1, &im);
-    const NlemGroup &g = groups[0];
-    NlemKernelInfo k = select_nlem_kernel(g.pr, g.m);
-    NlemLaunch L = make_launch(g, &im, lo, hi, rho, max_iter, tol, h->counters);
-    st = ctx_reset_counters(h, s, h->counters, 1);
+    return nlem_run(h, static_cast<hipStream_t>(stream), 1, &im, o);
+}
+
+extern "C" em_status_t nlem_denoise_ex(em_handle_t h, void *stream, int32_t count,
+                                       const nlem_image_t *images, const nlem_options_t *opt) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (count < 0 || (count > 0 && !images)) return fail(h, EM_ERR_INVALID_ARG, "bad image list");
+    for (int i = 0; i < count; ++i) {
+        em_status_t st = check_image(h, images[i]);
+        if (st != EM_OK) return st;
+    }
+    em_status_t st = check_options(h, opt);
     if (st != EM_OK) return st;
-    const int64_t total = L.prefix[L.count];
-    const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
-    void *args[] = {&L};
-    EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
-    return EM_OK;
+    if (count == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return nlem_run(h, static_cast<hipStream_t>(stream), count, images, *opt);
+}
+
+extern "C" em_status_t nlm_denoise(em_handle_t h, void *stream, const void *img, int32_t img_is_f16,
+                                   int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                                   float h_param, float *out) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    nlem_image_t im{img, out, nullptr, H, W, patch_radius, window_radius, h_param, img_is_f16};
+    em_status_t st = check_image(h, im);
+    if (st != EM_OK) return st;
+    // the NLM patch as the starting point and no iterations: its centre is NLM
+    nlem_options_t o = admm_options(0.0f, 1.0f, 1.0f, 0, 0.0f);
+    o.init = NLEM_INIT_NLM;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return nlem_run(h, static_cast<hipStream_t>(stream), 1, &im, o);
 }
 
 static bool same_key(const std::vector<char> &a, const std::vector<char> &b) {
@@ -362,9 +430,9 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         em_status_t st = check_image(h, images[i]);
         if (st != EM_OK) return st;
     }
-    em_status_t st = check_solver_params(h, lo, hi, rho, max_iter, tol);
+    const nlem_options_t o = admm_options(lo, hi, rho, max_iter, tol);
+    em_status_t st = check_options(h, &o);
     if (st != EM_OK) return st;
-    if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(h, EM_ERR_INVALID_ARG, "nlem needs a finite box");
     if (count == 0) return EM_OK;
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -385,9 +453,9 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         EMX_HIP(h, hipGraphCreate(&graph, 0));
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const NlemGroup &g = groups[gi];
-            NlemKernelInfo k = select_nlem_kernel(g.pr, g.m);
+            NlemKernelInfo k = select_nlem_kernel(g.pr, g.m, NLEM_SOLVER_ADMM);
             unsigned int *counter = h->counters + gi;
-            NlemLaunch L = make_launch(g, images, lo, hi, rho, max_iter, tol, counter);
+            NlemLaunch L = make_launch(g, images, o, counter);
             // node 1: zero this group's work-queue head (a kernel, not a memset node)
             hipKernelNodeParams rp{};
             int one = 1;

@@ -30,6 +30,8 @@ struct NlemLaunch {
     float lo, hi;
     float tau;       // tol * (hi - lo); 0 = fixed iteration count
     float tau_arm;   // primal residual evaluated after an iteration with r_dual <= tau_arm
+    int32_t init_nlm;       // 1: start from the NLM patch instead of the noisy patch
+    float eps;              // IRLS surrogate parameter
     unsigned int *counter;  // work-queue head, zeroed before the launch
 };
 

@@ -26,6 +26,13 @@
 //    the wave, after which one lane per slice coordinate holds E and keeps
 //    z^t, z^{t-1}, E^t of that coordinate in registers; c is broadcast to the
 //    other lanes through LDS for the next pass.
+//  * Starting point (Section 3 compares two): the noisy patch P_i, or the
+//    Non-Local Means patch sum_j w_j P_j / sum_j w_j, computed by a weights
+//    pass before the loop; with zero iterations the output is then NLM.
+//  * SOLVER = 1 runs IRLS on the smooth surrogate (EM_surrogate) instead:
+//    omega_j = w_j / (||z - P_j||^2 + eps)^(1/2) and z' = P_C(sum_j omega_j
+//    P_j / sum_j omega_j) (majorise-minimise; the box projection is exact for
+//    the isotropic quadratic majoriser), 3 operations per point-coordinate.
 #pragma once
 
 #include <float.h>
@@ -75,9 +82,10 @@ struct NlemShape {
     static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
 };
 
-template <int PR, int M, int WC, int SW>
+template <int PR, int M, int WC, int SW, int SOLVER>
 __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, float *xn, float *xs,
                                           float *cvec, unsigned int *item_s) {
+    constexpr bool IRLS = SOLVER == 1;
     using S = NlemShape<PR, M, WC>;
     constexpr int J0 = SW * S::DS;
     constexpr int NJ = (S::D - J0 < S::DS) ? (S::D - J0) : S::DS;
@@ -93,8 +101,9 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     // coordinate write to a private slot in [64, 128) instead
     float *cv = cvec + SW * 128;
     const int cidx = myv ? myc : 64 + lane;
-    // points stay in registers when they fit (the compiler hoists the tile reads)
-    constexpr bool kKeep = M * NJ <= kKeepPointsInRegs;
+    // points stay in registers when they fit (the compiler hoists the tile
+    // reads); IRLS never changes g = -a, so it always keeps them
+    constexpr bool kKeep = IRLS || M * NJ <= kKeepPointsInRegs;
     // software prefetch of the next coordinate's points (off when occupancy
     // is the tighter constraint)
 #ifndef EMX_PREFETCH
@@ -169,6 +178,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         // without a coordinate hold z = clamp(0) and E = 0, a fixed point of
         // the z-update, so they need no masking below.
         float zr = myv ? tile[R * S::P + R + myoff] : clampf(0.0f, L.lo, L.hi);  // z^t
+        const float pc = zr;                                                // P_i (own coordinate)
         float zp = zr;                                                      // z^{t-1}
         float Ep = 0.0f;                                                    // E^t
         cv[cidx] = zr;
@@ -177,6 +187,93 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         for (int q = 0; q < M; ++q)
 #pragma unroll
             for (int jj = 0; jj < NJ; ++jj) g[q][jj] = -tile[pbase(q) + poff(jj)];
+
+        // sums of per-wave partials over the WC waves (identical in every wave)
+        auto exchange = [&](float (&v)[M], float *X) {
+            if constexpr (WC > 1) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = v[q];
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    float sum = X[q * 64 + lane];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
+                    v[q] = sum;
+                }
+            }
+        };
+        // a2: NLM weights w_j = exp(-||P_i - P_j||^2 / h^2) from the squared
+        // distances (invalid window slots get 0); false if a distance is not finite
+        auto weights_from = [&](const float (&nrm)[M], float (&wt)[M]) {
+            bool nonfinite = false;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                const bool valid = lam[q] >= 0.0f;   // -1 marks window slots outside the image
+                nonfinite |= valid && !(nrm[q] <= FLT_MAX);
+                wt[q] = valid ? exp2f(-nrm[q] * I.k_h) : 0.0f;
+            }
+            return !__any(nonfinite);
+        };
+
+        bool bad = false;
+        float wt[M];           // IRLS: the NLM weights (ADMM keeps lam = w / mu)
+        const bool pre = IRLS || L.init_nlm;
+        if (pre) {
+            // weights pass before the loop: ||P_i - P_j||^2 with c = P_i, g = -a
+            float nrm[M];
+#pragma unroll
+            for (int q = 0; q < M; ++q) nrm[q] = kNu2Floor;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const float cj = cv[jj];
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const float dv = g[q][jj] + cj;
+                    nrm[q] = fmaf(dv, dv, nrm[q]);
+                }
+            }
+            exchange(nrm, xn);   // buffer 0: the loop starts on buffer 1
+            bad = !weights_from(nrm, wt);
+            if constexpr (IRLS) {
+                // IRLS works relative to the noisy patch: g = P_i - a and the
+                // iterate is held as z - P_i, so the distance to the pixel's
+                // own patch (which dominates the weights near the start, where
+                // it is ~ eps^(1/2)) carries FP32 precision of its own size
+                // rather than of the intensities.
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    const float cj = cv[jj];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) g[q][jj] += cj;
+                }
+                zr = 0.0f;
+                cv[cidx] = 0.0f;
+            }
+            if (!bad && L.init_nlm) {
+                // z^0 = the NLM patch sum_j w_j P_j / sum_j w_j (a3, second option)
+                float acc[NJ];
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    float ac = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) ac = fmaf(wt[q], g[q][jj], ac);
+                    acc[jj] = ac;
+                }
+                float wl = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) wl += wt[q];
+                const float inv_ws = 1.0f / readfirstlane(wave_sum(wl));
+                const float Ev = reduce_scatter_full<NJ>(acc, lane);   // -sum_j w_j P_j
+                if (myv) zr = -Ev * inv_ws;   // ADMM: the NLM patch; IRLS: it minus P_i
+                zp = zr;
+                cv[cidx] = zr;
+            }
+            if constexpr (!IRLS) {
+#pragma unroll
+                for (int q = 0; q < M; ++q) lam[q] = wt[q] * L.inv_mu;
+            }
+        }
 
         const float inv_n = 1.0f / (float)n;
         const float fn = (float)n;
@@ -189,9 +286,73 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         int iters = 0, flags = EM_MAXITER;
         float rp2 = 0.0f, rd2 = 0.0f;  // mean squares of the last evaluated iteration
         float rd_w = 0.0f, rp_w = 0.0f;
-        bool armed_last = false, bad = false, done = false;
+        bool armed_last = false, done = false;
         int t = 1;
-        for (; t <= max_iter; ++t) {
+        if constexpr (IRLS) {
+            const float eps = L.eps;
+            for (; t <= max_iter && !bad; ++t) {
+                // ---- ||z - P_j||^2 (c = z; g = -a never changes)
+                float nrm[M];   // + eps, counted once over the WC partial sums
+#pragma unroll
+                for (int q = 0; q < M; ++q) nrm[q] = (SW == 0) ? eps : 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    const float cj = cv[jj];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const float dv = g[q][jj] + cj;
+                        nrm[q] = fmaf(dv, dv, nrm[q]);
+                    }
+                }
+                float rd_all = rd_w;
+                if constexpr (WC > 1) {
+                    float *XS = xs + (t & 1) * WC * 4;
+                    if (lane == 0) XS[SW * 4] = rd_w;
+                    exchange(nrm, xn + (t & 1) * WC * M * 64);
+                    rd_all = XS[0];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
+                    rd_all = readfirstlane(rd_all);
+                }
+                // stop test for iteration t-1 (dual residual only)
+                if (t > 1) {
+                    rd2 = rd_all * inv_d;
+                    if (uniform(tau2 > 0.0f && rd2 <= tau2)) {
+                        flags = EM_CONVERGED;
+                        iters = t - 1;
+                        done = true;
+                        break;
+                    }
+                }
+                // ---- omega_j = w_j (||z - P_j||^2 + eps)^(-1/2); sum_j omega_j P_j
+                float om[M];
+                float ol = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    om[q] = wt[q] * __builtin_amdgcn_rsqf(nrm[q]);
+                    ol += om[q];
+                }
+                float acc[NJ];
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    float ac = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) ac = fmaf(om[q], g[q][jj], ac);
+                    acc[jj] = ac;
+                }
+                const float Ev = reduce_scatter_full<NJ>(acc, lane);   // -sum_j omega_j P_j
+                const float inv_os = 1.0f / readfirstlane(wave_sum(ol));
+                // z' - P_i = P_C(P_i + raw) - P_i, exact when the box is inactive
+                const float raw = -Ev * inv_os;
+                const float zab = pc + raw;
+                const float zn = !myv ? zr : (zab < L.lo ? L.lo - pc : (zab > L.hi ? L.hi - pc : raw));
+                const float dz = zn - zr;
+                cv[cidx] = zn;
+                rd_w = readfirstlane(wave_sum(dz * dz));
+                zr = zn;
+            }
+        } else
+        for (; t <= max_iter && !bad; ++t) {
             // Large slices read the points from the LDS tile every iteration;
             // without this the compiler hoists the loop-invariant tile reads
             // and keeps all M*NJ points live in registers.
@@ -248,19 +409,16 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     break;
                 }
             }
-            // ---- a2: NLM weights from the first iteration's distances
-            if (t == 1) {
-                bool nonfinite = false;
-#pragma unroll
-                for (int q = 0; q < M; ++q) {
-                    const bool valid = lam[q] >= 0.0f;   // -1 marks window slots outside the image
-                    nonfinite |= valid && !(nrm[q] <= FLT_MAX);
-                    lam[q] = valid ? exp2f(-nrm[q] * I.k_h) * L.inv_mu : 0.0f;
-                }
-                if (__any(nonfinite)) {
+            // ---- a2: NLM weights from the first iteration's distances (the
+            // noisy start: delta = P_i - P_j), unless the pre-pass made them
+            if (t == 1 && !pre) {
+                float w1[M];
+                if (!weights_from(nrm, w1)) {
                     bad = true;
                     break;
                 }
+#pragma unroll
+                for (int q = 0; q < M; ++q) lam[q] = w1[q] * L.inv_mu;
             }
             const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
             float s[M];
@@ -392,7 +550,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     rp_all = readfirstlane(rp_all);
                 }
                 rd2 = rd_all * inv_d;
-                rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                rp2 = IRLS ? 0.0f : fmaxf(rp_all, 0.0f) * inv_nd;
                 flags = (tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
             }
         }
@@ -406,7 +564,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         // ---- a9: the centre coordinate of the solution patch
         if constexpr (JC >= J0 && JC < J0 + NJ) {
             constexpr int lc = RSx::lane_of(JC - J0);
-            if (lane == lc) I.out[pix] = bad ? __builtin_nanf("") : zr;
+            if (lane == lc) I.out[pix] = bad ? __builtin_nanf("") : (IRLS ? pc + zr : zr);
         }
         if (SW == 0 && lane == 0 && I.stats != nullptr) {
             em_stats_t st;
@@ -419,20 +577,20 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     }
 }
 
-template <int PR, int M, int WC, int SW>
+template <int PR, int M, int WC, int SW, int SOLVER>
 __device__ __forceinline__ void nlem_dispatch(int wave, const NlemLaunch &L, float *tile, float *xn,
                                               float *xs, float *cvec, unsigned int *item_s) {
     if constexpr (SW + 1 == WC) {
-        nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, cvec, item_s);
+        nlem_wave<PR, M, WC, SW, SOLVER>(L, tile, xn, xs, cvec, item_s);
     } else {
         if (wave == SW)
-            nlem_wave<PR, M, WC, SW>(L, tile, xn, xs, cvec, item_s);
+            nlem_wave<PR, M, WC, SW, SOLVER>(L, tile, xn, xs, cvec, item_s);
         else
-            nlem_dispatch<PR, M, WC, SW + 1>(wave, L, tile, xn, xs, cvec, item_s);
+            nlem_dispatch<PR, M, WC, SW + 1, SOLVER>(wave, L, tile, xn, xs, cvec, item_s);
     }
 }
 
-template <int PR, int M, int WC>
+template <int PR, int M, int WC, int SOLVER = 0>
 #ifndef EMX_NLEM_MIN_WAVES
 #define EMX_NLEM_MIN_WAVES 2
 #endif
@@ -444,7 +602,7 @@ __global__ __launch_bounds__(64 * WC, EMX_NLEM_MIN_WAVES) void nlem_solve_kernel
     __shared__ float cvec[WC * 128];
     __shared__ unsigned int item_s;
     const int wave = uniform_int(threadIdx.x >> 6);
-    nlem_dispatch<PR, M, WC, 0>(wave, L, tile, xn, xs, cvec, &item_s);
+    nlem_dispatch<PR, M, WC, 0, SOLVER>(wave, L, tile, xn, xs, cvec, &item_s);
 }
 
 }  // namespace emx

@@ -1,20 +1,38 @@
-// Compiled NLEM shapes for patch radius 1 (d = 9).
+// Compiled NLEM shapes for patch radius 1 (d = 9): EM-ADMM for every
+// listed coordinate-wave count, IRLS for the default one.
 #include "nlem_kernel.hpp"
 #include "nlem_table.hpp"
 
 namespace emx {
 
-NlemKernelInfo nlem_kernels_pr1(int m, int wc) {
-    switch (m * 8 + wc) {
-        case 9: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 1, 1>), 64};
-        case 17: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 2, 1>), 64};
-        case 25: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 3, 1>), 64};
-        case 33: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 4, 1>), 64};
-        case 41: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 5, 1>), 64};
-        case 49: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 6, 1>), 64};
-        case 57: return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<1, 7, 1>), 64};
-        default: return NlemKernelInfo{nullptr, 0};
+template <int PR, int M, int WC, int SOLVER>
+static NlemKernelInfo info() {
+    return NlemKernelInfo{reinterpret_cast<const void *>(&nlem_solve_kernel<PR, M, WC, SOLVER>), 64 * WC};
+}
+
+NlemKernelInfo nlem_kernels_pr1(int m, int wc, int solver) {
+    if (solver == 0) {
+        switch (m * 8 + wc) {
+            case 9: return info<1, 1, 1, 0>();
+            case 17: return info<1, 2, 1, 0>();
+            case 25: return info<1, 3, 1, 0>();
+            case 33: return info<1, 4, 1, 0>();
+            case 41: return info<1, 5, 1, 0>();
+            case 49: return info<1, 6, 1, 0>();
+            case 57: return info<1, 7, 1, 0>();
+        }
+    } else if (solver == 1) {
+        switch (m * 8 + wc) {
+            case 9: return info<1, 1, 1, 1>();
+            case 17: return info<1, 2, 1, 1>();
+            case 25: return info<1, 3, 1, 1>();
+            case 33: return info<1, 4, 1, 1>();
+            case 41: return info<1, 5, 1, 1>();
+            case 49: return info<1, 6, 1, 1>();
+            case 57: return info<1, 7, 1, 1>();
+        }
     }
+    return NlemKernelInfo{nullptr, 0};
 }
 
 }  // namespace emx

@@ -8,11 +8,12 @@ struct NlemKernelInfo {
     int threads;
 };
 
-// m = points per lane (1..7), wc = waves per pixel over the patch coordinates
-NlemKernelInfo nlem_kernels_pr0(int m, int wc);
-NlemKernelInfo nlem_kernels_pr1(int m, int wc);
-NlemKernelInfo nlem_kernels_pr2(int m, int wc);
-NlemKernelInfo nlem_kernels_pr3(int m, int wc);
+// m = points per lane (1..7), wc = waves per pixel over the patch coordinates,
+// solver 0 = EM-ADMM (every compiled wc), 1 = IRLS (the default wc only)
+NlemKernelInfo nlem_kernels_pr0(int m, int wc, int solver);
+NlemKernelInfo nlem_kernels_pr1(int m, int wc, int solver);
+NlemKernelInfo nlem_kernels_pr2(int m, int wc, int solver);
+NlemKernelInfo nlem_kernels_pr3(int m, int wc, int solver);
 
 // Default coordinate-wave count per (patch radius, points per lane), from
 // timing the compiled candidates on MI355X (256x256 image, d = 49, n <= 441:
@@ -23,12 +24,12 @@ inline int nlem_default_wc(int pr, int m) {
     return 2;
 }
 
-inline NlemKernelInfo nlem_kernel(int pr, int m, int wc) {
+inline NlemKernelInfo nlem_kernel(int pr, int m, int wc, int solver) {
     switch (pr) {
-        case 0: return nlem_kernels_pr0(m, wc);
-        case 1: return nlem_kernels_pr1(m, wc);
-        case 2: return nlem_kernels_pr2(m, wc);
-        case 3: return nlem_kernels_pr3(m, wc);
+        case 0: return nlem_kernels_pr0(m, wc, solver);
+        case 1: return nlem_kernels_pr1(m, wc, solver);
+        case 2: return nlem_kernels_pr2(m, wc, solver);
+        case 3: return nlem_kernels_pr3(m, wc, solver);
     }
     return NlemKernelInfo{nullptr, 0};
 }

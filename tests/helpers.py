@@ -75,3 +75,45 @@ def rel_errors(got, ref, D):
 
 def report(name, emax, erms):
     print(f"[parity] {name}: max_rel={emax:.3e} rms_rel={erms:.3e}", flush=True)
+
+
+def run_nlem_ex(images, *, solver, init, max_iter, tol, mu=1e-3, eps=1e-6, lo=0.0, hi=255.0,
+                fp16=False):
+    """nlem_denoise_ex on the GPU for a list of (img_np, pr, wr, h); returns a
+    list of (out float64 [H*W], stats dict)."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    items = []
+    for img_np, pr, wr, h in images:
+        t = torch.from_numpy(np.ascontiguousarray(img_np, dtype=np.float32)).to(dev)
+        if fp16:
+            t = t.half()
+        items.append(dict(img=t, out=torch.full(t.shape, -7.0, dtype=torch.float32, device=dev),
+                          stats=torch.zeros((t.numel(), 4), dtype=torch.int32, device=dev),
+                          patch_radius=pr, window_radius=wr, h=h))
+    hd = handle()
+    hd.nlem_denoise_ex(items, solver=solver, init=init, lo=lo, hi=hi, rho=mu, eps=eps,
+                       max_iter=max_iter, tol=tol)
+    hd.sync()
+    res = []
+    for it in items:
+        i, f, rp, rd = emx.stats_view(it["stats"])
+        res.append((it["out"].cpu().numpy().reshape(-1).astype(np.float64),
+                    dict(iters=i.cpu().numpy(), flags=f.cpu().numpy(), r_pri=rp.cpu().numpy(),
+                         r_dual=rd.cpu().numpy())))
+    return res
+
+
+def run_nlm(img_np, pr, wr, h, fp16=False):
+    """nlm_denoise on the GPU; returns out float64 [H*W]."""
+    import torch
+    dev = gpu()
+    t = torch.from_numpy(np.ascontiguousarray(img_np, dtype=np.float32)).to(dev)
+    if fp16:
+        t = t.half()
+    out = torch.full(t.shape, -7.0, dtype=torch.float32, device=dev)
+    hd = handle()
+    hd.nlm_denoise(t, out, patch_radius=pr, window_radius=wr, h=h)
+    hd.sync()
+    return out.cpu().numpy().reshape(-1).astype(np.float64)

@@ -31,7 +31,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("em_create", "em_destroy", "em_solve_batch", "em_solve_plain", "nlem_denoise",
-                 "nlem_denoise_multi", "em_sync", "em_status_string", "em_last_error"):
+                 "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_sync",
+                 "em_status_string", "em_last_error"):
         assert must in names
 
 
@@ -46,6 +47,7 @@ def test_struct_sizes_match_the_header():
     import paper_1501_03879_amd as emx
     assert INSTANCE_DTYPE.itemsize == 32                     # em_instance_t
     assert C.sizeof(emx.NlemImage) == 8 * 3 + 4 * 6          # nlem_image_t
+    assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
 
 
 def test_null_handle_is_rejected_without_device_work():
@@ -59,6 +61,11 @@ def test_null_handle_is_rejected_without_device_work():
     lib.em_destroy.argtypes = [vp]
     assert lib.em_solve_batch(None, None, 1, None, None, None, 0, 1, 1, 1, 0, 0, None, None) == -1
     assert lib.nlem_denoise(None, None, None, 0, 8, 8, 1, 1, 1.0, 0, 255, 1e-3, 1, 0, None, None) == -1
+    lib.nlem_denoise_ex.argtypes = [vp, vp, C.c_int32, vp, vp]
+    assert lib.nlem_denoise_ex(None, None, 0, None, None) == -1
+    lib.nlm_denoise.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                C.c_float, vp]
+    assert lib.nlm_denoise(None, None, None, 0, 8, 8, 1, 1, 1.0, None) == -1
     assert lib.em_sync(None, None) == -1
     assert lib.em_destroy(None) == 0
     lib.em_create.argtypes = [C.POINTER(vp), C.c_int]
