@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--plain", type=int, default=0,
                     help="also time the plain one-instance-per-launch path on N pixels")
+    ap.add_argument("--study", choices=["psnr", "evolution", "objective"], default=None,
+                    help="instead of the timing line, run a denoising-quality study on the GPU: "
+                         "the PSNR table (NLM / NLEM-IRLS / NLEM-ADMM, 4 iterations), PSNR per "
+                         "iteration, or the objective per iteration at sampled pixels")
+    ap.add_argument("--realizations", type=int, default=10, help="noise realizations per study cell")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy (3 times): the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -83,6 +88,78 @@ def profiled_traffic():
     return float(m_t.group(1))
 
 
+def _denoise(hd, noisy, method, sigma, iters, init):
+    """One GPU denoising run (patch 7x7, window 21x21, h = 10 sigma, box
+    [0, 255], mu = 1e-3, eps = 1e-6, fixed iteration count)."""
+    import torch
+
+    import paper_1501_03879_amd as emx
+    img = torch.from_numpy(noisy).cuda()
+    out = torch.empty_like(img)
+    if method == "nlm":
+        hd.nlm_denoise(img, out, patch_radius=3, window_radius=10, h=10.0 * sigma)
+    else:
+        item = dict(img=img, out=out, patch_radius=3, window_radius=10, h=10.0 * sigma)
+        hd.nlem_denoise_ex([item], solver=emx.SOLVER_ADMM if method == "admm" else emx.SOLVER_IRLS,
+                           init=init, lo=0.0, hi=255.0, rho=1e-3, eps=1e-6, max_iter=iters, tol=0.0)
+    hd.sync()
+    return out.cpu().numpy()
+
+
+def study_psnr(args):
+    """Table 1 analogue: PSNR (dB, mean over noise realizations) of NLM,
+    NLEM-IRLS and NLEM-ADMM (4 iterations each; starting from the noisy patch
+    for sigma <= 60 and from the NLM patch above, as in Section 3)."""
+    import numpy as np
+
+    import paper_1501_03879_amd as emx
+    import synth
+    hd = emx.handle(0)
+    rows = []
+    for name, clean in synth.study_images().items():
+        for sigma in synth.STUDY_SIGMAS:
+            init = emx.NLEM_INIT_NOISY if sigma <= 60 else emx.NLEM_INIT_NLM
+            acc = {"noisy": [], "nlm": [], "irls": [], "admm": []}
+            for r in range(args.realizations):
+                noisy = synth.study_noise(clean, sigma, r)
+                acc["noisy"].append(synth.psnr(noisy, clean))
+                for m in ("nlm", "irls", "admm"):
+                    acc[m].append(synth.psnr(_denoise(hd, noisy, m, sigma, 4, init), clean))
+            row = {"image": name, "sigma": sigma, "init": "noisy" if init == 0 else "nlm",
+                   **{k: float(np.mean(v)) for k, v in acc.items()},
+                   "admm_std": float(np.std(acc["admm"])), "realizations": args.realizations}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    print(json.dumps({"study": "psnr", "rows": len(rows),
+                      "admm_minus_nlm_mean_db": float(np.mean([r["admm"] - r["nlm"] for r in rows])),
+                      "admm_minus_irls_mean_db": float(np.mean([r["admm"] - r["irls"] for r in rows]))}),
+          flush=True)
+
+
+def study_evolution(args):
+    """PSNR after t = 0..10 iterations of NLEM-ADMM and NLEM-IRLS started from
+    the noisy patch (the PSNR-evolution figure of Section 3), sigma 10 and 40."""
+    import numpy as np
+
+    import paper_1501_03879_amd as emx
+    import synth
+    hd = emx.handle(0)
+    for name in ("smooth-512", "shapes-512"):
+        clean = synth.study_images()[name]
+        for sigma in (10.0, 40.0):
+            curves = {"admm": np.zeros(11), "irls": np.zeros(11)}
+            K = max(1, min(args.realizations, 3))
+            for r in range(K):
+                noisy = synth.study_noise(clean, sigma, r)
+                for m in curves:
+                    for t in range(11):
+                        curves[m][t] += synth.psnr(_denoise(hd, noisy, m, sigma, t, emx.NLEM_INIT_NOISY),
+                                                   clean) / K
+            print(json.dumps({"image": name, "sigma": sigma, "realizations": K,
+                              **{m: [round(float(v), 3) for v in c] for m, c in curves.items()}}),
+                  flush=True)
+
+
 def window_sizes(H, W, R):
     import numpy as np
     y = np.arange(H)
@@ -96,6 +173,12 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.study:
+        if args.gpus != 1:
+            print("studies run on one GPU (--gpus 1)", file=sys.stderr)
+            sys.exit(2)
+        {"psnr": study_psnr, "evolution": study_evolution, "objective": study_objective}[args.study](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: each pixel's solve is independent, so the "

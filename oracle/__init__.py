@@ -55,6 +55,18 @@ def _load():
                                         C.c_double, dp, dp, dp, C.c_int64, C.c_double,
                                         i64p, dp, dp]
         lib.oracle_em_solve.restype = C.c_int
+        lib.oracle_em_solve_ex.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp, dp,
+                                           dp, C.c_int64, C.c_double, C.c_int64, C.c_double,
+                                           C.c_double, i64p, dp, dp, dp]
+        lib.oracle_em_solve_ex.restype = C.c_int
+        lib.oracle_irls_solve_ex.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
+                                             C.c_int64, C.c_double, i64p, dp, dp]
+        lib.oracle_irls_solve_ex.restype = C.c_int
+        lib.oracle_em_batch_ex.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p, C.c_int,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, fp, fp,
+                                           C.c_int64, i32p, C.c_double, C.c_int, C.c_int64,
+                                           C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_int]
+        lib.oracle_em_batch_ex.restype = C.c_int
         lib.oracle_em_batch.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p,
                                         C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
                                         C.c_double, C.c_int, dp, i32p, i32p, dp, dp, C.c_int]
@@ -102,9 +114,17 @@ def prox(v, u, lam: float) -> np.ndarray:
     return out
 
 
-def em_solve(a, w, mu: float, lo: float, hi: float, z0, y0=None, max_iter: int = 100,
-             tol: float = 0.0) -> dict:
-    """One instance of Algorithm 1 in FP64; returns z, y, x, iters, residuals, flags."""
+def _box(lo, hi, d):
+    lv = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, np.float64), (d,)), dtype=np.float64)
+    hv = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, np.float64), (d,)), dtype=np.float64)
+    return lv, hv
+
+
+def em_solve(a, w, mu: float, lo, hi, z0, y0=None, max_iter: int = 100, tol: float = 0.0,
+             adapt_every: int = 0, adapt_ratio: float = 10.0, adapt_factor: float = 2.0) -> dict:
+    """One instance of Algorithm 1 in FP64 over the box [lo, hi] (scalars or
+    per-coordinate arrays), optionally with the adaptive penalty; returns z,
+    y, x, iters, residuals, flags and the final penalty mu."""
     a = np.ascontiguousarray(a, dtype=np.float64)
     if a.ndim == 1:
         a = a.reshape(-1, 1)
@@ -115,20 +135,29 @@ def em_solve(a, w, mu: float, lo: float, hi: float, z0, y0=None, max_iter: int =
     assert z.size == d
     y = np.zeros((n, d)) if y0 is None else np.array(y0, dtype=np.float64).reshape(n, d).copy()
     x = np.zeros((n, d))
+    lv, hv = _box(lo, hi, d)
     it = C.c_int64(0)
     rp = C.c_double(0.0)
     rd = C.c_double(0.0)
-    f = _load().oracle_em_solve(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
-                                float(lo), float(hi), _p(z, C.c_double), _p(y, C.c_double),
-                                _p(x, C.c_double), int(max_iter), float(tol), C.byref(it),
-                                C.byref(rp), C.byref(rd))
-    return dict(z=z, y=y, x=x, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f))
+    mf = C.c_double(0.0)
+    f = _load().oracle_em_solve_ex(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                   _p(lv, C.c_double), _p(hv, C.c_double), _p(z, C.c_double),
+                                   _p(y, C.c_double), _p(x, C.c_double), int(max_iter), float(tol),
+                                   int(adapt_every), float(adapt_ratio), float(adapt_factor),
+                                   C.byref(it), C.byref(rp), C.byref(rd), C.byref(mf))
+    return dict(z=z, y=y, x=x, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f),
+                mu=mf.value)
 
 
 def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW, z0=None,
-             max_iter_each=None, nthreads: int = 0) -> dict:
+             max_iter_each=None, nthreads: int = 0, solver: int = SOLVER_ADMM, eps: float = 1e-6,
+             box_lo=None, box_hi=None, adapt_every: int = 0, adapt_ratio: float = 10.0,
+             adapt_factor: float = 2.0) -> dict:
     """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
-    z_size, lo, hi).  Returns z (float64, concatenated), iters, flags, residuals."""
+    z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty)
+    or SOLVER_IRLS; box_lo / box_hi: optional float32 per-coordinate bounds
+    indexed like z.  Returns z (float64, concatenated), iters, flags,
+    residuals and the final penalties."""
     inst = batch.inst
     B = int(inst.shape[0])
     a = np.ascontiguousarray(batch.a, dtype=np.float32)
@@ -139,18 +168,23 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     n = np.ascontiguousarray(inst["n"], dtype=np.int32)
     d = np.ascontiguousarray(inst["d"], dtype=np.int32)
     z = np.zeros(batch.z_size, dtype=np.float64) if z0 is None else np.array(z0, np.float64).copy()
+    bl = None if box_lo is None else np.ascontiguousarray(box_lo, dtype=np.float32)
+    bh = None if box_hi is None else np.ascontiguousarray(box_hi, dtype=np.float32)
     iters = np.zeros(B, np.int32)
     flags = np.zeros(B, np.int32)
     rp = np.zeros(B)
     rd = np.zeros(B)
+    mf = np.zeros(B)
     mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
-    _load().oracle_em_batch(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
-                            _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
-                            _p(d, C.c_int32), float(mu), float(batch.lo), float(batch.hi),
-                            int(max_iter), _p(mie, C.c_int32), float(tol), int(init),
-                            _p(z, C.c_double), _p(iters, C.c_int32), _p(flags, C.c_int32),
-                            _p(rp, C.c_double), _p(rd, C.c_double), int(nthreads))
-    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd)
+    _load().oracle_em_batch_ex(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
+                               _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
+                               _p(d, C.c_int32), int(solver), float(mu), float(eps), float(batch.lo),
+                               float(batch.hi), _p(bl, C.c_float), _p(bh, C.c_float), int(max_iter),
+                               _p(mie, C.c_int32), float(tol), int(init), int(adapt_every),
+                               float(adapt_ratio), float(adapt_factor), _p(z, C.c_double),
+                               _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
+                               _p(rd, C.c_double), _p(mf, C.c_double), int(nthreads))
+    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf)
 
 
 def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: float,
@@ -201,7 +235,8 @@ def nlm(img, patch_radius: int, window_radius: int, h: float, pix=None, want_z: 
 def irls_solve(a, w, eps: float, lo: float, hi: float, z0, max_iter: int = 100,
                tol: float = 0.0) -> dict:
     """IRLS (majorise-minimise) on the surrogate sum_k w_k (||z - a_k||^2 + eps)^(1/2)
-    over the box, in FP64; returns z, iters, r_dual, flags."""
+    over the box [lo, hi] (scalars or per-coordinate arrays), in FP64; returns
+    z, iters, r_dual, flags."""
     a = np.ascontiguousarray(a, dtype=np.float64)
     if a.ndim == 1:
         a = a.reshape(-1, 1)
@@ -209,12 +244,13 @@ def irls_solve(a, w, eps: float, lo: float, hi: float, z0, max_iter: int = 100,
     w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
     z = np.array(z0, dtype=np.float64).reshape(-1).copy()
     assert w.size == n and z.size == d
+    lv, hv = _box(lo, hi, d)
     it = C.c_int64(0)
     rp = C.c_double(0.0)
     rd = C.c_double(0.0)
-    f = _load().oracle_irls_solve(n, d, _p(a, C.c_double), _p(w, C.c_double), float(eps),
-                                  float(lo), float(hi), _p(z, C.c_double), int(max_iter),
-                                  float(tol), C.byref(it), C.byref(rp), C.byref(rd))
+    f = _load().oracle_irls_solve_ex(n, d, _p(a, C.c_double), _p(w, C.c_double), float(eps),
+                                     _p(lv, C.c_double), _p(hv, C.c_double), _p(z, C.c_double),
+                                     int(max_iter), float(tol), C.byref(it), C.byref(rp), C.byref(rd))
     return dict(z=z, iters=int(it.value), r_dual=rd.value, flags=int(f))
 
 

@@ -64,18 +64,33 @@ static double clamp_box(double x, double lo, double hi)
 }
 
 /*
- * Scale D of the relative stopping tolerance: the box width hi - lo when it
- * is finite and positive, otherwise max(1, max_k ||a_k||_inf).
+ * Scale D of the relative stopping tolerance: the largest box width
+ * max_j (hi_j - lo_j) when it is finite and positive (hi - lo for a scalar
+ * box), otherwise max(1, max_k ||a_k||_inf).
  */
-static double tol_scale(int64_t n, int64_t d, const double *a, double lo, double hi)
+static double tol_scale_box(int64_t n, int64_t d, const double *a, const double *lo,
+                            const double *hi)
 {
-    if (isfinite(lo) && isfinite(hi) && hi > lo) return hi - lo;
+    double wmax = 0.0;
+    for (int64_t j = 0; j < d; ++j) {
+        double wj = hi[j] - lo[j];
+        if (!(wj <= wmax)) wmax = wj;   /* also takes inf */
+    }
+    if (isfinite(wmax) && wmax > 0.0) return wmax;
     double m = 1.0;
     for (int64_t i = 0; i < n * d; ++i) {
         double t = fabs(a[i]);
         if (t > m) m = t;
     }
     return m;
+}
+
+/* A box given per coordinate is valid when lo_j <= hi_j and neither is NaN. */
+static int box_ok(int64_t d, const double *lo, const double *hi)
+{
+    for (int64_t j = 0; j < d; ++j)
+        if (!(lo[j] <= hi[j])) return 0;
+    return 1;
 }
 
 /*
@@ -85,30 +100,45 @@ static double tol_scale(int64_t n, int64_t d, const double *a, double lo, double
  *          for k: x_k = Psi_{w_k/mu}(z - y_k/mu, a_k);  r += x_k + y_k/mu
  *          z = P_C(r / N)                       (N = n, the points present)
  *          for k: y_k += mu (x_k - z)
+ * C is the box prod_j [lo_j, hi_j] (Section 3 uses one interval for every
+ * coordinate; per-coordinate bounds are the general box).
  * The loop stops after max_iter iterations, or earlier when tol > 0 and both
  *   r_pri  = sqrt(sum_k ||x_k - z||^2 / (n d))
  *   r_dual = sqrt(||z - z_prev||^2 / d)
  * are <= tol * D (the paper leaves the criterion open; this is the primal and
  * dual residual pair of the ADMM literature, checked every iteration).
  *
+ * Adaptive penalty (adapt_every > 0; the conclusion names it as future work,
+ * the rule is residual balancing as in Boyd et al. 2011, Section 3.4.1):
+ * after an iteration t that did not stop and with t % adapt_every == 0, with
+ *   ||r|| = (sum_k ||x_k - z||^2)^(1/2),  ||s|| = mu (n ||z - z_prev||^2)^(1/2)
+ * (the stacked primal and dual residuals of the consensus form):
+ *   ||r|| > ratio ||s||  ->  mu = mu * factor,
+ *   ||s|| > ratio ||r||  ->  mu = mu / factor,
+ * keeping the unscaled y_k (so nothing else changes).  *mu_out receives the
+ * final penalty (nullable).
+ *
  * a: n*d points (point-major), w: n weights, z: d values in/out (the initial
  * z is used unprojected), y: n*d multipliers in/out (NULL means start from
  * zero and discard), x_out: n*d last local variables (NULL to skip).
  * Returns the flag word; *iters, *r_pri, *r_dual receive the iteration count
  * and the residuals of the last iteration run (0 when none ran).
- * n = 0: z is left as given (EMPTY).  A negative or non-finite weight, or a
- * non-finite point or initial z: z is set to NaN (BAD_INPUT).
+ * n = 0: z is left as given (EMPTY).  A negative or non-finite weight, a
+ * non-finite point or initial z, or an invalid box: z is set to NaN
+ * (BAD_INPUT).
  */
-int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
-                    double mu, double lo, double hi, double *z, double *y,
-                    double *x_out, int64_t max_iter, double tol,
-                    int64_t *iters, double *r_pri, double *r_dual)
+int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
+                       double mu, const double *lo, const double *hi, double *z, double *y,
+                       double *x_out, int64_t max_iter, double tol, int64_t adapt_every,
+                       double adapt_ratio, double adapt_factor, int64_t *iters, double *r_pri,
+                       double *r_dual, double *mu_out)
 {
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
+    if (mu_out) *mu_out = mu;
     if (n == 0) return OR_EMPTY;
-    int bad = 0;
+    int bad = !box_ok(d, lo, hi);
     for (int64_t k = 0; k < n; ++k)
         if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
     for (int64_t i = 0; i < n * d; ++i)
@@ -119,7 +149,7 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale(n, d, a, lo, hi);
+    double D = tol_scale_box(n, d, a, lo, hi);
 
     double *ybuf = y ? y : (double *)calloc((size_t)(n * d), sizeof(double));
     double *x = (double *)malloc((size_t)(n * d) * sizeof(double));
@@ -141,7 +171,7 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
         }
         for (int64_t j = 0; j < d; ++j) {
             zprev[j] = z[j];
-            z[j] = clamp_box(r[j] / (double)n, lo, hi);
+            z[j] = clamp_box(r[j] / (double)n, lo[j], hi[j]);
         }
         for (int64_t k = 0; k < n; ++k)
             for (int64_t j = 0; j < d; ++j)
@@ -164,7 +194,16 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
             flags = OR_CONVERGED;
             break;
         }
+        if (adapt_every > 0 && t % adapt_every == 0) {
+            double rnorm = sqrt(sp);
+            double snorm = mu * sqrt((double)n * sd);
+            if (rnorm > adapt_ratio * snorm)
+                mu *= adapt_factor;
+            else if (snorm > adapt_ratio * rnorm)
+                mu /= adapt_factor;
+        }
     }
+    if (mu_out) *mu_out = mu;
     if (x_out) memcpy(x_out, x, (size_t)(n * d) * sizeof(double));
     if (!y) free(ybuf);
     free(x);
@@ -172,6 +211,25 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
     free(r);
     free(zprev);
     return flags;
+}
+
+/* Algorithm 1 with the scalar box [lo, hi]^d and a fixed penalty. */
+int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
+                    double mu, double lo, double hi, double *z, double *y,
+                    double *x_out, int64_t max_iter, double tol,
+                    int64_t *iters, double *r_pri, double *r_dual)
+{
+    double *lv = (double *)malloc((size_t)(d + 1) * sizeof(double));
+    double *hv = (double *)malloc((size_t)(d + 1) * sizeof(double));
+    for (int64_t j = 0; j < d; ++j) {
+        lv[j] = lo;
+        hv[j] = hi;
+    }
+    int f = oracle_em_solve_ex(n, d, a, w, mu, lv, hv, z, y, x_out, max_iter, tol, 0, 10.0, 2.0,
+                               iters, r_pri, r_dual, NULL);
+    free(lv);
+    free(hv);
+    return f;
 }
 
 /*
@@ -212,7 +270,7 @@ double oracle_surrogate_objective(int64_t n, int64_t d, const double *a, const d
 }
 
 /*
- * IRLS for the surrogate (EM_surrogate) over the box C = [lo, hi]^d.  The
+ * IRLS for the surrogate (EM_surrogate) over the box C = prod_j [lo_j, hi_j].  The
  * paper names the method but does not print its steps; they follow from
  * majorise-minimise: sqrt is concave, so at the current iterate z^t
  *   (q + eps)^(1/2) <= (q_t + eps)^(1/2) + (q - q_t) / (2 (q_t + eps)^(1/2)),
@@ -229,15 +287,15 @@ double oracle_surrogate_objective(int64_t n, int64_t d, const double *a, const d
  * the solve reports CONVERGED after one iteration.
  * Flags, init and the n = 0 / bad-input rules are those of oracle_em_solve.
  */
-int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, double eps,
-                      double lo, double hi, double *z, int64_t max_iter, double tol,
-                      int64_t *iters, double *r_pri, double *r_dual)
+int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                         const double *lo, const double *hi, double *z, int64_t max_iter,
+                         double tol, int64_t *iters, double *r_pri, double *r_dual)
 {
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
     if (n == 0) return OR_EMPTY;
-    int bad = !(eps > 0.0);
+    int bad = !(eps > 0.0) || !box_ok(d, lo, hi);
     for (int64_t k = 0; k < n; ++k)
         if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
     for (int64_t i = 0; i < n * d; ++i)
@@ -248,7 +306,7 @@ int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, do
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale(n, d, a, lo, hi);
+    double D = tol_scale_box(n, d, a, lo, hi);
     double *num = (double *)malloc((size_t)d * sizeof(double));
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
@@ -267,7 +325,7 @@ int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, do
         double sd = 0.0;
         if (den > 0.0) {
             for (int64_t j = 0; j < d; ++j) {
-                double zn = clamp_box(num[j] / den, lo, hi);
+                double zn = clamp_box(num[j] / den, lo[j], hi[j]);
                 double e = zn - z[j];
                 sd += e * e;
                 z[j] = zn;
@@ -282,6 +340,23 @@ int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, do
     }
     free(num);
     return flags;
+}
+
+/* IRLS over the scalar box [lo, hi]^d. */
+int oracle_irls_solve(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                      double lo, double hi, double *z, int64_t max_iter, double tol,
+                      int64_t *iters, double *r_pri, double *r_dual)
+{
+    double *lv = (double *)malloc((size_t)(d + 1) * sizeof(double));
+    double *hv = (double *)malloc((size_t)(d + 1) * sizeof(double));
+    for (int64_t j = 0; j < d; ++j) {
+        lv[j] = lo;
+        hv[j] = hi;
+    }
+    int f = oracle_irls_solve_ex(n, d, a, w, eps, lv, hv, z, max_iter, tol, iters, r_pri, r_dual);
+    free(lv);
+    free(hv);
+    return f;
 }
 
 static void set_threads(int nthreads)
@@ -309,13 +384,18 @@ int oracle_max_threads(void)
  * result at z + z_off[b].  init = GIVEN uses z as the initial value; init =
  * MAXW starts from the point of largest weight (lowest index on ties).
  * max_iter_each (nullable) overrides max_iter per instance.
+ * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
+ * on the surrogate with eps.  box_lo / box_hi (nullable, float32, indexed like
+ * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
+ * mu_out (nullable): the final penalty per instance.
  */
-int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_off,
-                    const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
-                    const int32_t *d_arr, double mu, double lo, double hi,
-                    int64_t max_iter, const int32_t *max_iter_each, double tol, int init,
-                    double *z, int32_t *iters, int32_t *flags, double *r_pri,
-                    double *r_dual, int nthreads)
+int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t *a_off,
+                       const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
+                       const int32_t *d_arr, int solver, double mu, double eps, double lo, double hi,
+                       const float *box_lo, const float *box_hi, int64_t max_iter,
+                       const int32_t *max_iter_each, double tol, int init, int64_t adapt_every,
+                       double adapt_ratio, double adapt_factor, double *z, int32_t *iters,
+                       int32_t *flags, double *r_pri, double *r_dual, double *mu_out, int nthreads)
 {
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -323,8 +403,14 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
         int64_t n = n_arr[b], d = d_arr[b];
         double *ab = (double *)malloc((size_t)(n * d + 1) * sizeof(double));
         double *wb = (double *)malloc((size_t)(n + 1) * sizeof(double));
+        double *lv = (double *)malloc((size_t)(d + 1) * sizeof(double));
+        double *hv = (double *)malloc((size_t)(d + 1) * sizeof(double));
         for (int64_t i = 0; i < n * d; ++i) ab[i] = (double)a[a_off[b] + i];
         for (int64_t k = 0; k < n; ++k) wb[k] = (double)w[w_off[b] + k];
+        for (int64_t j = 0; j < d; ++j) {
+            lv[j] = box_lo ? (double)box_lo[z_off[b] + j] : lo;
+            hv[j] = box_hi ? (double)box_hi[z_off[b] + j] : hi;
+        }
         double *zb = z + z_off[b];
         if (init == OR_INIT_MAXW && n > 0) {
             int64_t best = 0;
@@ -333,17 +419,36 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
             for (int64_t j = 0; j < d; ++j) zb[j] = ab[best * d + j];
         }
         int64_t it = 0;
-        double rp = 0.0, rd = 0.0;
+        double rp = 0.0, rd = 0.0, mf = mu;
         int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
-        int f = oracle_em_solve(n, d, ab, wb, mu, lo, hi, zb, NULL, NULL, mi, tol, &it, &rp, &rd);
+        int f = (solver == 1)
+                    ? oracle_irls_solve_ex(n, d, ab, wb, eps, lv, hv, zb, mi, tol, &it, &rp, &rd)
+                    : oracle_em_solve_ex(n, d, ab, wb, mu, lv, hv, zb, NULL, NULL, mi, tol, adapt_every,
+                                         adapt_ratio, adapt_factor, &it, &rp, &rd, &mf);
         if (iters) iters[b] = (int32_t)it;
         if (flags) flags[b] = f;
         if (r_pri) r_pri[b] = rp;
         if (r_dual) r_dual[b] = rd;
+        if (mu_out) mu_out[b] = mf;
         free(ab);
         free(wb);
+        free(lv);
+        free(hv);
     }
     return 0;
+}
+
+/* The batch with EM-ADMM, a fixed penalty and the scalar box. */
+int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_off,
+                    const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
+                    const int32_t *d_arr, double mu, double lo, double hi,
+                    int64_t max_iter, const int32_t *max_iter_each, double tol, int init,
+                    double *z, int32_t *iters, int32_t *flags, double *r_pri,
+                    double *r_dual, int nthreads)
+{
+    return oracle_em_batch_ex(B, a, w, a_off, w_off, z_off, n_arr, d_arr, 0, mu, 1.0, lo, hi, NULL,
+                              NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z, iters, flags,
+                              r_pri, r_dual, NULL, nthreads);
 }
 
 /* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */

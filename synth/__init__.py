@@ -23,4 +23,7 @@ from .configs import (  # noqa: F401
     nlem_512_mixed,
     nlem_multi_image,
     pointset_workload,
+    study_images,
+    study_noise,
+    STUDY_SIGMAS,
 )

@@ -119,3 +119,29 @@ def pointset_workload(B: int = 1 << 20, seed: int = 505):
     """Uneven point sets: n ~ U{8..512}, d ~ U{2,3,16,49,64}, 20% Student-t
     (nu 1.5, scale 50) outliers, weights Exp(1), box [-3, 3]^d."""
     return make_pointset_batch(seed, B)
+
+
+# ---- denoising-quality study (Table 1 and the PSNR-vs-iteration figure of
+# Section 3, on synthetic stand-ins for the paper's four test images)
+
+STUDY_SIGMAS = (10.0, 20.0, 40.0, 60.0, 80.0)
+
+
+def study_images(seed: int = 606):
+    """Four clean grey images standing in for the paper's test images (two of
+    256 x 256 and two of 512 x 512, as House/Peppers and Lena/Barbara):
+    name -> float64 array in [0, 255]."""
+    rngs = _rngs(seed, 4)
+    return {
+        "shapes-256": gradient_shapes_image(rngs[0], 256, 256),
+        "smooth-256": piecewise_smooth_image(rngs[1], 256, 256),
+        "shapes-512": gradient_shapes_image(rngs[2], 512, 512),
+        "smooth-512": piecewise_smooth_image(rngs[3], 512, 512),
+    }
+
+
+def study_noise(clean, sigma: float, realization: int, seed: int = 707) -> np.ndarray:
+    """One noise realization of g = f + sigma xi (float32), seeded by
+    (seed, sigma, realization)."""
+    rng = np.random.default_rng([seed, int(round(sigma * 10)), realization])
+    return add_gaussian_noise(rng, clean, sigma).astype(np.float32)

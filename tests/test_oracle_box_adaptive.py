@@ -1,0 +1,174 @@
+"""Pins of the oracle's general box (per-coordinate bounds, the box C of
+(EM) with one interval per coordinate), of the adaptive penalty (residual
+balancing, the first extension the conclusion names) and of the batched
+IRLS entry.
+
+Pins: the KKT / normal-cone certificate of the box-constrained minimiser,
+coordinate-wise translation equivariance (a swapped coordinate index of the
+bounds fails it), the 1-D clamp property, agreement of the adaptive and
+fixed-penalty solvers at the (unique) minimiser, factor = 1 reducing to the
+fixed penalty exactly, and the adaptive rule moving a badly scaled penalty in
+the right direction.
+"""
+
+import numpy as np
+
+import synth
+
+
+def _certificate(a, w, z, lo, hi, tol):
+    """0 in grad F(z) + N_C(z) for the box prod_j [lo_j, hi_j] (points at z
+    contribute subgradients of norm <= their weight)."""
+    dist = np.linalg.norm(a - z[None], axis=1)
+    K0 = dist <= 1e-6
+    W0 = w[K0].sum()
+    g = ((w[~K0] / dist[~K0])[:, None] * (z[None] - a[~K0])).sum(axis=0)
+    q = g.copy()
+    at_lo = z <= lo + 1e-12
+    at_hi = z >= hi - 1e-12
+    q[at_lo] = np.minimum(g[at_lo], 0.0)
+    q[at_hi] = np.maximum(g[at_hi], 0.0)
+    return np.linalg.norm(q) <= W0 + tol * w.sum()
+
+
+def test_per_coordinate_box_certificate(orc):
+    rng = np.random.default_rng(70)
+    bound_hits = 0
+    for _ in range(12):
+        n, d = int(rng.integers(4, 20)), int(rng.integers(2, 6))
+        a = rng.normal(size=(n, d)) * 2
+        w = rng.uniform(0.1, 2.0, size=n)
+        lo = rng.uniform(-1.5, 0.0, size=d)
+        hi = lo + rng.uniform(0.2, 1.5, size=d)
+        r = orc.em_solve(a, w, 0.5, lo, hi, a[0], max_iter=60000, tol=1e-13)
+        z = r["z"]
+        assert np.all(z >= lo) and np.all(z <= hi)
+        assert _certificate(a, w, z, lo, hi, 1e-5)
+        bound_hits += int(np.sum((z <= lo) | (z >= hi)))
+        ri = orc.irls_solve(a, w, 1e-10, lo, hi, a[0], max_iter=200000, tol=1e-15)
+        assert np.all(ri["z"] >= lo) and np.all(ri["z"] <= hi)
+        assert np.linalg.norm(ri["z"] - z) <= 1e-3
+    assert bound_hits > 5, "the boxes should bind some coordinates"
+
+
+def test_per_coordinate_box_translation_equivariance(orc):
+    """Shifting the points and the bounds by a vector t shifts the minimiser
+    by t (with a different shift per coordinate)."""
+    rng = np.random.default_rng(71)
+    n, d = 17, 4
+    a = rng.normal(size=(n, d))
+    w = rng.uniform(0.2, 1.0, size=n)
+    lo = np.array([-0.3, -2.0, 0.1, -0.6])
+    hi = np.array([0.4, -0.5, 1.0, 0.6])
+    t = np.array([5.0, -3.0, 11.0, 0.25])
+    r0 = orc.em_solve(a, w, 0.5, lo, hi, a[0], max_iter=40000, tol=1e-13)
+    r1 = orc.em_solve(a + t, w, 0.5, lo + t, hi + t, a[0] + t, max_iter=40000, tol=1e-13)
+    np.testing.assert_allclose(r1["z"], r0["z"] + t, atol=1e-8)
+
+
+def test_one_dimension_per_coordinate_equals_scalar_clamp(orc):
+    """d = 1: the box minimiser is the weighted median clamped to [lo, hi]."""
+    rng = np.random.default_rng(72)
+    a = rng.normal(size=(9, 1)) * 3
+    w = rng.uniform(0.5, 1.5, size=9)
+    order = np.argsort(a[:, 0])
+    cw = np.cumsum(w[order])
+    med = a[order[np.searchsorted(cw, cw[-1] / 2)], 0]
+    for lo, hi in [(-10.0, 10.0), (med + 0.3, med + 1.0), (med - 2.0, med - 0.1)]:
+        r = orc.em_solve(a, w, 0.3, np.array([lo]), np.array([hi]), [lo], max_iter=20000, tol=1e-13)
+        assert abs(r["z"][0] - np.clip(med, lo, hi)) <= 1e-8
+
+
+def test_invalid_per_coordinate_box_is_bad_input(orc):
+    a = np.ones((3, 2))
+    r = orc.em_solve(a, [1, 1, 1], 1.0, [0.0, 1.0], [1.0, 0.5], [0.5, 0.5])
+    assert r["flags"] == orc.BAD_INPUT and np.all(np.isnan(r["z"]))
+    r = orc.irls_solve(a, [1, 1, 1], 1e-6, [0.0, np.nan], [1.0, 1.0], [0.5, 0.5])
+    assert r["flags"] == orc.BAD_INPUT
+
+
+def test_tolerance_scale_per_coordinate(orc):
+    """D = the widest coordinate interval: with tol chosen between the
+    residuals measured against D and against a narrower width, the solve
+    stops exactly as the rule says."""
+    rng = np.random.default_rng(73)
+    a = rng.normal(size=(20, 3))
+    w = np.ones(20)
+    lo = np.array([-1.0, -1.0, -1.0])
+    hi = np.array([1.0, 3.0, 0.0])     # widths 2, 4, 1: D = 4
+    r = orc.em_solve(a, w, 0.5, lo, hi, a[0], max_iter=500, tol=1e-4)
+    assert r["flags"] == orc.CONVERGED
+    assert r["r_pri"] <= 4e-4 and r["r_dual"] <= 4e-4
+    ref = orc.em_solve(a, w, 0.5, lo, hi, a[0], max_iter=r["iters"] - 1, tol=0.0)
+    assert ref["r_pri"] > 4e-4 or ref["r_dual"] > 4e-4
+
+
+def test_adaptive_penalty_reaches_the_same_minimiser(orc):
+    rng = np.random.default_rng(74)
+    for seed in range(6):
+        n, d = int(rng.integers(5, 60)), int(rng.integers(2, 10))
+        a = rng.normal(size=(n, d)) * 2
+        w = rng.uniform(0.1, 1.0, size=n)
+        fixed = orc.em_solve(a, w, 0.5, -1.0, 1.0, a[0], max_iter=100000, tol=1e-12)
+        for mu0 in (1e-4, 0.5, 1e3):
+            ad = orc.em_solve(a, w, mu0, -1.0, 1.0, a[0], max_iter=100000, tol=1e-12, adapt_every=1)
+            assert ad["flags"] == orc.CONVERGED
+            np.testing.assert_allclose(ad["z"], fixed["z"], atol=1e-7)
+
+
+def test_adaptive_factor_one_is_the_fixed_penalty(orc):
+    rng = np.random.default_rng(75)
+    a = rng.normal(size=(30, 5))
+    w = rng.uniform(0.2, 1.0, size=30)
+    f = orc.em_solve(a, w, 0.05, -1.0, 1.0, a[3], max_iter=37)
+    g = orc.em_solve(a, w, 0.05, -1.0, 1.0, a[3], max_iter=37, adapt_every=1, adapt_factor=1.0)
+    np.testing.assert_array_equal(f["z"], g["z"])
+    np.testing.assert_array_equal(f["y"], g["y"])
+    assert g["mu"] == 0.05
+
+
+def test_adaptive_penalty_moves_towards_balance_and_saves_iterations(orc):
+    """A penalty far too small lets the primal residual dominate: mu grows and
+    the adaptive solver converges where the fixed one stalls.  A penalty far
+    too large lets the dual residual dominate: mu shrinks, and the adaptive
+    solve still ends at the minimiser (the fixed one stops early on tiny steps
+    there, which the residual test cannot tell from convergence)."""
+    rng = np.random.default_rng(76)
+    a = rng.normal(size=(200, 16)) * 2
+    w = rng.uniform(0.2, 1.0, size=200)
+    ref = orc.em_solve(a, w, 0.3, -3.0, 3.0, a[0], max_iter=100000, tol=1e-13)
+    fixed = orc.em_solve(a, w, 1e-5, -3.0, 3.0, a[0], max_iter=3000, tol=1e-5)
+    ad = orc.em_solve(a, w, 1e-5, -3.0, 3.0, a[0], max_iter=3000, tol=1e-5, adapt_every=1)
+    assert fixed["flags"] == orc.MAXITER and ad["flags"] == orc.CONVERGED
+    assert ad["mu"] > 1e-5 and ad["iters"] * 10 < fixed["iters"]
+    ad = orc.em_solve(a, w, 1e4, -3.0, 3.0, a[0], max_iter=3000, tol=1e-9, adapt_every=1)
+    assert ad["flags"] == orc.CONVERGED and ad["mu"] < 1e4
+    assert np.linalg.norm(ad["z"] - ref["z"]) <= 1e-6
+
+
+def test_batch_ex_matches_single_solves(orc):
+    """The batched entry (IRLS, adaptive ADMM, per-coordinate boxes) equals
+    the single-instance solvers on every instance."""
+    b = synth.pointsets.make_pointset_batch(9, 24, n_lo=1, n_hi=40, d_choices=(1, 3, 7))
+    rng = np.random.default_rng(77)
+    blo = rng.uniform(-2.0, -0.5, size=b.z_size).astype(np.float32)
+    bhi = (blo + rng.uniform(0.5, 3.0, size=b.z_size)).astype(np.float32)
+    for kw in (dict(solver=orc.SOLVER_IRLS, eps=1e-4), dict(solver=orc.SOLVER_ADMM, adapt_every=2)):
+        res = orc.em_batch(b, 0.3, 200, 1e-6, init=orc.INIT_MAXW, box_lo=blo, box_hi=bhi, **kw)
+        for i in range(b.B):
+            e = b.inst[i]
+            n, d = int(e["n"]), int(e["d"])
+            if n == 0:
+                continue
+            a = b.a[e["a_off"]:e["a_off"] + n * d].reshape(n, d).astype(np.float64)
+            w = b.w[e["w_off"]:e["w_off"] + n].astype(np.float64)
+            lo = blo[e["z_off"]:e["z_off"] + d].astype(np.float64)
+            hi = bhi[e["z_off"]:e["z_off"] + d].astype(np.float64)
+            z0 = a[int(np.argmax(w))]
+            if kw["solver"] == orc.SOLVER_IRLS:
+                ref = orc.irls_solve(a, w, 1e-4, lo, hi, z0, max_iter=200, tol=1e-6)
+            else:
+                ref = orc.em_solve(a, w, 0.3, lo, hi, z0, max_iter=200, tol=1e-6, adapt_every=2)
+                assert res["mu"][i] == ref["mu"]
+            np.testing.assert_array_equal(res["z"][e["z_off"]:e["z_off"] + d], ref["z"])
+            assert res["iters"][i] == ref["iters"] and res["flags"][i] == ref["flags"]
