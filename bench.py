@@ -160,6 +160,82 @@ def study_evolution(args):
                   flush=True)
 
 
+def _window_instances(noisy, pixels, sigma):
+    """The NLEM instances (window patches, NLM weights) of the given pixels as
+    an explicit point-set batch, built on the host in float64."""
+    import numpy as np
+
+    import synth
+    H, W = noisy.shape
+    P = np.pad(noisy.astype(np.float64), 3, mode="symmetric")
+    pts, ws, z0 = [], [], []
+    for iy, ix in pixels:
+        a = np.array([P[y:y + 7, x:x + 7].reshape(-1) for y in range(max(iy - 10, 0), min(iy + 10, H - 1) + 1)
+                      for x in range(max(ix - 10, 0), min(ix + 10, W - 1) + 1)])
+        c = P[iy:iy + 7, ix:ix + 7].reshape(-1)
+        pts.append(a.astype(np.float32))
+        ws.append(np.exp(-np.sum((a - c) ** 2, axis=1) / (10.0 * sigma) ** 2).astype(np.float32))
+        z0.append(c.astype(np.float32))
+    return synth.pointsets.pack_instances(pts, ws, 0.0, 255.0), np.concatenate(z0)
+
+
+def study_objective(args):
+    """Objective per iteration at sampled pixels (the convergence figure of
+    Section 3): (EM) along the EM-ADMM iterates (mu = 1e-3) and the surrogate
+    along the IRLS iterates (eps = 1e-6), both from the noisy patch, sigma 40,
+    computed by em_solve_batch_ex with max_iter = t; reported relative to the
+    best value found (2000 ADMM iterations) and as the first iteration that
+    is within 1e-3 of it."""
+    import numpy as np
+    import torch
+
+    import paper_1501_03879_amd as emx
+    import synth
+    hd = emx.handle(0)
+    clean = synth.study_images()["shapes-256"]
+    noisy = synth.study_noise(clean, 40.0, 0)
+    rng = np.random.default_rng(8)
+    pixels = [tuple(int(v) for v in rng.integers(10, 246, size=2)) for _ in range(64)]
+    b, z0 = _window_instances(noisy, pixels, 40.0)
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(b.a).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    inst = emx.instances_tensor(b.inst, dev)
+
+    def run(solver, T):
+        z = torch.from_numpy(z0.copy()).to(dev)
+        hd.em_solve_batch_ex(a, w, inst, z, solver=solver, init=emx.INIT_GIVEN, lo=0.0, hi=255.0,
+                             rho=1e-3, eps=1e-6, max_iter=T, tol=0.0)
+        hd.sync()
+        return z.cpu().numpy().astype(np.float64)
+
+    def objective(zs, eps=None):
+        out = []
+        for k in range(b.B):
+            e = b.inst[k]
+            n, d = int(e["n"]), int(e["d"])
+            A = b.a[e["a_off"]:e["a_off"] + n * d].reshape(n, d).astype(np.float64)
+            Wk = b.w[e["w_off"]:e["w_off"] + n].astype(np.float64)
+            q = np.sum((zs[e["z_off"]:e["z_off"] + d][None, :] - A) ** 2, axis=1)
+            out.append(np.sum(Wk * np.sqrt(q if eps is None else q + eps)))
+        return np.array(out)
+
+    best = objective(run(emx.SOLVER_ADMM, 2000))
+    curves = {"admm": [], "irls": []}
+    for t in range(11):
+        curves["admm"].append(objective(run(emx.SOLVER_ADMM, t)) / best - 1.0)
+        curves["irls"].append(objective(run(emx.SOLVER_IRLS, t), 1e-6) / best - 1.0)
+    res = {"study": "objective", "pixels": len(pixels), "sigma": 40.0}
+    for m, c in curves.items():
+        c = np.array(c)                                    # [t, pixel]
+        res[m + "_median_rel_gap"] = [float(f"{v:.3e}") for v in np.median(c, axis=1)]
+        first = [int(np.argmax(c[:, k] <= 1e-3)) if np.any(c[:, k] <= 1e-3) else -1 for k in range(c.shape[1])]
+        res[m + "_iters_to_1e-3_median"] = float(np.median([f for f in first if f >= 0])) if any(
+            f >= 0 for f in first) else None
+        res[m + "_reached_1e-3_within_10"] = float(np.mean([f >= 0 for f in first]))
+    print(json.dumps(res), flush=True)
+
+
 def window_sizes(H, W, R):
     import numpy as np
     y = np.arange(H)
@@ -178,6 +254,8 @@ def main():
         if args.gpus != 1:
             print("studies run on one GPU (--gpus 1)", file=sys.stderr)
             sys.exit(2)
+        import torch
+        torch.zeros(1, device="cuda:0")   # the device is set up by torch before the library
         {"psnr": study_psnr, "evolution": study_evolution, "objective": study_objective}[args.study](args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -136,6 +136,60 @@ em_status_t em_solve_batch(em_handle_t handle, void *stream, int64_t B,
                            float lo, float hi, float rho, int32_t max_iter, float tol,
                            int32_t init, float *z, em_stats_t *stats);
 
+/* Solver of em_solve_batch_ex. */
+typedef enum {
+    EM_SOLVER_ADMM = 0,          /* Algorithm 1, fixed penalty rho (as em_solve_batch) */
+    EM_SOLVER_IRLS = 1,          /* IRLS on the smooth surrogate (EM_surrogate), parameter eps */
+    EM_SOLVER_ADMM_ADAPTIVE = 2  /* Algorithm 1 with the penalty adapted by residual balancing */
+} em_solver_t;
+
+/* Options of em_solve_batch_ex (host memory; the box arrays are device memory). */
+typedef struct {
+    int32_t solver;        /* em_solver_t */
+    int32_t init;          /* em_init_t */
+    float lo, hi;          /* one interval for every coordinate (when box_lo is NULL) */
+    const float *box_lo;   /* NULL, or per-coordinate lower bounds, device, indexed like z */
+    const float *box_hi;   /* NULL, or per-coordinate upper bounds (both NULL or both set) */
+    float rho;             /* ADMM penalty mu (the starting penalty for ADAPTIVE) */
+    float eps;             /* IRLS surrogate parameter */
+    int32_t max_iter;
+    float tol;
+    int32_t adapt_every;   /* ADAPTIVE: balance after every adapt_every-th iteration (>= 1) */
+    float adapt_ratio;     /* ADAPTIVE: imbalance ratio that triggers a change (> 1, e.g. 10) */
+    float adapt_factor;    /* ADAPTIVE: factor applied to rho (> 1, e.g. 2) */
+} em_options_t;
+
+/*
+ * em_solve_batch_ex - em_solve_batch with a choice of solver and a general box.
+ *   Box: [lo, hi] for every coordinate, or per coordinate: instance b,
+ *     coordinate j uses [box_lo[z_off + j], box_hi[z_off + j]] (same layout
+ *     as z).  An instance whose bounds have lo_j > hi_j or a NaN gets
+ *     flags = EM_BAD_INPUT and z = NaN.  The tolerance scale D is the widest
+ *     interval max_j (hi_j - lo_j) when finite and > 0, else
+ *     max(1, max_k ||a_k||_inf).
+ *   EM_SOLVER_ADMM: Algorithm 1 exactly as em_solve_batch.
+ *   EM_SOLVER_ADMM_ADAPTIVE: after every adapt_every-th iteration t that did
+ *     not stop, with ||r|| = (sum_k ||x_k - z||^2)^(1/2) and
+ *     ||s|| = rho (n ||z^t - z^{t-1}||^2)^(1/2) (residual balancing, the
+ *     extension the paper's conclusion names; Boyd et al. 2011, 3.4.1):
+ *     ||r|| > adapt_ratio ||s|| multiplies rho by adapt_factor,
+ *     ||s|| > adapt_ratio ||r|| divides it; the multipliers y_k are kept.
+ *     Both residuals are evaluated on those iterations.
+ *   EM_SOLVER_IRLS: omega_k = w_k / (||z - a_k||^2 + eps)^(1/2),
+ *     z' = P_C(sum_k omega_k a_k / sum_k omega_k) (majorise-minimise steps of
+ *     the surrogate; the box projection is exact for its isotropic
+ *     quadratic majoriser); stopped on r_dual alone (stats r_pri = 0); all
+ *     weights zero leaves z unchanged and reports CONVERGED.
+ * Other arguments, limits and per-instance rules as for em_solve_batch.
+ * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
+ * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1
+ * for ADAPTIVE, one of box_lo / box_hi NULL, and em_solve_batch's errors);
+ * HIP.
+ */
+em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
+                              const float *a, const float *w, const em_instance_t *inst,
+                              const em_options_t *opt, float *z, em_stats_t *stats);
+
 /*
  * em_solve_plain - the same computation as em_solve_batch with one kernel
  * launch per instance and the iterates kept in device memory: the simple

@@ -1,0 +1,285 @@
+// Host side of the batched solvers: the device classification pre-pass, one
+// persistent launch per shape class, and the plain one-launch-per-instance
+// baseline (literal Algorithm 1 with the iterates in device memory).
+#include <float.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "batch_kernel.hpp"
+
+namespace emx {
+
+int blocks_per_cu(em_context *ctx, const void *fn, int threads);
+int ctx_num_cus(em_context *ctx);
+em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg);
+em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what);
+unsigned int *ctx_counters(em_context *ctx, int n);
+em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, int n);
+void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st);
+void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
+
+// Classify: counts per class; empty / malformed instances finished here.
+__global__ void batch_classify_count(const em_instance_t *inst, int64_t B, float *z, em_stats_t *stats,
+                                     unsigned int *counts) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const em_instance_t e = inst[b];
+    if (e.n == 0 && e.d >= 1 && e.d <= EM_MAX_D) {
+        if (stats) stats[b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
+        return;
+    }
+    if (e.n < 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
+        if (e.d >= 1 && e.d <= EM_MAX_D)
+            for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
+        if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
+        return;
+    }
+    atomicAdd(&counts[class_of(e.n, e.d)], 1u);
+}
+
+__global__ void batch_classify_scan(const unsigned int *counts, unsigned int *offsets) {
+    if (threadIdx.x == 0) {
+        unsigned int s = 0;
+        for (int c = 0; c < kNumClasses; ++c) {
+            offsets[c] = s;
+            s += counts[c];
+        }
+        offsets[kNumClasses] = s;
+    }
+}
+
+__global__ void batch_classify_scatter(const em_instance_t *inst, int64_t B, const unsigned int *offsets,
+                                       unsigned int *fill, int32_t *list) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const em_instance_t e = inst[b];
+    if (e.n <= 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) return;
+    const int c = class_of(e.n, e.d);
+    const unsigned int k = atomicAdd(&fill[c], 1u);
+    list[offsets[c] + k] = (int32_t)b;
+}
+
+em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
+                        const em_instance_t *inst, const em_options_t &o, float *z, em_stats_t *stats) {
+    // workspace: list[B] int32
+    em_status_t st;
+    int32_t *list = static_cast<int32_t *>(ctx_workspace(ctx, (size_t)B * sizeof(int32_t), &st));
+    if (!list) return st;
+    // counters: [0, K) class counts, [K, 2K+1) offsets, [2K+1, 3K+1) fill, [3K+1, 4K+1) queue heads
+    unsigned int *cnt = ctx_counters(ctx, 4 * kNumClasses + 1);
+    if (!cnt) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
+    unsigned int *counts = cnt, *offsets = cnt + kNumClasses, *fill = cnt + 2 * kNumClasses + 1,
+                 *heads = cnt + 3 * kNumClasses + 1;
+    st = ctx_reset_counters(ctx, s, cnt, 4 * kNumClasses + 1);
+    if (st != EM_OK) return st;
+    const unsigned nb = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts);
+    hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
+    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
+    const ClassKernel *tab = (o.solver == EM_SOLVER_IRLS)            ? batch_class_table_irls()
+                             : (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? batch_class_table_adapt()
+                                                                     : batch_class_table_admm();
+    const bool vbox = o.box_lo != nullptr;
+    for (int c = 0; c < kNumClasses; ++c) {
+        ClassLaunch L;
+        memset(&L, 0, sizeof(L));
+        L.a = a;
+        L.w = w;
+        L.inst = inst;
+        L.list = list;
+        L.offsets = offsets;
+        L.counter = heads + c;
+        L.z = z;
+        L.stats = stats;
+        L.box_lo = o.box_lo;
+        L.box_hi = o.box_hi;
+        L.lo = vbox ? 0.0f : o.lo;   // padded coordinates clamp to 0 when the box is per coordinate
+        L.hi = vbox ? 0.0f : o.hi;
+        L.mu = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
+        L.tol = o.tol;
+        L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
+        L.eps = o.eps;
+        L.adapt_every = (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? o.adapt_every : 0;
+        L.adapt_ratio2 = o.adapt_ratio * o.adapt_ratio;
+        L.adapt_factor = o.adapt_factor;
+        L.max_iter = o.max_iter;
+        L.init = o.init;
+        L.cls = c;
+        const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, tab[c].fn, tab[c].threads);
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
+        void *args[] = {&L};
+        e = hipLaunchKernel(tab[c].fn, dim3(grid), dim3(tab[c].threads), args, 0, s);
+        if (e != hipSuccess) return ctx_hip_error(ctx, e, "batch class launch");
+    }
+    return EM_OK;
+}
+
+// ------------------------------------------------------------------ plain
+
+// One instance per launch, literal Algorithm 1 with the iterates in device
+// memory: thread per point for the prox, thread per coordinate for the
+// z-update, thread per point for the multiplier update, residuals every
+// iteration.  The simple baseline for the batched solver.
+struct PlainArgs {
+    const float *a;
+    const float *w;
+    const em_instance_t *inst;
+    float *z;
+    em_stats_t *stats;
+    float *u;  // n*d scaled multipliers y/mu
+    float *x;  // n*d local variables
+    float lo, hi, mu, tol;
+    int32_t max_iter, init;
+    int64_t b;
+};
+
+__global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
+    __shared__ float zs[EM_MAX_D], zprev[EM_MAX_D];
+    __shared__ float red[256];
+    __shared__ int flag;
+    __shared__ float amax_s;
+    const int tid = threadIdx.x;
+    const em_instance_t e = P.inst[P.b];
+    const int n = e.n, d = e.d;
+    float *Z = P.z + e.z_off;
+    if (n == 0 && d >= 1 && d <= EM_MAX_D) {
+        if (tid == 0 && P.stats) P.stats[P.b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
+        return;
+    }
+    const float *A = P.a + e.a_off;
+    const float *Wt = P.w + e.w_off;
+    if (tid == 0) {
+        flag = 0;
+        amax_s = 0.0f;
+    }
+    __syncthreads();
+    if (n < 0 || n > EM_MAX_N || d < 1 || d > EM_MAX_D) {
+        if (tid == 0) flag = 1;
+    } else {
+        for (int i = tid; i < n * d; i += 256) {
+            if (!(fabsf(A[i]) <= FLT_MAX)) flag = 1;
+            atomicMax(reinterpret_cast<int *>(&amax_s), __float_as_int(fabsf(A[i])));
+        }
+        for (int k = tid; k < n; k += 256)
+            if (!(Wt[k] >= 0.0f && Wt[k] <= FLT_MAX)) flag = 1;
+    }
+    __syncthreads();
+    if (flag == 0 && tid == 0) {
+        int best = 0;
+        if (P.init == EM_INIT_MAXW)
+            for (int k = 1; k < n; ++k)
+                if (Wt[k] > Wt[best]) best = k;
+        for (int j = 0; j < d; ++j) {
+            zs[j] = (P.init == EM_INIT_MAXW) ? A[best * d + j] : Z[j];
+            if (!(fabsf(zs[j]) <= FLT_MAX)) flag = 1;
+        }
+    }
+    __syncthreads();
+    if (flag) {
+        if (tid == 0) {
+            if (d >= 1 && d <= EM_MAX_D)
+                for (int j = 0; j < d; ++j) Z[j] = __builtin_nanf("");
+            if (P.stats) P.stats[P.b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
+        }
+        return;
+    }
+    const float Dscale = (__builtin_isfinite(P.lo) && __builtin_isfinite(P.hi) && P.hi > P.lo)
+                             ? (P.hi - P.lo) : fmaxf(1.0f, amax_s);
+    const float tau = P.tol * Dscale;
+    for (int i = tid; i < n * d; i += 256) P.u[i] = 0.0f;
+    __syncthreads();
+    int iters = 0, flags = EM_MAXITER;
+    float rpri = 0.0f, rdual = 0.0f;
+    for (int t = 1; t <= P.max_iter; ++t) {
+        // x_k = prox_{w_k/mu}(z - u_k, a_k)
+        for (int k = tid; k < n; k += 256) {
+            const float lam = Wt[k] / P.mu;
+            float nu2 = 0.0f;
+            for (int j = 0; j < d; ++j) {
+                const float dl = zs[j] - P.u[k * d + j] - A[k * d + j];
+                nu2 = fmaf(dl, dl, nu2);
+            }
+            const float nu = sqrtf(nu2);
+            const float sh = (nu <= lam) ? 1.0f : lam / nu;
+            for (int j = 0; j < d; ++j) {
+                const float v = zs[j] - P.u[k * d + j];
+                P.x[k * d + j] = v - sh * (v - A[k * d + j]);
+            }
+        }
+        __syncthreads();
+        // z = P_C(mean_k(x_k + u_k))
+        for (int j = tid; j < d; j += 256) {
+            float r = 0.0f;
+            for (int k = 0; k < n; ++k) r += P.x[k * d + j] + P.u[k * d + j];
+            zprev[j] = zs[j];
+            zs[j] = clampf(r / (float)n, P.lo, P.hi);
+        }
+        __syncthreads();
+        // u_k += x_k - z, primal residual
+        float rp = 0.0f;
+        for (int i = tid; i < n * d; i += 256) {
+            const float dlt = P.x[i] - zs[i % d];
+            P.u[i] += dlt;
+            rp = fmaf(dlt, dlt, rp);
+        }
+        red[tid] = rp;
+        __syncthreads();
+        for (int s2 = 128; s2 > 0; s2 >>= 1) {
+            if (tid < s2) red[tid] += red[tid + s2];
+            __syncthreads();
+        }
+        float rd = 0.0f;
+        for (int j = 0; j < d; ++j) rd += (zs[j] - zprev[j]) * (zs[j] - zprev[j]);
+        rpri = sqrtf(red[0] / ((float)n * (float)d));
+        rdual = sqrtf(rd / (float)d);
+        iters = t;
+        __syncthreads();
+        if (tau > 0.0f && rpri <= tau && rdual <= tau) {
+            flags = EM_CONVERGED;
+            break;
+        }
+    }
+    if (tid < d) Z[tid] = zs[tid];
+    if (tid == 0 && P.stats) P.stats[P.b] = em_stats_t{iters, flags, rpri, rdual};
+}
+
+em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
+                        const em_instance_t *inst, const em_instance_t *inst_host, float lo, float hi,
+                        float rho, int32_t max_iter, float tol, int32_t init, float *z, em_stats_t *stats) {
+    int64_t maxnd = 1;
+    for (int64_t b = 0; b < B; ++b) {
+        const int64_t n = inst_host[b].n, d = inst_host[b].d;
+        if (n > 0 && n <= EM_MAX_N && d >= 1 && d <= EM_MAX_D) maxnd = std::max(maxnd, n * d);
+    }
+    em_status_t st;
+    float *ws = static_cast<float *>(ctx_plain_workspace(ctx, (size_t)(2 * maxnd) * sizeof(float), &st));
+    if (!ws) return st;
+    PlainArgs P;
+    P.a = a;
+    P.w = w;
+    P.inst = inst;
+    P.z = z;
+    P.stats = stats;
+    P.u = ws;
+    P.x = ws + maxnd;
+    P.lo = lo;
+    P.hi = hi;
+    P.mu = rho;
+    P.tol = tol;
+    P.max_iter = max_iter;
+    P.init = init;
+    for (int64_t b = 0; b < B; ++b) {
+        P.b = b;
+        hipLaunchKernelGGL(plain_solve_kernel, dim3(1), dim3(256), 0, s, P);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return ctx_hip_error(ctx, e, "plain launch");
+    return EM_OK;
+}
+
+}  // namespace emx

@@ -1,8 +1,7 @@
-// Batched EM-ADMM over independent point sets of uneven size (Algorithm 1 of
-// arXiv:1501.03879 for every instance), and the plain one-launch-per-instance
-// baseline.
+// Batched solvers over independent point sets of uneven size: EM-ADMM
+// (Algorithm 1 of arXiv:1501.03879 for every instance, optionally with an
+// adaptive penalty) and IRLS on the smooth surrogate (EM_surrogate).
 //
-// Batched solver
 //  * A device pre-pass sorts instances into shape classes (coordinate slice
 //    DS, points per lane M, waves over coordinates WC, waves over points WP)
 //    with a counting sort; empty and malformed instances are finished there.
@@ -12,29 +11,31 @@
 //    and the iteration state (g = e - a, see the NLEM kernel) stay in
 //    registers for the whole solve; the points are read from HBM once,
 //    coalesced, through an LDS staging buffer.
-//  * Per iteration: pass 1 (delta = g + c, partial ||delta||^2), norms summed
+//  * ADMM iteration: pass 1 (delta = g + c, partial ||delta||^2), norms summed
 //    over the WC coordinate waves in LDS, shrink factor, pass 2 (E += s delta,
 //    g = s delta - a), wave reduce-scatter of E, sum over the WP point waves
 //    in LDS, then z = clamp(z - E / n), c = 2 z - z_prev.
-#include <float.h>
+//  * Box: one interval for all coordinates, or per-coordinate bounds read
+//    from device arrays indexed like z.
+//  * Adaptive penalty (residual balancing): on every k-th iteration both
+//    residuals are evaluated; the next iteration compares them and may scale
+//    mu by a factor.  The multipliers y are unchanged by that, so the scaled
+//    state is rescaled: with tau = mu'/mu, the current delta = v - a becomes
+//    delta / tau + (1 - 1/tau)(z - a), lambda = w / mu becomes lambda / tau,
+//    the prox displacement sum E^t becomes E^t / tau and
+//    c = v - e becomes c / tau + (1 - 1/tau) z.
+//  * IRLS iteration: omega_k = w_k (||z - a_k||^2 + eps)^(-1/2), then
+//    z' = P_C(sum_k omega_k a_k / sum_k omega_k), held relative to the
+//    starting point z0 (points as z0 - a) so the distance to a point at z0
+//    keeps FP32 precision of its own size.
+#pragma once
 
-#include <string>
+#include <float.h>
 
 #include "em_device.hpp"
 #include "emx_internal.hpp"
 
 namespace emx {
-
-int blocks_per_cu(em_context *ctx, const void *fn, int threads);
-int ctx_num_cus(em_context *ctx);
-em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg);
-em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what);
-unsigned int *ctx_counters(em_context *ctx, int n);
-em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, int n);
-void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st);
-void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
-
-// ------------------------------------------------------------------ classes
 
 struct ClassShape {
     int ds, m, wc, wp;
@@ -61,47 +62,6 @@ __host__ __device__ inline int class_of(int n, int d) {
     return 4 + (wc - 1) * 4 + k;
 }
 
-// Classify: counts per class; empty / malformed instances finished here.
-__global__ void batch_classify_count(const em_instance_t *inst, int64_t B, float *z, em_stats_t *stats,
-                                     unsigned int *counts) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const em_instance_t e = inst[b];
-    if (e.n == 0 && e.d >= 1 && e.d <= EM_MAX_D) {
-        if (stats) stats[b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
-        return;
-    }
-    if (e.n < 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
-        if (e.d >= 1 && e.d <= EM_MAX_D)
-            for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
-        if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
-        return;
-    }
-    atomicAdd(&counts[class_of(e.n, e.d)], 1u);
-}
-
-__global__ void batch_classify_scan(const unsigned int *counts, unsigned int *offsets) {
-    if (threadIdx.x == 0) {
-        unsigned int s = 0;
-        for (int c = 0; c < kNumClasses; ++c) {
-            offsets[c] = s;
-            s += counts[c];
-        }
-        offsets[kNumClasses] = s;
-    }
-}
-
-__global__ void batch_classify_scatter(const em_instance_t *inst, int64_t B, const unsigned int *offsets,
-                                       unsigned int *fill, int32_t *list) {
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const em_instance_t e = inst[b];
-    if (e.n <= 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) return;
-    const int c = class_of(e.n, e.d);
-    const unsigned int k = atomicAdd(&fill[c], 1u);
-    list[offsets[c] + k] = (int32_t)b;
-}
-
 // Kernel arguments of one class launch.
 struct ClassLaunch {
     const float *a;
@@ -112,8 +72,19 @@ struct ClassLaunch {
     unsigned int *counter;        // work-queue head of this class
     float *z;
     em_stats_t *stats;
-    float lo, hi, mu, inv_mu, tol, arm;
+    const float *box_lo;          // per-coordinate bounds (indexed like z) or null
+    const float *box_hi;
+    float lo, hi, mu, tol, arm;
+    float eps;                    // IRLS
+    float adapt_ratio2;           // ADMM: (residual ratio)^2 that triggers a penalty change
+    float adapt_factor;           // ADMM: penalty scale factor
+    int32_t adapt_every;          // ADMM: 0 = fixed penalty
     int32_t max_iter, init, cls;
+};
+
+struct ClassKernel {
+    const void *fn;
+    int threads;
 };
 
 template <int DS, int M, int WC, int WP>
@@ -121,19 +92,26 @@ struct BatchShape {
     static constexpr int THREADS = 64 * WC * WP;
     static constexpr int H2 = RS<DS>::H2;
     static constexpr int STAGE = 64 * 65 + 1;  // one 64-point chunk, odd pitch <= 65
+    static constexpr int XNB = WC * WP * M * 64;  // one buffer of per-wave norm partials
 };
 
-template <int DS, int M, int WC, int WP>
+template <int DS, int M, int WC, int WP, int SOLVER>
 __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunch L) {
+    constexpr bool IRLS = SOLVER == 1;
+    constexpr bool ADAPT = SOLVER == 2;   // adaptive penalty (a separate kernel: it needs registers)
     using S = BatchShape<DS, M, WC, WP>;
     using RSx = RS<DS>;
     constexpr int H2 = S::H2;
     __shared__ float stage[S::STAGE];
-    __shared__ float xn[(WC > 1) ? 2 * WC * WP * M * 64 : 1];
+    // buffers 0/1 alternate by iteration; buffer 2 is the penalty-rescale exchange
+    __shared__ float xn[(WC > 1) ? (ADAPT ? 3 : 2) * S::XNB : 1];
     __shared__ float xe[(WP > 1) ? 2 * WP * WC * H2 * 4 : 1];
+    __shared__ float xo[(WP > 1) ? 2 * WP : 1];
     __shared__ float xs[2 * WC * WP * 4];
-    __shared__ float zpE[WC * 2 * H2 * 4 * WP];
+    __shared__ float Epv[WC * H2 * 4 * WP];
+    __shared__ float Bv[WC * WP * 2 * H2 * 4];
     __shared__ float cvec[WC * WP * DS];
+    __shared__ float zvec[ADAPT ? WC * WP * DS : 1];
     __shared__ unsigned int item_s;
     __shared__ int flag_s[4];
 
@@ -141,18 +119,22 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     const int row = lane >> 4;
     const int wave = uniform_int(threadIdx.x >> 6);
     const int cw = wave % WC, pw = wave / WC;
-    float *zp_s = zpE + wave * 2 * H2 * 4;  // per wave: z^{t-1}, E^t in the reduced layout
-    float *Ep_s = zp_s + H2 * 4;
-    float *cv = cvec + wave * DS;           // per wave: c = 2 z^t - z^{t-1} of the slice
+    float *Ep_s = Epv + wave * H2 * 4;  // per wave: E^t in the reduced layout [slot][row]
+    float *cv = cvec + wave * DS;       // per wave: c of the slice (ADMM), z - z0 (IRLS)
+    float *zb = zvec + wave * DS;       // per wave: z of the slice, for a penalty rescale
+    float *Bl_s = Bv + wave * 2 * H2 * 4;  // per wave: the box in the reduced layout
+    float *Bh_s = Bl_s + H2 * 4;
     const unsigned int cbeg = L.offsets[L.cls];
     const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
+    const bool vbox = L.box_lo != nullptr;
 
     for (;;) {
         if (threadIdx.x == 0) {
             item_s = atomicAdd(L.counter, 1u);
             flag_s[0] = 0;  // a point or weight is bad
             flag_s[1] = 0;  // max |a| (float bits, non-negative)
-            flag_s[2] = 0;  // the starting z is bad
+            flag_s[2] = 0;  // the starting z or the box is bad
+            flag_s[3] = 0;  // widest box interval (float bits, non-negative)
         }
         __syncthreads();
         const unsigned int it = (unsigned int)uniform_int((int)item_s);
@@ -234,46 +216,229 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 best = uniform_int((int)pmin);
             }
         }
-        __syncthreads();
-        const bool bad = uniform(flag_s[0] != 0);
-        const float Dscale = (__builtin_isfinite(L.lo) && __builtin_isfinite(L.hi) && L.hi > L.lo)
-                                 ? (L.hi - L.lo)
-                                 : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
-        const float tau = L.tol * Dscale;
-        const float tau2 = tau * tau;
-        const float arm2 = (L.arm * tau) * (L.arm * tau);
 
-        // ---- starting z in the reduced layout; c = z
+        // ---- starting z and the box in the reduced layout
         float zr[H2];
         bool zbad = false;
+        float wid = 0.0f;
 #pragma unroll
         for (int j = 0; j < H2; ++j) {
             const int cc = cw * DS + RSx::coord(row, j);
             const bool vj = RSx::valid(row, j) && cc < d;
-            float zv = 0.0f;
-            if (vj) zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc] : Z[cc];
+            float zv = 0.0f, lv = L.lo, hv = L.hi;
+            if (vj) {
+                zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc] : Z[cc];
+                if (vbox) {
+                    lv = L.box_lo[e.z_off + cc];
+                    hv = L.box_hi[e.z_off + cc];
+                }
+            }
             zbad |= vj && !(fabsf(zv) <= FLT_MAX);
+            zbad |= vj && !(lv <= hv);
+            const float wj = hv - lv;
+            if (vj && !(wj <= wid)) wid = wj;   // also takes inf
             zr[j] = zv;
             if (lane == 16 * row) {
-                zp_s[j * 4 + row] = zv;
-                Ep_s[j * 4 + row] = 0.0f;
-                if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = zv;  // 0 on padded coordinates
+                Bl_s[j * 4 + row] = lv;
+                Bh_s[j * 4 + row] = hv;
             }
         }
+        const float wwid = wave_max(wid);
         if (__any(zbad) && lane == 0) flag_s[2] = 1;
+        if (lane == 0) atomicMax(&flag_s[3], __float_as_int(wwid));
         __syncthreads();
-        const bool bad_all = uniform(bad || (flag_s[2] != 0));
+        const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
+        const float wmax = readfirstlane(__int_as_float(flag_s[3]));
+        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f)
+                                 ? wmax : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
+        const float tau = L.tol * Dscale;
+        const float tau2 = tau * tau;
+        const float arm2 = (L.arm * tau) * (L.arm * tau);
         __syncthreads();  // flags are reset by the next pop
+
+        // c = z (ADMM); IRLS keeps z0 per slot and iterates z - z0 from 0
+        float z0[IRLS ? H2 : 1];
+        if (lane == 16 * row) {
+#pragma unroll
+            for (int j = 0; j < H2; ++j) {
+                Ep_s[j * 4 + row] = 0.0f;
+                if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = zr[j];  // 0 on padded coordinates
+            }
+        }
+        if constexpr (IRLS) {
+#pragma unroll
+            for (int j = 0; j < H2; ++j) z0[j] = zr[j];
+        }
 
         int iters = 0, flags = EM_MAXITER;
         float rp2 = 0.0f, rd2 = 0.0f;
         if (bad_all) {
             flags = EM_BAD_INPUT;
+        } else if constexpr (IRLS) {
+            // ---- points relative to z0 (na = z0 - a); iterate dz = z - z0
+#pragma unroll
+            for (int jj = 0; jj < DS; ++jj) {
+                const float cj = cv[jj];
+#pragma unroll
+                for (int q = 0; q < M; ++q) na[q][jj] += cj;
+            }
+#pragma unroll
+            for (int j = 0; j < H2; ++j) zr[j] = 0.0f;
+            if (lane == 16 * row) {
+#pragma unroll
+                for (int j = 0; j < H2; ++j)
+                    if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < M; ++q) lam[q] = fmaxf(lam[q], 0.0f);   // the weights
+            const float eps = L.eps;
+            const float inv_d = 1.0f / (float)d;
+            const int max_iter = L.max_iter;
+            float rd_w = 0.0f;
+            bool done = false;
+            int t = 1;
+            for (; t <= max_iter; ++t) {
+                // ---- ||z - a_k||^2 (+ eps, counted once over the coordinate waves)
+                float nrm[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) nrm[q] = (cw == 0) ? eps : 0.0f;
+#pragma unroll
+                for (int jj = 0; jj < DS; ++jj) {
+                    const float cj = cv[jj];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const float dv = na[q][jj] + cj;
+                        nrm[q] = fmaf(dv, dv, nrm[q]);
+                    }
+                }
+                float rd_all = rd_w;
+                if constexpr (WC > 1 || WP > 1) {
+                    float *XS = xs + (t & 1) * WC * WP * 4;
+                    if constexpr (WC > 1) {
+                        float *X = xn + (t & 1) * S::XNB;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) X[((pw * WC + cw) * M + q) * 64 + lane] = nrm[q];
+                    }
+                    if (lane == 0) XS[wave * 4] = rd_w;
+                    __syncthreads();
+                    if constexpr (WC > 1) {
+                        float *X = xn + (t & 1) * S::XNB;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            float sum = X[(pw * WC * M + q) * 64 + lane];
+#pragma unroll
+                            for (int v = 1; v < WC; ++v) sum += X[((pw * WC + v) * M + q) * 64 + lane];
+                            nrm[q] = sum;
+                        }
+                    }
+                    rd_all = 0.0f;
+#pragma unroll
+                    for (int v = 0; v < WC * WP; ++v) rd_all += XS[v * 4];
+                    rd_all = readfirstlane(rd_all);
+                }
+                if (t > 1) {
+                    rd2 = rd_all * inv_d;
+                    if (uniform(tau2 > 0.0f && rd2 <= tau2)) {
+                        flags = EM_CONVERGED;
+                        iters = t - 1;
+                        done = true;
+                        break;
+                    }
+                }
+                // ---- omega_k and the omega-weighted sums
+                float om[M];
+                float ol = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    om[q] = lam[q] * __builtin_amdgcn_rsqf(nrm[q]);
+                    ol += om[q];
+                }
+                float acc[DS];
+#pragma unroll
+                for (int jj = 0; jj < DS; ++jj) {
+                    float ac = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) ac = fmaf(om[q], na[q][jj], ac);
+                    acc[jj] = ac;
+                }
+                float E[H2];
+                reduce_scatter<DS>(acc, E);   // sum_k omega_k (z0 - a_k)
+                float Om = readfirstlane(wave_sum(ol));
+                if constexpr (WP > 1) {
+                    float *XE = xe + (t & 1) * WP * WC * H2 * 4;
+                    float *XO = xo + (t & 1) * WP;
+                    if (lane == 16 * row) {
+#pragma unroll
+                        for (int j = 0; j < H2; ++j) XE[((pw * WC + cw) * H2 + j) * 4 + row] = E[j];
+                    }
+                    if (cw == 0 && lane == 0) XO[pw] = Om;
+                    __syncthreads();
+#pragma unroll
+                    for (int j = 0; j < H2; ++j) {
+                        float sum = XE[(cw * H2 + j) * 4 + row];
+#pragma unroll
+                        for (int v = 1; v < WP; ++v) sum += XE[((v * WC + cw) * H2 + j) * 4 + row];
+                        E[j] = sum;
+                    }
+                    float os = XO[0];
+#pragma unroll
+                    for (int v = 1; v < WP; ++v) os += XO[v];
+                    Om = readfirstlane(os);
+                }
+                const float inv_om = (Om > 0.0f) ? 1.0f / Om : 0.0f;
+                float rdx = 0.0f;
+#pragma unroll
+                for (int j = 0; j < H2; ++j) {
+                    const int cc = cw * DS + RSx::coord(row, j);
+                    const bool vj = RSx::valid(row, j) && cc < d;
+                    // z' - z0 = P_C(z0 + raw) - z0, exact when the box is inactive
+                    const float raw = -E[j] * inv_om;
+                    const float zab = z0[j] + raw;
+                    const float bl = Bl_s[j * 4 + row], bh = Bh_s[j * 4 + row];
+                    float zn = (zab < bl) ? bl - z0[j] : ((zab > bh) ? bh - z0[j] : raw);
+                    zn = (vj && Om > 0.0f) ? zn : zr[j];
+                    const float dz = zn - zr[j];
+                    rdx += dz * dz;
+                    if (lane == 16 * row && RSx::valid(row, j)) cv[RSx::coord(row, j)] = zn;
+                    zr[j] = zn;
+                }
+                const float rdw = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) +
+                                                (readlane(rdx, 32) + readlane(rdx, 48)));
+                rd_w = (pw == 0) ? rdw : 0.0f;
+                if (uniform(!(Om > 0.0f))) {   // all weights zero: every z is a minimiser
+                    flags = EM_CONVERGED;
+                    iters = t;
+                    rd2 = 0.0f;
+                    done = true;
+                    break;
+                }
+            }
+            if (!done) {
+                iters = max_iter;
+                if (max_iter >= 1) {
+                    float rd_all = rd_w;
+                    if constexpr (WC > 1 || WP > 1) {
+                        float *XS = xs + (t & 1) * WC * WP * 4;
+                        if (lane == 0) XS[wave * 4] = rd_w;
+                        __syncthreads();
+                        rd_all = 0.0f;
+#pragma unroll
+                        for (int v = 0; v < WC * WP; ++v) rd_all += XS[v * 4];
+                        rd_all = readfirstlane(rd_all);
+                    }
+                    rd2 = rd_all * inv_d;
+                    flags = (tau2 > 0.0f && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < H2; ++j) zr[j] = z0[j] + zr[j];
         } else {
             float g[M][DS];
+            float mu_c = L.mu;
+            const float inv_mu0 = 1.0f / L.mu;
 #pragma unroll
             for (int q = 0; q < M; ++q) {
-                lam[q] = (lam[q] >= 0.0f) ? lam[q] * L.inv_mu : 0.0f;
+                lam[q] = (lam[q] >= 0.0f) ? lam[q] * inv_mu0 : 0.0f;
 #pragma unroll
                 for (int jj = 0; jj < DS; ++jj) g[q][jj] = na[q][jj];
             }
@@ -282,6 +447,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             const float inv_d = 1.0f / (float)d;
             const float inv_nd = 1.0f / ((float)n * (float)d);
             const int max_iter = L.max_iter;
+            const int every = ADAPT ? L.adapt_every : 0;
             float rd_w = 0.0f, rp_w = 0.0f;
             bool armed_last = false, done = false;
             int t = 1;
@@ -303,7 +469,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 if constexpr (WC > 1 || WP > 1) {
                     float *XS = xs + (t & 1) * WC * WP * 4;
                     if constexpr (WC > 1) {
-                        float *X = xn + (t & 1) * WC * WP * M * 64;
+                        float *X = xn + (t & 1) * S::XNB;
 #pragma unroll
                         for (int q = 0; q < M; ++q) X[((pw * WC + cw) * M + q) * 64 + lane] = nrm[q];
                     }
@@ -313,7 +479,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     }
                     __syncthreads();
                     if constexpr (WC > 1) {
-                        float *X = xn + (t & 1) * WC * WP * M * 64;
+                        float *X = xn + (t & 1) * S::XNB;
 #pragma unroll
                         for (int q = 0; q < M; ++q) {
                             float sum = X[(pw * WC * M + q) * 64 + lane];
@@ -343,7 +509,64 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         break;
                     }
                 }
-                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
+                // ---- adaptive penalty after a balancing iteration t-1: compare
+                // ||r||^2 = n d rp2 with (ratio ||s||)^2 = ratio^2 mu^2 n d rd2
+                if (ADAPT && t > 1 && (t - 1) % every == 0) {
+                    const float m2 = mu_c * mu_c;
+                    float tf = 1.0f;
+                    if (rp2 > L.adapt_ratio2 * m2 * rd2)
+                        tf = L.adapt_factor;
+                    else if (m2 * rd2 > L.adapt_ratio2 * rp2)
+                        tf = 1.0f / L.adapt_factor;
+                    if (uniform(tf != 1.0f)) {
+                        const float it_ = 1.0f / tf, omt = 1.0f - it_;
+                        mu_c *= tf;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) lam[q] *= it_;
+                        // z of the slice to every lane; E^t and c rescaled
+                        if (lane == 16 * row) {
+#pragma unroll
+                            for (int j = 0; j < H2; ++j) {
+                                if (RSx::valid(row, j)) zb[RSx::coord(row, j)] = zr[j];
+                                Ep_s[j * 4 + row] *= it_;
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < M; ++q) nrm[q] = kNu2Floor;
+#pragma unroll
+                        for (int jj = 0; jj < DS; ++jj) {
+                            const float zj = zb[jj];
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                g[q][jj] = fmaf(g[q][jj], it_, omt * (na[q][jj] + zj));
+                                nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                            }
+                        }
+                        if (lane == 16 * row) {
+#pragma unroll
+                            for (int j = 0; j < H2; ++j)
+                                if (RSx::valid(row, j)) {
+                                    const int k = RSx::coord(row, j);
+                                    cv[k] = fmaf(cv[k], it_, omt * zr[j]);
+                                }
+                        }
+                        if constexpr (WC > 1) {
+                            float *X = xn + 2 * S::XNB;
+#pragma unroll
+                            for (int q = 0; q < M; ++q) X[((pw * WC + cw) * M + q) * 64 + lane] = nrm[q];
+                            __syncthreads();
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                float sum = X[(pw * WC * M + q) * 64 + lane];
+#pragma unroll
+                                for (int v = 1; v < WC; ++v) sum += X[((pw * WC + v) * M + q) * 64 + lane];
+                                nrm[q] = sum;
+                            }
+                        }
+                    }
+                }
+                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2) ||
+                                           (ADAPT && t % every == 0));
                 float s[M];
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
@@ -405,20 +628,20 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 for (int j = 0; j < H2; ++j) {
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
-                    const float zn = clampf(zr[j] - E[j] * inv_n, L.lo, L.hi);
+                    const int k = RSx::valid(row, j) ? RSx::coord(row, j) : 0;
+                    const float zn = clampf(zr[j] - E[j] * inv_n, Bl_s[j * 4 + row], Bh_s[j * 4 + row]);
                     const float dz = zn - zr[j];
-                    const float zpj = zp_s[j * 4 + row];
+                    const float cj = cv[k];
                     if (armed) {
                         // x_k - z' = (x_k - c) + (c - z'), sum_k (x_k - c) = E^t - E^{t+1}
                         const float Epj = Ep_s[j * 4 + row];
-                        const float cz = (2.0f * zr[j] - zpj) - zn;
+                        const float cz = cj - zn;
                         rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
                     }
                     rdx += vj ? dz * dz : 0.0f;
                     if (lane == 16 * row) {
-                        zp_s[j * 4 + row] = zr[j];
                         Ep_s[j * 4 + row] = E[j];
-                        if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = vj ? (2.0f * zn - zr[j]) : 0.0f;
+                        if (RSx::valid(row, j)) cv[k] = vj ? (2.0f * zn - zr[j]) : 0.0f;
                     }
                     zr[j] = vj ? zn : 0.0f;
                 }
@@ -475,246 +698,37 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             em_stats_t st;
             st.iters = bad_all ? 0 : iters;
             st.flags = flags;
-            st.r_pri = bad_all ? 0.0f : sqrtf(rp2);
+            st.r_pri = (bad_all || IRLS) ? 0.0f : sqrtf(rp2);
             st.r_dual = bad_all ? 0.0f : sqrtf(rd2);
             L.stats[b] = st;
         }
     }
 }
 
-struct ClassKernel {
-    const void *fn;
-    int threads;
-};
-
-template <int C>
+template <int C, int SOLVER>
 constexpr ClassKernel class_kernel() {
     constexpr ClassShape s = class_shape(C);
-    return ClassKernel{reinterpret_cast<const void *>(&batch_solve_kernel<s.ds, s.m, s.wc, s.wp>),
+    return ClassKernel{reinterpret_cast<const void *>(&batch_solve_kernel<s.ds, s.m, s.wc, s.wp, SOLVER>),
                        64 * s.wc * s.wp};
 }
 
-static const ClassKernel *class_table() {
+template <int SOLVER>
+const ClassKernel *class_table_for() {
     static const ClassKernel t[kNumClasses] = {
-        class_kernel<0>(),  class_kernel<1>(),  class_kernel<2>(),  class_kernel<3>(),
-        class_kernel<4>(),  class_kernel<5>(),  class_kernel<6>(),  class_kernel<7>(),
-        class_kernel<8>(),  class_kernel<9>(),  class_kernel<10>(), class_kernel<11>(),
-        class_kernel<12>(), class_kernel<13>(), class_kernel<14>(), class_kernel<15>(),
-        class_kernel<16>(), class_kernel<17>(), class_kernel<18>(), class_kernel<19>(),
+        class_kernel<0, SOLVER>(),  class_kernel<1, SOLVER>(),  class_kernel<2, SOLVER>(),
+        class_kernel<3, SOLVER>(),  class_kernel<4, SOLVER>(),  class_kernel<5, SOLVER>(),
+        class_kernel<6, SOLVER>(),  class_kernel<7, SOLVER>(),  class_kernel<8, SOLVER>(),
+        class_kernel<9, SOLVER>(),  class_kernel<10, SOLVER>(), class_kernel<11, SOLVER>(),
+        class_kernel<12, SOLVER>(), class_kernel<13, SOLVER>(), class_kernel<14, SOLVER>(),
+        class_kernel<15, SOLVER>(), class_kernel<16, SOLVER>(), class_kernel<17, SOLVER>(),
+        class_kernel<18, SOLVER>(), class_kernel<19, SOLVER>(),
     };
     return t;
 }
 
-em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
-                        const em_instance_t *inst, float lo, float hi, float rho, int32_t max_iter,
-                        float tol, int32_t init, float *z, em_stats_t *stats) {
-    // workspace: list[B] int32
-    em_status_t st;
-    int32_t *list = static_cast<int32_t *>(ctx_workspace(ctx, (size_t)B * sizeof(int32_t), &st));
-    if (!list) return st;
-    // counters: [0, K) class counts, [K, 2K+1) offsets, [2K+1, 3K+1) fill, [3K+1, 4K+1) queue heads
-    unsigned int *cnt = ctx_counters(ctx, 4 * kNumClasses + 1);
-    if (!cnt) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
-    unsigned int *counts = cnt, *offsets = cnt + kNumClasses, *fill = cnt + 2 * kNumClasses + 1,
-                 *heads = cnt + 3 * kNumClasses + 1;
-    st = ctx_reset_counters(ctx, s, cnt, 4 * kNumClasses + 1);
-    if (st != EM_OK) return st;
-    const unsigned nb = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts);
-    hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
-    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
-    const ClassKernel *tab = class_table();
-    for (int c = 0; c < kNumClasses; ++c) {
-        ClassLaunch L;
-        L.a = a;
-        L.w = w;
-        L.inst = inst;
-        L.list = list;
-        L.offsets = offsets;
-        L.counter = heads + c;
-        L.z = z;
-        L.stats = stats;
-        L.lo = lo;
-        L.hi = hi;
-        L.mu = rho;
-        L.inv_mu = 1.0f / rho;
-        L.tol = tol;
-        L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
-        L.max_iter = max_iter;
-        L.init = init;
-        L.cls = c;
-        const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, tab[c].fn, tab[c].threads);
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
-        void *args[] = {&L};
-        e = hipLaunchKernel(tab[c].fn, dim3(grid), dim3(tab[c].threads), args, 0, s);
-        if (e != hipSuccess) return ctx_hip_error(ctx, e, "batch class launch");
-    }
-    return EM_OK;
-}
-
-// ------------------------------------------------------------------ plain
-
-// One instance per launch, literal Algorithm 1 with the iterates in device
-// memory: thread per point for the prox, thread per coordinate for the
-// z-update, thread per point for the multiplier update, residuals every
-// iteration.  The simple baseline for the batched solver.
-struct PlainArgs {
-    const float *a;
-    const float *w;
-    const em_instance_t *inst;
-    float *z;
-    em_stats_t *stats;
-    float *u;  // n*d scaled multipliers y/mu
-    float *x;  // n*d local variables
-    float lo, hi, mu, tol;
-    int32_t max_iter, init;
-    int64_t b;
-};
-
-__global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
-    __shared__ float zs[EM_MAX_D], zprev[EM_MAX_D];
-    __shared__ float red[256];
-    __shared__ int flag;
-    __shared__ float amax_s;
-    const int tid = threadIdx.x;
-    const em_instance_t e = P.inst[P.b];
-    const int n = e.n, d = e.d;
-    float *Z = P.z + e.z_off;
-    if (n == 0 && d >= 1 && d <= EM_MAX_D) {
-        if (tid == 0 && P.stats) P.stats[P.b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
-        return;
-    }
-    const float *A = P.a + e.a_off;
-    const float *Wt = P.w + e.w_off;
-    if (tid == 0) {
-        flag = 0;
-        amax_s = 0.0f;
-    }
-    __syncthreads();
-    if (n < 0 || n > EM_MAX_N || d < 1 || d > EM_MAX_D) {
-        if (tid == 0) flag = 1;
-    } else {
-        for (int i = tid; i < n * d; i += 256) {
-            if (!(fabsf(A[i]) <= FLT_MAX)) flag = 1;
-            atomicMax(reinterpret_cast<int *>(&amax_s), __float_as_int(fabsf(A[i])));
-        }
-        for (int k = tid; k < n; k += 256)
-            if (!(Wt[k] >= 0.0f && Wt[k] <= FLT_MAX)) flag = 1;
-    }
-    __syncthreads();
-    if (flag == 0 && tid == 0) {
-        int best = 0;
-        if (P.init == EM_INIT_MAXW)
-            for (int k = 1; k < n; ++k)
-                if (Wt[k] > Wt[best]) best = k;
-        for (int j = 0; j < d; ++j) {
-            zs[j] = (P.init == EM_INIT_MAXW) ? A[best * d + j] : Z[j];
-            if (!(fabsf(zs[j]) <= FLT_MAX)) flag = 1;
-        }
-    }
-    __syncthreads();
-    if (flag) {
-        if (tid == 0) {
-            if (d >= 1 && d <= EM_MAX_D)
-                for (int j = 0; j < d; ++j) Z[j] = __builtin_nanf("");
-            if (P.stats) P.stats[P.b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
-        }
-        return;
-    }
-    const float Dscale = (__builtin_isfinite(P.lo) && __builtin_isfinite(P.hi) && P.hi > P.lo)
-                             ? (P.hi - P.lo) : fmaxf(1.0f, amax_s);
-    const float tau = P.tol * Dscale;
-    for (int i = tid; i < n * d; i += 256) P.u[i] = 0.0f;
-    __syncthreads();
-    int iters = 0, flags = EM_MAXITER;
-    float rpri = 0.0f, rdual = 0.0f;
-    for (int t = 1; t <= P.max_iter; ++t) {
-        // x_k = prox_{w_k/mu}(z - u_k, a_k)
-        for (int k = tid; k < n; k += 256) {
-            const float lam = Wt[k] / P.mu;
-            float nu2 = 0.0f;
-            for (int j = 0; j < d; ++j) {
-                const float dl = zs[j] - P.u[k * d + j] - A[k * d + j];
-                nu2 = fmaf(dl, dl, nu2);
-            }
-            const float nu = sqrtf(nu2);
-            const float sh = (nu <= lam) ? 1.0f : lam / nu;
-            for (int j = 0; j < d; ++j) {
-                const float v = zs[j] - P.u[k * d + j];
-                P.x[k * d + j] = v - sh * (v - A[k * d + j]);
-            }
-        }
-        __syncthreads();
-        // z = P_C(mean_k(x_k + u_k))
-        for (int j = tid; j < d; j += 256) {
-            float r = 0.0f;
-            for (int k = 0; k < n; ++k) r += P.x[k * d + j] + P.u[k * d + j];
-            zprev[j] = zs[j];
-            zs[j] = clampf(r / (float)n, P.lo, P.hi);
-        }
-        __syncthreads();
-        // u_k += x_k - z, primal residual
-        float rp = 0.0f;
-        for (int i = tid; i < n * d; i += 256) {
-            const float dlt = P.x[i] - zs[i % d];
-            P.u[i] += dlt;
-            rp = fmaf(dlt, dlt, rp);
-        }
-        red[tid] = rp;
-        __syncthreads();
-        for (int s2 = 128; s2 > 0; s2 >>= 1) {
-            if (tid < s2) red[tid] += red[tid + s2];
-            __syncthreads();
-        }
-        float rd = 0.0f;
-        for (int j = 0; j < d; ++j) rd += (zs[j] - zprev[j]) * (zs[j] - zprev[j]);
-        rpri = sqrtf(red[0] / ((float)n * (float)d));
-        rdual = sqrtf(rd / (float)d);
-        iters = t;
-        __syncthreads();
-        if (tau > 0.0f && rpri <= tau && rdual <= tau) {
-            flags = EM_CONVERGED;
-            break;
-        }
-    }
-    if (tid < d) Z[tid] = zs[tid];
-    if (tid == 0 && P.stats) P.stats[P.b] = em_stats_t{iters, flags, rpri, rdual};
-}
-
-em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
-                        const em_instance_t *inst, const em_instance_t *inst_host, float lo, float hi,
-                        float rho, int32_t max_iter, float tol, int32_t init, float *z, em_stats_t *stats) {
-    int64_t maxnd = 1;
-    for (int64_t b = 0; b < B; ++b) {
-        const int64_t n = inst_host[b].n, d = inst_host[b].d;
-        if (n > 0 && n <= EM_MAX_N && d >= 1 && d <= EM_MAX_D) maxnd = std::max(maxnd, n * d);
-    }
-    em_status_t st;
-    float *ws = static_cast<float *>(ctx_plain_workspace(ctx, (size_t)(2 * maxnd) * sizeof(float), &st));
-    if (!ws) return st;
-    PlainArgs P;
-    P.a = a;
-    P.w = w;
-    P.inst = inst;
-    P.z = z;
-    P.stats = stats;
-    P.u = ws;
-    P.x = ws + maxnd;
-    P.lo = lo;
-    P.hi = hi;
-    P.mu = rho;
-    P.tol = tol;
-    P.max_iter = max_iter;
-    P.init = init;
-    for (int64_t b = 0; b < B; ++b) {
-        P.b = b;
-        hipLaunchKernelGGL(plain_solve_kernel, dim3(1), dim3(256), 0, s, P);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return ctx_hip_error(ctx, e, "plain launch");
-    return EM_OK;
-}
+// Class kernel tables, one translation unit per solver.
+const ClassKernel *batch_class_table_admm();
+const ClassKernel *batch_class_table_irls();
+const ClassKernel *batch_class_table_adapt();
 
 }  // namespace emx

@@ -18,8 +18,8 @@ namespace emx {
 
 // batch_kernel.hip
 em_status_t batch_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
-                        const float *w, const em_instance_t *inst, float lo, float hi, float rho,
-                        int32_t max_iter, float tol, int32_t init, float *z, em_stats_t *stats);
+                        const float *w, const em_instance_t *inst, const em_options_t &o, float *z,
+                        em_stats_t *stats);
 em_status_t plain_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
                         const float *w, const em_instance_t *inst, const em_instance_t *inst_host,
                         float lo, float hi, float rho, int32_t max_iter, float tol, int32_t init,
@@ -525,8 +525,41 @@ extern "C" em_status_t em_solve_batch(em_handle_t h, void *stream, int64_t B, co
     if (st != EM_OK) return st;
     if (B == 0) return EM_OK;
     EMX_HIP(h, hipSetDevice(h->device));
-    return batch_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, lo, hi, rho, max_iter, tol,
-                       init, z, stats);
+    em_options_t o{};
+    o.solver = EM_SOLVER_ADMM;
+    o.init = init;
+    o.lo = lo;
+    o.hi = hi;
+    o.rho = rho;
+    o.eps = 1e-6f;
+    o.max_iter = max_iter;
+    o.tol = tol;
+    return batch_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, o, z, stats);
+}
+
+extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B, const float *a,
+                                         const float *w, const em_instance_t *inst,
+                                         const em_options_t *opt, float *z, em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
+    const em_options_t &o = *opt;
+    if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_IRLS && o.solver != EM_SOLVER_ADMM_ADAPTIVE)
+        return fail(h, EM_ERR_INVALID_ARG, "bad solver");
+    if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
+        return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");
+    if (o.solver == EM_SOLVER_IRLS && (!(o.eps > 0.0f) || !std::isfinite(o.eps)))
+        return fail(h, EM_ERR_INVALID_ARG, "eps must be finite and > 0");
+    if (o.solver == EM_SOLVER_ADMM_ADAPTIVE &&
+        (o.adapt_every < 1 || !(o.adapt_ratio > 1.0f) || !(o.adapt_factor > 1.0f) ||
+         !std::isfinite(o.adapt_ratio) || !std::isfinite(o.adapt_factor)))
+        return fail(h, EM_ERR_INVALID_ARG, "adaptive penalty needs adapt_every >= 1, ratio > 1, factor > 1");
+    const float lo = o.box_lo ? 0.0f : o.lo, hi = o.box_lo ? 0.0f : o.hi;
+    const float rho = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
+    em_status_t st = check_batch_args(h, B, a, w, inst, z, lo, hi, rho, o.max_iter, o.tol, o.init);
+    if (st != EM_OK) return st;
+    if (B == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return batch_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, o, z, stats);
 }
 
 extern "C" em_status_t em_solve_plain(em_handle_t h, void *stream, int64_t B, const float *a,

@@ -117,3 +117,30 @@ def run_nlm(img_np, pr, wr, h, fp16=False):
     hd.nlm_denoise(t, out, patch_radius=pr, window_radius=wr, h=h)
     hd.sync()
     return out.cpu().numpy().reshape(-1).astype(np.float64)
+
+
+def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo=None,
+                 box_hi=None, adapt_every=1, adapt_ratio=10.0, adapt_factor=2.0, z0=None):
+    """em_solve_batch_ex on the GPU for a synth.PointSetBatch (box from the
+    batch's lo/hi unless per-coordinate arrays are given)."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    a = torch.from_numpy(np.ascontiguousarray(batch.a, dtype=np.float32)).to(dev)
+    w = torch.from_numpy(np.ascontiguousarray(batch.w, dtype=np.float32)).to(dev)
+    inst = emx.instances_tensor(batch.inst, dev)
+    zsz = max(batch.z_size, 1)
+    z = (torch.zeros(zsz, dtype=torch.float32, device=dev) if z0 is None else
+         torch.from_numpy(np.ascontiguousarray(z0, dtype=np.float32)).to(dev))
+    bl = None if box_lo is None else torch.from_numpy(np.ascontiguousarray(box_lo, np.float32)).to(dev)
+    bh = None if box_hi is None else torch.from_numpy(np.ascontiguousarray(box_hi, np.float32)).to(dev)
+    stats = torch.zeros((max(batch.B, 1), 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    hd.em_solve_batch_ex(a, w, inst, z, stats, solver=solver, init=init, lo=batch.lo, hi=batch.hi,
+                         box_lo=bl, box_hi=bh, rho=mu, eps=eps, max_iter=max_iter, tol=tol,
+                         adapt_every=adapt_every, adapt_ratio=adapt_ratio, adapt_factor=adapt_factor)
+    hd.sync()
+    it, fl, rp, rd = emx.stats_view(stats)
+    return (z.cpu().numpy().astype(np.float64),
+            dict(iters=it.cpu().numpy()[:batch.B], flags=fl.cpu().numpy()[:batch.B],
+                 r_pri=rp.cpu().numpy()[:batch.B], r_dual=rd.cpu().numpy()[:batch.B]))

@@ -1,0 +1,157 @@
+"""GPU parity of em_solve_batch_ex against the FP64 oracle: IRLS on the smooth
+surrogate, per-coordinate boxes and the adaptive penalty, over every shape
+class (uneven n in [1, 512], d in {1..64}).
+
+Tolerance: max |z_gpu - z_oracle| <= 1e-4 D per coordinate (D = the widest
+box interval), as for em_solve_batch.  In tolerance mode the GPU's iteration
+counts are fed back to the oracle.  The adaptive penalty is a decision taken
+on FP32 residuals on the GPU and FP64 ones in the oracle; on these inputs no
+comparison falls within rounding of the threshold, so the two follow the same
+penalty sequence.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import rel_errors, report, run_batch_ex
+
+pytestmark = pytest.mark.gpu
+ADMM, IRLS, ADAPT = 0, 1, 2
+DIMS = (1, 2, 3, 4, 5, 8, 15, 16, 17, 31, 33, 48, 49, 64)
+
+
+def _mixed(seed, B):
+    return synth.make_pointset_batch(seed, B, n_lo=1, n_hi=512, d_choices=DIMS)
+
+
+def _boxes(batch, seed):
+    rng = np.random.default_rng(seed)
+    lo = rng.uniform(-2.5, -0.2, size=batch.z_size).astype(np.float32)
+    hi = (lo + rng.uniform(0.3, 3.0, size=batch.z_size)).astype(np.float32)
+    return lo, hi
+
+
+def _check(batch, got, ref, D, name, tol=1e-4):
+    e, r = rel_errors(got[:batch.z_size], ref[:batch.z_size], D)
+    report(name, e, r)
+    assert e <= tol
+
+
+@pytest.mark.parametrize("eps,dims", [(1e-4, DIMS), (1e-6, (16, 17, 31, 33, 48, 49, 64))])
+def test_irls_mixed_shapes_fixed_iterations(eps, dims):
+    """eps is a squared length: 1e-4 on these unit-scale sets (any d), and
+    1e-6 where d >= 16 keeps the points apart.  (With eps = 1e-6 and hundreds
+    of 1-D points within 1e-3 of the iterate the IRLS map itself is
+    ill-conditioned and FP32 cannot track FP64 to this bar.)"""
+    b = synth.make_pointset_batch(21, 400, n_lo=1, n_hi=512, d_choices=dims)
+    got, st = run_batch_ex(b, solver=IRLS, max_iter=25, tol=0.0, init=oracle.INIT_MAXW, eps=eps)
+    ref = oracle.em_batch(b, 1.0, 25, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_IRLS, eps=eps)
+    _check(b, got, ref["z"], 6.0, f"batch irls mixed eps={eps} T25")
+    live = b.inst["n"] > 0
+    assert np.all(st["iters"][live] == 25) and np.all(st["r_pri"] == 0)
+
+
+def test_irls_ill_conditioned_small_eps_report():
+    """Measured, not asserted to the 1e-4 bar: eps = 1e-6 on crowded 1-D and
+    2-D sets.  The error is bounded by 1e-2 D and reported for the design
+    notes."""
+    b = synth.make_pointset_batch(21, 200, n_lo=256, n_hi=512, d_choices=(1, 2))
+    got, st = run_batch_ex(b, solver=IRLS, max_iter=25, tol=0.0, init=oracle.INIT_MAXW, eps=1e-6)
+    ref = oracle.em_batch(b, 1.0, 25, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_IRLS, eps=1e-6)
+    _check(b, got, ref["z"], 6.0, "batch irls eps=1e-6 crowded d<=2 T25 (ill-conditioned)", tol=1e-2)
+
+
+def test_irls_tolerance_mode_given_start():
+    b = _mixed(22, 300)
+    rng = np.random.default_rng(5)
+    z0 = rng.uniform(-1, 1, size=b.z_size).astype(np.float32)
+    got, st = run_batch_ex(b, solver=IRLS, max_iter=400, tol=1e-5, init=oracle.INIT_GIVEN, eps=1e-4,
+                           z0=z0)
+    ref_t = oracle.em_batch(b, 1.0, 400, 1e-5, init=oracle.INIT_GIVEN, z0=z0, solver=oracle.SOLVER_IRLS,
+                            eps=1e-4)
+    live = b.inst["n"] > 0
+    close = np.abs(st["iters"].astype(int) - ref_t["iters"])[live] <= 1
+    ref = oracle.em_batch(b, 1.0, 400, 0.0, init=oracle.INIT_GIVEN, z0=z0, solver=oracle.SOLVER_IRLS,
+                          eps=1e-4, max_iter_each=st["iters"])
+    _check(b, got, ref["z"], 6.0, f"batch irls tol 1e-5 (iters within 1: {close.mean():.3f}, mean "
+                                  f"{st['iters'][live].mean():.1f})")
+    assert close.mean() >= 0.95
+
+
+def test_admm_per_coordinate_boxes():
+    b = _mixed(23, 400)
+    lo, hi = _boxes(b, 1)
+    got, st = run_batch_ex(b, solver=ADMM, max_iter=25, tol=0.0, init=oracle.INIT_MAXW, box_lo=lo, box_hi=hi)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_MAXW, box_lo=lo, box_hi=hi)
+    _check(b, got, ref["z"], 3.0, "batch admm per-coordinate boxes T25")
+    zz = got[:b.z_size]
+    assert np.all(zz >= lo) and np.all(zz <= hi)
+
+
+def test_irls_per_coordinate_boxes_tolerance_mode():
+    b = _mixed(24, 300)
+    lo, hi = _boxes(b, 2)
+    got, st = run_batch_ex(b, solver=IRLS, max_iter=300, tol=1e-5, init=oracle.INIT_MAXW, eps=1e-3,
+                           box_lo=lo, box_hi=hi)
+    ref = oracle.em_batch(b, 1.0, 300, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_IRLS, eps=1e-3,
+                          box_lo=lo, box_hi=hi, max_iter_each=st["iters"])
+    _check(b, got, ref["z"], 3.0, "batch irls per-coordinate boxes tol")
+
+
+@pytest.mark.parametrize("mu0,every", [(1e-3, 1), (0.5, 3), (50.0, 2)])
+def test_adaptive_penalty_fixed_iterations(mu0, every):
+    b = _mixed(25 + every, 300)
+    got, st = run_batch_ex(b, solver=ADAPT, max_iter=30, tol=0.0, init=oracle.INIT_MAXW, mu=mu0,
+                           adapt_every=every)
+    ref = oracle.em_batch(b, mu0, 30, 0.0, init=oracle.INIT_MAXW, adapt_every=every)
+    _check(b, got, ref["z"], 6.0, f"batch adaptive mu0={mu0} every={every} T30")
+
+
+def test_adaptive_penalty_tolerance_mode_and_speed():
+    """A badly scaled starting penalty: the adaptive solver converges in far
+    fewer iterations than the fixed one, on the GPU as in the oracle."""
+    b = synth.make_pointset_batch(505, 256)
+    got, st = run_batch_ex(b, solver=ADAPT, max_iter=2000, tol=1e-4, init=oracle.INIT_MAXW, mu=1e-3,
+                           adapt_every=1)
+    _, stf = run_batch_ex(b, solver=ADMM, max_iter=2000, tol=1e-4, init=oracle.INIT_MAXW, mu=1e-3)
+    ref = oracle.em_batch(b, 1e-3, 2000, 0.0, init=oracle.INIT_MAXW, adapt_every=1,
+                          max_iter_each=st["iters"])
+    _check(b, got, ref["z"], 6.0, f"batch adaptive tol (mean iters {st['iters'].mean():.1f} vs fixed "
+                                  f"{stf['iters'].mean():.1f})")
+    assert st["iters"].mean() * 3 < stf["iters"].mean()
+    assert np.mean(st["flags"] == 1) >= 0.99
+
+
+def test_bad_boxes_zero_weights_and_invalid_args():
+    import torch
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    pts = [np.ones((3, 2), np.float32), np.arange(8, dtype=np.float32).reshape(4, 2),
+           np.ones((2, 3), np.float32)]
+    ws = [np.ones(3, np.float32), np.zeros(4, np.float32), np.ones(2, np.float32)]
+    b = synth.pointsets.pack_instances(pts, ws, -5.0, 5.0)
+    lo = np.full(b.z_size, -5.0, np.float32)
+    hi = np.full(b.z_size, 5.0, np.float32)
+    lo[b.inst[0]["z_off"] + 1] = 6.0                    # lo > hi: BAD_INPUT
+    hi[b.inst[2]["z_off"]] = np.nan                     # NaN bound: BAD_INPUT
+    z0 = np.full(b.z_size, 0.25, np.float32)
+    for solver in (ADMM, IRLS, ADAPT):
+        got, st = run_batch_ex(b, solver=solver, max_iter=10, tol=1e-4, init=oracle.INIT_GIVEN,
+                               box_lo=lo, box_hi=hi, z0=z0)
+        assert st["flags"][0] == 8 and st["flags"][2] == 8
+        assert np.all(np.isnan(got[b.inst[0]["z_off"]:b.inst[0]["z_off"] + 2]))
+        if solver == IRLS:   # all weights zero: z unchanged, CONVERGED after one iteration
+            assert st["flags"][1] == 1 and st["iters"][1] == 1
+            np.testing.assert_array_equal(got[b.inst[1]["z_off"]:b.inst[1]["z_off"] + 2], 0.25)
+    dev = gpu()
+    a = torch.zeros(4, device=dev)
+    inst = emx.instances_tensor(b.inst, dev)
+    z = torch.zeros(b.z_size, device=dev)
+    hd = handle()
+    for kw in (dict(solver=7), dict(solver=IRLS, eps=0.0), dict(solver=ADAPT, adapt_every=0),
+               dict(solver=ADAPT, adapt_factor=1.0), dict(solver=ADAPT, adapt_ratio=0.5),
+               dict(box_lo=z), dict(solver=ADMM, rho=-1.0), dict(init=9)):
+        with pytest.raises(emx.EmxError):
+            hd.em_solve_batch_ex(a, a, inst, z, **kw)
