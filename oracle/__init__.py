@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "libemoracle.so")
 
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW = 0, 1
-SOLVER_ADMM, SOLVER_IRLS = 0, 1
+SOLVER_ADMM, SOLVER_IRLS, SOLVER_FAST_ADMM = 0, 1, 3
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 
 
@@ -59,13 +59,17 @@ def _load():
                                            dp, C.c_int64, C.c_double, C.c_int64, C.c_double,
                                            C.c_double, i64p, dp, dp, dp]
         lib.oracle_em_solve_ex.restype = C.c_int
+        lib.oracle_em_solve_fast.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
+                                             C.c_int64, C.c_double, C.c_double, i64p, dp, dp, i64p]
+        lib.oracle_em_solve_fast.restype = C.c_int
         lib.oracle_irls_solve_ex.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
                                              C.c_int64, C.c_double, i64p, dp, dp]
         lib.oracle_irls_solve_ex.restype = C.c_int
         lib.oracle_em_batch_ex.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p, C.c_int,
                                            C.c_double, C.c_double, C.c_double, C.c_double, fp, fp,
                                            C.c_int64, i32p, C.c_double, C.c_int, C.c_int64,
-                                           C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_int]
+                                           C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_double,
+                                           C.c_int]
         lib.oracle_em_batch_ex.restype = C.c_int
         lib.oracle_em_batch.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p,
                                         C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
@@ -149,13 +153,38 @@ def em_solve(a, w, mu: float, lo, hi, z0, y0=None, max_iter: int = 100, tol: flo
                 mu=mf.value)
 
 
+def em_solve_fast(a, w, mu: float, lo, hi, z0, max_iter: int = 100, tol: float = 0.0,
+                  eta: float = 0.999) -> dict:
+    """Accelerated ADMM (fast ADMM with restart) in FP64 over the box [lo, hi];
+    returns z, iters, residuals, flags and the number of restarts."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    assert w.size == n and z.size == d
+    lv, hv = _box(lo, hi, d)
+    it = C.c_int64(0)
+    rs = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    f = _load().oracle_em_solve_fast(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                     _p(lv, C.c_double), _p(hv, C.c_double), _p(z, C.c_double),
+                                     int(max_iter), float(tol), float(eta), C.byref(it),
+                                     C.byref(rp), C.byref(rd), C.byref(rs))
+    return dict(z=z, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f),
+                restarts=int(rs.value))
+
+
 def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW, z0=None,
              max_iter_each=None, nthreads: int = 0, solver: int = SOLVER_ADMM, eps: float = 1e-6,
              box_lo=None, box_hi=None, adapt_every: int = 0, adapt_ratio: float = 10.0,
-             adapt_factor: float = 2.0) -> dict:
+             adapt_factor: float = 2.0, eta: float = 0.999) -> dict:
     """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
-    z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty)
-    or SOLVER_IRLS; box_lo / box_hi: optional float32 per-coordinate bounds
+    z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty),
+    SOLVER_IRLS or SOLVER_FAST_ADMM (restart parameter eta); box_lo / box_hi:
+    optional float32 per-coordinate bounds
     indexed like z.  Returns z (float64, concatenated), iters, flags,
     residuals and the final penalties."""
     inst = batch.inst
@@ -183,7 +212,7 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
                                _p(mie, C.c_int32), float(tol), int(init), int(adapt_every),
                                float(adapt_ratio), float(adapt_factor), _p(z, C.c_double),
                                _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
-                               _p(rd, C.c_double), _p(mf, C.c_double), int(nthreads))
+                               _p(rd, C.c_double), _p(mf, C.c_double), float(eta), int(nthreads))
     return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf)
 
 

@@ -233,6 +233,122 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
 }
 
 /*
+ * Accelerated ADMM, the second extension the conclusion names ([Goldstein2012]:
+ * "fast ADMM with restart" for weakly convex problems), applied to the
+ * splitting (splitting) with u = (x_k), v = z, constraint x_k - z = 0 and
+ * penalty mu.  With predictor values z_hat, y_hat (z_hat = z0, y_hat = 0 at
+ * the start, alpha = 1, c_prev = +inf):
+ *   x_k   = Psi_{w_k/mu}(z_hat - y_hat_k / mu, a_k)
+ *   z     = P_C( mean_k (x_k + y_hat_k / mu) )
+ *   y_k   = y_hat_k + mu (x_k - z)
+ *   c     = mu ( sum_k ||x_k - z||^2 + n ||z - z_hat||^2 )
+ *         (= ||y - y_hat||^2 / mu + mu ||B (z - z_hat)||^2 of the reference)
+ *   if c < eta c_prev:  alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2,
+ *                       beta = (alpha - 1) / alpha',
+ *                       z_hat = z + beta (z - z_prev), y_hat = y + beta (y - y_prev)
+ *   else (restart):     alpha' = 1, z_hat = z_prev, y_hat = y_prev,
+ *                       c = c_prev / eta
+ * where z_prev, y_prev are the previous iteration's z, y (the starting z and
+ * zero before the first).  Residuals and stopping as for oracle_em_solve
+ * (r_dual from z - z_prev).  eta = 0.999 in the reference.
+ * *restarts (nullable) receives the number of restarts.
+ */
+int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                         const double *lo, const double *hi, double *z, int64_t max_iter,
+                         double tol, double eta, int64_t *iters, double *r_pri, double *r_dual,
+                         int64_t *restarts)
+{
+    *iters = 0;
+    *r_pri = 0.0;
+    *r_dual = 0.0;
+    if (restarts) *restarts = 0;
+    if (n == 0) return OR_EMPTY;
+    int bad = !box_ok(d, lo, hi);
+    for (int64_t k = 0; k < n; ++k)
+        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!isfinite(a[i])) bad = 1;
+    for (int64_t j = 0; j < d; ++j)
+        if (!isfinite(z[j])) bad = 1;
+    if (bad) {
+        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
+        return OR_BAD_INPUT;
+    }
+    double D = tol_scale_box(n, d, a, lo, hi);
+    size_t nd = (size_t)(n * d);
+    double *y = (double *)calloc(nd, sizeof(double));
+    double *yp = (double *)calloc(nd, sizeof(double));
+    double *yh = (double *)calloc(nd, sizeof(double));
+    double *x = (double *)malloc(nd * sizeof(double));
+    double *v = (double *)malloc((size_t)d * sizeof(double));
+    double *r = (double *)malloc((size_t)d * sizeof(double));
+    double *zp = (double *)malloc((size_t)d * sizeof(double));
+    double *zh = (double *)malloc((size_t)d * sizeof(double));
+    memcpy(zp, z, (size_t)d * sizeof(double));
+    memcpy(zh, z, (size_t)d * sizeof(double));
+    double alpha = 1.0, c_prev = INFINITY;
+
+    int flags = OR_MAXITER;
+    for (int64_t t = 1; t <= max_iter; ++t) {
+        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            const double *yk = yh + k * d;
+            double *xk = x + k * d;
+            for (int64_t j = 0; j < d; ++j) v[j] = zh[j] - yk[j] / mu;
+            oracle_prox(d, v, a + k * d, w[k] / mu, xk);
+            for (int64_t j = 0; j < d; ++j) r[j] += xk[j] + yk[j] / mu;
+        }
+        double sd = 0.0, sh = 0.0, sp = 0.0;
+        for (int64_t j = 0; j < d; ++j) {
+            double zn = clamp_box(r[j] / (double)n, lo[j], hi[j]);
+            double e = zn - z[j];
+            sd += e * e;
+            double eh = zn - zh[j];
+            sh += eh * eh;
+            zp[j] = z[j];          /* previous iterate */
+            z[j] = zn;
+        }
+        for (int64_t i = 0; i < n * d; ++i) {
+            yp[i] = y[i];
+            y[i] = yh[i] + mu * (x[i] - z[i % d]);
+            double e = x[i] - z[i % d];
+            sp += e * e;
+        }
+        *r_pri = sqrt(sp / (double)(n * d));
+        *r_dual = sqrt(sd / (double)d);
+        *iters = t;
+        if (tol > 0.0 && *r_pri <= tol * D && *r_dual <= tol * D) {
+            flags = OR_CONVERGED;
+            break;
+        }
+        double c = mu * (sp + (double)n * sh);
+        if (c < eta * c_prev) {
+            double alpha_n = 0.5 * (1.0 + sqrt(1.0 + 4.0 * alpha * alpha));
+            double beta = (alpha - 1.0) / alpha_n;
+            for (int64_t j = 0; j < d; ++j) zh[j] = z[j] + beta * (z[j] - zp[j]);
+            for (int64_t i = 0; i < n * d; ++i) yh[i] = y[i] + beta * (y[i] - yp[i]);
+            alpha = alpha_n;
+            c_prev = c;
+        } else {
+            for (int64_t j = 0; j < d; ++j) zh[j] = zp[j];
+            for (int64_t i = 0; i < n * d; ++i) yh[i] = yp[i];
+            alpha = 1.0;
+            c_prev = c_prev / eta;
+            if (restarts) ++*restarts;
+        }
+    }
+    free(y);
+    free(yp);
+    free(yh);
+    free(x);
+    free(v);
+    free(r);
+    free(zp);
+    free(zh);
+    return flags;
+}
+
+/*
  * Objective of (EM) at z: sum_k w_k ||z - a_k||_2.
  */
 double oracle_em_objective(int64_t n, int64_t d, const double *a, const double *w, const double *z)
@@ -385,7 +501,8 @@ int oracle_max_threads(void)
  * MAXW starts from the point of largest weight (lowest index on ties).
  * max_iter_each (nullable) overrides max_iter per instance.
  * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
- * on the surrogate with eps.  box_lo / box_hi (nullable, float32, indexed like
+ * on the surrogate with eps, 3 = accelerated ADMM with restart parameter eta.
+ * box_lo / box_hi (nullable, float32, indexed like
  * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
  * mu_out (nullable): the final penalty per instance.
  */
@@ -395,7 +512,8 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
                        const float *box_lo, const float *box_hi, int64_t max_iter,
                        const int32_t *max_iter_each, double tol, int init, int64_t adapt_every,
                        double adapt_ratio, double adapt_factor, double *z, int32_t *iters,
-                       int32_t *flags, double *r_pri, double *r_dual, double *mu_out, int nthreads)
+                       int32_t *flags, double *r_pri, double *r_dual, double *mu_out, double eta,
+                       int nthreads)
 {
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -421,10 +539,14 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         int64_t it = 0;
         double rp = 0.0, rd = 0.0, mf = mu;
         int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
-        int f = (solver == 1)
-                    ? oracle_irls_solve_ex(n, d, ab, wb, eps, lv, hv, zb, mi, tol, &it, &rp, &rd)
-                    : oracle_em_solve_ex(n, d, ab, wb, mu, lv, hv, zb, NULL, NULL, mi, tol, adapt_every,
-                                         adapt_ratio, adapt_factor, &it, &rp, &rd, &mf);
+        int f;
+        if (solver == 1)
+            f = oracle_irls_solve_ex(n, d, ab, wb, eps, lv, hv, zb, mi, tol, &it, &rp, &rd);
+        else if (solver == 3)
+            f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, NULL);
+        else
+            f = oracle_em_solve_ex(n, d, ab, wb, mu, lv, hv, zb, NULL, NULL, mi, tol, adapt_every,
+                                   adapt_ratio, adapt_factor, &it, &rp, &rd, &mf);
         if (iters) iters[b] = (int32_t)it;
         if (flags) flags[b] = f;
         if (r_pri) r_pri[b] = rp;
@@ -448,7 +570,7 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
 {
     return oracle_em_batch_ex(B, a, w, a_off, w_off, z_off, n_arr, d_arr, 0, mu, 1.0, lo, hi, NULL,
                               NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z, iters, flags,
-                              r_pri, r_dual, NULL, nthreads);
+                              r_pri, r_dual, NULL, 0.999, nthreads);
 }
 
 /* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */

@@ -172,3 +172,54 @@ def test_batch_ex_matches_single_solves(orc):
                 assert res["mu"][i] == ref["mu"]
             np.testing.assert_array_equal(res["z"][e["z_off"]:e["z_off"] + d], ref["z"])
             assert res["iters"][i] == ref["iters"] and res["flags"][i] == ref["flags"]
+
+
+# ---- accelerated ADMM (fast ADMM with restart) ------------------------------
+
+def test_fast_admm_first_two_iterations_are_plain_admm(orc):
+    """alpha starts at 1, so the first momentum weight (alpha - 1)/alpha' is 0:
+    iterations 1 and 2 equal Algorithm 1 exactly; the third differs."""
+    rng = np.random.default_rng(80)
+    a = rng.normal(size=(40, 6)) * 2
+    w = rng.uniform(0.2, 1.0, size=40)
+    for T in (1, 2):
+        f = orc.em_solve(a, w, 0.7, -1.0, 1.5, a[2], max_iter=T)
+        g = orc.em_solve_fast(a, w, 0.7, -1.0, 1.5, a[2], max_iter=T)
+        np.testing.assert_array_equal(f["z"], g["z"])
+        assert f["r_pri"] == g["r_pri"] and f["r_dual"] == g["r_dual"]
+    f = orc.em_solve(a, w, 0.7, -1.0, 1.5, a[2], max_iter=3)
+    g = orc.em_solve_fast(a, w, 0.7, -1.0, 1.5, a[2], max_iter=3)
+    assert np.max(np.abs(f["z"] - g["z"])) > 1e-9
+
+
+def test_fast_admm_reaches_the_minimiser(orc):
+    """Same (unique) minimiser as Algorithm 1, with its box certificate, for
+    penalties over four decades (restarts happen on some)."""
+    rng = np.random.default_rng(81)
+    restarts = 0
+    for _ in range(6):
+        n, d = int(rng.integers(5, 80)), int(rng.integers(2, 12))
+        a = rng.normal(size=(n, d)) * 2
+        w = rng.uniform(0.1, 1.0, size=n)
+        lo = rng.uniform(-1.5, -0.2, size=d)
+        hi = lo + rng.uniform(0.5, 2.5, size=d)
+        ref = orc.em_solve(a, w, 0.5, lo, hi, a[0], max_iter=200000, tol=1e-13)
+        for mu in (1e-2, 0.5, 10.0):
+            g = orc.em_solve_fast(a, w, mu, lo, hi, a[0], max_iter=200000, tol=1e-13)
+            assert g["flags"] == orc.CONVERGED
+            np.testing.assert_allclose(g["z"], ref["z"], atol=1e-7)
+            assert _certificate(a, w, g["z"], lo, hi, 1e-5)
+            restarts += g["restarts"]
+    assert restarts > 0
+
+
+def test_fast_admm_fewer_iterations_with_a_large_penalty(orc):
+    """The reason for acceleration: with a penalty too large for the data the
+    plain iteration is slow, the accelerated one several times faster."""
+    rng = np.random.default_rng(82)
+    a = rng.normal(size=(200, 16)) * 2
+    w = rng.uniform(0.2, 1.0, size=200)
+    f = orc.em_solve(a, w, 10.0, -3.0, 3.0, a[0], max_iter=5000, tol=1e-6)
+    g = orc.em_solve_fast(a, w, 10.0, -3.0, 3.0, a[0], max_iter=5000, tol=1e-6)
+    assert f["flags"] == g["flags"] == orc.CONVERGED
+    assert g["iters"] * 4 < f["iters"]
