@@ -140,7 +140,8 @@ em_status_t em_solve_batch(em_handle_t handle, void *stream, int64_t B,
 typedef enum {
     EM_SOLVER_ADMM = 0,          /* Algorithm 1, fixed penalty rho (as em_solve_batch) */
     EM_SOLVER_IRLS = 1,          /* IRLS on the smooth surrogate (EM_surrogate), parameter eps */
-    EM_SOLVER_ADMM_ADAPTIVE = 2  /* Algorithm 1 with the penalty adapted by residual balancing */
+    EM_SOLVER_ADMM_ADAPTIVE = 2, /* Algorithm 1 with the penalty adapted by residual balancing */
+    EM_SOLVER_ADMM_FAST = 3      /* accelerated ADMM with restart (em_solve_plain_ex only) */
 } em_solver_t;
 
 /* Options of em_solve_batch_ex (host memory; the box arrays are device memory). */
@@ -157,6 +158,7 @@ typedef struct {
     int32_t adapt_every;   /* ADAPTIVE: balance after every adapt_every-th iteration (>= 1) */
     float adapt_ratio;     /* ADAPTIVE: imbalance ratio that triggers a change (> 1, e.g. 10) */
     float adapt_factor;    /* ADAPTIVE: factor applied to rho (> 1, e.g. 2) */
+    float fast_eta;        /* FAST: restart parameter eta in (0, 1) (0.999 in the reference) */
 } em_options_t;
 
 /*
@@ -184,11 +186,36 @@ typedef struct {
  * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
  * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1
  * for ADAPTIVE, one of box_lo / box_hi NULL, and em_solve_batch's errors);
- * HIP.
+ * UNSUPPORTED for EM_SOLVER_ADMM_FAST (see em_solve_plain_ex); HIP.
  */
 em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
                               const float *a, const float *w, const em_instance_t *inst,
                               const em_options_t *opt, float *z, em_stats_t *stats);
+
+/*
+ * em_solve_plain_ex - the one-launch-per-instance path with options: solver
+ * EM_SOLVER_ADMM (as em_solve_plain, with the general box) or
+ * EM_SOLVER_ADMM_FAST, the accelerated ADMM the conclusion names
+ * ([Goldstein2012], fast ADMM with restart for weakly convex problems) on the
+ * same splitting, with predictors z_hat, y_hat (starting at z0 and 0):
+ *   x_k = prox at z_hat - y_hat_k / rho, z = P_C(mean_k(x_k + y_hat_k / rho)),
+ *   y_k = y_hat_k + rho (x_k - z),
+ *   c = rho (sum_k ||x_k - z||^2 + n ||z - z_hat||^2);
+ *   c < fast_eta c_prev: alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2, beta =
+ *     (alpha - 1) / alpha', z_hat = z + beta (z - z_prev),
+ *     y_hat = y + beta (y - y_prev);
+ *   otherwise restart: z_hat = z_prev, y_hat = y_prev, alpha = 1,
+ *     c_prev = c_prev / fast_eta
+ * (alpha = 1 and c_prev = +inf at the start).  Residuals and stopping as for
+ * em_solve_batch, evaluated every iteration.  Its momentum needs the previous
+ * multipliers, a second n x d state, which this path keeps in device memory.
+ * Other solvers return EM_ERR_UNSUPPORTED; arguments and errors otherwise as
+ * em_solve_plain and em_solve_batch_ex (fast_eta must be in (0, 1)).
+ */
+em_status_t em_solve_plain_ex(em_handle_t handle, void *stream, int64_t B,
+                              const float *a, const float *w, const em_instance_t *inst,
+                              const em_instance_t *inst_host, const em_options_t *opt, float *z,
+                              em_stats_t *stats);
 
 /*
  * em_solve_plain - the same computation as em_solve_batch with one kernel

@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("EMX_LIBRARY") or os.path.join(HERE, "libemx.so")
 EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW = 0, 1
-SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE = 0, 1, 2
+SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST = 0, 1, 2, 3
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10
 
@@ -49,7 +49,8 @@ class EmOptions(C.Structure):
     _fields_ = [("solver", C.c_int32), ("init", C.c_int32), ("lo", C.c_float), ("hi", C.c_float),
                 ("box_lo", C.c_void_p), ("box_hi", C.c_void_p), ("rho", C.c_float),
                 ("eps", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_float),
-                ("adapt_every", C.c_int32), ("adapt_ratio", C.c_float), ("adapt_factor", C.c_float)]
+                ("adapt_every", C.c_int32), ("adapt_ratio", C.c_float), ("adapt_factor", C.c_float),
+                ("fast_eta", C.c_float)]
 
 
 _lib = None
@@ -75,6 +76,8 @@ def load_library():
         lib.em_solve_batch.restype = C.c_int
         lib.em_solve_batch_ex.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(EmOptions), vp, vp]
         lib.em_solve_batch_ex.restype = C.c_int
+        lib.em_solve_plain_ex.argtypes = [vp, vp, i64, vp, vp, vp, vp, C.POINTER(EmOptions), vp, vp]
+        lib.em_solve_plain_ex.restype = C.c_int
         lib.em_solve_plain.argtypes = [vp, vp, i64, vp, vp, vp, vp, f32, f32, f32, i32, f32, i32, vp, vp]
         lib.em_solve_plain.restype = C.c_int
         lib.nlem_denoise.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, f32, f32, i32, f32,
@@ -157,14 +160,24 @@ class Handle:
         and optional per-coordinate bounds box_lo / box_hi (float32 device
         tensors laid out like z)."""
         B = int(inst.numel() * inst.element_size() // 32)
-        opt = EmOptions(int(solver), int(init), float(lo), float(hi),
-                        None if box_lo is None else box_lo.data_ptr(),
-                        None if box_hi is None else box_hi.data_ptr(), float(rho), float(eps),
-                        int(max_iter), float(tol), int(adapt_every), float(adapt_ratio),
-                        float(adapt_factor))
+        opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every,
+                       adapt_ratio, adapt_factor, 0.999)
         st = self.lib.em_solve_batch_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
                                         C.byref(opt), _ptr(z), _ptr(stats))
         self._check(st, "em_solve_batch_ex")
+
+    def em_solve_plain_ex(self, a, w, inst, inst_host, z, stats=None, *, solver=SOLVER_ADMM,
+                          init=INIT_MAXW, lo=-float("inf"), hi=float("inf"), box_lo=None, box_hi=None,
+                          rho=1.0, max_iter=1000, tol=1e-4, eta=0.999, stream=None):
+        """em_solve_plain with options: solver SOLVER_ADMM or SOLVER_ADMM_FAST
+        (accelerated ADMM with restart parameter eta), optional per-coordinate
+        bounds."""
+        B = int(inst.numel() * inst.element_size() // 32)
+        hp = inst_host.ctypes.data if hasattr(inst_host, "ctypes") else inst_host.data_ptr()
+        opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, 1e-6, max_iter, tol, 1, 10.0, 2.0, eta)
+        st = self.lib.em_solve_plain_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
+                                        C.c_void_p(hp), C.byref(opt), _ptr(z), _ptr(stats))
+        self._check(st, "em_solve_plain_ex")
 
     def em_solve_plain(self, a, w, inst, inst_host, z, stats=None, *, lo, hi, rho, max_iter, tol,
                        init=INIT_MAXW, stream=None):
@@ -220,6 +233,15 @@ class Handle:
 
     def sync(self, stream=None):
         self._check(self.lib.em_sync(self.h, _stream(stream)), "em_sync")
+
+
+def _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every, adapt_ratio,
+             adapt_factor, eta):
+    return EmOptions(int(solver), int(init), float(lo), float(hi),
+                     None if box_lo is None else box_lo.data_ptr(),
+                     None if box_hi is None else box_hi.data_ptr(), float(rho), float(eps),
+                     int(max_iter), float(tol), int(adapt_every), float(adapt_ratio),
+                     float(adapt_factor), float(eta))
 
 
 def _image_array(items):

@@ -121,25 +121,53 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
 
 // ------------------------------------------------------------------ plain
 
-// One instance per launch, literal Algorithm 1 with the iterates in device
-// memory: thread per point for the prox, thread per coordinate for the
-// z-update, thread per point for the multiplier update, residuals every
-// iteration.  The simple baseline for the batched solver.
+// One instance per launch with the iterates in device memory: the simple
+// baseline for the batched solver, and the home of the accelerated variant
+// (its momentum needs the previous multipliers, a second n x d state).
+//   FAST = false: literal Algorithm 1 (thread per point for the prox and the
+//     multiplier update, thread per coordinate for the mean), residuals
+//     every iteration.
+//   FAST = true: fast ADMM with restart ([Goldstein2012], weakly convex
+//     case) on the same splitting: the prox and the mean use the predictors
+//     z_hat, u_hat; after the update, c = mu (sum_k ||x_k - z||^2 +
+//     n ||z - z_hat||^2) decides between momentum
+//     (z_hat = z + beta (z - z_prev), u_hat = u + beta (u - u_prev),
+//     beta = (alpha - 1) / alpha', alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2) and
+//     a restart (z_hat = z_prev, u_hat = u_prev, alpha = 1, c_prev /= eta).
+//     u = y / mu throughout (mu is fixed).
 struct PlainArgs {
     const float *a;
     const float *w;
     const em_instance_t *inst;
     float *z;
     em_stats_t *stats;
-    float *u;  // n*d scaled multipliers y/mu
-    float *x;  // n*d local variables
-    float lo, hi, mu, tol;
+    const float *box_lo;  // per-coordinate bounds (indexed like z) or null
+    const float *box_hi;
+    float *u;   // n*d scaled multipliers y/mu
+    float *x;   // n*d local variables
+    float *up;  // FAST: n*d previous u
+    float *uh;  // FAST: n*d predictor u_hat
+    float lo, hi, mu, tol, eta;
     int32_t max_iter, init;
     int64_t b;
 };
 
+__device__ __forceinline__ float block_sum256(float v, float *red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (tid < s2) red[tid] += red[tid + s2];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
+template <bool FAST>
 __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
-    __shared__ float zs[EM_MAX_D], zprev[EM_MAX_D];
+    __shared__ float zs[EM_MAX_D], zprev[EM_MAX_D], zh[EM_MAX_D], blo[EM_MAX_D], bhi[EM_MAX_D];
     __shared__ float red[256];
     __shared__ int flag;
     __shared__ float amax_s;
@@ -169,6 +197,7 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
             if (!(Wt[k] >= 0.0f && Wt[k] <= FLT_MAX)) flag = 1;
     }
     __syncthreads();
+    float wmax = 0.0f;
     if (flag == 0 && tid == 0) {
         int best = 0;
         if (P.init == EM_INIT_MAXW)
@@ -176,8 +205,15 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
                 if (Wt[k] > Wt[best]) best = k;
         for (int j = 0; j < d; ++j) {
             zs[j] = (P.init == EM_INIT_MAXW) ? A[best * d + j] : Z[j];
-            if (!(fabsf(zs[j]) <= FLT_MAX)) flag = 1;
+            blo[j] = P.box_lo ? P.box_lo[e.z_off + j] : P.lo;
+            bhi[j] = P.box_lo ? P.box_hi[e.z_off + j] : P.hi;
+            if (!(fabsf(zs[j]) <= FLT_MAX) || !(blo[j] <= bhi[j])) flag = 1;
+            const float wj = bhi[j] - blo[j];
+            if (!(wj <= wmax)) wmax = wj;
+            zprev[j] = zs[j];
+            zh[j] = zs[j];
         }
+        red[0] = wmax;
     }
     __syncthreads();
     if (flag) {
@@ -188,60 +224,87 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
         }
         return;
     }
-    const float Dscale = (__builtin_isfinite(P.lo) && __builtin_isfinite(P.hi) && P.hi > P.lo)
-                             ? (P.hi - P.lo) : fmaxf(1.0f, amax_s);
-    const float tau = P.tol * Dscale;
-    for (int i = tid; i < n * d; i += 256) P.u[i] = 0.0f;
+    wmax = red[0];
     __syncthreads();
+    const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f) ? wmax : fmaxf(1.0f, amax_s);
+    const float tau = P.tol * Dscale;
+    for (int i = tid; i < n * d; i += 256) {
+        P.u[i] = 0.0f;
+        if constexpr (FAST) {
+            P.up[i] = 0.0f;
+            P.uh[i] = 0.0f;
+        }
+    }
+    __syncthreads();
+    const float *UH = FAST ? P.uh : P.u;   // the multipliers the prox and the mean use
+    const float *ZH = FAST ? zh : zs;
+    float alpha = 1.0f, c_prev = INFINITY;
     int iters = 0, flags = EM_MAXITER;
     float rpri = 0.0f, rdual = 0.0f;
     for (int t = 1; t <= P.max_iter; ++t) {
-        // x_k = prox_{w_k/mu}(z - u_k, a_k)
+        // x_k = prox_{w_k/mu}(z_hat - u_hat_k, a_k)
         for (int k = tid; k < n; k += 256) {
             const float lam = Wt[k] / P.mu;
             float nu2 = 0.0f;
             for (int j = 0; j < d; ++j) {
-                const float dl = zs[j] - P.u[k * d + j] - A[k * d + j];
+                const float dl = ZH[j] - UH[k * d + j] - A[k * d + j];
                 nu2 = fmaf(dl, dl, nu2);
             }
             const float nu = sqrtf(nu2);
             const float sh = (nu <= lam) ? 1.0f : lam / nu;
             for (int j = 0; j < d; ++j) {
-                const float v = zs[j] - P.u[k * d + j];
+                const float v = ZH[j] - UH[k * d + j];
                 P.x[k * d + j] = v - sh * (v - A[k * d + j]);
             }
         }
         __syncthreads();
-        // z = P_C(mean_k(x_k + u_k))
+        // z = P_C(mean_k(x_k + u_hat_k))
+        float sdl = 0.0f, shl = 0.0f;
         for (int j = tid; j < d; j += 256) {
             float r = 0.0f;
-            for (int k = 0; k < n; ++k) r += P.x[k * d + j] + P.u[k * d + j];
+            for (int k = 0; k < n; ++k) r += P.x[k * d + j] + UH[k * d + j];
+            const float zn = clampf(r / (float)n, blo[j], bhi[j]);
+            sdl = fmaf(zn - zs[j], zn - zs[j], sdl);
+            shl = fmaf(zn - ZH[j], zn - ZH[j], shl);
             zprev[j] = zs[j];
-            zs[j] = clampf(r / (float)n, P.lo, P.hi);
+            zs[j] = zn;
         }
         __syncthreads();
-        // u_k += x_k - z, primal residual
+        // u_k = u_hat_k + x_k - z, primal residual
         float rp = 0.0f;
         for (int i = tid; i < n * d; i += 256) {
             const float dlt = P.x[i] - zs[i % d];
-            P.u[i] += dlt;
+            const float un = UH[i] + dlt;
+            if constexpr (FAST) P.up[i] = P.u[i];
+            P.u[i] = un;
             rp = fmaf(dlt, dlt, rp);
         }
-        red[tid] = rp;
-        __syncthreads();
-        for (int s2 = 128; s2 > 0; s2 >>= 1) {
-            if (tid < s2) red[tid] += red[tid + s2];
-            __syncthreads();
-        }
-        float rd = 0.0f;
-        for (int j = 0; j < d; ++j) rd += (zs[j] - zprev[j]) * (zs[j] - zprev[j]);
-        rpri = sqrtf(red[0] / ((float)n * (float)d));
-        rdual = sqrtf(rd / (float)d);
+        const float sp = block_sum256(rp, red);
+        const float sd = block_sum256(sdl, red);
+        rpri = sqrtf(sp / ((float)n * (float)d));
+        rdual = sqrtf(sd / (float)d);
         iters = t;
-        __syncthreads();
         if (tau > 0.0f && rpri <= tau && rdual <= tau) {
             flags = EM_CONVERGED;
             break;
+        }
+        if constexpr (FAST) {
+            const float sh2 = block_sum256(shl, red);
+            const float c = P.mu * (sp + (float)n * sh2);
+            if (c < P.eta * c_prev) {
+                const float an = 0.5f * (1.0f + sqrtf(1.0f + 4.0f * alpha * alpha));
+                const float beta = (alpha - 1.0f) / an;
+                for (int j = tid; j < d; j += 256) zh[j] = zs[j] + beta * (zs[j] - zprev[j]);
+                for (int i = tid; i < n * d; i += 256) P.uh[i] = P.u[i] + beta * (P.u[i] - P.up[i]);
+                alpha = an;
+                c_prev = c;
+            } else {
+                for (int j = tid; j < d; j += 256) zh[j] = zprev[j];
+                for (int i = tid; i < n * d; i += 256) P.uh[i] = P.up[i];
+                alpha = 1.0f;
+                c_prev = c_prev / P.eta;
+            }
+            __syncthreads();
         }
     }
     if (tid < d) Z[tid] = zs[tid];
@@ -249,33 +312,44 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
 }
 
 em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
-                        const em_instance_t *inst, const em_instance_t *inst_host, float lo, float hi,
-                        float rho, int32_t max_iter, float tol, int32_t init, float *z, em_stats_t *stats) {
+                        const em_instance_t *inst, const em_instance_t *inst_host, const em_options_t &o,
+                        float *z, em_stats_t *stats) {
+    const bool fast = o.solver == EM_SOLVER_ADMM_FAST;
     int64_t maxnd = 1;
     for (int64_t b = 0; b < B; ++b) {
         const int64_t n = inst_host[b].n, d = inst_host[b].d;
         if (n > 0 && n <= EM_MAX_N && d >= 1 && d <= EM_MAX_D) maxnd = std::max(maxnd, n * d);
     }
     em_status_t st;
-    float *ws = static_cast<float *>(ctx_plain_workspace(ctx, (size_t)(2 * maxnd) * sizeof(float), &st));
+    const int64_t arrays = fast ? 4 : 2;
+    float *ws = static_cast<float *>(ctx_plain_workspace(ctx, (size_t)(arrays * maxnd) * sizeof(float), &st));
     if (!ws) return st;
     PlainArgs P;
+    memset(&P, 0, sizeof(P));
     P.a = a;
     P.w = w;
     P.inst = inst;
     P.z = z;
     P.stats = stats;
+    P.box_lo = o.box_lo;
+    P.box_hi = o.box_hi;
     P.u = ws;
     P.x = ws + maxnd;
-    P.lo = lo;
-    P.hi = hi;
-    P.mu = rho;
-    P.tol = tol;
-    P.max_iter = max_iter;
-    P.init = init;
+    P.up = fast ? ws + 2 * maxnd : nullptr;
+    P.uh = fast ? ws + 3 * maxnd : nullptr;
+    P.lo = o.lo;
+    P.hi = o.hi;
+    P.mu = o.rho;
+    P.tol = o.tol;
+    P.eta = o.fast_eta;
+    P.max_iter = o.max_iter;
+    P.init = o.init;
     for (int64_t b = 0; b < B; ++b) {
         P.b = b;
-        hipLaunchKernelGGL(plain_solve_kernel, dim3(1), dim3(256), 0, s, P);
+        if (fast)
+            hipLaunchKernelGGL(plain_solve_kernel<true>, dim3(1), dim3(256), 0, s, P);
+        else
+            hipLaunchKernelGGL(plain_solve_kernel<false>, dim3(1), dim3(256), 0, s, P);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "plain launch");

@@ -22,8 +22,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t stream, int64_t B, const fl
                         em_stats_t *stats);
 em_status_t plain_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
                         const float *w, const em_instance_t *inst, const em_instance_t *inst_host,
-                        float lo, float hi, float rho, int32_t max_iter, float tol, int32_t init,
-                        float *z, em_stats_t *stats);
+                        const em_options_t &o, float *z, em_stats_t *stats);
 
 __global__ void reset_counters_kernel(unsigned int *c, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -543,6 +542,8 @@ extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B,
     if (!h) return EM_ERR_INVALID_ARG;
     if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
     const em_options_t &o = *opt;
+    if (o.solver == EM_SOLVER_ADMM_FAST)
+        return fail(h, EM_ERR_UNSUPPORTED, "accelerated ADMM runs in em_solve_plain_ex");
     if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_IRLS && o.solver != EM_SOLVER_ADMM_ADAPTIVE)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");
     if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
@@ -573,6 +574,37 @@ extern "C" em_status_t em_solve_plain(em_handle_t h, void *stream, int64_t B, co
     if (B > 0 && !inst_host) return fail(h, EM_ERR_INVALID_ARG, "inst_host is required");
     if (B == 0) return EM_OK;
     EMX_HIP(h, hipSetDevice(h->device));
-    return plain_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, inst_host, lo, hi, rho,
-                       max_iter, tol, init, z, stats);
+    em_options_t o{};
+    o.solver = EM_SOLVER_ADMM;
+    o.init = init;
+    o.lo = lo;
+    o.hi = hi;
+    o.rho = rho;
+    o.max_iter = max_iter;
+    o.tol = tol;
+    return plain_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, inst_host, o, z, stats);
+}
+
+extern "C" em_status_t em_solve_plain_ex(em_handle_t h, void *stream, int64_t B, const float *a,
+                                         const float *w, const em_instance_t *inst,
+                                         const em_instance_t *inst_host, const em_options_t *opt,
+                                         float *z, em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
+    const em_options_t &o = *opt;
+    if (o.solver == EM_SOLVER_IRLS || o.solver == EM_SOLVER_ADMM_ADAPTIVE)
+        return fail(h, EM_ERR_UNSUPPORTED, "this solver runs in em_solve_batch_ex");
+    if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_ADMM_FAST)
+        return fail(h, EM_ERR_INVALID_ARG, "bad solver");
+    if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
+        return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");
+    if (o.solver == EM_SOLVER_ADMM_FAST && !(o.fast_eta > 0.0f && o.fast_eta < 1.0f))
+        return fail(h, EM_ERR_INVALID_ARG, "fast_eta must be in (0, 1)");
+    const float lo = o.box_lo ? 0.0f : o.lo, hi = o.box_lo ? 0.0f : o.hi;
+    em_status_t st = check_batch_args(h, B, a, w, inst, z, lo, hi, o.rho, o.max_iter, o.tol, o.init);
+    if (st != EM_OK) return st;
+    if (B > 0 && !inst_host) return fail(h, EM_ERR_INVALID_ARG, "inst_host is required");
+    if (B == 0) return EM_OK;
+    EMX_HIP(h, hipSetDevice(h->device));
+    return plain_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, inst_host, o, z, stats);
 }

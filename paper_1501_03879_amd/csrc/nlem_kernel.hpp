@@ -104,12 +104,6 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     // points stay in registers when they fit (the compiler hoists the tile
     // reads); IRLS never changes g = -a, so it always keeps them
     constexpr bool kKeep = IRLS || M * NJ <= kKeepPointsInRegs;
-    // software prefetch of the next coordinate's points (off when occupancy
-    // is the tighter constraint)
-#ifndef EMX_PREFETCH
-#define EMX_PREFETCH 1
-#endif
-    constexpr bool PF = EMX_PREFETCH != 0;
     // tile offset of slice coordinate jj within a patch (folded after unrolling)
     auto poff = [](int jj) { return ((J0 + jj) / S::PS) * S::P + ((J0 + jj) % S::PS); };
 
@@ -173,6 +167,38 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         }
         // tile offset of point slot q (its patch's top-left corner)
         auto pbase = [&](int q) { return S::ROWMAP ? base[0] + q : base[q]; };
+        // Stream of the values -a of slice coordinates jj = 0, 1, ... for the
+        // lane's M points, loaded one coordinate ahead.  With the row mapping
+        // the lane's points are consecutive window columns, so coordinate
+        // (r, c + 1) of point q is coordinate (r, c) of point q + 1: moving
+        // along a patch row loads one new value, a new row loads M.
+        auto same_row = [](int jj) { return (J0 + jj) / S::PS == (J0 + jj + 1) / S::PS; };
+        auto st_begin = [&](float (&win)[M]) {
+#pragma unroll
+            for (int q = 0; q < M; ++q) win[q] = -tile[pbase(q) + poff(0)];
+        };
+        auto st_prefetch = [&](int jj, float (&nx)[M]) {
+            if (jj + 1 < NJ) {
+                if (S::ROWMAP && same_row(jj)) {
+                    nx[M - 1] = -tile[pbase(M - 1) + poff(jj + 1)];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < M; ++q) nx[q] = -tile[pbase(q) + poff(jj + 1)];
+                }
+            }
+        };
+        auto st_advance = [&](int jj, float (&win)[M], const float (&nx)[M]) {
+            if (jj + 1 < NJ) {
+                if (S::ROWMAP && same_row(jj)) {
+#pragma unroll
+                    for (int q = 0; q + 1 < M; ++q) win[q] = win[q + 1];
+                    win[M - 1] = nx[M - 1];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < M; ++q) win[q] = nx[q];
+                }
+            }
+        };
 
         // ---- a3: z = P_i (unprojected), u = 0  (so g = -a, c = z).  Lanes
         // without a coordinate hold z = clamp(0) and E = 0, a fixed point of
@@ -286,7 +312,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         int iters = 0, flags = EM_MAXITER;
         float rp2 = 0.0f, rd2 = 0.0f;  // mean squares of the last evaluated iteration
         float rd_w = 0.0f, rp_w = 0.0f;
-        bool armed_last = false, done = false;
+        bool done = false;
         int t = 1;
         if constexpr (IRLS) {
             const float eps = L.eps;
@@ -370,45 +396,19 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
                 }
             }
-            float rd_all = rd_w, rp_all = rp_w;
+            float rd_all = rd_w;
             if constexpr (WC > 1) {
-                float *X = xn + (t & 1) * WC * M * 64;
                 float *XS = xs + (t & 1) * WC * 4;
+                if (lane == 0) XS[SW * 4] = rd_w;
+                exchange(nrm, xn + (t & 1) * WC * M * 64);
+                rd_all = XS[0];
 #pragma unroll
-                for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = nrm[q];
-                if (lane == 0) {
-                    XS[SW * 4 + 0] = rd_w;
-                    XS[SW * 4 + 1] = rp_w;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < M; ++q) {
-                    float sum = X[q * 64 + lane];
-#pragma unroll
-                    for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
-                    nrm[q] = sum;
-                }
-                rd_all = 0.0f;
-                rp_all = 0.0f;
-#pragma unroll
-                for (int w = 0; w < WC; ++w) {
-                    rd_all += XS[w * 4 + 0];
-                    rp_all += XS[w * 4 + 1];
-                }
+                for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
                 rd_all = readfirstlane(rd_all);
-                rp_all = readfirstlane(rp_all);
             }
-            // ---- a8: stop test for iteration t-1 (all waves hold identical sums)
-            if (t > 1) {
-                rd2 = rd_all * inv_d;
-                rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
-                if (uniform(tau2 > 0.0f && armed_last && rp2 <= tau2 && rd2 <= tau2)) {
-                    flags = EM_CONVERGED;
-                    iters = t - 1;
-                    done = true;
-                    break;
-                }
-            }
+            // dual residual of iteration t-1 (all waves hold identical sums),
+            // which arms the primal residual of this iteration
+            if (t > 1) rd2 = rd_all * inv_d;
             // ---- a2: NLM weights from the first iteration's distances (the
             // noisy start: delta = P_i - P_j), unless the pre-pass made them
             if (t == 1 && !pre) {
@@ -432,31 +432,18 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 float rq[M];
 #pragma unroll
                 for (int q = 0; q < M; ++q) rq[q] = 0.0f;
-                float na[M];
-                if constexpr (PF) {
-#pragma unroll
-                    for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(0)];
-                }
+                float win[M], nx[M];
+                st_begin(win);
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) {
                     const float cj = cv[jj];
-                    float cur[M];
-                    if constexpr (PF) {
-#pragma unroll
-                        for (int q = 0; q < M; ++q) cur[q] = na[q];
-                        if (jj + 1 < NJ) {
-#pragma unroll
-                            for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(jj + 1)];
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < M; ++q) cur[q] = -tile[pbase(q) + poff(jj)];
-                    }
+                    st_prefetch(jj, nx);
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
-                        const float y = fmaf(1.0f - s[q], g[q][jj], -(cur[q] + cj));
+                        const float y = fmaf(1.0f - s[q], g[q][jj], -(win[q] + cj));
                         rq[q] = fmaf(y, y, rq[q]);
                     }
+                    st_advance(jj, win, nx);
                     if constexpr (!kKeep) __builtin_amdgcn_sched_barrier(0);
                 }
                 // Absent window slots need no mask: their s is 0 and their state
@@ -468,36 +455,23 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             if constexpr (!kKeep) asm volatile("" ::: "memory");
 
             // ---- a4 (second half) + a5 partial sums: E = sum_k s delta, g = s delta - a
-            // (tile reads pipelined one coordinate ahead unless PF = 0)
+            // (tile reads streamed one coordinate ahead)
             float acc[NJ];
             {
-                float na[M];
-                if constexpr (PF) {
-#pragma unroll
-                    for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(0)];
-                }
+                float win[M], nx[M];
+                st_begin(win);
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) {
-                    float cur[M];
-                    if constexpr (PF) {
-#pragma unroll
-                        for (int q = 0; q < M; ++q) cur[q] = na[q];
-                        if (jj + 1 < NJ) {
-#pragma unroll
-                            for (int q = 0; q < M; ++q) na[q] = -tile[pbase(q) + poff(jj + 1)];
-                        }
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < M; ++q) cur[q] = -tile[pbase(q) + poff(jj)];
-                    }
+                    st_prefetch(jj, nx);
                     float ac = 0.0f;
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
                         const float d = g[q][jj];
                         ac = fmaf(s[q], d, ac);
-                        g[q][jj] = fmaf(s[q], d, cur[q]);
+                        g[q][jj] = fmaf(s[q], d, win[q]);
                     }
                     acc[jj] = ac;
+                    st_advance(jj, win, nx);
                     if constexpr (!kKeep) __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -513,22 +487,48 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             const float dz = zn - zr;
             cv[cidx] = zn + dz;
             rd_w = readfirstlane(wave_sum(dz * dz));
-            if (armed) {
-                // sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
-                // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1}
-                const float cz = (2.0f * zr - zp) - zn;
-                const float rpx = cz * fmaf(fn, cz, 2.0f * (Ep - Ev));
-                rp_w = readfirstlane(wave_sum(rp_lane + rpx));
-            } else {
-                rp_w = 0.0f;
-            }
+            const float cz = (2.0f * zr - zp) - zn;
             zp = zr;
             zr = zn;
+            if (armed) {
+                // ---- a8: sum_k ||x_k - z'||^2 from the lane sums of ||x_k - c||^2:
+                // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1};
+                // the stop test is taken right away (one barrier for WC > 1)
+                const float rpx = cz * fmaf(fn, cz, 2.0f * (Ep - Ev));
+                rp_w = readfirstlane(wave_sum(rp_lane + rpx));
+                float rd_all = rd_w, rp_all = rp_w;
+                if constexpr (WC > 1) {
+                    float *XS = xs + 2 * WC * 4;   // its own slot: armed iterations only
+                    if (lane == 0) {
+                        XS[SW * 4 + 0] = rd_w;
+                        XS[SW * 4 + 1] = rp_w;
+                    }
+                    __syncthreads();
+                    rd_all = XS[0];
+                    rp_all = XS[1];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) {
+                        rd_all += XS[w * 4 + 0];
+                        rp_all += XS[w * 4 + 1];
+                    }
+                    rd_all = readfirstlane(rd_all);
+                    rp_all = readfirstlane(rp_all);
+                }
+                rd2 = rd_all * inv_d;
+                rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
+                if (uniform(tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2)) {
+                    flags = EM_CONVERGED;
+                    iters = t;
+                    done = true;
+                    break;
+                }
+            }
             Ep = Ev;
-            armed_last = armed;
         }
 
-        if (!done && !bad) {
+        if (!IRLS && !done && !bad) {
+            iters = max_iter;   // the last iteration was armed and tested
+        } else if (!done && !bad) {
             iters = max_iter;
             if (max_iter >= 1) {
                 float rd_all = rd_w, rp_all = rp_w;
@@ -550,8 +550,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     rp_all = readfirstlane(rp_all);
                 }
                 rd2 = rd_all * inv_d;
-                rp2 = IRLS ? 0.0f : fmaxf(rp_all, 0.0f) * inv_nd;
-                flags = (tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
+                rp2 = 0.0f;
+                flags = (tau2 > 0.0f && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
             }
         }
         if (bad) {
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(64 * WC, EMX_NLEM_MIN_WAVES) void nlem_solve_kernel
     using S = NlemShape<PR, M, WC>;
     __shared__ float tile[S::TILE];
     __shared__ float xn[S::XN];
-    __shared__ float xs[2 * WC * 4];
+    __shared__ float xs[3 * WC * 4];
     __shared__ float cvec[WC * 128];
     __shared__ unsigned int item_s;
     const int wave = uniform_int(threadIdx.x >> 6);

@@ -144,3 +144,26 @@ def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo
     return (z.cpu().numpy().astype(np.float64),
             dict(iters=it.cpu().numpy()[:batch.B], flags=fl.cpu().numpy()[:batch.B],
                  r_pri=rp.cpu().numpy()[:batch.B], r_dual=rd.cpu().numpy()[:batch.B]))
+
+
+def run_plain_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eta=0.999, box_lo=None, box_hi=None):
+    """em_solve_plain_ex on the GPU for a synth.PointSetBatch."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    a = torch.from_numpy(np.ascontiguousarray(batch.a, dtype=np.float32)).to(dev)
+    w = torch.from_numpy(np.ascontiguousarray(batch.w, dtype=np.float32)).to(dev)
+    inst = emx.instances_tensor(batch.inst, dev)
+    z = torch.zeros(max(batch.z_size, 1), dtype=torch.float32, device=dev)
+    bl = None if box_lo is None else torch.from_numpy(np.ascontiguousarray(box_lo, np.float32)).to(dev)
+    bh = None if box_hi is None else torch.from_numpy(np.ascontiguousarray(box_hi, np.float32)).to(dev)
+    stats = torch.zeros((max(batch.B, 1), 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    hd.em_solve_plain_ex(a, w, inst, np.ascontiguousarray(batch.inst), z, stats, solver=solver, init=init,
+                         lo=batch.lo, hi=batch.hi, box_lo=bl, box_hi=bh, rho=mu, max_iter=max_iter,
+                         tol=tol, eta=eta)
+    hd.sync()
+    it, fl, rp, rd = emx.stats_view(stats)
+    return (z.cpu().numpy().astype(np.float64),
+            dict(iters=it.cpu().numpy()[:batch.B], flags=fl.cpu().numpy()[:batch.B],
+                 r_pri=rp.cpu().numpy()[:batch.B], r_dual=rd.cpu().numpy()[:batch.B]))

@@ -31,7 +31,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("em_create", "em_destroy", "em_solve_batch", "em_solve_plain", "nlem_denoise",
-                 "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_solve_batch_ex", "em_sync",
+                 "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_solve_batch_ex", "em_solve_plain_ex",
+                 "em_sync",
                  "em_status_string", "em_last_error"):
         assert must in names
 
@@ -48,7 +49,7 @@ def test_struct_sizes_match_the_header():
     assert INSTANCE_DTYPE.itemsize == 32                     # em_instance_t
     assert C.sizeof(emx.NlemImage) == 8 * 3 + 4 * 6          # nlem_image_t
     assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
-    assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8   # em_options_t (with padding)
+    assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8   # em_options_t
 
 
 def test_null_handle_is_rejected_without_device_work():
@@ -64,6 +65,8 @@ def test_null_handle_is_rejected_without_device_work():
     assert lib.nlem_denoise(None, None, None, 0, 8, 8, 1, 1, 1.0, 0, 255, 1e-3, 1, 0, None, None) == -1
     lib.em_solve_batch_ex.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp]
     assert lib.em_solve_batch_ex(None, None, 1, None, None, None, None, None, None) == -1
+    lib.em_solve_plain_ex.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+    assert lib.em_solve_plain_ex(None, None, 1, None, None, None, None, None, None, None) == -1
     lib.nlem_denoise_ex.argtypes = [vp, vp, C.c_int32, vp, vp]
     assert lib.nlem_denoise_ex(None, None, 0, None, None) == -1
     lib.nlm_denoise.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
