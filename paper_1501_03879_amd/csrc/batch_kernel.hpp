@@ -107,7 +107,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     __shared__ float xn[(WC > 1) ? (ADAPT ? 3 : 2) * S::XNB : 1];
     __shared__ float xe[(WP > 1) ? 2 * WP * WC * H2 * 4 : 1];
     __shared__ float xo[(WP > 1) ? 2 * WP : 1];
-    __shared__ float xs[2 * WC * WP * 4];
+    __shared__ float xs[3 * WC * WP * 4];   // third slot: the test after armed iterations
     __shared__ float Epv[WC * H2 * 4 * WP];
     __shared__ float Bv[WC * WP * 2 * H2 * 4];
     __shared__ float cvec[WC * WP * DS];
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             const int max_iter = L.max_iter;
             const int every = ADAPT ? L.adapt_every : 0;
             float rd_w = 0.0f, rp_w = 0.0f;
-            bool armed_last = false, done = false;
+            bool done = false;
             int t = 1;
             for (; t <= max_iter; ++t) {
                 // ---- pass 1: delta = g + c, partial ||delta||^2
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
                     }
                 }
-                float rd_all = rd_w, rp_all = rp_w;
+                float rd_all = rd_w;
                 if constexpr (WC > 1 || WP > 1) {
                     float *XS = xs + (t & 1) * WC * WP * 4;
                     if constexpr (WC > 1) {
@@ -473,10 +473,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
 #pragma unroll
                         for (int q = 0; q < M; ++q) X[((pw * WC + cw) * M + q) * 64 + lane] = nrm[q];
                     }
-                    if (lane == 0) {
-                        XS[wave * 4 + 0] = rd_w;
-                        XS[wave * 4 + 1] = rp_w;
-                    }
+                    if (lane == 0) XS[wave * 4] = rd_w;
                     __syncthreads();
                     if constexpr (WC > 1) {
                         float *X = xn + (t & 1) * S::XNB;
@@ -489,26 +486,13 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         }
                     }
                     rd_all = 0.0f;
-                    rp_all = 0.0f;
 #pragma unroll
-                    for (int v = 0; v < WC * WP; ++v) {
-                        rd_all += XS[v * 4 + 0];
-                        rp_all += XS[v * 4 + 1];
-                    }
+                    for (int v = 0; v < WC * WP; ++v) rd_all += XS[v * 4];
                     rd_all = readfirstlane(rd_all);
-                    rp_all = readfirstlane(rp_all);
                 }
-                // ---- stop test for iteration t-1 (all waves hold identical sums)
-                if (t > 1) {
-                    rd2 = rd_all * inv_d;
-                    rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
-                    if (uniform(tau2 > 0.0f && armed_last && rp2 <= tau2 && rd2 <= tau2)) {
-                        flags = EM_CONVERGED;
-                        iters = t - 1;
-                        done = true;
-                        break;
-                    }
-                }
+                // dual residual of iteration t-1 (all waves hold identical sums), which
+                // arms this iteration; the stop test itself follows armed iterations
+                if (t > 1) rd2 = rd_all * inv_d;
                 // ---- adaptive penalty after a balancing iteration t-1: compare
                 // ||r||^2 = n d rp2 with (ratio ||s||)^2 = ratio^2 mu^2 n d rd2
                 if (ADAPT && t > 1 && (t - 1) % every == 0) {
@@ -654,17 +638,10 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     const float px = readfirstlane((readlane(rpx, 0) + readlane(rpx, 16)) +
                                                    (readlane(rpx, 32) + readlane(rpx, 48)));
                     rp_w = tot + ((pw == 0) ? px : 0.0f);
-                } else {
-                    rp_w = 0.0f;
-                }
-                armed_last = armed;
-            }
-            if (!done) {
-                iters = max_iter;
-                if (max_iter >= 1) {
+                    // ---- stop test right after the armed iteration
                     float rd_all = rd_w, rp_all = rp_w;
                     if constexpr (WC > 1 || WP > 1) {
-                        float *XS = xs + (t & 1) * WC * WP * 4;
+                        float *XS = xs + 2 * WC * WP * 4;
                         if (lane == 0) {
                             XS[wave * 4 + 0] = rd_w;
                             XS[wave * 4 + 1] = rp_w;
@@ -682,9 +659,17 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     }
                     rd2 = rd_all * inv_d;
                     rp2 = fmaxf(rp_all, 0.0f) * inv_nd;
-                    flags = (tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2) ? EM_CONVERGED : EM_MAXITER;
+                    if (uniform(tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2)) {
+                        flags = EM_CONVERGED;
+                        iters = t;
+                        done = true;
+                        break;
+                    }
+                } else {
+                    rp_w = 0.0f;
                 }
             }
+            if (!done) iters = max_iter;   // the last iteration was armed and tested
         }
         // ---- write z (point-wave 0 of each coordinate slice) and stats
         if (pw == 0 && lane == 16 * row) {

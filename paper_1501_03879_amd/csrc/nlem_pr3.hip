@@ -41,9 +41,9 @@ NlemKernelInfo nlem_kernels_pr3(int m, int wc, int solver) {
             case 18: return info<3, 2, 2, 1>();
             case 26: return info<3, 3, 2, 1>();
             case 34: return info<3, 4, 2, 1>();
-            case 42: return info<3, 5, 2, 1>();
-            case 50: return info<3, 6, 2, 1>();
-            case 58: return info<3, 7, 2, 1>();
+            case 44: return info<3, 5, 4, 1>();
+            case 52: return info<3, 6, 4, 1>();
+            case 60: return info<3, 7, 4, 1>();
         }
     }
     return NlemKernelInfo{nullptr, 0};

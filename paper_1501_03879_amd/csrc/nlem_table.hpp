@@ -16,12 +16,13 @@ NlemKernelInfo nlem_kernels_pr2(int m, int wc, int solver);
 NlemKernelInfo nlem_kernels_pr3(int m, int wc, int solver);
 
 // Default coordinate-wave count per (patch radius, points per lane), from
-// timing the compiled candidates on MI355X (256x256 image, d = 49, n <= 441:
-// 2 waves 4.77 ms, 3 waves 6.31 ms, 4 waves 5.59 ms per image).
+// timing the compiled candidates on MI355X (256x256 image, d = 49, n <= 441,
+// tol 1e-4: 2 waves 3.09 ms, 3 waves 4.12 ms, 4 waves 3.02 ms per image;
+// a 3-wave workgroup leaves wave slots of a CU unused).
 inline int nlem_default_wc(int pr, int m) {
     if (pr <= 1) return 1;
     if (pr == 2) return (m <= 3) ? 1 : 2;
-    return 2;
+    return (m >= 5) ? 4 : 2;
 }
 
 inline NlemKernelInfo nlem_kernel(int pr, int m, int wc, int solver) {
