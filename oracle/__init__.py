@@ -65,8 +65,15 @@ def _load():
         lib.oracle_irls_solve_ex.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
                                              C.c_int64, C.c_double, i64p, dp, dp]
         lib.oracle_irls_solve_ex.restype = C.c_int
+        lib.oracle_em_solve_ball.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, C.c_double,
+                                             dp, dp, dp, C.c_int64, C.c_double, C.c_int64, C.c_double,
+                                             C.c_double, i64p, dp, dp, dp]
+        lib.oracle_em_solve_ball.restype = C.c_int
+        lib.oracle_irls_solve_ball.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, C.c_double,
+                                               dp, C.c_int64, C.c_double, i64p, dp, dp]
+        lib.oracle_irls_solve_ball.restype = C.c_int
         lib.oracle_em_batch_ex.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p, C.c_int,
-                                           C.c_double, C.c_double, C.c_double, C.c_double, fp, fp,
+                                           C.c_double, C.c_double, C.c_double, C.c_double, fp, fp, fp, fp,
                                            C.c_int64, i32p, C.c_double, C.c_int, C.c_int64,
                                            C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_double,
                                            C.c_int]
@@ -153,6 +160,51 @@ def em_solve(a, w, mu: float, lo, hi, z0, y0=None, max_iter: int = 100, tol: flo
                 mu=mf.value)
 
 
+def em_solve_ball(a, w, mu: float, center, radius: float, z0, max_iter: int = 100,
+                  tol: float = 0.0, adapt_every: int = 0, adapt_ratio: float = 10.0,
+                  adapt_factor: float = 2.0) -> dict:
+    """Algorithm 1 in FP64 over the ball ||z - center|| <= radius."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    cen = np.ascontiguousarray(np.broadcast_to(np.asarray(center, np.float64), (d,)), dtype=np.float64)
+    y = np.zeros((n, d))
+    x = np.zeros((n, d))
+    it = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    mf = C.c_double(0.0)
+    f = _load().oracle_em_solve_ball(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                     _p(cen, C.c_double), float(radius), _p(z, C.c_double),
+                                     _p(y, C.c_double), _p(x, C.c_double), int(max_iter), float(tol),
+                                     int(adapt_every), float(adapt_ratio), float(adapt_factor),
+                                     C.byref(it), C.byref(rp), C.byref(rd), C.byref(mf))
+    return dict(z=z, y=y, x=x, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f),
+                mu=mf.value)
+
+
+def irls_solve_ball(a, w, eps: float, center, radius: float, z0, max_iter: int = 100,
+                    tol: float = 0.0) -> dict:
+    """IRLS on the surrogate in FP64 over the ball ||z - center|| <= radius."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    cen = np.ascontiguousarray(np.broadcast_to(np.asarray(center, np.float64), (d,)), dtype=np.float64)
+    it = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    f = _load().oracle_irls_solve_ball(n, d, _p(a, C.c_double), _p(w, C.c_double), float(eps),
+                                       _p(cen, C.c_double), float(radius), _p(z, C.c_double),
+                                       int(max_iter), float(tol), C.byref(it), C.byref(rp), C.byref(rd))
+    return dict(z=z, iters=int(it.value), r_dual=rd.value, flags=int(f))
+
+
 def em_solve_fast(a, w, mu: float, lo, hi, z0, max_iter: int = 100, tol: float = 0.0,
                   eta: float = 0.999) -> dict:
     """Accelerated ADMM (fast ADMM with restart) in FP64 over the box [lo, hi];
@@ -180,13 +232,15 @@ def em_solve_fast(a, w, mu: float, lo, hi, z0, max_iter: int = 100, tol: float =
 def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW, z0=None,
              max_iter_each=None, nthreads: int = 0, solver: int = SOLVER_ADMM, eps: float = 1e-6,
              box_lo=None, box_hi=None, adapt_every: int = 0, adapt_ratio: float = 10.0,
-             adapt_factor: float = 2.0, eta: float = 0.999) -> dict:
+             adapt_factor: float = 2.0, eta: float = 0.999, ball_center=None,
+             ball_radius=None) -> dict:
     """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
     z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty),
     SOLVER_IRLS or SOLVER_FAST_ADMM (restart parameter eta); box_lo / box_hi:
-    optional float32 per-coordinate bounds
-    indexed like z.  Returns z (float64, concatenated), iters, flags,
-    residuals and the final penalties."""
+    optional float32 per-coordinate bounds indexed like z; ball_radius
+    (float32, one per instance) selects the ball constraint with centres
+    ball_center (float32 indexed like z, None = origin).  Returns z (float64,
+    concatenated), iters, flags, residuals and the final penalties."""
     inst = batch.inst
     B = int(inst.shape[0])
     a = np.ascontiguousarray(batch.a, dtype=np.float32)
@@ -199,6 +253,8 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     z = np.zeros(batch.z_size, dtype=np.float64) if z0 is None else np.array(z0, np.float64).copy()
     bl = None if box_lo is None else np.ascontiguousarray(box_lo, dtype=np.float32)
     bh = None if box_hi is None else np.ascontiguousarray(box_hi, dtype=np.float32)
+    bc = None if ball_center is None else np.ascontiguousarray(ball_center, dtype=np.float32)
+    br = None if ball_radius is None else np.ascontiguousarray(ball_radius, dtype=np.float32)
     iters = np.zeros(B, np.int32)
     flags = np.zeros(B, np.int32)
     rp = np.zeros(B)
@@ -208,7 +264,8 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     _load().oracle_em_batch_ex(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
                                _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
                                _p(d, C.c_int32), int(solver), float(mu), float(eps), float(batch.lo),
-                               float(batch.hi), _p(bl, C.c_float), _p(bh, C.c_float), int(max_iter),
+                               float(batch.hi), _p(bl, C.c_float), _p(bh, C.c_float),
+                               _p(bc, C.c_float), _p(br, C.c_float), int(max_iter),
                                _p(mie, C.c_int32), float(tol), int(init), int(adapt_every),
                                float(adapt_ratio), float(adapt_factor), _p(z, C.c_double),
                                _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),

@@ -64,17 +64,49 @@ static double clamp_box(double x, double lo, double hi)
 }
 
 /*
- * Scale D of the relative stopping tolerance: the largest box width
- * max_j (hi_j - lo_j) when it is finite and positive (hi - lo for a scalar
- * box), otherwise max(1, max_k ||a_k||_inf).
+ * The convex set C of (EM).  Section 3 uses a box; the general statement of
+ * (EM) allows any closed convex set, and the Euclidean ball
+ * {z : ||z - center|| <= radius} is the other set with a closed-form
+ * projection supported here: P(z) = center + (z - center) min(1, radius /
+ * ||z - center||).  center != NULL selects the ball.
  */
-static double tol_scale_box(int64_t n, int64_t d, const double *a, const double *lo,
-                            const double *hi)
+typedef struct {
+    const double *lo, *hi;   /* box bounds per coordinate */
+    const double *center;    /* ball centre (d values) or NULL */
+    double radius;           /* ball radius (>= 0, may be +inf) */
+} or_set_t;
+
+static void project_set(const or_set_t *C, int64_t d, const double *m, double *out)
+{
+    if (C->center) {
+        double q = 0.0;
+        for (int64_t j = 0; j < d; ++j) {
+            double t = m[j] - C->center[j];
+            q += t * t;
+        }
+        double nr = sqrt(q);
+        double f = (nr > C->radius) ? C->radius / nr : 1.0;
+        for (int64_t j = 0; j < d; ++j) out[j] = C->center[j] + (m[j] - C->center[j]) * f;
+    } else {
+        for (int64_t j = 0; j < d; ++j) out[j] = clamp_box(m[j], C->lo[j], C->hi[j]);
+    }
+}
+
+/*
+ * Scale D of the relative stopping tolerance: the largest box width
+ * max_j (hi_j - lo_j) (hi - lo for a scalar box), or the ball's diameter,
+ * when it is finite and positive; otherwise max(1, max_k ||a_k||_inf).
+ */
+static double tol_scale_set(int64_t n, int64_t d, const double *a, const or_set_t *C)
 {
     double wmax = 0.0;
-    for (int64_t j = 0; j < d; ++j) {
-        double wj = hi[j] - lo[j];
-        if (!(wj <= wmax)) wmax = wj;   /* also takes inf */
+    if (C->center) {
+        wmax = 2.0 * C->radius;
+    } else {
+        for (int64_t j = 0; j < d; ++j) {
+            double wj = C->hi[j] - C->lo[j];
+            if (!(wj <= wmax)) wmax = wj;   /* also takes inf */
+        }
     }
     if (isfinite(wmax) && wmax > 0.0) return wmax;
     double m = 1.0;
@@ -85,11 +117,18 @@ static double tol_scale_box(int64_t n, int64_t d, const double *a, const double 
     return m;
 }
 
-/* A box given per coordinate is valid when lo_j <= hi_j and neither is NaN. */
-static int box_ok(int64_t d, const double *lo, const double *hi)
+/* A box is valid when lo_j <= hi_j (no NaN); a ball when its centre is finite
+ * and its radius >= 0 (not NaN). */
+static int set_ok(int64_t d, const or_set_t *C)
 {
+    if (C->center) {
+        if (!(C->radius >= 0.0)) return 0;
+        for (int64_t j = 0; j < d; ++j)
+            if (!isfinite(C->center[j])) return 0;
+        return 1;
+    }
     for (int64_t j = 0; j < d; ++j)
-        if (!(lo[j] <= hi[j])) return 0;
+        if (!(C->lo[j] <= C->hi[j])) return 0;
     return 1;
 }
 
@@ -127,18 +166,17 @@ static int box_ok(int64_t d, const double *lo, const double *hi)
  * non-finite point or initial z, or an invalid box: z is set to NaN
  * (BAD_INPUT).
  */
-int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
-                       double mu, const double *lo, const double *hi, double *z, double *y,
-                       double *x_out, int64_t max_iter, double tol, int64_t adapt_every,
-                       double adapt_ratio, double adapt_factor, int64_t *iters, double *r_pri,
-                       double *r_dual, double *mu_out)
+static int em_solve_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                        const or_set_t *C, double *z, double *y, double *x_out, int64_t max_iter,
+                        double tol, int64_t adapt_every, double adapt_ratio, double adapt_factor,
+                        int64_t *iters, double *r_pri, double *r_dual, double *mu_out)
 {
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
     if (mu_out) *mu_out = mu;
     if (n == 0) return OR_EMPTY;
-    int bad = !box_ok(d, lo, hi);
+    int bad = !set_ok(d, C);
     for (int64_t k = 0; k < n; ++k)
         if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
     for (int64_t i = 0; i < n * d; ++i)
@@ -149,7 +187,7 @@ int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale_box(n, d, a, lo, hi);
+    double D = tol_scale_set(n, d, a, C);
 
     double *ybuf = y ? y : (double *)calloc((size_t)(n * d), sizeof(double));
     double *x = (double *)malloc((size_t)(n * d) * sizeof(double));
@@ -171,8 +209,9 @@ int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
         }
         for (int64_t j = 0; j < d; ++j) {
             zprev[j] = z[j];
-            z[j] = clamp_box(r[j] / (double)n, lo[j], hi[j]);
+            r[j] = r[j] / (double)n;
         }
+        project_set(C, d, r, z);
         for (int64_t k = 0; k < n; ++k)
             for (int64_t j = 0; j < d; ++j)
                 ybuf[k * d + j] += mu * (x[k * d + j] - z[j]);
@@ -211,6 +250,30 @@ int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
     free(r);
     free(zprev);
     return flags;
+}
+
+/* Algorithm 1 over the box prod_j [lo_j, hi_j] (adapt_every > 0: adaptive penalty). */
+int oracle_em_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
+                       double mu, const double *lo, const double *hi, double *z, double *y,
+                       double *x_out, int64_t max_iter, double tol, int64_t adapt_every,
+                       double adapt_ratio, double adapt_factor, int64_t *iters, double *r_pri,
+                       double *r_dual, double *mu_out)
+{
+    or_set_t C = {lo, hi, NULL, 0.0};
+    return em_solve_set(n, d, a, w, mu, &C, z, y, x_out, max_iter, tol, adapt_every, adapt_ratio,
+                        adapt_factor, iters, r_pri, r_dual, mu_out);
+}
+
+/* Algorithm 1 over the ball ||z - center|| <= radius (adapt_every > 0: adaptive penalty). */
+int oracle_em_solve_ball(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                         const double *center, double radius, double *z, double *y,
+                         double *x_out, int64_t max_iter, double tol, int64_t adapt_every,
+                         double adapt_ratio, double adapt_factor, int64_t *iters, double *r_pri,
+                         double *r_dual, double *mu_out)
+{
+    or_set_t C = {NULL, NULL, center, radius};
+    return em_solve_set(n, d, a, w, mu, &C, z, y, x_out, max_iter, tol, adapt_every, adapt_ratio,
+                        adapt_factor, iters, r_pri, r_dual, mu_out);
 }
 
 /* Algorithm 1 with the scalar box [lo, hi]^d and a fixed penalty. */
@@ -263,7 +326,8 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
     *r_dual = 0.0;
     if (restarts) *restarts = 0;
     if (n == 0) return OR_EMPTY;
-    int bad = !box_ok(d, lo, hi);
+    or_set_t C = {lo, hi, NULL, 0.0};
+    int bad = !set_ok(d, &C);
     for (int64_t k = 0; k < n; ++k)
         if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
     for (int64_t i = 0; i < n * d; ++i)
@@ -274,7 +338,7 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale_box(n, d, a, lo, hi);
+    double D = tol_scale_set(n, d, a, &C);
     size_t nd = (size_t)(n * d);
     double *y = (double *)calloc(nd, sizeof(double));
     double *yp = (double *)calloc(nd, sizeof(double));
@@ -403,15 +467,15 @@ double oracle_surrogate_objective(int64_t n, int64_t d, const double *a, const d
  * the solve reports CONVERGED after one iteration.
  * Flags, init and the n = 0 / bad-input rules are those of oracle_em_solve.
  */
-int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w, double eps,
-                         const double *lo, const double *hi, double *z, int64_t max_iter,
-                         double tol, int64_t *iters, double *r_pri, double *r_dual)
+static int irls_solve_set(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                          const or_set_t *C, double *z, int64_t max_iter, double tol,
+                          int64_t *iters, double *r_pri, double *r_dual)
 {
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
     if (n == 0) return OR_EMPTY;
-    int bad = !(eps > 0.0) || !box_ok(d, lo, hi);
+    int bad = !(eps > 0.0) || !set_ok(d, C);
     for (int64_t k = 0; k < n; ++k)
         if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
     for (int64_t i = 0; i < n * d; ++i)
@@ -422,8 +486,9 @@ int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale_box(n, d, a, lo, hi);
+    double D = tol_scale_set(n, d, a, C);
     double *num = (double *)malloc((size_t)d * sizeof(double));
+    double *zn = (double *)malloc((size_t)d * sizeof(double));
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
         double den = 0.0;
@@ -440,11 +505,12 @@ int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
         }
         double sd = 0.0;
         if (den > 0.0) {
+            for (int64_t j = 0; j < d; ++j) num[j] = num[j] / den;
+            project_set(C, d, num, zn);
             for (int64_t j = 0; j < d; ++j) {
-                double zn = clamp_box(num[j] / den, lo[j], hi[j]);
-                double e = zn - z[j];
+                double e = zn[j] - z[j];
                 sd += e * e;
-                z[j] = zn;
+                z[j] = zn[j];
             }
         }
         *r_dual = sqrt(sd / (double)d);
@@ -455,7 +521,26 @@ int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w,
         }
     }
     free(num);
+    free(zn);
     return flags;
+}
+
+/* IRLS over the box prod_j [lo_j, hi_j]. */
+int oracle_irls_solve_ex(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                         const double *lo, const double *hi, double *z, int64_t max_iter,
+                         double tol, int64_t *iters, double *r_pri, double *r_dual)
+{
+    or_set_t C = {lo, hi, NULL, 0.0};
+    return irls_solve_set(n, d, a, w, eps, &C, z, max_iter, tol, iters, r_pri, r_dual);
+}
+
+/* IRLS over the ball ||z - center|| <= radius. */
+int oracle_irls_solve_ball(int64_t n, int64_t d, const double *a, const double *w, double eps,
+                           const double *center, double radius, double *z, int64_t max_iter,
+                           double tol, int64_t *iters, double *r_pri, double *r_dual)
+{
+    or_set_t C = {NULL, NULL, center, radius};
+    return irls_solve_set(n, d, a, w, eps, &C, z, max_iter, tol, iters, r_pri, r_dual);
 }
 
 /* IRLS over the scalar box [lo, hi]^d. */
@@ -502,14 +587,17 @@ int oracle_max_threads(void)
  * max_iter_each (nullable) overrides max_iter per instance.
  * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
  * on the surrogate with eps, 3 = accelerated ADMM with restart parameter eta.
- * box_lo / box_hi (nullable, float32, indexed like
+ * ball_radius (nullable, one per instance) selects the ball constraint with
+ * centres ball_center (nullable = origin, indexed like z; solvers 0 and 1).
+ * Otherwise box_lo / box_hi (nullable, float32, indexed like
  * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
  * mu_out (nullable): the final penalty per instance.
  */
 int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t *a_off,
                        const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
                        const int32_t *d_arr, int solver, double mu, double eps, double lo, double hi,
-                       const float *box_lo, const float *box_hi, int64_t max_iter,
+                       const float *box_lo, const float *box_hi, const float *ball_center,
+                       const float *ball_radius, int64_t max_iter,
                        const int32_t *max_iter_each, double tol, int init, int64_t adapt_every,
                        double adapt_ratio, double adapt_factor, double *z, int32_t *iters,
                        int32_t *flags, double *r_pri, double *r_dual, double *mu_out, double eta,
@@ -528,7 +616,10 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         for (int64_t j = 0; j < d; ++j) {
             lv[j] = box_lo ? (double)box_lo[z_off[b] + j] : lo;
             hv[j] = box_hi ? (double)box_hi[z_off[b] + j] : hi;
+            if (ball_radius) lv[j] = ball_center ? (double)ball_center[z_off[b] + j] : 0.0;
         }
+        /* ball_radius != NULL selects the ball (centre in lv, origin when no centres) */
+        or_set_t C = {lv, hv, ball_radius ? lv : NULL, ball_radius ? (double)ball_radius[b] : 0.0};
         double *zb = z + z_off[b];
         if (init == OR_INIT_MAXW && n > 0) {
             int64_t best = 0;
@@ -541,12 +632,12 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
         int f;
         if (solver == 1)
-            f = oracle_irls_solve_ex(n, d, ab, wb, eps, lv, hv, zb, mi, tol, &it, &rp, &rd);
+            f = irls_solve_set(n, d, ab, wb, eps, &C, zb, mi, tol, &it, &rp, &rd);
         else if (solver == 3)
             f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, NULL);
         else
-            f = oracle_em_solve_ex(n, d, ab, wb, mu, lv, hv, zb, NULL, NULL, mi, tol, adapt_every,
-                                   adapt_ratio, adapt_factor, &it, &rp, &rd, &mf);
+            f = em_solve_set(n, d, ab, wb, mu, &C, zb, NULL, NULL, mi, tol, adapt_every, adapt_ratio,
+                             adapt_factor, &it, &rp, &rd, &mf);
         if (iters) iters[b] = (int32_t)it;
         if (flags) flags[b] = f;
         if (r_pri) r_pri[b] = rp;
@@ -569,8 +660,8 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
                     double *r_dual, int nthreads)
 {
     return oracle_em_batch_ex(B, a, w, a_off, w_off, z_off, n_arr, d_arr, 0, mu, 1.0, lo, hi, NULL,
-                              NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z, iters, flags,
-                              r_pri, r_dual, NULL, 0.999, nthreads);
+                              NULL, NULL, NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z,
+                              iters, flags, r_pri, r_dual, NULL, 0.999, nthreads);
 }
 
 /* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */

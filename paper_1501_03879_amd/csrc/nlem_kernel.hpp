@@ -9,9 +9,13 @@
 //    (symmetric reflection at the borders) into LDS once; every point a_j is
 //    then read from that tile, never materialised.
 //  * Wave w owns a fixed slice of the d = (2r+1)^2 patch coordinates; lane l
-//    owns window positions p = l + 64 q, q < M.  Per point and slice it keeps
-//    one state value g = e - a in registers for the whole solve, where e is
-//    the prox displacement s (v - a) of the last iteration.
+//    owns window positions p = l + 64 q, q < M (for R = 10: M = 7 consecutive
+//    columns of one window row).  Per point and slice it keeps one state
+//    value g = e - a in registers for the whole solve, where e is the prox
+//    displacement s (v - a) of the last iteration.  Point values are read
+//    from the tile along patch rows: with consecutive columns, coordinate
+//    (r, c + 1) of point q is coordinate (r, c) of point q + 1, so each
+//    further coordinate costs one LDS read per lane.
 //  * Per iteration (exactly Algorithm 1, rewritten with the scaled multiplier
 //    u_k = y_k / mu; c = 2 z^t - z^{t-1}):
 //      delta = g + c = v_k - a_k             (v_k = z - u_k)
@@ -26,6 +30,9 @@
 //    the wave, after which one lane per slice coordinate holds E and keeps
 //    z^t, z^{t-1}, E^t of that coordinate in registers; c is broadcast to the
 //    other lanes through LDS for the next pass.
+//  * Stopping: the primal residual is evaluated on iterations that follow one
+//    with r_dual <= tol (hi - lo) ("armed") and the stop test is taken right
+//    after them.
 //  * Starting point (Section 3 compares two): the noisy patch P_i, or the
 //    Non-Local Means patch sum_j w_j P_j / sum_j w_j, computed by a weights
 //    pass before the loop; with zero iterations the output is then NLM.
@@ -80,6 +87,7 @@ struct NlemShape {
     // offsets reaches all its points.  Used only for R = RMAX.
     static constexpr bool ROWMAP = M > 1 && (WSM % M == 0) && (WSM / M) * WSM <= 64;
     static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
+    static_assert(TW <= 64, "tile rows are staged one column per lane");
 };
 
 template <int PR, int M, int WC, int SW, int SOLVER>
@@ -122,16 +130,22 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         const int TWr = 2 * (R + PR) + 1;
 
         // ---- a1: stage the tile (rows iy-R-r .. iy+R+r), reflected at borders
-        for (int idx = threadIdx.x; idx < TWr * TWr; idx += 64 * WC) {
-            const int ty = idx / TWr, tx = idx - (idx / TWr) * TWr;
-            const int gy = reflect_idx(iy - R - PR + ty, H);
-            const int gx = reflect_idx(ix - R - PR + tx, W);
-            float v;
-            if (I.is_f16)
-                v = __half2float(reinterpret_cast<const __half *>(I.img)[(int64_t)gy * W + gx]);
-            else
-                v = reinterpret_cast<const float *>(I.img)[(int64_t)gy * W + gx];
-            tile[ty * S::P + tx] = v;
+        // (rows outside the reflection range are clamped; only window slots
+        // outside the image read them).  Wave w loads rows w, w + WC, ...,
+        // one column per lane (TW <= 64).
+        {
+            const int gx = reflect_idx(ix - R - PR + lane, W);
+            for (int ty = SW; ty < TWr; ty += WC) {
+                const int64_t gy = reflect_idx(iy - R - PR + ty, H);
+                if (lane < TWr) {
+                    float v;
+                    if (I.is_f16)
+                        v = __half2float(reinterpret_cast<const __half *>(I.img)[gy * W + gx]);
+                    else
+                        v = reinterpret_cast<const float *>(I.img)[gy * W + gx];
+                    tile[ty * S::P + lane] = v;
+                }
+            }
         }
         __syncthreads();
 

@@ -223,3 +223,88 @@ def test_fast_admm_fewer_iterations_with_a_large_penalty(orc):
     g = orc.em_solve_fast(a, w, 10.0, -3.0, 3.0, a[0], max_iter=5000, tol=1e-6)
     assert f["flags"] == g["flags"] == orc.CONVERGED
     assert g["iters"] * 4 < f["iters"]
+
+
+# ---- the Euclidean ball as the constraint set -----------------------------------
+
+def _ball_certificate(a, w, z, center, radius, tol):
+    """0 in grad F(z) + N_C(z) for the ball: inside, the (sub)gradient
+    vanishes; on the sphere, -grad F(z) = lam (z - center) with lam >= 0."""
+    dist = np.linalg.norm(a - z[None], axis=1)
+    K0 = dist <= 1e-6
+    W0 = w[K0].sum()
+    g = ((w[~K0] / dist[~K0])[:, None] * (z[None] - a[~K0])).sum(axis=0)
+    u = z - center
+    if np.linalg.norm(u) >= radius * (1 - 1e-9):
+        un = u / np.linalg.norm(u)
+        lam = max(0.0, -float(g @ un))   # best multiplier of the normal cone
+        q = g + lam * un
+    else:
+        q = g
+    return np.linalg.norm(q) <= W0 + tol * w.sum()
+
+
+def test_ball_certificate_and_scipy(orc):
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(90)
+    on_sphere = 0
+    for _ in range(8):
+        n, d = int(rng.integers(5, 30)), int(rng.integers(2, 6))
+        a = rng.normal(size=(n, d)) * 2 + 1.5
+        w = rng.uniform(0.1, 1.0, size=n)
+        c = rng.normal(size=d) * 0.3
+        r = float(rng.uniform(0.3, 1.5))
+        res = orc.em_solve_ball(a, w, 0.5, c, r, c, max_iter=60000, tol=1e-13)
+        z = res["z"]
+        assert np.linalg.norm(z - c) <= r * (1 + 1e-12)
+        assert _ball_certificate(a, w, z, c, r, 1e-5)
+        on_sphere += int(np.linalg.norm(z - c) >= r * (1 - 1e-9))
+        f = lambda t: np.sum(w * np.linalg.norm(a - t[None], axis=1))
+        ref = minimize(f, c, method="SLSQP",
+                       constraints=[dict(type="ineq", fun=lambda t: r * r - np.sum((t - c) ** 2))],
+                       options=dict(ftol=1e-14, maxiter=2000))
+        assert orc.em_objective(a, w, z) <= ref.fun + 1e-7 * max(1.0, ref.fun)
+    assert on_sphere >= 4, "the balls should bind"
+
+
+def test_ball_in_one_dimension_is_the_interval(orc):
+    """d = 1: the ball [c - r, c + r] is a box; both sets give the same solve."""
+    rng = np.random.default_rng(91)
+    a = rng.normal(size=(15, 1)) * 2
+    w = rng.uniform(0.2, 1.0, size=15)
+    for c, r in [(0.0, 0.5), (1.2, 0.3), (-3.0, 10.0)]:
+        zb = orc.em_solve_ball(a, w, 0.4, [c], r, [c], max_iter=300)["z"]
+        zx = orc.em_solve(a, w, 0.4, c - r, c + r, [c], max_iter=300)["z"]
+        np.testing.assert_allclose(zb, zx, rtol=0, atol=1e-12)
+        ib = orc.irls_solve_ball(a, w, 1e-3, [c], r, [c], max_iter=50)["z"]
+        ix = orc.irls_solve(a, w, 1e-3, c - r, c + r, [c], max_iter=50)["z"]
+        np.testing.assert_allclose(ib, ix, rtol=0, atol=1e-12)
+
+
+def test_ball_rotation_equivariance(orc):
+    """The ball (unlike a box) is invariant under rotations about its centre:
+    rotating the points rotates the minimiser (ADMM and IRLS)."""
+    rng = np.random.default_rng(92)
+    n, d = 20, 4
+    a = rng.normal(size=(n, d)) * 2 + 1.0
+    w = rng.uniform(0.2, 1.0, size=n)
+    c = np.array([0.3, -0.2, 0.1, 0.0])
+    Q, _ = np.linalg.qr(rng.normal(size=(d, d)))
+    ar = (a - c) @ Q.T + c
+    r0 = orc.em_solve_ball(a, w, 0.5, c, 0.8, c, max_iter=40000, tol=1e-13)["z"]
+    r1 = orc.em_solve_ball(ar, w, 0.5, c, 0.8, c, max_iter=40000, tol=1e-13)["z"]
+    np.testing.assert_allclose(r1, (r0 - c) @ Q.T + c, atol=1e-8)
+    i0 = orc.irls_solve_ball(a, w, 1e-4, c, 0.8, c, max_iter=5000, tol=1e-15)["z"]
+    i1 = orc.irls_solve_ball(ar, w, 1e-4, c, 0.8, c, max_iter=5000, tol=1e-15)["z"]
+    np.testing.assert_allclose(i1, (i0 - c) @ Q.T + c, atol=1e-8)
+
+
+def test_ball_containing_the_median_changes_nothing_and_bad_radius(orc):
+    rng = np.random.default_rng(93)
+    a = rng.normal(size=(25, 3))
+    w = rng.uniform(0.2, 1.0, size=25)
+    free = orc.em_solve(a, w, 0.5, -np.inf, np.inf, a[0], max_iter=40000, tol=1e-13)["z"]
+    big = orc.em_solve_ball(a, w, 0.5, np.zeros(3), 1e3, a[0], max_iter=40000, tol=1e-13)["z"]
+    np.testing.assert_allclose(big, free, atol=1e-9)
+    r = orc.em_solve_ball(a, w, 0.5, np.zeros(3), -1.0, a[0])
+    assert r["flags"] == orc.BAD_INPUT and np.all(np.isnan(r["z"]))
