@@ -144,6 +144,12 @@ typedef enum {
     EM_SOLVER_ADMM_FAST = 3      /* accelerated ADMM with restart (em_solve_plain_ex only) */
 } em_solver_t;
 
+/* The convex set C of (EM) for em_solve_batch_ex. */
+typedef enum {
+    EM_SET_BOX = 0,  /* [lo, hi] per coordinate (Section 3 uses [0, 255]^d) */
+    EM_SET_BALL = 1  /* {z : ||z - center|| <= radius}: projection scales z - center */
+} em_set_t;
+
 /* Options of em_solve_batch_ex (host memory; the box arrays are device memory). */
 typedef struct {
     int32_t solver;        /* em_solver_t */
@@ -159,16 +165,27 @@ typedef struct {
     float adapt_ratio;     /* ADAPTIVE: imbalance ratio that triggers a change (> 1, e.g. 10) */
     float adapt_factor;    /* ADAPTIVE: factor applied to rho (> 1, e.g. 2) */
     float fast_eta;        /* FAST: restart parameter eta in (0, 1) (0.999 in the reference) */
+    int32_t set;           /* em_set_t: the convex set C */
+    const float *ball_center; /* BALL: NULL (origin) or centres, device, indexed like z */
+    const float *ball_radius; /* BALL: NULL (use radius) or one radius per instance, device */
+    float radius;          /* BALL: the radius when ball_radius is NULL */
 } em_options_t;
 
 /*
  * em_solve_batch_ex - em_solve_batch with a choice of solver and a general box.
- *   Box: [lo, hi] for every coordinate, or per coordinate: instance b,
- *     coordinate j uses [box_lo[z_off + j], box_hi[z_off + j]] (same layout
- *     as z).  An instance whose bounds have lo_j > hi_j or a NaN gets
- *     flags = EM_BAD_INPUT and z = NaN.  The tolerance scale D is the widest
- *     interval max_j (hi_j - lo_j) when finite and > 0, else
- *     max(1, max_k ||a_k||_inf).
+ *   Box (set = EM_SET_BOX): [lo, hi] for every coordinate, or per
+ *     coordinate: instance b, coordinate j uses [box_lo[z_off + j],
+ *     box_hi[z_off + j]] (same layout as z).  An instance whose bounds have
+ *     lo_j > hi_j or a NaN gets flags = EM_BAD_INPUT and z = NaN.  The
+ *     tolerance scale D is the widest interval max_j (hi_j - lo_j) when
+ *     finite and > 0, else max(1, max_k ||a_k||_inf).
+ *   Ball (set = EM_SET_BALL; (EM) allows any closed convex C, and the ball
+ *     has the closed-form projection center + (z - center) min(1, radius /
+ *     ||z - center||)): centre ball_center[z_off + j] (origin when NULL),
+ *     radius ball_radius[b] (or `radius`); a negative or NaN radius or a
+ *     non-finite centre gives EM_BAD_INPUT; D = 2 radius when finite and
+ *     > 0.  Solvers ADMM and IRLS (not ADAPTIVE); box_lo / box_hi must be
+ *     NULL.
  *   EM_SOLVER_ADMM: Algorithm 1 exactly as em_solve_batch.
  *   EM_SOLVER_ADMM_ADAPTIVE: after every adapt_every-th iteration t that did
  *     not stop, with ||r|| = (sum_k ||x_k - z||^2)^(1/2) and
@@ -185,8 +202,9 @@ typedef struct {
  * Other arguments, limits and per-instance rules as for em_solve_batch.
  * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
  * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1
- * for ADAPTIVE, one of box_lo / box_hi NULL, and em_solve_batch's errors);
- * UNSUPPORTED for EM_SOLVER_ADMM_FAST (see em_solve_plain_ex); HIP.
+ * for ADAPTIVE, one of box_lo / box_hi NULL, a bad set, a ball with box
+ * arrays, and em_solve_batch's errors); UNSUPPORTED for EM_SOLVER_ADMM_FAST
+ * (see em_solve_plain_ex) and for the ball with ADAPTIVE; HIP.
  */
 em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
                               const float *a, const float *w, const em_instance_t *inst,
@@ -209,8 +227,9 @@ em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
  * (alpha = 1 and c_prev = +inf at the start).  Residuals and stopping as for
  * em_solve_batch, evaluated every iteration.  Its momentum needs the previous
  * multipliers, a second n x d state, which this path keeps in device memory.
- * Other solvers return EM_ERR_UNSUPPORTED; arguments and errors otherwise as
- * em_solve_plain and em_solve_batch_ex (fast_eta must be in (0, 1)).
+ * Other solvers and the ball return EM_ERR_UNSUPPORTED; arguments and errors
+ * otherwise as em_solve_plain and em_solve_batch_ex (fast_eta must be in
+ * (0, 1)).
  */
 em_status_t em_solve_plain_ex(em_handle_t handle, void *stream, int64_t B,
                               const float *a, const float *w, const em_instance_t *inst,

@@ -21,6 +21,7 @@ EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP 
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW = 0, 1
 SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST = 0, 1, 2, 3
+SET_BOX, SET_BALL = 0, 1
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10
 
@@ -50,7 +51,8 @@ class EmOptions(C.Structure):
                 ("box_lo", C.c_void_p), ("box_hi", C.c_void_p), ("rho", C.c_float),
                 ("eps", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_float),
                 ("adapt_every", C.c_int32), ("adapt_ratio", C.c_float), ("adapt_factor", C.c_float),
-                ("fast_eta", C.c_float)]
+                ("fast_eta", C.c_float), ("set", C.c_int32), ("ball_center", C.c_void_p),
+                ("ball_radius", C.c_void_p), ("radius", C.c_float)]
 
 
 _lib = None
@@ -155,13 +157,16 @@ class Handle:
     def em_solve_batch_ex(self, a, w, inst, z, stats=None, *, solver=SOLVER_ADMM, init=INIT_MAXW,
                           lo=-float("inf"), hi=float("inf"), box_lo=None, box_hi=None, rho=1.0,
                           eps=1e-6, max_iter=1000, tol=1e-4, adapt_every=1, adapt_ratio=10.0,
-                          adapt_factor=2.0, stream=None):
+                          adapt_factor=2.0, ball_center=None, ball_radius=None, radius=None,
+                          stream=None):
         """em_solve_batch with a solver choice (ADMM, IRLS, adaptive-penalty ADMM)
-        and optional per-coordinate bounds box_lo / box_hi (float32 device
-        tensors laid out like z)."""
+        and a general set: per-coordinate bounds box_lo / box_hi (float32 device
+        tensors laid out like z), or the Euclidean ball when `radius` (scalar)
+        or `ball_radius` (one per instance) is given, centred at ball_center
+        (laid out like z; origin when None)."""
         B = int(inst.numel() * inst.element_size() // 32)
         opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every,
-                       adapt_ratio, adapt_factor, 0.999)
+                       adapt_ratio, adapt_factor, 0.999, ball_center, ball_radius, radius)
         st = self.lib.em_solve_batch_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
                                         C.byref(opt), _ptr(z), _ptr(stats))
         self._check(st, "em_solve_batch_ex")
@@ -236,12 +241,16 @@ class Handle:
 
 
 def _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every, adapt_ratio,
-             adapt_factor, eta):
+             adapt_factor, eta, ball_center=None, ball_radius=None, radius=None):
+    ball = radius is not None or ball_radius is not None
     return EmOptions(int(solver), int(init), float(lo), float(hi),
                      None if box_lo is None else box_lo.data_ptr(),
                      None if box_hi is None else box_hi.data_ptr(), float(rho), float(eps),
                      int(max_iter), float(tol), int(adapt_every), float(adapt_ratio),
-                     float(adapt_factor), float(eta))
+                     float(adapt_factor), float(eta), SET_BALL if ball else SET_BOX,
+                     None if ball_center is None else ball_center.data_ptr(),
+                     None if ball_radius is None else ball_radius.data_ptr(),
+                     float(0.0 if radius is None else radius))
 
 
 def _image_array(items):

@@ -81,10 +81,13 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
-    const ClassKernel *tab = (o.solver == EM_SOLVER_IRLS)            ? batch_class_table_irls()
-                             : (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? batch_class_table_adapt()
-                                                                     : batch_class_table_admm();
-    const bool vbox = o.box_lo != nullptr;
+    const bool ball = o.set == EM_SET_BALL;
+    const ClassKernel *tab = (o.solver == EM_SOLVER_IRLS)
+                                 ? (ball ? batch_class_table_irls_ball() : batch_class_table_irls())
+                             : (o.solver == EM_SOLVER_ADMM_ADAPTIVE)
+                                 ? batch_class_table_adapt()
+                                 : (ball ? batch_class_table_admm_ball() : batch_class_table_admm());
+    const bool vbox = ball || o.box_lo != nullptr;
     for (int c = 0; c < kNumClasses; ++c) {
         ClassLaunch L;
         memset(&L, 0, sizeof(L));
@@ -96,8 +99,11 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         L.counter = heads + c;
         L.z = z;
         L.stats = stats;
-        L.box_lo = o.box_lo;
-        L.box_hi = o.box_hi;
+        L.box_lo = ball ? nullptr : o.box_lo;
+        L.box_hi = ball ? nullptr : o.box_hi;
+        L.ball_center = ball ? o.ball_center : nullptr;
+        L.ball_radius = ball ? o.ball_radius : nullptr;
+        L.radius = o.radius;
         L.lo = vbox ? 0.0f : o.lo;   // padded coordinates clamp to 0 when the box is per coordinate
         L.hi = vbox ? 0.0f : o.hi;
         L.mu = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;

@@ -1,8 +1,8 @@
-// Batched IRLS kernels for the smooth surrogate, one per shape class.
+// Batched IRLS kernels for the smooth surrogate over a box, one per shape class.
 #include "batch_kernel.hpp"
 
 namespace emx {
 
-const ClassKernel *batch_class_table_irls() { return class_table_for<1>(); }
+const ClassKernel *batch_class_table_irls() { return class_table_for<1, 0>(); }
 
 }  // namespace emx

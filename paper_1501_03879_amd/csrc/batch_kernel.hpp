@@ -15,8 +15,11 @@
 //    over the WC coordinate waves in LDS, shrink factor, pass 2 (E += s delta,
 //    g = s delta - a), wave reduce-scatter of E, sum over the WP point waves
 //    in LDS, then z = clamp(z - E / n), c = 2 z - z_prev.
-//  * Box: one interval for all coordinates, or per-coordinate bounds read
-//    from device arrays indexed like z.
+//  * Set C: a box (one interval for all coordinates, or per-coordinate
+//    bounds read from device arrays indexed like z), or (SET = 1) the
+//    Euclidean ball ||z - center|| <= radius, whose projection scales
+//    z - center by min(1, radius / ||z - center||): one more sum over the
+//    coordinates (rows, then the coordinate waves through LDS) per iteration.
 //  * Adaptive penalty (residual balancing): on every k-th iteration both
 //    residuals are evaluated; the next iteration compares them and may scale
 //    mu by a factor.  The multipliers y are unchanged by that, so the scaled
@@ -26,8 +29,8 @@
 //    c = v - e becomes c / tau + (1 - 1/tau) z.
 //  * IRLS iteration: omega_k = w_k (||z - a_k||^2 + eps)^(-1/2), then
 //    z' = P_C(sum_k omega_k a_k / sum_k omega_k), held relative to the
-//    starting point z0 (points as z0 - a) so the distance to a point at z0
-//    keeps FP32 precision of its own size.
+//    starting point projected onto C, o = P_C(z0) (points as o - a), so the
+//    distance to a point at o keeps FP32 precision of its own size.
 #pragma once
 
 #include <float.h>
@@ -74,6 +77,9 @@ struct ClassLaunch {
     em_stats_t *stats;
     const float *box_lo;          // per-coordinate bounds (indexed like z) or null
     const float *box_hi;
+    const float *ball_center;     // SET = 1: centres (indexed like z) or null (origin)
+    const float *ball_radius;     // SET = 1: radii (one per instance) or null (radius below)
+    float radius;
     float lo, hi, mu, tol, arm;
     float eps;                    // IRLS
     float adapt_ratio2;           // ADMM: (residual ratio)^2 that triggers a penalty change
@@ -95,9 +101,10 @@ struct BatchShape {
     static constexpr int XNB = WC * WP * M * 64;  // one buffer of per-wave norm partials
 };
 
-template <int DS, int M, int WC, int WP, int SOLVER>
+template <int DS, int M, int WC, int WP, int SOLVER, int SET>
 __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunch L) {
     constexpr bool IRLS = SOLVER == 1;
+    constexpr bool BALL = SET == 1;
     constexpr bool ADAPT = SOLVER == 2;   // adaptive penalty (a separate kernel: it needs registers)
     using S = BatchShape<DS, M, WC, WP>;
     using RSx = RS<DS>;
@@ -109,7 +116,8 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     __shared__ float xo[(WP > 1) ? 2 * WP : 1];
     __shared__ float xs[3 * WC * WP * 4];   // third slot: the test after armed iterations
     __shared__ float Epv[WC * H2 * 4 * WP];
-    __shared__ float Bv[WC * WP * 2 * H2 * 4];
+    __shared__ float Bv[WC * WP * 2 * H2 * 4];   // box bounds, or the ball centre
+    __shared__ float xb[BALL ? 2 * WC * WP : 1];  // ball: per-wave sums of squares
     __shared__ float cvec[WC * WP * DS];
     __shared__ float zvec[ADAPT ? WC * WP * DS : 1];
     __shared__ unsigned int item_s;
@@ -122,7 +130,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     float *Ep_s = Epv + wave * H2 * 4;  // per wave: E^t in the reduced layout [slot][row]
     float *cv = cvec + wave * DS;       // per wave: c of the slice (ADMM), z - z0 (IRLS)
     float *zb = zvec + wave * DS;       // per wave: z of the slice, for a penalty rescale
-    float *Bl_s = Bv + wave * 2 * H2 * 4;  // per wave: the box in the reduced layout
+    float *Bl_s = Bv + wave * 2 * H2 * 4;  // per wave: the box (ball: centre) in the reduced layout
     float *Bh_s = Bl_s + H2 * 4;
     const unsigned int cbeg = L.offsets[L.cls];
     const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
@@ -225,16 +233,18 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         for (int j = 0; j < H2; ++j) {
             const int cc = cw * DS + RSx::coord(row, j);
             const bool vj = RSx::valid(row, j) && cc < d;
-            float zv = 0.0f, lv = L.lo, hv = L.hi;
+            float zv = 0.0f, lv = BALL ? 0.0f : L.lo, hv = BALL ? 0.0f : L.hi;
             if (vj) {
                 zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc] : Z[cc];
-                if (vbox) {
+                if (BALL) {
+                    if (L.ball_center) lv = L.ball_center[e.z_off + cc];
+                } else if (vbox) {
                     lv = L.box_lo[e.z_off + cc];
                     hv = L.box_hi[e.z_off + cc];
                 }
             }
             zbad |= vj && !(fabsf(zv) <= FLT_MAX);
-            zbad |= vj && !(lv <= hv);
+            zbad |= vj && (BALL ? !(fabsf(lv) <= FLT_MAX) : !(lv <= hv));
             const float wj = hv - lv;
             if (vj && !(wj <= wid)) wid = wj;   // also takes inf
             zr[j] = zv;
@@ -247,8 +257,9 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         if (__any(zbad) && lane == 0) flag_s[2] = 1;
         if (lane == 0) atomicMax(&flag_s[3], __float_as_int(wwid));
         __syncthreads();
-        const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
-        const float wmax = readfirstlane(__int_as_float(flag_s[3]));
+        const float rad = BALL ? (L.ball_radius ? readfirstlane(L.ball_radius[b]) : L.radius) : 0.0f;
+        const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0 || (BALL && !(rad >= 0.0f)));
+        const float wmax = BALL ? 2.0f * rad : readfirstlane(__int_as_float(flag_s[3]));
         const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f)
                                  ? wmax : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
         const float tau = L.tol * Dscale;
@@ -256,7 +267,25 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         const float arm2 = (L.arm * tau) * (L.arm * tau);
         __syncthreads();  // flags are reset by the next pop
 
-        // c = z (ADMM); IRLS keeps z0 per slot and iterates z - z0 from 0
+        // Ball projection factor min(1, radius / ||m - center||) from the lane's
+        // row partial sum of (m_j - center_j)^2 (identical on the row's lanes);
+        // rows summed by readlanes, coordinate waves through LDS.
+        auto ball_factor = [&](float s2row, int t) -> float {
+            float S = readfirstlane((readlane(s2row, 0) + readlane(s2row, 16)) +
+                                    (readlane(s2row, 32) + readlane(s2row, 48)));
+            if constexpr (WC > 1) {
+                float *XB = xb + (t & 1) * WC * WP;
+                if (lane == 0) XB[pw * WC + cw] = S;
+                __syncthreads();
+                S = XB[pw * WC];
+#pragma unroll
+                for (int v = 1; v < WC; ++v) S += XB[pw * WC + v];
+                S = readfirstlane(S);
+            }
+            return (S > rad * rad) ? rad / sqrtf(S) : 1.0f;
+        };
+
+        // c = z (ADMM); IRLS keeps its frame origin per slot (below)
         float z0[IRLS ? H2 : 1];
         if (lane == 16 * row) {
 #pragma unroll
@@ -275,19 +304,46 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         if (bad_all) {
             flags = EM_BAD_INPUT;
         } else if constexpr (IRLS) {
-            // ---- points relative to z0 (na = z0 - a); iterate dz = z - z0
+            // ---- frame origin o = P_C(z0): points as o - a, iterate z - o (the
+            // distance to a point at o keeps FP32 precision of its own size;
+            // projecting keeps |z - o| within the set's diameter when z0 is a
+            // far point)
+            {
+                float fo = 1.0f;
+                if constexpr (BALL) {
+                    float s2 = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < H2; ++j) {
+                        const int cc = cw * DS + RSx::coord(row, j);
+                        const bool vj = RSx::valid(row, j) && cc < d;
+                        const float dv = z0[j] - Bl_s[j * 4 + row];
+                        s2 += vj ? dv * dv : 0.0f;
+                    }
+                    fo = ball_factor(s2, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < H2; ++j) {
+                    const float bl = Bl_s[j * 4 + row], bh = Bh_s[j * 4 + row];
+                    const float o = BALL ? ((fo < 1.0f) ? bl + (z0[j] - bl) * fo : z0[j]) : clampf(z0[j], bl, bh);
+                    zr[j] = z0[j] - o;   // the start relative to o
+                    z0[j] = o;
+                }
+            }
+            if (lane == 16 * row) {
+#pragma unroll
+                for (int j = 0; j < H2; ++j)
+                    if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = z0[j];
+            }
 #pragma unroll
             for (int jj = 0; jj < DS; ++jj) {
                 const float cj = cv[jj];
 #pragma unroll
                 for (int q = 0; q < M; ++q) na[q][jj] += cj;
             }
-#pragma unroll
-            for (int j = 0; j < H2; ++j) zr[j] = 0.0f;
             if (lane == 16 * row) {
 #pragma unroll
                 for (int j = 0; j < H2; ++j)
-                    if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = 0.0f;
+                    if (RSx::valid(row, j)) cv[RSx::coord(row, j)] = zr[j];
             }
 #pragma unroll
             for (int q = 0; q < M; ++q) lam[q] = fmaxf(lam[q], 0.0f);   // the weights
@@ -386,16 +442,34 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     Om = readfirstlane(os);
                 }
                 const float inv_om = (Om > 0.0f) ? 1.0f / Om : 0.0f;
+                float fb = 1.0f;
+                if constexpr (BALL) {
+                    float s2 = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < H2; ++j) {
+                        const int cc = cw * DS + RSx::coord(row, j);
+                        const bool vj = RSx::valid(row, j) && cc < d;
+                        const float dv = (z0[j] - Bl_s[j * 4 + row]) + (-E[j] * inv_om);
+                        s2 += vj ? dv * dv : 0.0f;
+                    }
+                    fb = ball_factor(s2, t);
+                }
                 float rdx = 0.0f;
 #pragma unroll
                 for (int j = 0; j < H2; ++j) {
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
-                    // z' - z0 = P_C(z0 + raw) - z0, exact when the box is inactive
+                    // z' - z0 = P_C(z0 + raw) - z0, exact when the set is inactive
                     const float raw = -E[j] * inv_om;
-                    const float zab = z0[j] + raw;
-                    const float bl = Bl_s[j * 4 + row], bh = Bh_s[j * 4 + row];
-                    float zn = (zab < bl) ? bl - z0[j] : ((zab > bh) ? bh - z0[j] : raw);
+                    float zn;
+                    if constexpr (BALL) {
+                        const float cn = Bl_s[j * 4 + row];
+                        zn = (fb < 1.0f) ? (cn - z0[j]) + ((z0[j] - cn) + raw) * fb : raw;
+                    } else {
+                        const float zab = z0[j] + raw;
+                        const float bl = Bl_s[j * 4 + row], bh = Bh_s[j * 4 + row];
+                        zn = (zab < bl) ? bl - z0[j] : ((zab > bh) ? bh - z0[j] : raw);
+                    }
                     zn = (vj && Om > 0.0f) ? zn : zr[j];
                     const float dz = zn - zr[j];
                     rdx += dz * dz;
@@ -607,13 +681,27 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         E[j] = sum;
                     }
                 }
+                float fb = 1.0f;
+                if constexpr (BALL) {
+                    float s2 = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < H2; ++j) {
+                        const int cc = cw * DS + RSx::coord(row, j);
+                        const bool vj = RSx::valid(row, j) && cc < d;
+                        const float dv = (zr[j] - E[j] * inv_n) - Bl_s[j * 4 + row];
+                        s2 += vj ? dv * dv : 0.0f;
+                    }
+                    fb = ball_factor(s2, t);
+                }
                 float rdx = 0.0f, rpx = 0.0f;
 #pragma unroll
                 for (int j = 0; j < H2; ++j) {
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
                     const int k = RSx::valid(row, j) ? RSx::coord(row, j) : 0;
-                    const float zn = clampf(zr[j] - E[j] * inv_n, Bl_s[j * 4 + row], Bh_s[j * 4 + row]);
+                    const float zu = zr[j] - E[j] * inv_n;
+                    const float zn = BALL ? ((fb < 1.0f) ? Bl_s[j * 4 + row] + (zu - Bl_s[j * 4 + row]) * fb : zu)
+                                          : clampf(zu, Bl_s[j * 4 + row], Bh_s[j * 4 + row]);
                     const float dz = zn - zr[j];
                     const float cj = cv[k];
                     if (armed) {
@@ -690,30 +778,33 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     }
 }
 
-template <int C, int SOLVER>
+template <int C, int SOLVER, int SET>
 constexpr ClassKernel class_kernel() {
     constexpr ClassShape s = class_shape(C);
-    return ClassKernel{reinterpret_cast<const void *>(&batch_solve_kernel<s.ds, s.m, s.wc, s.wp, SOLVER>),
-                       64 * s.wc * s.wp};
+    return ClassKernel{
+        reinterpret_cast<const void *>(&batch_solve_kernel<s.ds, s.m, s.wc, s.wp, SOLVER, SET>),
+        64 * s.wc * s.wp};
 }
 
-template <int SOLVER>
+template <int SOLVER, int SET>
 const ClassKernel *class_table_for() {
     static const ClassKernel t[kNumClasses] = {
-        class_kernel<0, SOLVER>(),  class_kernel<1, SOLVER>(),  class_kernel<2, SOLVER>(),
-        class_kernel<3, SOLVER>(),  class_kernel<4, SOLVER>(),  class_kernel<5, SOLVER>(),
-        class_kernel<6, SOLVER>(),  class_kernel<7, SOLVER>(),  class_kernel<8, SOLVER>(),
-        class_kernel<9, SOLVER>(),  class_kernel<10, SOLVER>(), class_kernel<11, SOLVER>(),
-        class_kernel<12, SOLVER>(), class_kernel<13, SOLVER>(), class_kernel<14, SOLVER>(),
-        class_kernel<15, SOLVER>(), class_kernel<16, SOLVER>(), class_kernel<17, SOLVER>(),
-        class_kernel<18, SOLVER>(), class_kernel<19, SOLVER>(),
+        class_kernel<0, SOLVER, SET>(),  class_kernel<1, SOLVER, SET>(),  class_kernel<2, SOLVER, SET>(),
+        class_kernel<3, SOLVER, SET>(),  class_kernel<4, SOLVER, SET>(),  class_kernel<5, SOLVER, SET>(),
+        class_kernel<6, SOLVER, SET>(),  class_kernel<7, SOLVER, SET>(),  class_kernel<8, SOLVER, SET>(),
+        class_kernel<9, SOLVER, SET>(),  class_kernel<10, SOLVER, SET>(), class_kernel<11, SOLVER, SET>(),
+        class_kernel<12, SOLVER, SET>(), class_kernel<13, SOLVER, SET>(), class_kernel<14, SOLVER, SET>(),
+        class_kernel<15, SOLVER, SET>(), class_kernel<16, SOLVER, SET>(), class_kernel<17, SOLVER, SET>(),
+        class_kernel<18, SOLVER, SET>(), class_kernel<19, SOLVER, SET>(),
     };
     return t;
 }
 
-// Class kernel tables, one translation unit per solver.
+// Class kernel tables, one translation unit per (solver, set).
 const ClassKernel *batch_class_table_admm();
 const ClassKernel *batch_class_table_irls();
 const ClassKernel *batch_class_table_adapt();
+const ClassKernel *batch_class_table_admm_ball();
+const ClassKernel *batch_class_table_irls_ball();
 
 }  // namespace emx

@@ -554,7 +554,14 @@ extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B,
         (o.adapt_every < 1 || !(o.adapt_ratio > 1.0f) || !(o.adapt_factor > 1.0f) ||
          !std::isfinite(o.adapt_ratio) || !std::isfinite(o.adapt_factor)))
         return fail(h, EM_ERR_INVALID_ARG, "adaptive penalty needs adapt_every >= 1, ratio > 1, factor > 1");
-    const float lo = o.box_lo ? 0.0f : o.lo, hi = o.box_lo ? 0.0f : o.hi;
+    if (o.set != EM_SET_BOX && o.set != EM_SET_BALL) return fail(h, EM_ERR_INVALID_ARG, "bad set");
+    if (o.set == EM_SET_BALL && o.box_lo) return fail(h, EM_ERR_INVALID_ARG, "a ball takes no box arrays");
+    if (o.set == EM_SET_BALL && o.solver == EM_SOLVER_ADMM_ADAPTIVE)
+        return fail(h, EM_ERR_UNSUPPORTED, "the ball is supported with ADMM and IRLS");
+    if (o.set == EM_SET_BALL && !o.ball_radius && !(o.radius >= 0.0f))
+        return fail(h, EM_ERR_INVALID_ARG, "radius must be >= 0");
+    const bool scalar_box = o.set == EM_SET_BOX && !o.box_lo;
+    const float lo = scalar_box ? o.lo : 0.0f, hi = scalar_box ? o.hi : 0.0f;
     const float rho = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
     em_status_t st = check_batch_args(h, B, a, w, inst, z, lo, hi, rho, o.max_iter, o.tol, o.init);
     if (st != EM_OK) return st;
@@ -596,6 +603,8 @@ extern "C" em_status_t em_solve_plain_ex(em_handle_t h, void *stream, int64_t B,
         return fail(h, EM_ERR_UNSUPPORTED, "this solver runs in em_solve_batch_ex");
     if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_ADMM_FAST)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");
+    if (o.set == EM_SET_BALL) return fail(h, EM_ERR_UNSUPPORTED, "the ball runs in em_solve_batch_ex");
+    if (o.set != EM_SET_BOX) return fail(h, EM_ERR_INVALID_ARG, "bad set");
     if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
         return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");
     if (o.solver == EM_SOLVER_ADMM_FAST && !(o.fast_eta > 0.0f && o.fast_eta < 1.0f))

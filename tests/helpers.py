@@ -120,7 +120,8 @@ def run_nlm(img_np, pr, wr, h, fp16=False):
 
 
 def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo=None,
-                 box_hi=None, adapt_every=1, adapt_ratio=10.0, adapt_factor=2.0, z0=None):
+                 box_hi=None, adapt_every=1, adapt_ratio=10.0, adapt_factor=2.0, z0=None,
+                 ball_center=None, ball_radius=None, radius=None):
     """em_solve_batch_ex on the GPU for a synth.PointSetBatch (box from the
     batch's lo/hi unless per-coordinate arrays are given)."""
     import torch
@@ -134,11 +135,14 @@ def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo
          torch.from_numpy(np.ascontiguousarray(z0, dtype=np.float32)).to(dev))
     bl = None if box_lo is None else torch.from_numpy(np.ascontiguousarray(box_lo, np.float32)).to(dev)
     bh = None if box_hi is None else torch.from_numpy(np.ascontiguousarray(box_hi, np.float32)).to(dev)
+    bc = None if ball_center is None else torch.from_numpy(np.ascontiguousarray(ball_center, np.float32)).to(dev)
+    br = None if ball_radius is None else torch.from_numpy(np.ascontiguousarray(ball_radius, np.float32)).to(dev)
     stats = torch.zeros((max(batch.B, 1), 4), dtype=torch.int32, device=dev)
     hd = handle()
     hd.em_solve_batch_ex(a, w, inst, z, stats, solver=solver, init=init, lo=batch.lo, hi=batch.hi,
                          box_lo=bl, box_hi=bh, rho=mu, eps=eps, max_iter=max_iter, tol=tol,
-                         adapt_every=adapt_every, adapt_ratio=adapt_ratio, adapt_factor=adapt_factor)
+                         adapt_every=adapt_every, adapt_ratio=adapt_ratio, adapt_factor=adapt_factor,
+                         ball_center=bc, ball_radius=br, radius=radius)
     hd.sync()
     it, fl, rp, rd = emx.stats_view(stats)
     return (z.cpu().numpy().astype(np.float64),

@@ -49,7 +49,7 @@ def test_struct_sizes_match_the_header():
     assert INSTANCE_DTYPE.itemsize == 32                     # em_instance_t
     assert C.sizeof(emx.NlemImage) == 8 * 3 + 4 * 6          # nlem_image_t
     assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
-    assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8   # em_options_t
+    assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8 + 8 + 8 * 2 + 8   # em_options_t
 
 
 def test_null_handle_is_rejected_without_device_work():
