@@ -354,6 +354,27 @@ em_status_t nlm_denoise(em_handle_t handle, void *stream, const void *img, int32
                         int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
                         float h_param, float *out);
 
+/*
+ * nlem_autotune - time every compiled coordinate-wave count (waves per pixel
+ * over the patch coordinates) for this image's shape and solver, `repeats`
+ * runs each after one warm-up, on `stream` (synchronously), and keep the
+ * fastest as the handle's plan for (patch radius, window class, solver).
+ * nlem_denoise, nlem_denoise_ex and nlem_denoise_multi use the plan from
+ * then on (the environment variable EMX_NLEM_WC still overrides).  When
+ * EMX_AUTOTUNE_CACHE names a file, the choice is appended to it and every
+ * later em_create on the same architecture loads it.  The image's out and
+ * stats are written by the trials (the last variant's results).
+ * chosen: NULL or receives the chosen count.
+ * Errors: as nlem_denoise_ex for one image, INVALID_ARG for repeats < 1; HIP.
+ */
+em_status_t nlem_autotune(em_handle_t handle, void *stream, const nlem_image_t *image,
+                          const nlem_options_t *opt, int32_t repeats, int32_t *chosen);
+
+/* The coordinate-wave count the handle uses for a shape and solver (the
+ * autotuned plan, else the built-in default).  Errors: INVALID_ARG. */
+em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
+                      int32_t solver, int32_t *waves);
+
 /* Wait for the stream and report any asynchronous HIP error as EM_ERR_HIP. */
 em_status_t em_sync(em_handle_t handle, void *stream);
 

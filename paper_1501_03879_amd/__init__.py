@@ -91,6 +91,11 @@ def load_library():
         lib.nlem_denoise_ex.restype = C.c_int
         lib.nlm_denoise.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, vp]
         lib.nlm_denoise.restype = C.c_int
+        lib.nlem_autotune.argtypes = [vp, vp, C.POINTER(NlemImage), C.POINTER(NlemOptions), i32,
+                                      C.POINTER(i32)]
+        lib.nlem_autotune.restype = C.c_int
+        lib.nlem_plan.argtypes = [vp, i32, i32, i32, C.POINTER(i32)]
+        lib.nlem_plan.restype = C.c_int
         lib.em_sync.argtypes = [vp, vp]
         lib.em_sync.restype = C.c_int
         lib.em_status_string.argtypes = [C.c_int]
@@ -226,6 +231,26 @@ class Handle:
                           int(max_iter), float(tol))
         st = self.lib.nlem_denoise_ex(self.h, _stream(stream), len(items), arr, C.byref(opt))
         self._check(st, "nlem_denoise_ex")
+
+    def nlem_autotune(self, item, *, solver=SOLVER_ADMM, init=NLEM_INIT_NOISY, lo=0.0, hi=255.0,
+                      rho=1e-3, eps=1e-6, max_iter=200, tol=1e-4, repeats=2, stream=None):
+        """Time the compiled coordinate-wave counts on one image (a dict as
+        for nlem_denoise_ex) and keep the fastest; returns the chosen count."""
+        arr = _image_array([item])
+        opt = NlemOptions(int(solver), int(init), float(lo), float(hi), float(rho), float(eps),
+                          int(max_iter), float(tol))
+        chosen = C.c_int32(0)
+        st = self.lib.nlem_autotune(self.h, _stream(stream), arr, C.byref(opt), int(repeats),
+                                    C.byref(chosen))
+        self._check(st, "nlem_autotune")
+        return chosen.value
+
+    def nlem_plan(self, patch_radius, window_radius, solver=SOLVER_ADMM):
+        """Coordinate-wave count used for this shape and solver."""
+        waves = C.c_int32(0)
+        self._check(self.lib.nlem_plan(self.h, int(patch_radius), int(window_radius), int(solver),
+                                       C.byref(waves)), "nlem_plan")
+        return waves.value
 
     def nlm_denoise(self, img, out, *, patch_radius, window_radius, h, stream=None):
         """Non-Local Means: img H x W float32/float16, out H x W float32."""

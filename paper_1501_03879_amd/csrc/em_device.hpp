@@ -173,31 +173,6 @@ __device__ __forceinline__ float reduce_scatter_full(const float (&x)[V], int la
     return rs_dpp_stage<0xB1>(e[0], (1 < K5) ? e[1] : 0.0f, u1);                                          // lane ^ 1
 }
 
-// The second half of reduce_scatter, for callers that produced the stage-A
-// pairs t[j] = swap32_sum(x[j], x[j + H1]) themselves (streaming stage A
-// inside the loop that computes x keeps only H1 partial sums live).
-template <int V>
-__device__ __forceinline__ void reduce_scatter_from_pairs(const float (&t)[RS<V>::H1],
-                                                          float (&out)[RS<V>::H2]) {
-    constexpr int H1 = RS<V>::H1, H2 = RS<V>::H2;
-#pragma unroll
-    for (int j = 0; j < H2; ++j) out[j] = swap16_sum(t[j], (j + H2 < H1) ? t[j + H2] : 0.0f);
-#pragma unroll
-    for (int j = 0; j < H2; ++j) out[j] = row_sum16(out[j]);
-}
-
-// Order in which a streaming producer visits V coordinates so that each
-// stage-A pair (k, k + H1) completes as early as possible: 0, H1, 1, H1+1, ...
-template <int V>
-__host__ __device__ constexpr int rs_visit(int u) {
-    constexpr int H1 = RS<V>::H1;
-    return (u & 1) ? (u >> 1) + H1 : (u >> 1);
-}
-template <int V>
-__host__ __device__ constexpr int rs_visits() {
-    return 2 * RS<V>::H1 - ((V & 1) ? 1 : 0);  // V visits; the unpaired last one is H1 - 1
-}
-
 // Reads a wave-uniform float held by lane `lane` of a VGPR into an SGPR.
 __device__ __forceinline__ float readlane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));

@@ -7,8 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "emx_internal.hpp"
@@ -16,7 +16,7 @@
 
 namespace emx {
 
-// batch_kernel.hip
+// batch_host.hip
 em_status_t batch_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
                         const float *w, const em_instance_t *inst, const em_options_t &o, float *z,
                         em_stats_t *stats);
@@ -38,9 +38,15 @@ struct MultiGraph {
     hipGraphExec_t exec = nullptr;
 };
 
+// Autotuned NLEM plans: (patch radius, points per lane, solver) -> coordinate waves.
+using PlanKey = std::tuple<int, int, int>;
+
 struct em_context {
     int device = 0;
     int num_cus = 0;
+    std::string arch;                   // gcnArchName of the device (cache key)
+    std::map<PlanKey, int> plans;       // measured by nlem_autotune or loaded from the cache
+    int plan_epoch = 0;                 // bumped when a plan changes (invalidates the multi graph)
     unsigned int *counters = nullptr;  // kNumCounters work-queue heads
     int num_counters = 0;
     std::string last_error;
@@ -144,6 +150,34 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
 }  // namespace emx
 
 // ---------------------------------------------------------------------------
+// autotune cache: text lines "nlem <arch> <patch radius> <points per lane>
+// <solver> <coordinate waves>" in the file named by EMX_AUTOTUNE_CACHE
+// ---------------------------------------------------------------------------
+
+static void load_plan_cache(em_context *ctx) {
+    const char *path = getenv("EMX_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char kind[16], arch[64];
+    int pr, m, solver, wc;
+    while (fscanf(f, "%15s %63s %d %d %d %d", kind, arch, &pr, &m, &solver, &wc) == 6) {
+        if (strcmp(kind, "nlem") == 0 && ctx->arch == arch && nlem_kernel(pr, m, wc, solver).fn)
+            ctx->plans[PlanKey{pr, m, solver}] = wc;   // later lines win
+    }
+    fclose(f);
+}
+
+static void append_plan_cache(const em_context *ctx, int pr, int m, int solver, int wc) {
+    const char *path = getenv("EMX_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "nlem %s %d %d %d %d\n", ctx->arch.c_str(), pr, m, solver, wc);
+    fclose(f);
+}
+
+// ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
 
@@ -165,6 +199,13 @@ extern "C" em_status_t em_create(em_handle_t *handle, int device) {
         return EM_ERR_HIP;
     }
     ctx->num_cus = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    {
+        std::string a = ctx->arch;
+        const size_t colon = a.find(':');
+        if (colon != std::string::npos) ctx->arch = a.substr(0, colon);
+    }
+    load_plan_cache(ctx);
     if (hipMalloc(&ctx->counters, kNumCounters * sizeof(unsigned int)) != hipSuccess) {
         delete ctx;
         return EM_ERR_OUT_OF_MEMORY;
@@ -225,12 +266,17 @@ static constexpr float kArmFactor = 1.0f;
 
 static int points_per_lane(int R) { return ((2 * R + 1) * (2 * R + 1) + 63) / 64; }
 
-// Kernel for a shape: the default coordinate-wave count, or EMX_NLEM_WC when
-// that variant is compiled (a tuning override).
-static NlemKernelInfo select_nlem_kernel(int pr, int m, int solver) {
+// Kernel for a shape: EMX_NLEM_WC when that variant is compiled (a manual
+// override), else the handle's autotuned plan, else the default table.
+static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solver) {
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
         NlemKernelInfo k = nlem_kernel(pr, m, atoi(env), solver);
+        if (k.fn) return k;
+    }
+    auto it = h->plans.find(PlanKey{pr, m, solver});
+    if (it != h->plans.end()) {
+        NlemKernelInfo k = nlem_kernel(pr, m, it->second, solver);
         if (k.fn) return k;
     }
     return nlem_kernel(pr, m, nlem_default_wc(pr, m), solver);
@@ -360,7 +406,7 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
     if (st != EM_OK) return st;
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const NlemGroup &g = groups[gi];
-        NlemKernelInfo k = select_nlem_kernel(g.pr, g.m, o.solver);
+        NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver);
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
         const int64_t total = L.prefix[L.count];
@@ -416,6 +462,70 @@ extern "C" em_status_t nlm_denoise(em_handle_t h, void *stream, const void *img,
     return nlem_run(h, static_cast<hipStream_t>(stream), 1, &im, o);
 }
 
+extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_image_t *image,
+                                     const nlem_options_t *opt, int32_t repeats, int32_t *chosen) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (!image) return fail(h, EM_ERR_INVALID_ARG, "image must be non-NULL");
+    em_status_t st = check_image(h, *image);
+    if (st != EM_OK) return st;
+    st = check_options(h, opt);
+    if (st != EM_OK) return st;
+    if (repeats < 1) return fail(h, EM_ERR_INVALID_ARG, "repeats must be >= 1");
+    EMX_HIP(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int pr = image->patch_radius, m = points_per_lane(image->window_radius);
+    const PlanKey key{pr, m, opt->solver};
+    hipEvent_t e0, e1;
+    EMX_HIP(h, hipEventCreate(&e0));
+    EMX_HIP(h, hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int wc = 1; wc <= 4; ++wc) {
+        if (!nlem_kernel(pr, m, wc, opt->solver).fn) continue;
+        h->plans[key] = wc;
+        st = nlem_run(h, s, 1, image, *opt);   // warm-up (and occupancy query)
+        if (st != EM_OK) break;
+        hipError_t e = hipEventRecord(e0, s);
+        for (int r = 0; r < repeats && st == EM_OK && e == hipSuccess; ++r) st = nlem_run(h, s, 1, image, *opt);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = hip_fail(h, e, "autotune timing");
+            break;
+        }
+        if (st != EM_OK) break;
+        if (best == 0 || ms < best_ms) {
+            best = wc;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != EM_OK || best == 0) {
+        h->plans.erase(key);
+        return st != EM_OK ? st : fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
+    }
+    h->plans[key] = best;
+    ++h->plan_epoch;
+    append_plan_cache(h, pr, m, opt->solver, best);
+    if (chosen) *chosen = best;
+    return EM_OK;
+}
+
+extern "C" em_status_t nlem_plan(em_handle_t h, int32_t patch_radius, int32_t window_radius,
+                                 int32_t solver, int32_t *waves) {
+    if (!h || !waves) return EM_ERR_INVALID_ARG;
+    if (patch_radius < 0 || patch_radius > EM_MAX_PATCH_RADIUS || window_radius < 0 ||
+        window_radius > EM_MAX_WINDOW_RADIUS || (solver != NLEM_SOLVER_ADMM && solver != NLEM_SOLVER_IRLS))
+        return fail(h, EM_ERR_INVALID_ARG, "bad shape or solver");
+    const int m = points_per_lane(window_radius);
+    auto it = h->plans.find(PlanKey{patch_radius, m, solver});
+    *waves = (it != h->plans.end()) ? it->second : nlem_default_wc(patch_radius, m);
+    return EM_OK;
+}
+
 static bool same_key(const std::vector<char> &a, const std::vector<char> &b) {
     return a.size() == b.size() && memcmp(a.data(), b.data(), a.size()) == 0;
 }
@@ -436,10 +546,11 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    std::vector<char> key(sizeof(nlem_image_t) * count + 5 * sizeof(float));
+    std::vector<char> key(sizeof(nlem_image_t) * count + 5 * sizeof(float) + sizeof(int));
     memcpy(key.data(), images, sizeof(nlem_image_t) * count);
     float params[5] = {lo, hi, rho, (float)max_iter, tol};
     memcpy(key.data() + sizeof(nlem_image_t) * count, params, sizeof(params));
+    memcpy(key.data() + sizeof(nlem_image_t) * count + sizeof(params), &h->plan_epoch, sizeof(int));
 
     if (!h->multi.exec || !same_key(key, h->multi.key)) {
         if (h->multi.exec) (void)hipGraphExecDestroy(h->multi.exec);
@@ -452,7 +563,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         EMX_HIP(h, hipGraphCreate(&graph, 0));
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const NlemGroup &g = groups[gi];
-            NlemKernelInfo k = select_nlem_kernel(g.pr, g.m, NLEM_SOLVER_ADMM);
+            NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM);
             unsigned int *counter = h->counters + gi;
             NlemLaunch L = make_launch(g, images, o, counter);
             // node 1: zero this group's work-queue head (a kernel, not a memset node)

@@ -35,22 +35,4 @@ struct NlemLaunch {
     unsigned int *counter;  // work-queue head, zeroed before the launch
 };
 
-// Batch solve: a shape class of instances (listed in `list`).
-struct BatchLaunch {
-    const float *a;
-    const float *w;
-    const em_instance_t *inst;
-    const int32_t *list;       // instance ids of this class
-    const unsigned int *list_count;
-    unsigned int *counter;     // work-queue head, zeroed before the launch
-    float *z;
-    em_stats_t *stats;
-    float lo, hi, inv_mu_unused;
-    float mu;
-    float tol;
-    float arm;                 // factor on tol*D for arming the primal residual
-    int32_t max_iter;
-    int32_t init;
-};
-
 }  // namespace emx

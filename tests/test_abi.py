@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("em_create", "em_destroy", "em_solve_batch", "em_solve_plain", "nlem_denoise",
                  "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_solve_batch_ex", "em_solve_plain_ex",
-                 "em_sync",
+                 "em_sync", "nlem_autotune", "nlem_plan",
                  "em_status_string", "em_last_error"):
         assert must in names
 
@@ -72,6 +72,10 @@ def test_null_handle_is_rejected_without_device_work():
     lib.nlm_denoise.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_float, vp]
     assert lib.nlm_denoise(None, None, None, 0, 8, 8, 1, 1, 1.0, None) == -1
+    lib.nlem_autotune.argtypes = [vp, vp, vp, vp, C.c_int32, vp]
+    assert lib.nlem_autotune(None, None, None, None, 1, None) == -1
+    lib.nlem_plan.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
+    assert lib.nlem_plan(None, 3, 10, 0, None) == -1
     assert lib.em_sync(None, None) == -1
     assert lib.em_destroy(None) == 0
     lib.em_create.argtypes = [C.POINTER(vp), C.c_int]
