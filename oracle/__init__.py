@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "em_oracle.c")
 _LIB = os.path.join(_HERE, "libemoracle.so")
 
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
-INIT_GIVEN, INIT_MAXW = 0, 1
+INIT_GIVEN, INIT_MAXW, INIT_WMEAN = 0, 1, 2
 SOLVER_ADMM, SOLVER_IRLS, SOLVER_FAST_ADMM = 0, 1, 3
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 

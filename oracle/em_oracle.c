@@ -33,6 +33,7 @@
 
 #define OR_INIT_GIVEN 0
 #define OR_INIT_MAXW 1
+#define OR_INIT_WMEAN 2
 
 /*
  * Proximal map of f(x) = lambda * ||x - u||_2, equation (closed-form):
@@ -583,7 +584,10 @@ int oracle_max_threads(void)
  * buffers the GPU reads, widened to binary64 here).  Instance b has n[b]
  * points of dimension d[b] at a + a_off[b], weights at w + w_off[b] and its
  * result at z + z_off[b].  init = GIVEN uses z as the initial value; init =
- * MAXW starts from the point of largest weight (lowest index on ties).
+ * MAXW starts from the point of largest weight (lowest index on ties); init =
+ * WMEAN from the weighted mean sum_k w_k a_k / sum_k w_k (the counterpart of
+ * the NLM patch that Section 4 starts from), or the plain mean of the points
+ * when every weight is zero.
  * max_iter_each (nullable) overrides max_iter per instance.
  * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
  * on the surrogate with eps, 3 = accelerated ADMM with restart parameter eta.
@@ -626,6 +630,15 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
             for (int64_t k = 1; k < n; ++k)
                 if (wb[k] > wb[best]) best = k;
             for (int64_t j = 0; j < d; ++j) zb[j] = ab[best * d + j];
+        }
+        if (init == OR_INIT_WMEAN && n > 0) {
+            double W = 0.0;
+            for (int64_t k = 0; k < n; ++k) W += wb[k];
+            for (int64_t j = 0; j < d; ++j) {
+                double s = 0.0;
+                for (int64_t k = 0; k < n; ++k) s += (W > 0.0 ? wb[k] : 1.0) * ab[k * d + j];
+                zb[j] = s / (W > 0.0 ? W : (double)n);
+            }
         }
         int64_t it = 0;
         double rp = 0.0, rd = 0.0, mf = mu;

@@ -8,7 +8,9 @@ coordinate-wise translation equivariance (a swapped coordinate index of the
 bounds fails it), the 1-D clamp property, agreement of the adaptive and
 fixed-penalty solvers at the (unique) minimiser, factor = 1 reducing to the
 fixed penalty exactly, and the adaptive rule moving a badly scaled penalty in
-the right direction.
+the right direction.  The weighted-mean start of the batch (the counterpart of
+the NLM patch) is pinned by closed-form means and by reaching the same
+minimiser as the largest-weight start.
 """
 
 import numpy as np
@@ -308,3 +310,47 @@ def test_ball_containing_the_median_changes_nothing_and_bad_radius(orc):
     np.testing.assert_allclose(big, free, atol=1e-9)
     r = orc.em_solve_ball(a, w, 0.5, np.zeros(3), -1.0, a[0])
     assert r["flags"] == orc.BAD_INPUT and np.all(np.isnan(r["z"]))
+
+
+# ------------------------------------------------------------ weighted-mean start
+
+def _wmean_batch():
+    """Instances whose weighted means have closed forms:
+    1-D {0, 2, 7} equal weights -> 3; 1-D {0, 4} weights (1, 3) -> 3;
+    a triangle (0,0), (4,0), (0,4) with weights (1, 1, 2) -> (1, 2);
+    one nonzero weight -> that point; every weight zero -> the plain mean."""
+    pts = [np.array([[0.0], [2.0], [7.0]]), np.array([[0.0], [4.0]]),
+           np.array([[0.0, 0.0], [4.0, 0.0], [0.0, 4.0]]),
+           np.array([[1.0, -2.0, 3.0], [5.0, 6.0, -7.0], [9.0, 1.0, 2.0]]),
+           np.array([[1.0, 2.0], [3.0, 8.0], [-4.0, 5.0], [8.0, -3.0]])]
+    wts = [np.ones(3), np.array([1.0, 3.0]), np.array([1.0, 1.0, 2.0]),
+           np.array([0.0, 2.5, 0.0]), np.zeros(4)]
+    want = [[3.0], [3.0], [1.0, 2.0], [5.0, 6.0, -7.0], [2.0, 3.0]]
+    return synth.pointsets.pack_instances(pts, wts, -100.0, 100.0), want
+
+
+def test_wmean_start_closed_forms(orc):
+    """max_iter = 0 returns the start unchanged: the weighted mean (exactly
+    representable here), not projected."""
+    b, want = _wmean_batch()
+    r = orc.em_batch(b, 1.0, 0, 0.0, init=orc.INIT_WMEAN)
+    for i, wv in enumerate(want):
+        e = b.inst[i]
+        np.testing.assert_allclose(r["z"][e["z_off"]:e["z_off"] + e["d"]], wv, rtol=0, atol=1e-12)
+    # unprojected: a box that excludes the mean leaves it in place at max_iter 0
+    b2 = synth.pointsets.pack_instances([np.array([[0.0], [2.0], [7.0]])], [np.ones(3)], 5.0, 6.0)
+    r2 = orc.em_batch(b2, 1.0, 0, 0.0, init=orc.INIT_WMEAN)
+    assert r2["z"][0] == 3.0
+    r3 = orc.em_batch(b2, 1.0, 1, 0.0, init=orc.INIT_WMEAN)
+    assert 5.0 <= r3["z"][0] <= 6.0
+
+
+def test_wmean_start_same_minimiser(orc):
+    """The minimiser does not depend on the start: WMEAN and MAXW starts reach
+    the same point (strictly convex instances, many iterations)."""
+    b = synth.make_pointset_batch(21, 12, n_lo=5, n_hi=40, d_choices=(2, 3, 7))
+    ra = orc.em_batch(b, 0.5, 4000, 0.0, init=orc.INIT_WMEAN)
+    rb = orc.em_batch(b, 0.5, 4000, 0.0, init=orc.INIT_MAXW)
+    np.testing.assert_allclose(ra["z"], rb["z"], rtol=0, atol=1e-6 * (b.hi - b.lo))
+    ri = orc.em_batch(b, 0.5, 400, 0.0, init=orc.INIT_WMEAN, solver=orc.SOLVER_IRLS, eps=1e-10)
+    np.testing.assert_allclose(ri["z"], rb["z"], rtol=0, atol=1e-4 * (b.hi - b.lo))
