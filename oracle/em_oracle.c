@@ -464,8 +464,9 @@ double oracle_surrogate_objective(int64_t n, int64_t d, const double *a, const d
  * Every step therefore decreases the surrogate (unless z^t is its minimiser).
  * Stopping: after iteration t, r_dual = sqrt(||z^{t+1} - z^t||^2 / d) <= tol D
  * with D as for EM-ADMM (there is no primal residual; *r_pri is set to 0).
- * All weights zero: every z minimises the surrogate; z is left as given and
- * the solve reports CONVERGED after one iteration.
+ * All weights zero: every point of C minimises the surrogate over C; the
+ * start projected onto C is returned (as EM-ADMM returns after its first
+ * z-update) and the solve reports CONVERGED after one iteration.
  * Flags, init and the n = 0 / bad-input rules are those of oracle_em_solve.
  */
 static int irls_solve_set(int64_t n, int64_t d, const double *a, const double *w, double eps,
@@ -508,11 +509,13 @@ static int irls_solve_set(int64_t n, int64_t d, const double *a, const double *w
         if (den > 0.0) {
             for (int64_t j = 0; j < d; ++j) num[j] = num[j] / den;
             project_set(C, d, num, zn);
-            for (int64_t j = 0; j < d; ++j) {
-                double e = zn[j] - z[j];
-                sd += e * e;
-                z[j] = zn[j];
-            }
+        } else {
+            project_set(C, d, z, zn);   /* the problem is posed over C */
+        }
+        for (int64_t j = 0; j < d; ++j) {
+            double e = zn[j] - z[j];
+            sd += e * e;
+            z[j] = zn[j];
         }
         *r_dual = sqrt(sd / (double)d);
         *iters = t;

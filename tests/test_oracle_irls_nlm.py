@@ -124,7 +124,8 @@ def test_irls_worked_example_three_points(orc):
 
 def test_irls_flags(orc):
     """n = 0 -> EMPTY; eps <= 0 or a bad weight -> BAD_INPUT (z = NaN); all
-    weights zero -> CONVERGED after one iteration with z unchanged."""
+    weights zero -> CONVERGED after one iteration with the start projected
+    onto C (unchanged when it lies in C; clamped per coordinate otherwise)."""
     assert orc.irls_solve(np.zeros((0, 2)), np.zeros(0), 1e-6, 0, 1, [0.5, 0.5])["flags"] == orc.EMPTY
     r = orc.irls_solve(np.ones((3, 2)), [1, 1, 1], 0.0, 0, 1, [0.5, 0.5])
     assert r["flags"] == orc.BAD_INPUT and np.all(np.isnan(r["z"]))
@@ -133,6 +134,12 @@ def test_irls_flags(orc):
     r = orc.irls_solve(np.ones((3, 2)), [0, 0, 0], 1e-6, 0, 1, [0.25, 0.5], max_iter=9, tol=1e-3)
     assert r["flags"] == orc.CONVERGED and r["iters"] == 1
     np.testing.assert_array_equal(r["z"], [0.25, 0.5])
+    r = orc.irls_solve(np.ones((3, 2)), [0, 0, 0], 1e-6, 0, 1, [-0.25, 1.5], max_iter=9, tol=1e-3)
+    assert r["flags"] == orc.CONVERGED and r["iters"] == 1
+    np.testing.assert_array_equal(r["z"], [0.0, 1.0])
+    r = orc.irls_solve_ball(np.ones((3, 2)), [0, 0, 0], 1e-6, [1.0, 1.0], 2.0, [4.0, 5.0], max_iter=9)
+    assert r["iters"] == 1
+    np.testing.assert_allclose(r["z"], [2.2, 2.6], rtol=0, atol=1e-14)
 
 
 # ---- Non-Local Means -------------------------------------------------------
