@@ -68,7 +68,10 @@ enum {
 /* Starting value of z for em_solve_batch / em_solve_plain. */
 typedef enum {
     EM_INIT_GIVEN = 0, /* the caller's z (in/out) */
-    EM_INIT_MAXW = 1   /* the point of largest weight, lowest index on ties */
+    EM_INIT_MAXW = 1,  /* the point of largest weight, lowest index on ties */
+    EM_INIT_WMEAN = 2  /* the weighted mean sum_k w_k a_k / sum_k w_k, the analogue of the
+                          NLM patch of Section 4 (the plain mean of the points when every
+                          weight is zero); not projected, like the other starts */
 } em_init_t;
 
 /* Limits of this build. */
@@ -198,7 +201,8 @@ typedef struct {
  *     z' = P_C(sum_k omega_k a_k / sum_k omega_k) (majorise-minimise steps of
  *     the surrogate; the box projection is exact for its isotropic
  *     quadratic majoriser); stopped on r_dual alone (stats r_pri = 0); all
- *     weights zero leaves z unchanged and reports CONVERGED.
+ *     weights zero: every point of C is a minimiser, z becomes the start
+ *     projected onto C and the solve reports CONVERGED after one iteration.
  * Other arguments, limits and per-instance rules as for em_solve_batch.
  * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
  * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1

@@ -203,6 +203,29 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
             if (!(Wt[k] >= 0.0f && Wt[k] <= FLT_MAX)) flag = 1;
     }
     __syncthreads();
+    if (flag == 0 && P.init == EM_INIT_WMEAN) {
+        // weighted mean, weights scaled by their largest value and points by 1/n
+        // (equal weights when every weight is zero); thread j sums coordinate j
+        if (tid == 0) {
+            float wm = 0.0f;
+            for (int k = 0; k < n; ++k) wm = fmaxf(wm, Wt[k]);
+            red[0] = wm;
+        }
+        __syncthreads();
+        const float wm = red[0];
+        const bool uni = !(wm > 0.0f);
+        const float inv_n = 1.0f / (float)n;
+        if (tid < d) {
+            float acc = 0.0f, cs = 0.0f;
+            for (int k = 0; k < n; ++k) {
+                const float c = (uni ? 1.0f : Wt[k] / wm) * inv_n;
+                cs += c;
+                acc = fmaf(c, A[k * d + tid], acc);
+            }
+            zs[tid] = acc / cs;
+        }
+        __syncthreads();
+    }
     float wmax = 0.0f;
     if (flag == 0 && tid == 0) {
         int best = 0;
@@ -210,7 +233,7 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
             for (int k = 1; k < n; ++k)
                 if (Wt[k] > Wt[best]) best = k;
         for (int j = 0; j < d; ++j) {
-            zs[j] = (P.init == EM_INIT_MAXW) ? A[best * d + j] : Z[j];
+            zs[j] = (P.init == EM_INIT_MAXW) ? A[best * d + j] : (P.init == EM_INIT_WMEAN) ? zs[j] : Z[j];
             blo[j] = P.box_lo ? P.box_lo[e.z_off + j] : P.lo;
             bhi[j] = P.box_lo ? P.box_hi[e.z_off + j] : P.hi;
             if (!(fabsf(zs[j]) <= FLT_MAX) || !(blo[j] <= bhi[j])) flag = 1;

@@ -225,6 +225,69 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             }
         }
 
+        // ---- WMEAN init: sum_k w_k a_k / sum_k w_k, the weights scaled by their
+        // largest value and the points by 1/n (no overflow); every weight zero:
+        // equal weights
+        float zw[H2];
+        if (L.init == EM_INIT_WMEAN) {
+            float wl = 0.0f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) wl = fmaxf(wl, lam[q]);
+            float wmx = wave_max(wl);
+            if constexpr (WP > 1) {
+                if (lane == 0) xs[wave * 4 + 2] = wmx;
+                __syncthreads();
+                wmx = xs[2];
+#pragma unroll
+                for (int v = 1; v < WP; ++v) wmx = fmaxf(wmx, xs[(v * WC) * 4 + 2]);
+            }
+            wmx = readfirstlane(wmx);
+            const bool uni = !(wmx > 0.0f);
+            const float sw = uni ? 0.0f : 1.0f / wmx;
+            const float inv_n = 1.0f / (float)n;
+            float cq[M];
+            float cs = 0.0f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                cq[q] = (lam[q] >= 0.0f) ? (uni ? 1.0f : lam[q] * sw) * inv_n : 0.0f;
+                cs += cq[q];
+            }
+            float acc[DS];
+#pragma unroll
+            for (int jj = 0; jj < DS; ++jj) {
+                float ac = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) ac = fmaf(-cq[q], na[q][jj], ac);   // na = -a
+                acc[jj] = ac;
+            }
+            reduce_scatter<DS>(acc, zw);
+            float Cs = readfirstlane(wave_sum(cs));
+            if constexpr (WP > 1) {
+                float *XE = xe;   // buffer 0; the solve's first exchange uses buffer 1
+                float *XO = xo;
+                if (lane == 16 * row) {
+#pragma unroll
+                    for (int j = 0; j < H2; ++j) XE[((pw * WC + cw) * H2 + j) * 4 + row] = zw[j];
+                }
+                if (cw == 0 && lane == 0) XO[pw] = Cs;
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < H2; ++j) {
+                    float sum = XE[(cw * H2 + j) * 4 + row];
+#pragma unroll
+                    for (int v = 1; v < WP; ++v) sum += XE[((v * WC + cw) * H2 + j) * 4 + row];
+                    zw[j] = sum;
+                }
+                float os = XO[0];
+#pragma unroll
+                for (int v = 1; v < WP; ++v) os += XO[v];
+                Cs = readfirstlane(os);
+            }
+            const float inv_c = 1.0f / Cs;
+#pragma unroll
+            for (int j = 0; j < H2; ++j) zw[j] *= inv_c;
+        }
+
         // ---- starting z and the box in the reduced layout
         float zr[H2];
         bool zbad = false;
@@ -235,7 +298,8 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             const bool vj = RSx::valid(row, j) && cc < d;
             float zv = 0.0f, lv = BALL ? 0.0f : L.lo, hv = BALL ? 0.0f : L.hi;
             if (vj) {
-                zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc] : Z[cc];
+                zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc]
+                     : (L.init == EM_INIT_WMEAN) ? zw[j] : Z[cc];
                 if (BALL) {
                     if (L.ball_center) lv = L.ball_center[e.z_off + cc];
                 } else if (vbox) {
@@ -441,7 +505,9 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     for (int v = 1; v < WP; ++v) os += XO[v];
                     Om = readfirstlane(os);
                 }
-                const float inv_om = (Om > 0.0f) ? 1.0f / Om : 0.0f;
+                // all weights zero: every point of C is a minimiser; z' = P_C(z)
+                const bool live = Om > 0.0f;
+                const float inv_om = live ? 1.0f / Om : 0.0f;
                 float fb = 1.0f;
                 if constexpr (BALL) {
                     float s2 = 0.0f;
@@ -449,7 +515,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     for (int j = 0; j < H2; ++j) {
                         const int cc = cw * DS + RSx::coord(row, j);
                         const bool vj = RSx::valid(row, j) && cc < d;
-                        const float dv = (z0[j] - Bl_s[j * 4 + row]) + (-E[j] * inv_om);
+                        const float dv = (z0[j] - Bl_s[j * 4 + row]) + (live ? -E[j] * inv_om : zr[j]);
                         s2 += vj ? dv * dv : 0.0f;
                     }
                     fb = ball_factor(s2, t);
@@ -460,7 +526,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
                     // z' - z0 = P_C(z0 + raw) - z0, exact when the set is inactive
-                    const float raw = -E[j] * inv_om;
+                    const float raw = live ? -E[j] * inv_om : zr[j];
                     float zn;
                     if constexpr (BALL) {
                         const float cn = Bl_s[j * 4 + row];
@@ -470,7 +536,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         const float bl = Bl_s[j * 4 + row], bh = Bh_s[j * 4 + row];
                         zn = (zab < bl) ? bl - z0[j] : ((zab > bh) ? bh - z0[j] : raw);
                     }
-                    zn = (vj && Om > 0.0f) ? zn : zr[j];
+                    zn = vj ? zn : zr[j];
                     const float dz = zn - zr[j];
                     rdx += dz * dz;
                     if (lane == 16 * row && RSx::valid(row, j)) cv[RSx::coord(row, j)] = zn;
@@ -479,10 +545,20 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 const float rdw = readfirstlane((readlane(rdx, 0) + readlane(rdx, 16)) +
                                                 (readlane(rdx, 32) + readlane(rdx, 48)));
                 rd_w = (pw == 0) ? rdw : 0.0f;
-                if (uniform(!(Om > 0.0f))) {   // all weights zero: every z is a minimiser
+                if (uniform(!live)) {   // all weights zero: done after the projection
+                    float rd_all = rd_w;
+                    if constexpr (WC > 1 || WP > 1) {
+                        float *XS = xs + 2 * WC * WP * 4;   // third slot (unused by IRLS otherwise)
+                        if (lane == 0) XS[wave * 4] = rd_w;
+                        __syncthreads();
+                        rd_all = 0.0f;
+#pragma unroll
+                        for (int v = 0; v < WC * WP; ++v) rd_all += XS[v * 4];
+                        rd_all = readfirstlane(rd_all);
+                    }
+                    rd2 = rd_all * inv_d;
                     flags = EM_CONVERGED;
                     iters = t;
-                    rd2 = 0.0f;
                     done = true;
                     break;
                 }

@@ -622,7 +622,8 @@ static em_status_t check_batch_args(em_context *h, int64_t B, const float *a, co
     if (B < 0) return fail(h, EM_ERR_INVALID_ARG, "B must be >= 0");
     if (B > 0 && (!a || !w || !inst || !z)) return fail(h, EM_ERR_INVALID_ARG, "NULL array with B > 0");
     if (B >= ((int64_t)1 << 31)) return fail(h, EM_ERR_UNSUPPORTED, "B too large");
-    if (init != EM_INIT_GIVEN && init != EM_INIT_MAXW) return fail(h, EM_ERR_INVALID_ARG, "bad init");
+    if (init != EM_INIT_GIVEN && init != EM_INIT_MAXW && init != EM_INIT_WMEAN)
+        return fail(h, EM_ERR_INVALID_ARG, "bad init");
     return check_solver_params(h, lo, hi, rho, max_iter, tol);
 }
 

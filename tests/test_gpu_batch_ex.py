@@ -210,6 +210,89 @@ def test_plain_admm_per_coordinate_boxes():
     _check(b, got, ref["z"], 3.0, "plain admm per-coordinate boxes T25")
 
 
+def _zero_some_weights(b, every=37):
+    """Every `every`-th instance gets all-zero weights (its weighted-mean start
+    is then the plain mean of its points)."""
+    w = b.w.copy()
+    for i in range(0, b.B, every):
+        e = b.inst[i]
+        w[e["w_off"]:e["w_off"] + e["n"]] = 0.0
+    b.w = w
+    return b
+
+
+def test_wmean_start_zero_iterations():
+    """max_iter = 0 returns the weighted-mean start (FP32 sums against FP64):
+    closed-form instances, then every shape class, batched and plain.  Bars:
+    1e-5 D for the batched kernel (in-lane sums of <= 8 terms, then a 64-lane
+    tree); the plain kernel sums each coordinate serially over n points, so
+    each coordinate gets the serial-sum bound of a weighted mean,
+    2 n u sum_k w_k |a_kj| / sum_k w_k (numerator and denominator, u = 2^-24),
+    plus 1e-7 D."""
+    pts = [np.array([[0.0], [2.0], [7.0]]), np.array([[0.0], [4.0]]),
+           np.array([[0.0, 0.0], [4.0, 0.0], [0.0, 4.0]]), np.array([[1.0, 2.0], [3.0, 8.0], [-4.0, 5.0], [8.0, -3.0]])]
+    wts = [np.ones(3), np.array([1.0, 3.0]), np.array([1.0, 1.0, 2.0]), np.zeros(4)]
+    bc = synth.pointsets.pack_instances(pts, wts, 5.0, 6.0)   # the box excludes every start
+    got, st = run_batch_ex(bc, solver=ADMM, max_iter=0, tol=0.0, init=oracle.INIT_WMEAN)
+    np.testing.assert_allclose(got[:bc.z_size], [3.0, 3.0, 1.0, 2.0, 2.0, 3.0], rtol=0, atol=1e-6)
+    # IRLS: the zero-weight instance ends at the projected start after one iteration
+    got, st = run_batch_ex(bc, solver=IRLS, max_iter=3, tol=0.0, init=oracle.INIT_WMEAN, eps=1e-4)
+    ref = oracle.em_batch(bc, 0.5, 3, 0.0, init=oracle.INIT_WMEAN, solver=oracle.SOLVER_IRLS, eps=1e-4)
+    _check(bc, got, ref["z"], 1.0, "batch irls wmean start, box excluding the starts T3")
+    np.testing.assert_array_equal(got[4:6], [5.0, 5.0])
+    assert st["iters"][3] == 1 and st["flags"][3] == 1 and np.all(st["iters"][:3] == 3)
+    b = _zero_some_weights(_mixed(41, 400))
+    for solver in (ADMM, IRLS):
+        got, st = run_batch_ex(b, solver=solver, max_iter=0, tol=0.0, init=oracle.INIT_WMEAN)
+        ref = oracle.em_batch(b, 0.5, 0, 0.0, init=oracle.INIT_WMEAN)
+        _check(b, got, ref["z"], 6.0, f"batch wmean start T0 solver {solver}", tol=1e-5)
+    bp = b.subset(np.arange(0, b.B, 5))
+    got, st = run_plain_ex(bp, solver=ADMM, max_iter=0, tol=0.0, init=oracle.INIT_WMEAN)
+    ref = oracle.em_batch(bp, 0.5, 0, 0.0, init=oracle.INIT_WMEAN)
+    bound = np.zeros(bp.z_size)
+    for i in range(bp.B):
+        e = bp.inst[i]
+        if e["n"] == 0:
+            continue
+        a = bp.points(i).astype(np.float64)
+        w = bp.weights(i).astype(np.float64)
+        w = w if w.sum() > 0 else np.ones_like(w)
+        bound[e["z_off"]:e["z_off"] + e["d"]] = 2 * e["n"] * 2.0 ** -24 * (w @ np.abs(a)) / w.sum()
+    err = np.abs(got[:bp.z_size] - ref["z"][:bp.z_size])
+    report("plain wmean start T0 (error / per-coordinate bound)", float(np.max(err / (bound + 6e-7))), 0.0)
+    assert np.all(err <= bound + 6e-7)
+
+
+@pytest.mark.parametrize("solver", [ADMM, IRLS, ADAPT])
+def test_wmean_start_fixed_iterations(solver):
+    b = _zero_some_weights(_mixed(42 + solver, 400))
+    got, st = run_batch_ex(b, solver=solver, max_iter=25, tol=0.0, init=oracle.INIT_WMEAN, eps=1e-4)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_WMEAN, eps=1e-4,
+                          solver=oracle.SOLVER_IRLS if solver == IRLS else oracle.SOLVER_ADMM,
+                          adapt_every=1 if solver == ADAPT else 0)
+    _check(b, got, ref["z"], 6.0, f"batch wmean start T25 solver {solver}")
+    live = b.inst["n"] > 0
+    zero = np.zeros(b.B, bool)
+    zero[::37] = True
+    if solver == IRLS:   # all weights zero: the projected start, after one iteration
+        assert np.all(st["iters"][live & zero] == 1) and np.all(st["flags"][live & zero] == 1)
+        assert np.all(st["iters"][live & ~zero] == 25)
+    else:
+        assert np.all(st["iters"][live] == 25)
+
+
+def test_wmean_start_plain_and_ball():
+    b = _zero_some_weights(_mixed(45, 60))
+    got, st = run_plain_ex(b, solver=ADMM, max_iter=25, tol=0.0, init=oracle.INIT_WMEAN)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_WMEAN)
+    _check(b, got, ref["z"], 6.0, "plain wmean start T25")
+    b = _zero_some_weights(_mixed(46, 300))
+    rad = np.full(b.B, 1.5, np.float32)
+    got, st = run_batch_ex(b, solver=ADMM, max_iter=25, tol=0.0, init=oracle.INIT_WMEAN, ball_radius=rad)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_WMEAN, ball_radius=rad)
+    _check(b, got, ref["z"], 3.0, "batch wmean start ball T25")
+
+
 def test_solver_routing_errors():
     import torch
     import paper_1501_03879_amd as emx
