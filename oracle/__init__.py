@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "libemoracle.so")
 
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW, INIT_WMEAN = 0, 1, 2
-SOLVER_ADMM, SOLVER_IRLS, SOLVER_FAST_ADMM = 0, 1, 3
+SOLVER_ADMM, SOLVER_IRLS, SOLVER_FAST_ADMM, SOLVER_WPEN = 0, 1, 3, 4
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 
 
@@ -59,6 +59,12 @@ def _load():
                                            dp, C.c_int64, C.c_double, C.c_int64, C.c_double,
                                            C.c_double, i64p, dp, dp, dp]
         lib.oracle_em_solve_ex.restype = C.c_int
+        lib.oracle_em_solve_wpen.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
+                                             C.c_int64, C.c_double, i64p, dp, dp]
+        lib.oracle_em_solve_wpen.restype = C.c_int
+        lib.oracle_em_solve_wpen_ball.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp,
+                                                  C.c_double, dp, C.c_int64, C.c_double, i64p, dp, dp]
+        lib.oracle_em_solve_wpen_ball.restype = C.c_int
         lib.oracle_em_solve_fast.argtypes = [C.c_int64, C.c_int64, dp, dp, C.c_double, dp, dp, dp,
                                              C.c_int64, C.c_double, C.c_double, i64p, dp, dp, i64p]
         lib.oracle_em_solve_fast.restype = C.c_int
@@ -205,6 +211,36 @@ def irls_solve_ball(a, w, eps: float, center, radius: float, z0, max_iter: int =
     return dict(z=z, iters=int(it.value), r_dual=rd.value, flags=int(f))
 
 
+def em_solve_wpen(a, w, mu: float, lo, hi, z0, max_iter: int = 100, tol: float = 0.0,
+                  center=None, radius=None) -> dict:
+    """The weighted-mean variant of the consensus ADMM (penalty mu w_k on the
+    constraint of point k) in FP64, over the box [lo, hi] (scalars or per
+    coordinate) or, when radius is given, the ball ||z - center|| <= radius."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    n, d = a.shape
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    z = np.array(z0, dtype=np.float64).reshape(-1).copy()
+    it = C.c_int64(0)
+    rp = C.c_double(0.0)
+    rd = C.c_double(0.0)
+    if radius is None:
+        lv = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, np.float64), (d,)), dtype=np.float64)
+        hv = np.ascontiguousarray(np.broadcast_to(np.asarray(hi, np.float64), (d,)), dtype=np.float64)
+        f = _load().oracle_em_solve_wpen(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                         _p(lv, C.c_double), _p(hv, C.c_double), _p(z, C.c_double),
+                                         int(max_iter), float(tol), C.byref(it), C.byref(rp), C.byref(rd))
+    else:
+        cen = np.zeros(d) if center is None else np.asarray(center, np.float64)
+        cen = np.ascontiguousarray(np.broadcast_to(cen, (d,)), dtype=np.float64)
+        f = _load().oracle_em_solve_wpen_ball(n, d, _p(a, C.c_double), _p(w, C.c_double), float(mu),
+                                              _p(cen, C.c_double), float(radius), _p(z, C.c_double),
+                                              int(max_iter), float(tol), C.byref(it), C.byref(rp),
+                                              C.byref(rd))
+    return dict(z=z, iters=int(it.value), r_pri=rp.value, r_dual=rd.value, flags=int(f))
+
+
 def em_solve_fast(a, w, mu: float, lo, hi, z0, max_iter: int = 100, tol: float = 0.0,
                   eta: float = 0.999) -> dict:
     """Accelerated ADMM (fast ADMM with restart) in FP64 over the box [lo, hi];
@@ -236,7 +272,8 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
              ball_radius=None) -> dict:
     """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
     z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty),
-    SOLVER_IRLS or SOLVER_FAST_ADMM (restart parameter eta); box_lo / box_hi:
+    SOLVER_IRLS, SOLVER_FAST_ADMM (restart parameter eta) or SOLVER_WPEN (the
+    weighted-mean variant, penalties mu w_k); box_lo / box_hi:
     optional float32 per-coordinate bounds indexed like z; ball_radius
     (float32, one per instance) selects the ball constraint with centres
     ball_center (float32 indexed like z, None = origin).  Returns z (float64,

@@ -277,6 +277,124 @@ int oracle_em_solve_ball(int64_t n, int64_t d, const double *a, const double *w,
                         adapt_factor, iters, r_pri, r_dual, mu_out);
 }
 
+/*
+ * The weighted-mean variant of the consensus ADMM (a different algorithm from
+ * Algorithm 1, which uses one penalty mu for every constraint x_k = z): the
+ * constraint of point k gets its own penalty mu_k = mu w_k, so the augmented
+ * Lagrangian is
+ *   sum_k w_k ||x_k - a_k|| + y_k.(x_k - z) + (mu_k / 2) ||x_k - z||^2.
+ * Minimising it over each block in turn, as in Algorithm 1:
+ *   x_k = Psi_{w_k / mu_k}(z - y_k / mu_k, a_k)      (threshold w_k/mu_k = 1/mu)
+ *   z   = P_C( sum_k mu_k (x_k + y_k / mu_k) / sum_k mu_k )   (a weighted mean;
+ *         exact over a box or a ball because the z-subproblem is an isotropic
+ *         quadratic)
+ *   y_k = y_k + mu_k (x_k - z).
+ * A point of weight zero has no term in the objective and no penalty: it is
+ * left out.  Every weight zero: z = P_C(z) (every point of C is a minimiser).
+ * Residuals over the n' points of positive weight: r_pri =
+ * sqrt(sum_k ||x_k - z||^2 / (n' d)) (0 when n' = 0), r_dual as for Algorithm 1;
+ * the stopping rule, D and the n = 0 / bad-input rules are those of
+ * oracle_em_solve.
+ */
+static int em_solve_wpen_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                             const or_set_t *C, double *z, int64_t max_iter, double tol,
+                             int64_t *iters, double *r_pri, double *r_dual)
+{
+    *iters = 0;
+    *r_pri = 0.0;
+    *r_dual = 0.0;
+    if (n == 0) return OR_EMPTY;
+    int bad = !set_ok(d, C);
+    for (int64_t k = 0; k < n; ++k)
+        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
+    for (int64_t i = 0; i < n * d; ++i)
+        if (!isfinite(a[i])) bad = 1;
+    for (int64_t j = 0; j < d; ++j)
+        if (!isfinite(z[j])) bad = 1;
+    if (bad) {
+        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
+        return OR_BAD_INPUT;
+    }
+    double D = tol_scale_set(n, d, a, C);
+    double *y = (double *)calloc((size_t)(n * d + 1), sizeof(double));
+    double *x = (double *)malloc((size_t)(n * d + 1) * sizeof(double));
+    double *v = (double *)malloc((size_t)d * sizeof(double));
+    double *r = (double *)malloc((size_t)d * sizeof(double));
+    double *zprev = (double *)malloc((size_t)d * sizeof(double));
+    int64_t npos = 0;
+    double msum = 0.0;
+    for (int64_t k = 0; k < n; ++k)
+        if (w[k] > 0.0) {
+            ++npos;
+            msum += mu * w[k];
+        }
+
+    int flags = OR_MAXITER;
+    for (int64_t t = 1; t <= max_iter; ++t) {
+        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (!(w[k] > 0.0)) continue;
+            const double mk = mu * w[k];                  /* mu_k = mu w_k */
+            const double *ak = a + k * d;
+            double *yk = y + k * d;
+            double *xk = x + k * d;
+            for (int64_t j = 0; j < d; ++j) v[j] = z[j] - yk[j] / mk;
+            oracle_prox(d, v, ak, w[k] / mk, xk);
+            for (int64_t j = 0; j < d; ++j) r[j] += mk * (xk[j] + yk[j] / mk);
+        }
+        for (int64_t j = 0; j < d; ++j) {
+            zprev[j] = z[j];
+            r[j] = (msum > 0.0) ? r[j] / msum : z[j];
+        }
+        project_set(C, d, r, z);
+        double sp = 0.0, sd = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (!(w[k] > 0.0)) continue;
+            const double mk = mu * w[k];
+            for (int64_t j = 0; j < d; ++j) {
+                double e = x[k * d + j] - z[j];
+                y[k * d + j] += mk * e;
+                sp += e * e;
+            }
+        }
+        for (int64_t j = 0; j < d; ++j) {
+            double e = z[j] - zprev[j];
+            sd += e * e;
+        }
+        *r_pri = (npos > 0) ? sqrt(sp / (double)(npos * d)) : 0.0;
+        *r_dual = sqrt(sd / (double)d);
+        *iters = t;
+        if (tol > 0.0 && *r_pri <= tol * D && *r_dual <= tol * D) {
+            flags = OR_CONVERGED;
+            break;
+        }
+    }
+    free(y);
+    free(x);
+    free(v);
+    free(r);
+    free(zprev);
+    return flags;
+}
+
+/* The weighted-mean variant over the box prod_j [lo_j, hi_j]. */
+int oracle_em_solve_wpen(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                         const double *lo, const double *hi, double *z, int64_t max_iter,
+                         double tol, int64_t *iters, double *r_pri, double *r_dual)
+{
+    or_set_t C = {lo, hi, NULL, 0.0};
+    return em_solve_wpen_set(n, d, a, w, mu, &C, z, max_iter, tol, iters, r_pri, r_dual);
+}
+
+/* The weighted-mean variant over the ball ||z - center|| <= radius. */
+int oracle_em_solve_wpen_ball(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                              const double *center, double radius, double *z, int64_t max_iter,
+                              double tol, int64_t *iters, double *r_pri, double *r_dual)
+{
+    or_set_t C = {NULL, NULL, center, radius};
+    return em_solve_wpen_set(n, d, a, w, mu, &C, z, max_iter, tol, iters, r_pri, r_dual);
+}
+
 /* Algorithm 1 with the scalar box [lo, hi]^d and a fixed penalty. */
 int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
                     double mu, double lo, double hi, double *z, double *y,
@@ -593,9 +711,10 @@ int oracle_max_threads(void)
  * when every weight is zero.
  * max_iter_each (nullable) overrides max_iter per instance.
  * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
- * on the surrogate with eps, 3 = accelerated ADMM with restart parameter eta.
+ * on the surrogate with eps, 3 = accelerated ADMM with restart parameter eta,
+ * 4 = the weighted-mean variant (penalties mu w_k).
  * ball_radius (nullable, one per instance) selects the ball constraint with
- * centres ball_center (nullable = origin, indexed like z; solvers 0 and 1).
+ * centres ball_center (nullable = origin, indexed like z; solvers 0, 1 and 4).
  * Otherwise box_lo / box_hi (nullable, float32, indexed like
  * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
  * mu_out (nullable): the final penalty per instance.
@@ -649,6 +768,8 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         int f;
         if (solver == 1)
             f = irls_solve_set(n, d, ab, wb, eps, &C, zb, mi, tol, &it, &rp, &rd);
+        else if (solver == 4)
+            f = em_solve_wpen_set(n, d, ab, wb, mu, &C, zb, mi, tol, &it, &rp, &rd);
         else if (solver == 3)
             f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, NULL);
         else

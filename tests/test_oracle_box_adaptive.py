@@ -10,7 +10,11 @@ fixed-penalty solvers at the (unique) minimiser, factor = 1 reducing to the
 fixed penalty exactly, and the adaptive rule moving a badly scaled penalty in
 the right direction.  The weighted-mean start of the batch (the counterpart of
 the NLM patch) is pinned by closed-form means and by reaching the same
-minimiser as the largest-weight start.
+minimiser as the largest-weight start.  The weighted-mean variant of the
+ADMM (penalty mu w_k per constraint) is pinned by three hand-worked
+iterations, its reduction to Algorithm 1 under equal weights, the
+replication, zero-weight and scaling invariances that distinguish it, and
+convergence to the same minimiser.
 """
 
 import numpy as np
@@ -354,3 +358,89 @@ def test_wmean_start_same_minimiser(orc):
     np.testing.assert_allclose(ra["z"], rb["z"], rtol=0, atol=1e-6 * (b.hi - b.lo))
     ri = orc.em_batch(b, 0.5, 400, 0.0, init=orc.INIT_WMEAN, solver=orc.SOLVER_IRLS, eps=1e-10)
     np.testing.assert_allclose(ri["z"], rb["z"], rtol=0, atol=1e-4 * (b.hi - b.lo))
+
+
+# ------------------------------------------------ weighted-mean ADMM variant
+
+def test_wpen_hand_worked_iterations(orc):
+    """d = 1, points 0, 1, 5 with weights 1, 2, 1, mu = 1 (penalties mu_k = 1, 2,
+    1, thresholds w_k / mu_k = 1), C = [0, 10], z = 3, y = 0, worked by hand:
+    t=1: v = 3, v - a = (3, 2, -2), x = v - sign = (2, 2, 4),
+         z = (1*2 + 2*2 + 1*4) / 4 = 5/2, y = mu_k (x - z) = (-1/2, -1, 3/2);
+    t=2: y/mu_k = (-1/2, -1/2, 3/2), v = (3, 3, 1), v - a = (3, 2, -4),
+         x = (2, 2, 2), z = (1.5 + 2*1.5 + 3.5) / 4 = 2, y unchanged (x = z);
+    t=3: v = (5/2, 5/2, 1/2), x = (3/2, 3/2, 3/2), z = (1 + 2 + 3) / 4 = 3/2.
+    Algorithm 1 (one penalty) gives z = 7/3 at t = 1 on the same data.  The
+    iterates reach the weighted median 1."""
+    a = [0.0, 1.0, 5.0]
+    for t, zt in ((1, 2.5), (2, 2.0), (3, 1.5)):
+        r = orc.em_solve_wpen(a, [1, 2, 1], 1.0, 0.0, 10.0, [3.0], max_iter=t)
+        assert abs(r["z"][0] - zt) <= 1e-15, (t, r["z"])
+    assert abs(orc.em_solve(np.array(a)[:, None], [1, 2, 1], 1.0, 0.0, 10.0, [3.0], max_iter=1)["z"][0]
+               - 7 / 3) <= 1e-15
+    r = orc.em_solve_wpen(a, [1, 2, 1], 1.0, 0.0, 10.0, [3.0], max_iter=2000, tol=1e-14)
+    assert abs(r["z"][0] - 1.0) <= 1e-9 and r["flags"] == 1
+
+
+def test_wpen_equal_weights_is_algorithm_1(orc):
+    """Equal weights c: penalties mu c for every constraint, thresholds 1/mu,
+    an unweighted mean: exactly Algorithm 1 with penalty mu c."""
+    rng = np.random.default_rng(81)
+    for c in (1.0, 0.37, 5.0):
+        a = rng.normal(size=(9, 3))
+        z0 = rng.normal(size=3)
+        for T in (1, 7, 40):
+            r = orc.em_solve_wpen(a, np.full(9, c), 0.8, -1.0, 1.0, z0, max_iter=T)
+            s = orc.em_solve(a, np.full(9, c), 0.8 * c, -1.0, 1.0, z0, max_iter=T)
+            np.testing.assert_allclose(r["z"], s["z"], rtol=0, atol=1e-12)
+
+
+def test_wpen_invariances(orc):
+    """Properties of the variant that Algorithm 1 does not have: a point of
+    weight 2 is two copies of weight 1 (same penalties and thresholds); a
+    point of weight 0 changes nothing, wherever it lies; scaling every weight
+    leaves the iterates unchanged."""
+    rng = np.random.default_rng(82)
+    a = rng.normal(size=(6, 4))
+    w = rng.uniform(0.2, 2.0, size=6)
+    w[2] = 2.0
+    z0 = rng.normal(size=4)
+    lo, hi = -0.7, 0.9
+    for T in (1, 5, 60):
+        base = orc.em_solve_wpen(a, w, 0.6, lo, hi, z0, max_iter=T)["z"]
+        w2 = w.copy()
+        w2[2] = 1.0
+        rep = orc.em_solve_wpen(np.vstack([a, a[2:3]]), np.append(w2, 1.0), 0.6, lo, hi, z0, max_iter=T)["z"]
+        np.testing.assert_allclose(rep, base, rtol=0, atol=1e-12)
+        far = orc.em_solve_wpen(np.vstack([a, [[1e6, -3e5, 7.0, 0.0]]]), np.append(w, 0.0), 0.6, lo, hi, z0,
+                                max_iter=T)["z"]
+        np.testing.assert_array_equal(far, base)
+        sc = orc.em_solve_wpen(a, 7.5 * w, 0.6, lo, hi, z0, max_iter=T)["z"]
+        np.testing.assert_allclose(sc, base, rtol=0, atol=1e-12)
+    # Algorithm 1 is not replication-invariant (thresholds w_k / mu differ)
+    s1 = orc.em_solve(a, w, 0.6, lo, hi, z0, max_iter=5)["z"]
+    s2 = orc.em_solve(np.vstack([a, a[2:3]]), np.append(w2, 1.0), 0.6, lo, hi, z0, max_iter=5)["z"]
+    assert np.max(np.abs(s1 - s2)) > 1e-6
+
+
+def test_wpen_converges_to_the_minimiser(orc):
+    """Same problem (EM), another algorithm: the limit satisfies the box
+    optimality certificate and equals Algorithm 1's limit; over a ball it
+    equals Algorithm 1's limit too.  Every weight zero: the start projected."""
+    rng = np.random.default_rng(83)
+    for _ in range(8):
+        n, d = int(rng.integers(3, 15)), int(rng.integers(1, 5))
+        a = rng.normal(size=(n, d)) * 2
+        w = rng.uniform(0.1, 2.0, size=n)
+        lo = rng.uniform(-2, 0, size=d)
+        hi = lo + rng.uniform(0.5, 3, size=d)
+        r = orc.em_solve_wpen(a, w, 1.0, lo, hi, a[0], max_iter=40000, tol=1e-13)
+        assert _certificate(a, w, r["z"], lo, hi, 1e-6)
+        s = orc.em_solve(a, w, 1.0, lo, hi, a[0], max_iter=40000, tol=1e-13)
+        np.testing.assert_allclose(r["z"], s["z"], rtol=0, atol=1e-6)
+        rb = orc.em_solve_wpen(a, w, 1.0, None, None, a[0], max_iter=40000, tol=1e-13, center=lo, radius=1.0)
+        sb = orc.em_solve_ball(a, w, 1.0, lo, 1.0, a[0], max_iter=40000, tol=1e-13)
+        np.testing.assert_allclose(rb["z"], sb["z"], rtol=0, atol=1e-6)
+    r = orc.em_solve_wpen(np.ones((3, 2)), np.zeros(3), 1.0, 0.0, 1.0, [-0.5, 2.0], max_iter=4)
+    np.testing.assert_array_equal(r["z"], [0.0, 1.0])
+    assert r["r_pri"] == 0.0
