@@ -144,7 +144,9 @@ typedef enum {
     EM_SOLVER_ADMM = 0,          /* Algorithm 1, fixed penalty rho (as em_solve_batch) */
     EM_SOLVER_IRLS = 1,          /* IRLS on the smooth surrogate (EM_surrogate), parameter eps */
     EM_SOLVER_ADMM_ADAPTIVE = 2, /* Algorithm 1 with the penalty adapted by residual balancing */
-    EM_SOLVER_ADMM_FAST = 3      /* accelerated ADMM with restart (em_solve_plain_ex only) */
+    EM_SOLVER_ADMM_FAST = 3,     /* accelerated ADMM with restart (em_solve_plain_ex only) */
+    EM_SOLVER_ADMM_WEIGHTED = 4  /* consensus ADMM with penalty rho w_k per constraint (a weighted-
+                                    mean z-update; a different algorithm from Algorithm 1) */
 } em_solver_t;
 
 /* The convex set C of (EM) for em_solve_batch_ex. */
@@ -187,8 +189,8 @@ typedef struct {
  *     ||z - center||)): centre ball_center[z_off + j] (origin when NULL),
  *     radius ball_radius[b] (or `radius`); a negative or NaN radius or a
  *     non-finite centre gives EM_BAD_INPUT; D = 2 radius when finite and
- *     > 0.  Solvers ADMM and IRLS (not ADAPTIVE); box_lo / box_hi must be
- *     NULL.
+ *     > 0.  Solvers ADMM, WEIGHTED and IRLS (not ADAPTIVE); box_lo / box_hi
+ *     must be NULL.
  *   EM_SOLVER_ADMM: Algorithm 1 exactly as em_solve_batch.
  *   EM_SOLVER_ADMM_ADAPTIVE: after every adapt_every-th iteration t that did
  *     not stop, with ||r|| = (sum_k ||x_k - z||^2)^(1/2) and
@@ -203,6 +205,13 @@ typedef struct {
  *     quadratic majoriser); stopped on r_dual alone (stats r_pri = 0); all
  *     weights zero: every point of C is a minimiser, z becomes the start
  *     projected onto C and the solve reports CONVERGED after one iteration.
+ *   EM_SOLVER_ADMM_WEIGHTED: the consensus splitting of Section 2 with the
+ *     penalty rho w_k on the constraint x_k = z of point k instead of one rho
+ *     for all: x_k = prox with threshold w_k / (rho w_k) = 1 / rho at
+ *     z - y_k / (rho w_k), z' = P_C(sum_k w_k (x_k + y_k / (rho w_k)) /
+ *     sum_k w_k), y_k += rho w_k (x_k - z').  Same minimiser as Algorithm 1,
+ *     other iterates; points of weight zero are left out (all weights zero:
+ *     z' = P_C(z)); r_pri runs over the points of positive weight.
  * Other arguments, limits and per-instance rules as for em_solve_batch.
  * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
  * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1

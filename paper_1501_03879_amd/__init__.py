@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("EMX_LIBRARY") or os.path.join(HERE, "libemx.so")
 EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
 INIT_GIVEN, INIT_MAXW, INIT_WMEAN = 0, 1, 2
-SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST = 0, 1, 2, 3
+SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST, SOLVER_ADMM_WEIGHTED = 0, 1, 2, 3, 4
 SET_BOX, SET_BALL = 0, 1
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10

@@ -86,6 +86,8 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
                                  ? (ball ? batch_class_table_irls_ball() : batch_class_table_irls())
                              : (o.solver == EM_SOLVER_ADMM_ADAPTIVE)
                                  ? batch_class_table_adapt()
+                             : (o.solver == EM_SOLVER_ADMM_WEIGHTED)
+                                 ? (ball ? batch_class_table_wpen_ball() : batch_class_table_wpen())
                                  : (ball ? batch_class_table_admm_ball() : batch_class_table_admm());
     const bool vbox = ball || o.box_lo != nullptr;
     for (int c = 0; c < kNumClasses; ++c) {

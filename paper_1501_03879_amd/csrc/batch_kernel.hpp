@@ -106,13 +106,15 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     constexpr bool IRLS = SOLVER == 1;
     constexpr bool BALL = SET == 1;
     constexpr bool ADAPT = SOLVER == 2;   // adaptive penalty (a separate kernel: it needs registers)
+    constexpr bool WPEN = SOLVER == 4;    // penalty mu w_k per constraint (weighted-mean z-update)
     using S = BatchShape<DS, M, WC, WP>;
     using RSx = RS<DS>;
     constexpr int H2 = S::H2;
     __shared__ float stage[S::STAGE];
     // buffers 0/1 alternate by iteration; buffer 2 is the penalty-rescale exchange
     __shared__ float xn[(WC > 1) ? (ADAPT ? 3 : 2) * S::XNB : 1];
-    __shared__ float xe[(WP > 1) ? 2 * WP * WC * H2 * 4 : 1];
+    // buffers 0/1 alternate by iteration; WPEN adds two for sum_k (x_k - c)
+    __shared__ float xe[(WP > 1) ? (WPEN ? 4 : 2) * WP * WC * H2 * 4 : 1];
     __shared__ float xo[(WP > 1) ? 2 * WP : 1];
     __shared__ float xs[3 * WC * WP * 4];   // third slot: the test after armed iterations
     __shared__ float Epv[WC * H2 * 4 * WP];
@@ -586,16 +588,66 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             float g[M][DS];
             float mu_c = L.mu;
             const float inv_mu0 = 1.0f / L.mu;
+            // z-update divisor (1/n, or 1/sum of the weights for WPEN) and the
+            // number of points the primal residual runs over
+            float zdiv = 1.0f / (float)n;
+            float fn = (float)n;
+            float wq[M];   // WPEN: weights scaled by their largest value (the iterates do not change)
+            if constexpr (WPEN) {
+                float wl = 0.0f;
 #pragma unroll
-            for (int q = 0; q < M; ++q) {
-                lam[q] = (lam[q] >= 0.0f) ? lam[q] * inv_mu0 : 0.0f;
+                for (int q = 0; q < M; ++q) wl = fmaxf(wl, lam[q]);
+                float wmx = wave_max(wl);
+                if constexpr (WP > 1) {
+                    if (lane == 0) xs[wave * 4 + 0] = wmx;
+                    __syncthreads();
+                    wmx = xs[0];
+#pragma unroll
+                    for (int v = 1; v < WP; ++v) wmx = fmaxf(wmx, xs[(v * WC) * 4 + 0]);
+                }
+                wmx = readfirstlane(wmx);
+                const float sc = (wmx > 0.0f) ? 1.0f / wmx : 0.0f;
+                float ws = 0.0f, ne = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    const bool pos = lam[q] > 0.0f;   // a point of weight zero is left out
+                    wq[q] = pos ? lam[q] * sc : 0.0f;
+                    ws += wq[q];
+                    ne += pos ? 1.0f : 0.0f;
+                    lam[q] = pos ? inv_mu0 : 0.0f;    // threshold w_k / (mu w_k)
+                }
+                ws = wave_sum(ws);
+                ne = wave_sum(ne);
+                if constexpr (WP > 1) {
+                    if (lane == 0) {
+                        xs[wave * 4 + 1] = ws;
+                        xs[wave * 4 + 2] = ne;
+                    }
+                    __syncthreads();
+                    ws = xs[1];
+                    ne = xs[2];
+#pragma unroll
+                    for (int v = 1; v < WP; ++v) {
+                        ws += xs[(v * WC) * 4 + 1];
+                        ne += xs[(v * WC) * 4 + 2];
+                    }
+                }
+                ws = readfirstlane(ws);
+                zdiv = (ws > 0.0f) ? 1.0f / ws : 0.0f;   // every weight zero: z' = P_C(z)
+                fn = readfirstlane(ne);
+            } else {
+#pragma unroll
+                for (int q = 0; q < M; ++q) {
+                    lam[q] = (lam[q] >= 0.0f) ? lam[q] * inv_mu0 : 0.0f;
+                    wq[q] = 1.0f;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < M; ++q)
 #pragma unroll
                 for (int jj = 0; jj < DS; ++jj) g[q][jj] = na[q][jj];
-            }
-            const float inv_n = 1.0f / (float)n;
-            const float fn = (float)n;
             const float inv_d = 1.0f / (float)d;
-            const float inv_nd = 1.0f / ((float)n * (float)d);
+            const float inv_nd = (fn > 0.0f) ? 1.0f / (fn * (float)d) : 0.0f;
             const int max_iter = L.max_iter;
             const int every = ADAPT ? L.adapt_every : 0;
             float rd_w = 0.0f, rp_w = 0.0f;
@@ -707,23 +759,32 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 // ---- armed iterations: lane sums of ||x_k - c||^2, x_k = a_k + (1 - s) delta.
                 // Absent points and padded coordinates give exactly 0 (g stays -a).
                 float rp_lane = 0.0f;
+                float Ys[H2];   // WPEN, armed: sum_k (x_k - c) in the reduced layout
                 if (armed) {
+                    float ysum[DS];   // WPEN: lane sums of x_k - c (points of weight zero give 0)
                     float rq[M];
 #pragma unroll
                     for (int q = 0; q < M; ++q) rq[q] = 0.0f;
 #pragma unroll
                     for (int jj = 0; jj < DS; ++jj) {
                         const float cj = cv[jj];
+                        float ys = 0.0f;
 #pragma unroll
                         for (int q = 0; q < M; ++q) {
                             const float y = fmaf(1.0f - s[q], g[q][jj], -(na[q][jj] + cj));
                             rq[q] = fmaf(y, y, rq[q]);
+                            if constexpr (WPEN) ys += y;
                         }
+                        ysum[jj] = ys;
                     }
 #pragma unroll
                     for (int q = 0; q < M; ++q) rp_lane += rq[q];
+                    if constexpr (WPEN) reduce_scatter<DS>(ysum, Ys);
                 }
-                // ---- pass 2: E = sum_k s delta, g = s delta - a
+                // ---- pass 2: E = sum_k s delta (WPEN: sum_k w_k s delta), g = s delta - a
+                float sw[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) sw[q] = WPEN ? s[q] * wq[q] : s[q];
                 float acc[DS];
 #pragma unroll
                 for (int jj = 0; jj < DS; ++jj) {
@@ -731,7 +792,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
                         const float dl = g[q][jj];
-                        ac = fmaf(s[q], dl, ac);
+                        ac = fmaf(sw[q], dl, ac);
                         g[q][jj] = fmaf(s[q], dl, na[q][jj]);
                     }
                     acc[jj] = ac;
@@ -744,17 +805,25 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 reduce_scatter<DS>(acc, E);
                 if constexpr (WP > 1) {
                     float *XE = xe + (t & 1) * WP * WC * H2 * 4;
+                    float *XY = xe + (2 + (t & 1)) * WP * WC * H2 * 4;
                     if (lane == 16 * row) {
 #pragma unroll
-                        for (int j = 0; j < H2; ++j) XE[((pw * WC + cw) * H2 + j) * 4 + row] = E[j];
+                        for (int j = 0; j < H2; ++j) {
+                            XE[((pw * WC + cw) * H2 + j) * 4 + row] = E[j];
+                            if (WPEN && armed) XY[((pw * WC + cw) * H2 + j) * 4 + row] = Ys[j];
+                        }
                     }
                     __syncthreads();
 #pragma unroll
                     for (int j = 0; j < H2; ++j) {
-                        float sum = 0.0f;
+                        float sum = 0.0f, ysm = 0.0f;
 #pragma unroll
-                        for (int v = 0; v < WP; ++v) sum += XE[((v * WC + cw) * H2 + j) * 4 + row];
+                        for (int v = 0; v < WP; ++v) {
+                            sum += XE[((v * WC + cw) * H2 + j) * 4 + row];
+                            if (WPEN && armed) ysm += XY[((v * WC + cw) * H2 + j) * 4 + row];
+                        }
                         E[j] = sum;
+                        if (WPEN && armed) Ys[j] = ysm;
                     }
                 }
                 float fb = 1.0f;
@@ -764,7 +833,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     for (int j = 0; j < H2; ++j) {
                         const int cc = cw * DS + RSx::coord(row, j);
                         const bool vj = RSx::valid(row, j) && cc < d;
-                        const float dv = (zr[j] - E[j] * inv_n) - Bl_s[j * 4 + row];
+                        const float dv = (zr[j] - E[j] * zdiv) - Bl_s[j * 4 + row];
                         s2 += vj ? dv * dv : 0.0f;
                     }
                     fb = ball_factor(s2, t);
@@ -775,16 +844,17 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     const int cc = cw * DS + RSx::coord(row, j);
                     const bool vj = RSx::valid(row, j) && cc < d;
                     const int k = RSx::valid(row, j) ? RSx::coord(row, j) : 0;
-                    const float zu = zr[j] - E[j] * inv_n;
+                    const float zu = zr[j] - E[j] * zdiv;
                     const float zn = BALL ? ((fb < 1.0f) ? Bl_s[j * 4 + row] + (zu - Bl_s[j * 4 + row]) * fb : zu)
                                           : clampf(zu, Bl_s[j * 4 + row], Bh_s[j * 4 + row]);
                     const float dz = zn - zr[j];
                     const float cj = cv[k];
                     if (armed) {
                         // x_k - z' = (x_k - c) + (c - z'), sum_k (x_k - c) = E^t - E^{t+1}
-                        const float Epj = Ep_s[j * 4 + row];
+                        // (WPEN: summed directly, E being weighted)
+                        const float sxc = WPEN ? Ys[j] : (Ep_s[j * 4 + row] - E[j]);
                         const float cz = cj - zn;
-                        rpx += vj ? (cz * (2.0f * (Epj - E[j]) + fn * cz)) : 0.0f;
+                        rpx += vj ? (cz * (2.0f * sxc + fn * cz)) : 0.0f;
                     }
                     rdx += vj ? dz * dz : 0.0f;
                     if (lane == 16 * row) {
@@ -882,5 +952,7 @@ const ClassKernel *batch_class_table_irls();
 const ClassKernel *batch_class_table_adapt();
 const ClassKernel *batch_class_table_admm_ball();
 const ClassKernel *batch_class_table_irls_ball();
+const ClassKernel *batch_class_table_wpen();
+const ClassKernel *batch_class_table_wpen_ball();
 
 }  // namespace emx

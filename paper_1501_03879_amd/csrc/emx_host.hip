@@ -656,7 +656,8 @@ extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B,
     const em_options_t &o = *opt;
     if (o.solver == EM_SOLVER_ADMM_FAST)
         return fail(h, EM_ERR_UNSUPPORTED, "accelerated ADMM runs in em_solve_plain_ex");
-    if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_IRLS && o.solver != EM_SOLVER_ADMM_ADAPTIVE)
+    if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_IRLS && o.solver != EM_SOLVER_ADMM_ADAPTIVE &&
+        o.solver != EM_SOLVER_ADMM_WEIGHTED)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");
     if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
         return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");
@@ -711,7 +712,7 @@ extern "C" em_status_t em_solve_plain_ex(em_handle_t h, void *stream, int64_t B,
     if (!h) return EM_ERR_INVALID_ARG;
     if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
     const em_options_t &o = *opt;
-    if (o.solver == EM_SOLVER_IRLS || o.solver == EM_SOLVER_ADMM_ADAPTIVE)
+    if (o.solver == EM_SOLVER_IRLS || o.solver == EM_SOLVER_ADMM_ADAPTIVE || o.solver == EM_SOLVER_ADMM_WEIGHTED)
         return fail(h, EM_ERR_UNSUPPORTED, "this solver runs in em_solve_batch_ex");
     if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_ADMM_FAST)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");

@@ -18,7 +18,7 @@ import synth
 from helpers import rel_errors, report, run_batch_ex, run_plain_ex
 
 pytestmark = pytest.mark.gpu
-ADMM, IRLS, ADAPT = 0, 1, 2
+ADMM, IRLS, ADAPT, WPEN = 0, 1, 2, 4
 DIMS = (1, 2, 3, 4, 5, 8, 15, 16, 17, 31, 33, 48, 49, 64)
 
 
@@ -293,6 +293,47 @@ def test_wmean_start_plain_and_ball():
     _check(b, got, ref["z"], 3.0, "batch wmean start ball T25")
 
 
+@pytest.mark.parametrize("init", [1, 2])
+def test_weighted_penalty_fixed_iterations(init):
+    """The weighted-mean variant (penalty rho w_k per constraint) over every
+    shape class, some instances with every weight zero, from the
+    largest-weight and the weighted-mean starts."""
+    b = _zero_some_weights(_mixed(51 + init, 400), every=29)
+    w = b.w.copy()
+    w[::7] = 0.0   # scattered points of weight zero (left out)
+    b.w = w
+    got, st = run_batch_ex(b, solver=WPEN, max_iter=25, tol=0.0, init=init)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=init, solver=oracle.SOLVER_WPEN)
+    _check(b, got, ref["z"], 6.0, f"batch weighted-penalty admm init {init} T25")
+    live = b.inst["n"] > 0
+    assert np.all(st["iters"][live] == 25)
+
+
+def test_weighted_penalty_boxes_ball_and_tolerance_mode():
+    b = _mixed(54, 300)
+    lo, hi = _boxes(b, 5)
+    got, st = run_batch_ex(b, solver=WPEN, max_iter=25, tol=0.0, init=oracle.INIT_MAXW, box_lo=lo, box_hi=hi)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_WPEN, box_lo=lo, box_hi=hi)
+    _check(b, got, ref["z"], 3.0, "batch weighted-penalty admm per-coordinate boxes T25")
+    rng = np.random.default_rng(55)
+    cen = rng.uniform(-1, 1, size=b.z_size).astype(np.float32)
+    rad = rng.uniform(0.3, 2.0, size=b.B).astype(np.float32)
+    got, st = run_batch_ex(b, solver=WPEN, max_iter=25, tol=0.0, init=oracle.INIT_MAXW, ball_center=cen,
+                           ball_radius=rad)
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_WPEN, ball_center=cen,
+                          ball_radius=rad)
+    D = np.repeat(2 * rad.astype(np.float64), b.inst["d"])
+    e = np.max(np.abs(got[:b.z_size] - ref["z"][:b.z_size]) / D)
+    report("batch weighted-penalty admm ball T25 (per-instance D = 2 radius)", e, 0.0)
+    assert e <= 1e-4
+    got, st = run_batch_ex(b, solver=WPEN, max_iter=3000, tol=1e-4, init=oracle.INIT_MAXW)
+    ref = oracle.em_batch(b, 0.5, 3000, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_WPEN,
+                          max_iter_each=st["iters"])
+    live = b.inst["n"] > 0
+    _check(b, got, ref["z"], 6.0, f"batch weighted-penalty admm tol 1e-4 (mean iters "
+                                  f"{st['iters'][live].mean():.1f}, converged {np.mean(st['flags'][live] == 1):.3f})")
+
+
 def test_solver_routing_errors():
     import torch
     import paper_1501_03879_amd as emx
@@ -307,9 +348,13 @@ def test_solver_routing_errors():
     with pytest.raises(emx.EmxError) as e:
         hd.em_solve_batch_ex(a, w, inst, z, solver=FAST)
     assert e.value.status == emx.EM_ERR_UNSUPPORTED
+    for solver in (IRLS, WPEN):
+        with pytest.raises(emx.EmxError) as e:
+            hd.em_solve_plain_ex(a, w, inst, b.inst, z, solver=solver)
+        assert e.value.status == emx.EM_ERR_UNSUPPORTED
     with pytest.raises(emx.EmxError) as e:
-        hd.em_solve_plain_ex(a, w, inst, b.inst, z, solver=IRLS)
-    assert e.value.status == emx.EM_ERR_UNSUPPORTED
+        hd.em_solve_batch_ex(a, w, inst, z, solver=5)
+    assert e.value.status == emx.EM_ERR_INVALID_ARG
     for eta in (0.0, 1.0):
         with pytest.raises(emx.EmxError):
             hd.em_solve_plain_ex(a, w, inst, b.inst, z, solver=FAST, eta=eta)
