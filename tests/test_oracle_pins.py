@@ -165,6 +165,28 @@ def test_worked_example_first_iteration(orc):
     np.testing.assert_allclose(r["z"], [1.0], atol=1e-9)
 
 
+def test_worked_example_iterations_two_to_six(orc):
+    """The same example continued by hand.  With y = (-2/3, -2/3, 4/3) after
+    t = 1 and z = 8/3: v = z - y = (10/3, 10/3, 4/3), v - a = (10/3, 7/3, -11/3),
+    all longer than 1, so x = v - sign(v - a) = (7/3, 7/3, 7/3) and z = (7 + 0)/3
+    = 7/3; x = z, so y is unchanged.  Each later step repeats this with z lower
+    by 1/3 (x = z - 1/3 per point): z = 2, 5/3, 4/3, and at t = 6,
+    v = (2, 2, 0), v - a = (2, 1, -5): the middle point sits exactly at the tie
+    |v - a| = lambda, where both prox branches give x_2 = 1, so z = 1.  The
+    primal residual x - z is exactly 0 for t = 2..6 while z still moves: a
+    stopping rule on the primal residual alone would stop at t = 2."""
+    a = np.array([[0.0], [1.0], [5.0]])
+    for t, zt in ((2, 7 / 3), (3, 2.0), (4, 5 / 3), (5, 4 / 3), (6, 1.0)):
+        r = orc.em_solve(a, [1, 1, 1], 1.0, 0.0, 10.0, [3.0], max_iter=t)
+        assert abs(r["z"][0] - zt) <= 1e-14, (t, r["z"])
+        np.testing.assert_allclose(r["y"].ravel(), [-2 / 3, -2 / 3, 4 / 3], rtol=0, atol=1e-14)
+        assert r["r_pri"] <= 1e-15
+        assert abs(r["r_dual"] - 1 / 3) <= 1e-14
+    # tol = 1e-3 (tol D = 0.01): the dual residual keeps the solve going past t = 2
+    r = orc.em_solve(a, [1, 1, 1], 1.0, 0.0, 10.0, [3.0], max_iter=400, tol=1e-3)
+    assert r["iters"] > 6 and abs(r["z"][0] - 1.0) <= 0.05
+
+
 # --------------------------------------------------- converged solutions
 
 def _solve(orc, a, w, lo=-INF, hi=INF, mu=None, z0=None, iters=20000):
