@@ -261,7 +261,7 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: each pixel's solve is independent, so the "
               "image would be split by rows across GPUs with no exchange; "
-              "multi-GPU runs are not part of this build (use --gpus 1).", file=sys.stderr)
+              "this benchmark runs on one GPU only (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -74,7 +74,7 @@ typedef enum {
                           weight is zero); not projected, like the other starts */
 } em_init_t;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define EM_MAX_D 64            /* largest dimension d per instance */
 #define EM_MAX_N 512           /* largest point count n per instance */
 #define EM_MAX_PATCH_RADIUS 3  /* nlem: patch side 2r+1 <= 7 (d <= 49) */
