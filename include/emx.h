@@ -23,6 +23,13 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Every compute call only queues work on it and returns; kernel faults
  *    surface from em_sync or from the caller's own synchronisation.
+ *  - Graph capture: em_solve_batch(_ex), em_solve_plain(_ex), nlem_denoise,
+ *    nlem_denoise_ex and nlm_denoise may be recorded into a HIP graph by
+ *    stream capture after an earlier call of the same sizes on the same
+ *    handle has sized its workspace: they then only
+ *    launch kernels (work-queue heads are cleared by a kernel, not a memset)
+ *    and neither allocate nor synchronise.  nlem_autotune synchronises and
+ *    cannot be captured.
  *  - Argument errors are detected on the host before anything is queued and
  *    return EM_ERR_INVALID_ARG (nothing is written).  Problems inside one
  *    instance (no points, a bad weight or point) are reported per instance in
