@@ -36,6 +36,7 @@ struct MultiGraph {
     std::vector<char> key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    void *ws = nullptr;   // the graph's own queue-order scratch (kept with the graph)
 };
 
 // Autotuned NLEM plans: (patch radius, points per lane, solver) -> coordinate waves.
@@ -226,6 +227,7 @@ extern "C" em_status_t em_destroy(em_handle_t h) {
     (void)hipDeviceSynchronize();
     if (h->multi.exec) (void)hipGraphExecDestroy(h->multi.exec);
     if (h->multi.graph) (void)hipGraphDestroy(h->multi.graph);
+    if (h->multi.ws) (void)hipFree(h->multi.ws);
     if (h->counters) (void)hipFree(h->counters);
     if (h->ws) (void)hipFree(h->ws);
     if (h->plain_ws) (void)hipFree(h->plain_ws);
@@ -396,19 +398,60 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, co
     return L;
 }
 
+// Longest-first queue order (see nlem_order.hip), on unless EMX_NLEM_ORDER=0;
+// pointless without iterations (every pixel then costs the same).
+static bool order_enabled(const nlem_options_t &o) {
+    if (o.max_iter <= 0) return false;
+    const char *e = getenv("EMX_NLEM_ORDER");
+    return !(e && e[0] == '0' && e[1] == '\0');
+}
+
+static int64_t group_pixels(const NlemGroup &g, const nlem_image_t *images) {
+    int64_t t = 0;
+    for (int i : g.images) t += (int64_t)images[i].H * images[i].W;
+    return t;
+}
+
+// Queue the order kernels of one launch (its pixel order lands in A.order).
+static em_status_t queue_order(em_context *h, hipStream_t s, const NlemOrderArgs &A) {
+    OrderKernel k[4];
+    nlem_order_kernels(A, h->num_cus, k);
+    for (const OrderKernel &x : k) {
+        void *args[] = {const_cast<NlemOrderArgs *>(&A)};
+        EMX_HIP(h, hipLaunchKernel(x.fn, dim3(x.grid), dim3(x.block), args, 0, s));
+    }
+    return EM_OK;
+}
+
 // Queue one persistent launch per (patch radius, points per lane) group of
-// the images, each after a reset of its work-queue head.
+// the images, each after a reset of its work-queue head (and the kernels
+// that put its pixels in longest-first order).
 static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const nlem_image_t *images,
                             const nlem_options_t &o) {
     auto groups = group_images(count, images);
     if ((int)groups.size() > h->num_counters) return fail(h, EM_ERR_UNSUPPORTED, "too many shape groups");
     em_status_t st = ctx_reset_counters(h, s, h->counters, (int)groups.size());
     if (st != EM_OK) return st;
+    const bool ord = order_enabled(o);
+    char *ws = nullptr;
+    if (ord) {
+        size_t bytes = 0;
+        for (const NlemGroup &g : groups) bytes += nlem_order_bytes(group_pixels(g, images));
+        ws = static_cast<char *>(ctx_workspace(h, bytes, &st));
+        if (!ws) return st;
+    }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const NlemGroup &g = groups[gi];
         NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver);
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
+        if (ord) {
+            const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
+            ws += nlem_order_bytes(L.prefix[L.count]);
+            st = queue_order(h, s, A);
+            if (st != EM_OK) return st;
+            L.order = A.order;
+        }
         const int64_t total = L.prefix[L.count];
         const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
@@ -546,57 +589,86 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    std::vector<char> key(sizeof(nlem_image_t) * count + 5 * sizeof(float) + sizeof(int));
+    const bool ord = order_enabled(o);
+    std::vector<char> key(sizeof(nlem_image_t) * count + 5 * sizeof(float) + 2 * sizeof(int));
     memcpy(key.data(), images, sizeof(nlem_image_t) * count);
     float params[5] = {lo, hi, rho, (float)max_iter, tol};
     memcpy(key.data() + sizeof(nlem_image_t) * count, params, sizeof(params));
-    memcpy(key.data() + sizeof(nlem_image_t) * count + sizeof(params), &h->plan_epoch, sizeof(int));
+    const int flags[2] = {h->plan_epoch, ord ? 1 : 0};
+    memcpy(key.data() + sizeof(nlem_image_t) * count + sizeof(params), flags, sizeof(flags));
 
     if (!h->multi.exec || !same_key(key, h->multi.key)) {
+        // the old graph may still run on some stream before its scratch goes
+        if (h->multi.exec || h->multi.ws) (void)hipDeviceSynchronize();
         if (h->multi.exec) (void)hipGraphExecDestroy(h->multi.exec);
         if (h->multi.graph) (void)hipGraphDestroy(h->multi.graph);
+        if (h->multi.ws) (void)hipFree(h->multi.ws);
         h->multi.exec = nullptr;
         h->multi.graph = nullptr;
+        h->multi.ws = nullptr;
+        h->multi.key.clear();
         auto groups = group_images(count, images);
         if ((int)groups.size() > h->num_counters) return fail(h, EM_ERR_UNSUPPORTED, "too many shape groups");
+        if (ord) {
+            size_t bytes = 0;
+            for (const NlemGroup &g : groups) bytes += nlem_order_bytes(group_pixels(g, images));
+            if (hipMalloc(&h->multi.ws, bytes) != hipSuccess) {
+                h->multi.ws = nullptr;
+                return fail(h, EM_ERR_OUT_OF_MEMORY, "queue-order scratch allocation failed");
+            }
+        }
+        char *ws = static_cast<char *>(h->multi.ws);
         hipGraph_t graph;
         EMX_HIP(h, hipGraphCreate(&graph, 0));
+        // one chain per group: reset head -> [order: clear, count, scan, scatter] -> NLEM
+        auto add = [&](hipGraphNode_t *node, const hipGraphNode_t *dep, const void *fn, dim3 grid, dim3 block,
+                       void **args, const char *what) -> em_status_t {
+            hipKernelNodeParams p{};
+            p.func = const_cast<void *>(fn);
+            p.gridDim = grid;
+            p.blockDim = block;
+            p.sharedMemBytes = 0;
+            p.kernelParams = args;
+            p.extra = nullptr;
+            hipError_t e = hipGraphAddKernelNode(node, graph, dep, dep ? 1 : 0, &p);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                return hip_fail(h, e, what);
+            }
+            return EM_OK;
+        };
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const NlemGroup &g = groups[gi];
             NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM);
             unsigned int *counter = h->counters + gi;
             NlemLaunch L = make_launch(g, images, o, counter);
-            // node 1: zero this group's work-queue head (a kernel, not a memset node)
-            hipKernelNodeParams rp{};
+            hipGraphNode_t prev;
             int one = 1;
             void *rargs[] = {&counter, &one};
-            rp.func = reinterpret_cast<void *>(&reset_counters_kernel);
-            rp.gridDim = dim3(1);
-            rp.blockDim = dim3(64);
-            rp.sharedMemBytes = 0;
-            rp.kernelParams = rargs;
-            rp.extra = nullptr;
-            hipGraphNode_t rnode, knode;
-            hipError_t e = hipGraphAddKernelNode(&rnode, graph, nullptr, 0, &rp);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return hip_fail(h, e, "hipGraphAddKernelNode(reset)");
+            st = add(&prev, nullptr, reinterpret_cast<const void *>(&reset_counters_kernel), dim3(1), dim3(64),
+                     rargs, "hipGraphAddKernelNode(reset)");
+            if (st != EM_OK) return st;
+            if (ord) {
+                const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
+                ws += nlem_order_bytes(L.prefix[L.count]);
+                OrderKernel ok[4];
+                nlem_order_kernels(A, h->num_cus, ok);
+                for (const OrderKernel &x : ok) {
+                    void *oargs[] = {const_cast<NlemOrderArgs *>(&A)};
+                    hipGraphNode_t nn;
+                    st = add(&nn, &prev, x.fn, dim3(x.grid), dim3(x.block), oargs, "hipGraphAddKernelNode(order)");
+                    if (st != EM_OK) return st;
+                    prev = nn;
+                }
+                L.order = A.order;
             }
             const int64_t total = L.prefix[L.count];
             const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
-            hipKernelNodeParams kp{};
             void *kargs[] = {&L};
-            kp.func = const_cast<void *>(k.fn);
-            kp.gridDim = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, cap)));
-            kp.blockDim = dim3(k.threads);
-            kp.sharedMemBytes = 0;
-            kp.kernelParams = kargs;
-            kp.extra = nullptr;
-            e = hipGraphAddKernelNode(&knode, graph, &rnode, 1, &kp);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return hip_fail(h, e, "hipGraphAddKernelNode(nlem)");
-            }
+            hipGraphNode_t knode;
+            st = add(&knode, &prev, k.fn, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, cap))),
+                     dim3(k.threads), kargs, "hipGraphAddKernelNode(nlem)");
+            if (st != EM_OK) return st;
         }
         hipGraphExec_t exec;
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

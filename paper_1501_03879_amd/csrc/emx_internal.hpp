@@ -33,6 +33,32 @@ struct NlemLaunch {
     int32_t init_nlm;       // 1: start from the NLM patch instead of the noisy patch
     float eps;              // IRLS surrogate parameter
     unsigned int *counter;  // work-queue head, zeroed before the launch
+    const int32_t *order;   // queue position -> pixel (prefix-based index); null: identity
 };
+
+// Longest-first queue order (nlem_order.hip): pixels by decreasing patch
+// standard deviation, counting-sorted over kOrderBuckets buckets.
+constexpr int kOrderBuckets = 256;
+
+struct NlemOrderArgs {
+    NlemLaunch L;          // the images (descriptors and pixel prefix sums)
+    int32_t pr;            // patch radius
+    float scale;           // 2 kOrderBuckets / (hi - lo)
+    int32_t *order;        // [total] queue position -> pixel
+    uint8_t *bucket;       // [total] bucket of each pixel
+    unsigned int *cnt;     // counts, offsets and fill cursors (3 kOrderBuckets + 1)
+};
+
+struct OrderKernel {
+    const void *fn;        // takes one NlemOrderArgs by value
+    unsigned grid, block;
+};
+
+// Device bytes of the order scratch for `total` pixels.
+size_t nlem_order_bytes(int64_t total);
+// Arguments with the scratch laid out in `ws` (nlem_order_bytes(total) bytes).
+NlemOrderArgs nlem_order_args(const NlemLaunch &L, int pr, float lo, float hi, void *ws);
+// The four kernels to run in order on one stream: clear, count, scan, scatter.
+void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[4]);
 
 }  // namespace emx

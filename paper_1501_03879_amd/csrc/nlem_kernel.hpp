@@ -118,8 +118,9 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     for (;;) {
         if (threadIdx.x == 0) *item_s = atomicAdd(L.counter, 1u);
         __syncthreads();
-        const int64_t item = (int64_t)(unsigned int)uniform_int((int)*item_s);
-        if (item >= L.prefix[L.count]) break;
+        const int64_t qpos = (int64_t)(unsigned int)uniform_int((int)*item_s);
+        if (qpos >= L.prefix[L.count]) break;
+        const int64_t item = L.order ? (int64_t)uniform_int(L.order[qpos]) : qpos;
         int b = 0;
         while (b + 1 < L.count && item >= L.prefix[b + 1]) ++b;
         const NlemImageDesc I = L.img[b];

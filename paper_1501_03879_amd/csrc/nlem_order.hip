@@ -1,0 +1,125 @@
+// Longest-first order of the NLEM work queue.
+//
+// The persistent NLEM kernel pops pixels from a queue; a pixel whose solve
+// needs many iterations and is popped late keeps a few workgroups busy after
+// the rest of the chip has run dry.  The iteration count grows with the
+// spread of the pixel's noisy patch (its standard deviation over the patch
+// predicts log(iterations) with correlation 0.89 on the 256x256, sigma 20
+// image with 7x7 patches), so the queue is ordered by decreasing patch
+// standard deviation: a counting sort over kOrderBuckets buckets of
+// std / (hi - lo).  The order only changes which workgroup solves a pixel
+// and when; every pixel's arithmetic is the same.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "em_device.hpp"
+#include "emx_internal.hpp"
+
+namespace emx {
+
+// counts [0, K), offsets [K, 2K + 1), fill [2K + 1, 3K + 1)
+static constexpr int kCnt = 3 * kOrderBuckets + 1;
+
+__global__ void nlem_order_clear(NlemOrderArgs A) {
+    for (int i = threadIdx.x; i < kCnt; i += blockDim.x) A.cnt[i] = 0u;
+}
+
+// Bucket of every pixel (stored) and the per-bucket counts.
+__global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
+    __shared__ unsigned int hist[kOrderBuckets];
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const NlemLaunch &L = A.L;
+    const int64_t total = L.prefix[L.count];
+    const int P = 2 * A.pr + 1;
+    const float inv_d = 1.0f / (float)(P * P);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        int b = 0;
+        while (b + 1 < L.count && q >= L.prefix[b + 1]) ++b;
+        const NlemImageDesc &I = L.img[b];
+        const int pix = (int)(q - L.prefix[b]);
+        const int iy = pix / I.W, ix = pix - (pix / I.W) * I.W;
+        const float *f32 = static_cast<const float *>(I.img);
+        const __half *f16 = static_cast<const __half *>(I.img);
+        auto val = [&](int dy, int dx) -> float {
+            const int64_t o = (int64_t)reflect_idx(iy + dy, I.H) * I.W + reflect_idx(ix + dx, I.W);
+            return I.is_f16 ? __half2float(f16[o]) : f32[o];
+        };
+        float m = 0.0f;
+        for (int dy = -A.pr; dy <= A.pr; ++dy)
+            for (int dx = -A.pr; dx <= A.pr; ++dx) m += val(dy, dx);
+        m *= inv_d;
+        float v = 0.0f;
+        for (int dy = -A.pr; dy <= A.pr; ++dy)
+            for (int dx = -A.pr; dx <= A.pr; ++dx) {
+                const float e = val(dy, dx) - m;
+                v = fmaf(e, e, v);
+            }
+        const float key = sqrtf(v * inv_d) * A.scale;   // std / (hi - lo) * 2K, in [0, K]
+        const int bk = (key >= 0.0f) ? min((int)key, kOrderBuckets - 1) : kOrderBuckets - 1;  // NaN: first
+        A.bucket[q] = (uint8_t)bk;
+        atomicAdd(&hist[bk], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
+        if (hist[i]) atomicAdd(&A.cnt[i], hist[i]);
+}
+
+// Offsets with the largest bucket first.
+__global__ void nlem_order_scan(NlemOrderArgs A) {
+    if (threadIdx.x != 0) return;
+    unsigned int s = 0;
+    for (int k = kOrderBuckets - 1; k >= 0; --k) {
+        A.cnt[kOrderBuckets + k] = s;
+        s += A.cnt[k];
+    }
+    A.cnt[2 * kOrderBuckets] = s;
+}
+
+__global__ __launch_bounds__(256) void nlem_order_scatter(NlemOrderArgs A) {
+    const NlemLaunch &L = A.L;
+    const int64_t total = L.prefix[L.count];
+    unsigned int *fill = A.cnt + 2 * kOrderBuckets + 1;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int bk = A.bucket[q];
+        const unsigned int k = atomicAdd(&fill[bk], 1u);
+        A.order[A.cnt[kOrderBuckets + bk] + k] = (int32_t)q;
+    }
+}
+
+size_t nlem_order_bytes(int64_t total) {
+    const size_t a = ((size_t)total * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t b = ((size_t)total + 255) & ~(size_t)255;
+    return (a + b + (size_t)kCnt * sizeof(unsigned int) + 255) & ~(size_t)255;
+}
+
+NlemOrderArgs nlem_order_args(const NlemLaunch &L, int pr, float lo, float hi, void *ws) {
+    NlemOrderArgs A;
+    A.L = L;
+    A.pr = pr;
+    const float range = (hi > lo && hi - lo <= 3.0e38f) ? hi - lo : 1.0f;
+    A.scale = (float)(2 * kOrderBuckets) / range;
+    const int64_t total = L.prefix[L.count];
+    char *p = static_cast<char *>(ws);
+    A.order = reinterpret_cast<int32_t *>(p);
+    p += ((size_t)total * sizeof(int32_t) + 255) & ~(size_t)255;
+    A.bucket = reinterpret_cast<uint8_t *>(p);
+    p += ((size_t)total + 255) & ~(size_t)255;
+    A.cnt = reinterpret_cast<unsigned int *>(p);
+    return A;
+}
+
+void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[4]) {
+    const int64_t total = A.L.prefix[A.L.count];
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4LL * num_cus));
+    k[0] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_clear), 1, 256};
+    k[1] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_count), grid, 256};
+    k[2] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_scan), 1, 64};
+    k[3] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_scatter), grid, 256};
+}
+
+}  // namespace emx
