@@ -336,7 +336,8 @@ def main():
                      "frac_nonpacked_fma_peak": tflops / FP32_NONPACKED_TFLOPS,
                      "flops_per_launch": flops, "traffic": profiled_traffic(),
                      "timing": "HIP events on the launch stream around the timed steps; each step "
-                               "is one reset kernel (~5 us) plus one NLEM kernel launch"},
+                               "is one nlem_denoise call: a queue-head reset, the four queue-order "
+                               "kernels and one NLEM kernel launch"},
     }
 
     if args.plain > 0:

@@ -79,15 +79,27 @@ __global__ void nlem_order_scan(NlemOrderArgs A) {
     A.cnt[2 * kOrderBuckets] = s;
 }
 
+// Each block takes 256 pixels at a time: ranks within the block come from LDS
+// atomics, then one global atomic per (block, bucket) reserves the range.
 __global__ __launch_bounds__(256) void nlem_order_scatter(NlemOrderArgs A) {
+    __shared__ unsigned int lcnt[kOrderBuckets];
+    __shared__ unsigned int lbase[kOrderBuckets];
     const NlemLaunch &L = A.L;
     const int64_t total = L.prefix[L.count];
     unsigned int *fill = A.cnt + 2 * kOrderBuckets + 1;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int bk = A.bucket[q];
-        const unsigned int k = atomicAdd(&fill[bk], 1u);
-        A.order[A.cnt[kOrderBuckets + bk] + k] = (int32_t)q;
+    for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x; q0 < total; q0 += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) lcnt[i] = 0u;
+        __syncthreads();
+        const int64_t q = q0 + threadIdx.x;
+        const bool valid = q < total;
+        const int bk = valid ? A.bucket[q] : 0;
+        const unsigned int rank = valid ? atomicAdd(&lcnt[bk], 1u) : 0u;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
+            lbase[i] = lcnt[i] ? atomicAdd(&fill[i], lcnt[i]) : 0u;
+        __syncthreads();
+        if (valid) A.order[A.cnt[kOrderBuckets + bk] + lbase[bk] + rank] = (int32_t)q;
+        __syncthreads();   // lcnt and lbase are reused by the next chunk
     }
 }
 
