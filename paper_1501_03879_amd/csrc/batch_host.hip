@@ -20,6 +20,7 @@ unsigned int *ctx_counters(em_context *ctx, int n);
 em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, int n);
 void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
+em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fork, hipEvent_t **join);
 
 // Classify: counts per class; empty / malformed instances finished here.
 __global__ void batch_classify_count(const em_instance_t *inst, int64_t B, float *z, em_stats_t *stats,
@@ -90,7 +91,20 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
                                  ? (ball ? batch_class_table_wpen_ball() : batch_class_table_wpen())
                                  : (ball ? batch_class_table_admm_ball() : batch_class_table_admm());
     const bool vbox = ball || o.box_lo != nullptr;
+    // The classes run concurrently on the caller's stream and the handle's
+    // side streams (fork after the classification, join before returning), so
+    // one class's tail overlaps the others' work.  Class c goes to stream
+    // c mod 4: the four n-classes of a d-family land on different streams.
+    hipStream_t *side;
+    hipEvent_t fork, *join;
+    st = ctx_side_streams(ctx, &side, &fork, &join);
+    if (st != EM_OK) return st;
+    e = hipEventRecord(fork, s);
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
+    if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the class streams");
     for (int c = 0; c < kNumClasses; ++c) {
+        const int si = c % (kSideStreams + 1);
+        hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L;
         memset(&L, 0, sizeof(L));
         L.a = a;
@@ -121,9 +135,14 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, tab[c].fn, tab[c].threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
         void *args[] = {&L};
-        e = hipLaunchKernel(tab[c].fn, dim3(grid), dim3(tab[c].threads), args, 0, s);
+        e = hipLaunchKernel(tab[c].fn, dim3(grid), dim3(tab[c].threads), args, 0, cs);
         if (e != hipSuccess) return ctx_hip_error(ctx, e, "batch class launch");
     }
+    for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {
+        e = hipEventRecord(join[i], side[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, join[i], 0);
+    }
+    if (e != hipSuccess) return ctx_hip_error(ctx, e, "join of the class streams");
     return EM_OK;
 }
 

@@ -59,6 +59,10 @@ struct em_context {
     // plain-path workspace
     void *plain_ws = nullptr;
     size_t plain_ws_bytes = 0;
+    // side streams for concurrent shape-class launches (created on first use)
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
 };
 
 static em_status_t fail(em_context *ctx, em_status_t st, const std::string &msg) {
@@ -89,6 +93,22 @@ int blocks_per_cu(em_context *ctx, const void *fn, int threads) {
 }
 
 int ctx_num_cus(em_context *ctx) { return ctx->num_cus; }
+
+// The handle's side streams (default priority, non-blocking) and their
+// fork/join events, created on first use.
+em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fork, hipEvent_t **join) {
+    if (!ctx->fork) {
+        for (int i = 0; i < kSideStreams; ++i) {
+            if (!ctx->side[i]) EMX_HIP(ctx, hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+            if (!ctx->join[i]) EMX_HIP(ctx, hipEventCreateWithFlags(&ctx->join[i], hipEventDisableTiming));
+        }
+        EMX_HIP(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    }
+    *side = ctx->side;
+    *fork = ctx->fork;
+    *join = ctx->join;
+    return EM_OK;
+}
 int ctx_device(em_context *ctx) { return ctx->device; }
 
 em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg) { return fail(ctx, st, msg); }
@@ -231,6 +251,11 @@ extern "C" em_status_t em_destroy(em_handle_t h) {
     if (h->counters) (void)hipFree(h->counters);
     if (h->ws) (void)hipFree(h->ws);
     if (h->plain_ws) (void)hipFree(h->plain_ws);
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
+        if (h->join[i]) (void)hipEventDestroy(h->join[i]);
+    }
+    if (h->fork) (void)hipEventDestroy(h->fork);
     delete h;
     return EM_OK;
 }

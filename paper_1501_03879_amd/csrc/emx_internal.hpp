@@ -8,6 +8,7 @@
 namespace emx {
 
 constexpr int kMaxImagesPerLaunch = 16;
+constexpr int kSideStreams = 3;   // with the caller's stream: four concurrent class launches
 
 // One image of a denoising launch (passed by value inside the kernel arguments).
 struct NlemImageDesc {
