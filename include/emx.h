@@ -23,6 +23,9 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Every compute call only queues work on it and returns; kernel faults
  *    surface from em_sync or from the caller's own synchronisation.
+ *    em_solve_batch(_ex) also runs shape classes on three internal streams
+ *    of the handle, forked from `stream` and joined back into it by events,
+ *    so its work is still ordered on `stream` as seen by the caller.
  *  - Graph capture: em_solve_batch(_ex), em_solve_plain(_ex), nlem_denoise,
  *    nlem_denoise_ex and nlm_denoise may be recorded into a HIP graph by
  *    stream capture after an earlier call of the same sizes on the same
