@@ -288,6 +288,10 @@ em_status_t em_solve_plain(em_handle_t handle, void *stream, int64_t B,
  * r = patch_radius in [0, EM_MAX_PATCH_RADIUS], R = window_radius in
  * [0, EM_MAX_WINDOW_RADIUS], both < min(H, W); h_param > 0.
  * stats: NULL or H*W records.  `out` must not alias `img`.
+ * Scheduling: the pixels are solved in longest-first order (decreasing
+ * standard deviation of the noisy patch, which tracks the iteration count);
+ * the environment variable EMX_NLEM_ORDER=0 keeps raster order.  Results do
+ * not depend on the order.
  * Errors: INVALID_ARG (NULL handle/img/out, H or W < 1, radii out of range,
  * h_param <= 0, lo/hi not finite or lo > hi, rho <= 0, max_iter < 0,
  * tol < 0); UNSUPPORTED (radii above the compiled limits); HIP.
