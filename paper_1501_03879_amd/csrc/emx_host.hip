@@ -424,7 +424,11 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, co
 }
 
 // Longest-first queue order (see nlem_order.hip), on unless EMX_NLEM_ORDER=0;
-// pointless without iterations (every pixel then costs the same).
+// pointless without iterations (every pixel then costs the same), and for a
+// queue not much longer than the resident workgroups (nearly every pixel
+// starts at once): used from kOrderMinRounds rounds of the grid on.
+static constexpr int kOrderMinRounds = 8;
+
 static bool order_enabled(const nlem_options_t &o) {
     if (o.max_iter <= 0) return false;
     const char *e = getenv("EMX_NLEM_ORDER");
@@ -470,15 +474,15 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
         NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver);
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
-        if (ord) {
+        const int64_t total = L.prefix[L.count];
+        const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+        if (ord && total >= kOrderMinRounds * cap) {
             const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
-            ws += nlem_order_bytes(L.prefix[L.count]);
             st = queue_order(h, s, A);
             if (st != EM_OK) return st;
             L.order = A.order;
         }
-        const int64_t total = L.prefix[L.count];
-        const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+        if (ord) ws += nlem_order_bytes(total);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
         void *args[] = {&L};
         EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
@@ -673,9 +677,10 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             st = add(&prev, nullptr, reinterpret_cast<const void *>(&reset_counters_kernel), dim3(1), dim3(64),
                      rargs, "hipGraphAddKernelNode(reset)");
             if (st != EM_OK) return st;
-            if (ord) {
+            const int64_t total = L.prefix[L.count];
+            const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+            if (ord && total >= kOrderMinRounds * cap) {
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
-                ws += nlem_order_bytes(L.prefix[L.count]);
                 OrderKernel ok[4];
                 nlem_order_kernels(A, h->num_cus, ok);
                 for (const OrderKernel &x : ok) {
@@ -687,8 +692,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
                 }
                 L.order = A.order;
             }
-            const int64_t total = L.prefix[L.count];
-            const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+            if (ord) ws += nlem_order_bytes(total);
             void *kargs[] = {&L};
             hipGraphNode_t knode;
             st = add(&knode, &prev, k.fn, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(total, cap))),
