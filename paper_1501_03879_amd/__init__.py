@@ -164,7 +164,8 @@ class Handle:
                           eps=1e-6, max_iter=1000, tol=1e-4, adapt_every=1, adapt_ratio=10.0,
                           adapt_factor=2.0, ball_center=None, ball_radius=None, radius=None,
                           stream=None):
-        """em_solve_batch with a solver choice (ADMM, IRLS, adaptive-penalty ADMM)
+        """em_solve_batch with a solver choice (ADMM, IRLS, adaptive-penalty ADMM,
+        weighted-penalty ADMM)
         and a general set: per-coordinate bounds box_lo / box_hi (float32 device
         tensors laid out like z), or the Euclidean ball when `radius` (scalar)
         or `ball_radius` (one per instance) is given, centred at ball_center

@@ -6,7 +6,8 @@ that the oracle recomputes one by one at the GPU's iteration counts.
   against the FP32-image oracle, and of both against their own inputs);
 * 16 images of uneven size and radii in one nlem_denoise_multi graph;
 * 1,048,576 uneven point sets (drawn on the device), 10,240 sampled
-  instances (2,048 per d).
+  instances (2,048 per d); the same batch with IRLS and with the
+  weighted-penalty ADMM from the weighted-mean start, 1,280 sampled.
 """
 
 import numpy as np
@@ -125,5 +126,48 @@ def test_pointsets_full_batch_sampled():
     e, r = rel_errors(got, ref["z"], 6.0)
     report(f"pointsets 2^20 instances, {sample.size} sampled (oracle at GPU iterations)", e, r)
     print(f"[parity] pointsets full batch: mean iters {iters.mean():.1f}, converged "
+          f"{np.mean(flags == 1):.4f}, max iters {iters.max()}", flush=True)
+    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("solver", [1, 4])
+def test_pointsets_full_batch_irls_and_weighted_sampled(solver):
+    """The same 2^20-instance workload with IRLS (eps 1e-4 in the unit-scale
+    set units) and with the weighted-penalty ADMM, weighted-mean start,
+    tolerance 1e-4; 1,280 sampled instances (256 per d) against the oracle
+    at the GPU's iteration counts."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    B = 1 << 20
+    a, w, inst, zs = synth.pointsets.make_pointset_batch_device(505, B, dev)
+    it = emx.instances_tensor(inst, dev)
+    z = torch.zeros(zs, dtype=torch.float32, device=dev)
+    stats = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+    mu = synth.configs.POINTSET_MU
+    hd = handle()
+    hd.em_solve_batch_ex(a, w, it, z, stats, solver=solver, init=emx.INIT_WMEAN, lo=-3.0, hi=3.0, rho=mu,
+                         eps=1e-4, max_iter=synth.configs.POINTSET_MAX_ITER, tol=synth.configs.POINTSET_TOL)
+    hd.sync()
+    iters = emx.stats_view(stats)[0].cpu().numpy()
+    flags = emx.stats_view(stats)[1].cpu().numpy()
+    zc = z.cpu().numpy()
+    rng = np.random.default_rng(4 + solver)
+    sample = np.concatenate([rng.choice(np.flatnonzero(inst["d"] == dv), 256, replace=False)
+                             for dv in (2, 3, 16, 49, 64)])
+    pts, ws = [], []
+    for b in sample:
+        e = inst[b]
+        n, d = int(e["n"]), int(e["d"])
+        pts.append(a[e["a_off"]:e["a_off"] + n * d].view(n, d).cpu().numpy())
+        ws.append(w[e["w_off"]:e["w_off"] + n].cpu().numpy())
+    sb = synth.pointsets.pack_instances(pts, ws, -3.0, 3.0)
+    ref = oracle.em_batch(sb, mu, synth.configs.POINTSET_MAX_ITER, 0.0, init=oracle.INIT_WMEAN,
+                          solver=solver, eps=1e-4, max_iter_each=iters[sample])
+    got = np.concatenate([zc[inst[b]["z_off"]:inst[b]["z_off"] + inst[b]["d"]] for b in sample])
+    e, r = rel_errors(got, ref["z"], 6.0)
+    name = "irls" if solver == 1 else "weighted-penalty admm"
+    report(f"pointsets 2^20 {name}, {sample.size} sampled (oracle at GPU iterations)", e, r)
+    print(f"[parity] pointsets full batch {name}: mean iters {iters.mean():.1f}, converged "
           f"{np.mean(flags == 1):.4f}, max iters {iters.max()}", flush=True)
     assert e <= 1e-4
