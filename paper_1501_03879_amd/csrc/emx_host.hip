@@ -306,7 +306,7 @@ static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solve
         NlemKernelInfo k = nlem_kernel(pr, m, it->second, solver);
         if (k.fn) return k;
     }
-    return nlem_kernel(pr, m, nlem_default_wc(pr, m), solver);
+    return nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
 }
 
 static em_status_t check_solver_params(em_context *ctx, float lo, float hi, float rho,
@@ -420,7 +420,25 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, co
         L.prefix[k + 1] = L.prefix[k] + (int64_t)im.H * im.W;
     }
     L.counter = counter;
+    L.chunk = 1;
     return L;
+}
+
+// Queue positions per atomic: about 24,576 point coordinates of work per
+// pop (one pixel at d = 49, n = 441; up to 8 for small windows and patches),
+// fewer when the queue would not give every workgroup 16 chunks.
+// EMX_NLEM_CHUNK (1..64) overrides the rule.
+static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
+    const char *env = getenv("EMX_NLEM_CHUNK");
+    if (env && *env) {
+        const int v = atoi(env);
+        if (v >= 1 && v <= 64) return v;
+    }
+    const int64_t side = 2 * (int64_t)g.pr + 1;
+    const int64_t elems = side * side * (int64_t)g.m * 64;   // d times the window slots
+    int64_t k = std::max<int64_t>(1, std::min<int64_t>(8, 24576 / std::max<int64_t>(1, elems)));
+    while (k > 1 && total < 16 * k * cap) --k;
+    return (int)k;
 }
 
 // Longest-first queue order (see nlem_order.hip), on unless EMX_NLEM_ORDER=0;
@@ -476,6 +494,7 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
         const int64_t total = L.prefix[L.count];
         const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+        L.chunk = queue_chunk(g, total, cap);
         if (ord && total >= kOrderMinRounds * cap) {
             const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
             st = queue_order(h, s, A);
@@ -594,7 +613,7 @@ extern "C" em_status_t nlem_plan(em_handle_t h, int32_t patch_radius, int32_t wi
         return fail(h, EM_ERR_INVALID_ARG, "bad shape or solver");
     const int m = points_per_lane(window_radius);
     auto it = h->plans.find(PlanKey{patch_radius, m, solver});
-    *waves = (it != h->plans.end()) ? it->second : nlem_default_wc(patch_radius, m);
+    *waves = (it != h->plans.end()) ? it->second : nlem_default_wc(patch_radius, m, solver);
     return EM_OK;
 }
 
@@ -679,6 +698,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             if (st != EM_OK) return st;
             const int64_t total = L.prefix[L.count];
             const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
+            L.chunk = queue_chunk(g, total, cap);
             if (ord && total >= kOrderMinRounds * cap) {
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
                 OrderKernel ok[4];

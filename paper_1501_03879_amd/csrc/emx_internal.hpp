@@ -35,6 +35,7 @@ struct NlemLaunch {
     float eps;              // IRLS surrogate parameter
     unsigned int *counter;  // work-queue head, zeroed before the launch
     const int32_t *order;   // queue position -> pixel (prefix-based index); null: identity
+    int32_t chunk;          // queue positions taken per atomic (>= 1)
 };
 
 // Longest-first queue order (nlem_order.hip): pixels by decreasing patch

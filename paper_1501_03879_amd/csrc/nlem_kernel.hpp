@@ -115,8 +115,19 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     // tile offset of slice coordinate jj within a patch (folded after unrolling)
     auto poff = [](int jj) { return ((J0 + jj) / S::PS) * S::P + ((J0 + jj) % S::PS); };
 
+    // The workgroup takes L.chunk consecutive queue positions per atomic: one
+    // global counter serves every workgroup, and for cheap pixels (small
+    // windows) its update rate, not the solves, would set the pace.
+    unsigned int cbase = 0, cleft = 0;   // thread 0: the rest of the current chunk
     for (;;) {
-        if (threadIdx.x == 0) *item_s = atomicAdd(L.counter, 1u);
+        if (threadIdx.x == 0) {
+            if (cleft == 0) {
+                cbase = atomicAdd(L.counter, (unsigned int)L.chunk);
+                cleft = (unsigned int)L.chunk;
+            }
+            *item_s = cbase++;
+            --cleft;
+        }
         __syncthreads();
         const int64_t qpos = (int64_t)(unsigned int)uniform_int((int)*item_s);
         if (qpos >= L.prefix[L.count]) break;

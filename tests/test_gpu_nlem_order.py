@@ -78,3 +78,29 @@ def test_order_multi_graph(monkeypatch):
 def torch_equal(a, b):
     import torch
     return bool(torch.equal(a, b))
+
+
+@pytest.mark.parametrize("chunk", [3, 8])
+def test_queue_chunks_parity(chunk, monkeypatch):
+    """Several queue positions per atomic (forced with EMX_NLEM_CHUNK): the
+    same outputs and statistics as one per atomic, bit for bit, and parity
+    with the oracle at a fixed iteration count (1e-4 of the range)."""
+    import oracle
+    from helpers import rel_errors, report
+    gpu()
+    hd = handle()
+    img = _img(21, 45, 52)
+    runs = []
+    for c in ("1", str(chunk)):
+        monkeypatch.setenv("EMX_NLEM_CHUNK", c)
+        items = _items([(21, 45, 52, 2, 5)])
+        hd.nlem_denoise_ex(items, max_iter=9, tol=0.0)
+        hd.sync()
+        runs.append(_snapshot(items))
+    (o1, s1), = runs[0]
+    (ok, sk), = runs[1]
+    assert torch_equal(o1, ok) and torch_equal(s1, sk)
+    ref = oracle.nlem(img, 2, 5, 200.0, 0, 255, 1e-3, 9, 0.0)
+    e, r = rel_errors(ok.cpu().numpy().reshape(-1).astype(np.float64), ref["out"], 255.0)
+    report(f"nlem r2 R5 T9, {chunk} queue positions per atomic", e, r)
+    assert e <= 1e-4
