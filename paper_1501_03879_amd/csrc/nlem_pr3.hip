@@ -1,5 +1,6 @@
 // Compiled NLEM shapes for patch radius 3 (d = 49): EM-ADMM for every
-// listed coordinate-wave count, IRLS for the default one.
+// listed coordinate-wave count (one wave only at m = 1, where the 49
+// coordinates of one point fit a wave's registers), IRLS for one count.
 #include "nlem_kernel.hpp"
 #include "nlem_table.hpp"
 
@@ -13,6 +14,7 @@ static NlemKernelInfo info() {
 NlemKernelInfo nlem_kernels_pr3(int m, int wc, int solver) {
     if (solver == 0) {
         switch (m * 8 + wc) {
+            case 9: return info<3, 1, 1, 0>();
             case 10: return info<3, 1, 2, 0>();
             case 11: return info<3, 1, 3, 0>();
             case 12: return info<3, 1, 4, 0>();

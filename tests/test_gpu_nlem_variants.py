@@ -14,7 +14,7 @@ from helpers import rel_errors, report, run_nlem
 pytestmark = pytest.mark.gpu
 D = 255.0
 # (patch radius, window radius) -> compiled coordinate-wave counts
-VARIANTS = [(3, 10, (2, 3, 4)), (3, 5, (2, 3, 4)), (2, 7, (1, 2, 3)), (2, 10, (1, 2, 3))]
+VARIANTS = [(3, 10, (2, 3, 4)), (3, 5, (2, 3, 4)), (3, 3, (1, 2, 3, 4)), (2, 7, (1, 2, 3)), (2, 10, (1, 2, 3))]
 
 
 def _img(seed, H, W, sigma=25.0):
