@@ -68,6 +68,10 @@ def load_library():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} not found: build the HIP library first "
                                "(python -c 'import __graft_entry__ as g; g.build()')")
+        # torch first: it brings its own HIP runtime (same soname as the system
+        # one), and libemx.so must bind to that runtime, not load a second one
+        # that torch would then pick up in place of its own.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         vp, i32, i64, f32 = C.c_void_p, C.c_int32, C.c_int64, C.c_float
         lib.em_create.argtypes = [C.POINTER(vp), C.c_int]
