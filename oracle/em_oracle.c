@@ -17,6 +17,11 @@
  * summed sequentially k = 1..n exactly in the order Algorithm 1 gives.
  * Readings where the paper is silent (stopping rule, tolerance scale, border
  * handling, flags) are stated next to the code that implements them.
+ *
+ * Parity unpinned: the NLEM output after a finite number of iterations at
+ * image scale is checked only through its parts (weights, patches, window,
+ * centre pixel, one-step and converged pins); the paper prints no per-pixel
+ * values to compare with.
  */
 #include <math.h>
 #include <stdint.h>
