@@ -80,7 +80,7 @@ typedef enum {
     EM_INIT_GIVEN = 0, /* the caller's z (in/out) */
     EM_INIT_MAXW = 1,  /* the point of largest weight, lowest index on ties */
     EM_INIT_WMEAN = 2  /* the weighted mean sum_k w_k a_k / sum_k w_k, the analogue of the
-                          NLM patch of Section 4 (the plain mean of the points when every
+                          NLM patch of Section 3 (the plain mean of the points when every
                           weight is zero); not projected, like the other starts */
 } em_init_t;
 

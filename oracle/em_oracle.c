@@ -712,7 +712,7 @@ int oracle_max_threads(void)
  * result at z + z_off[b].  init = GIVEN uses z as the initial value; init =
  * MAXW starts from the point of largest weight (lowest index on ties); init =
  * WMEAN from the weighted mean sum_k w_k a_k / sum_k w_k (the counterpart of
- * the NLM patch that Section 4 starts from), or the plain mean of the points
+ * the NLM patch that Section 3 starts from), or the plain mean of the points
  * when every weight is zero.
  * max_iter_each (nullable) overrides max_iter per instance.
  * solver: 0 = EM-ADMM (adapt_every > 0 adds the adaptive penalty), 1 = IRLS
