@@ -23,22 +23,30 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fork, hipEvent_t **join);
 
 // Classify: counts per class; empty / malformed instances finished here.
-__global__ void batch_classify_count(const em_instance_t *inst, int64_t B, float *z, em_stats_t *stats,
-                                     unsigned int *counts) {
+// Counts go through a per-block LDS histogram (one global atomic per block
+// and class): a million instances over twenty counters would otherwise
+// serialise on the hot ones.
+__global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t *inst, int64_t B, float *z,
+                                                            em_stats_t *stats, unsigned int *counts) {
+    __shared__ unsigned int hist[kNumClasses];
+    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const em_instance_t e = inst[b];
-    if (e.n == 0 && e.d >= 1 && e.d <= EM_MAX_D) {
-        if (stats) stats[b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
-        return;
+    if (b < B) {
+        const em_instance_t e = inst[b];
+        if (e.n == 0 && e.d >= 1 && e.d <= EM_MAX_D) {
+            if (stats) stats[b] = em_stats_t{0, EM_EMPTY, 0.0f, 0.0f};
+        } else if (e.n < 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
+            if (e.d >= 1 && e.d <= EM_MAX_D)
+                for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
+            if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
+        } else {
+            atomicAdd(&hist[class_of(e.n, e.d)], 1u);
+        }
     }
-    if (e.n < 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
-        if (e.d >= 1 && e.d <= EM_MAX_D)
-            for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
-        if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
-        return;
-    }
-    atomicAdd(&counts[class_of(e.n, e.d)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x)
+        if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
 __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *offsets) {
@@ -52,15 +60,30 @@ __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *of
     }
 }
 
-__global__ void batch_classify_scatter(const em_instance_t *inst, int64_t B, const unsigned int *offsets,
-                                       unsigned int *fill, int32_t *list) {
+// Ranks within the block from LDS atomics, then one global atomic per
+// (block, class) reserves the block's range of the class list.
+__global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_t *inst, int64_t B,
+                                                              const unsigned int *offsets, unsigned int *fill,
+                                                              int32_t *list) {
+    __shared__ unsigned int lcnt[kNumClasses];
+    __shared__ unsigned int lbase[kNumClasses];
+    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x) lcnt[i] = 0u;
+    __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const em_instance_t e = inst[b];
-    if (e.n <= 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) return;
-    const int c = class_of(e.n, e.d);
-    const unsigned int k = atomicAdd(&fill[c], 1u);
-    list[offsets[c] + k] = (int32_t)b;
+    int c = -1;
+    unsigned int rank = 0;
+    if (b < B) {
+        const em_instance_t e = inst[b];
+        if (e.n > 0 && e.n <= EM_MAX_N && e.d >= 1 && e.d <= EM_MAX_D) {
+            c = class_of(e.n, e.d);
+            rank = atomicAdd(&lcnt[c], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x)
+        lbase[i] = lcnt[i] ? atomicAdd(&fill[i], lcnt[i]) : 0u;
+    __syncthreads();
+    if (c >= 0) list[offsets[c] + lbase[c] + rank] = (int32_t)b;
 }
 
 em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
