@@ -291,7 +291,14 @@ extern "C" em_status_t em_sync(em_handle_t h, void *stream) {
 // already within kArmFactor * tol * D (both must be within tol * D to stop).
 static constexpr float kArmFactor = 1.0f;
 
-static int points_per_lane(int R) { return ((2 * R + 1) * (2 * R + 1) + 63) / 64; }
+// Points per lane M for a window radius (n = (2R+1)^2 <= 64 M): the
+// smallest M, except R = 9, which takes M = 7 for the kernels' row mapping
+// (3 runs of 7 columns x 19 rows; measured 4-5% faster than M = 6 slot by
+// slot).  M = 4 (R = 7) and M = 7 (R = 9, 10) use the row mapping.
+static int points_per_lane(int R) {
+    static const int kM[EM_MAX_WINDOW_RADIUS + 1] = {1, 1, 1, 1, 2, 2, 3, 4, 5, 7, 7};
+    return kM[R];
+}
 
 // Kernel for a shape: EMX_NLEM_WC when that variant is compiled (a manual
 // override), else the handle's autotuned plan, else the default table.

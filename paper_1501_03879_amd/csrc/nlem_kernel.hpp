@@ -81,11 +81,16 @@ struct NlemShape {
     static constexpr int P = WSM + EMX_TILE_PITCH_PAD;
     static constexpr int TILE = TW * P;
     static constexpr int DS = (D + WC - 1) / WC;
-    // Row mapping: when a window row splits into whole runs of M points and the
-    // window fits 64 lanes that way (21 = 3 x 7 for R = 10), lane l owns M
-    // consecutive columns of one row, so one base address plus immediate
-    // offsets reaches all its points.  Used only for R = RMAX.
-    static constexpr bool ROWMAP = M > 1 && (WSM % M == 0) && (WSM / M) * WSM <= 64;
+    // Row mapping: each window row is cut into ceil(WS / M) runs of M
+    // consecutive columns and lane l owns one run, so one base address plus
+    // immediate offsets reaches all its points and consecutive points share
+    // patch coordinates (one LDS read per coordinate instead of M).  The host
+    // gives M = 4 to R = 7 (4 runs x 15 rows = 60 lanes) and M = 7 to R = 9
+    // and 10 (3 runs x 19 or 21 rows); columns past the window in a last run
+    // are masked slots.  Other windows would need a larger M for their runs
+    // to fit 64 lanes, and the extra idle slots cost more than the loads
+    // save (measured), so M = 2, 3, 5, 6 read the points slot by slot.
+    static constexpr bool ROWMAP = (M == 4 || M == 7);
     static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
     static_assert(TW <= 64, "tile rows are staged one column per lane");
 };
@@ -140,16 +145,20 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         const int iy = pix / W, ix = pix - (pix / W) * W;
         const int WSr = 2 * R + 1;
         const int TWr = 2 * (R + PR) + 1;
+        const int LPR = (WSr + M - 1) / M;                       // runs per window row
+        const int TWs = S::ROWMAP ? max(TWr, LPR * M + 2 * PR) : TWr;   // staged columns
 
         // ---- a1: stage the tile (rows iy-R-r .. iy+R+r), reflected at borders
         // (rows outside the reflection range are clamped; only window slots
         // outside the image read them).  Wave w loads rows w, w + WC, ...,
-        // one column per lane (TW <= 64).
+        // one column per lane (TW <= 64); the columns a last partial run
+        // reaches past the window are staged too (finite values of masked
+        // slots).
         {
             const int gx = reflect_idx(ix - R - PR + lane, W);
             for (int ty = SW; ty < TWr; ty += WC) {
                 const int64_t gy = reflect_idx(iy - R - PR + ty, H);
-                if (lane < TWr) {
+                if (lane < TWs) {
                     float v;
                     if (I.is_f16)
                         v = __half2float(reinterpret_cast<const __half *>(I.img)[gy * W + gx]);
@@ -168,15 +177,14 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         int base[S::ROWMAP ? 1 : M];
         float lam[M];
         if constexpr (S::ROWMAP) {
-            // lane owns M consecutive columns of one window row (R = RMAX here)
-            constexpr int LPR = S::WSM / M;
+            // lane owns M consecutive columns of one window row
             const int wy = lane / LPR, wx0 = (lane - (lane / LPR) * LPR) * M;
-            const bool rowok = lane < LPR * S::WSM && iy - R + wy >= 0 && iy - R + wy < H;
+            const bool rowok = lane < LPR * WSr && iy - R + wy >= 0 && iy - R + wy < H;
             base[0] = rowok ? (wy * S::P + wx0) : 0;
 #pragma unroll
             for (int q = 0; q < M; ++q) {
                 const int px = ix - R + wx0 + q;
-                lam[q] = (rowok && px >= 0 && px < W) ? 0.0f : -1.0f;
+                lam[q] = (rowok && wx0 + q < WSr && px >= 0 && px < W) ? 0.0f : -1.0f;
             }
         } else {
             const float inv_ws = 1.0f / (float)WSr;
