@@ -290,8 +290,10 @@ em_status_t em_solve_plain(em_handle_t handle, void *stream, int64_t B,
  * stats: NULL or H*W records.  `out` must not alias `img`.
  * Scheduling: the pixels are solved in longest-first order (decreasing
  * standard deviation of the noisy patch, which tracks the iteration count);
- * the environment variable EMX_NLEM_ORDER=0 keeps raster order.  Results do
- * not depend on the order.
+ * the environment variable EMX_NLEM_ORDER=0 keeps raster order.  Each
+ * workgroup takes a few consecutive queue positions per atomic when pixels
+ * are cheap (small windows and patches); EMX_NLEM_CHUNK=k (1..64) fixes
+ * that count.  Results do not depend on either.
  * Errors: INVALID_ARG (NULL handle/img/out, H or W < 1, radii out of range,
  * h_param <= 0, lo/hi not finite or lo > hi, rho <= 0, max_iter < 0,
  * tol < 0); UNSUPPORTED (radii above the compiled limits); HIP.
