@@ -184,6 +184,8 @@ typedef struct {
     const float *ball_center; /* BALL: NULL (origin) or centres, device, indexed like z */
     const float *ball_radius; /* BALL: NULL (use radius) or one radius per instance, device */
     float radius;          /* BALL: the radius when ball_radius is NULL */
+    int32_t points_f16;    /* nonzero: `a` holds the points as FP16 (binary16), widened to FP32
+                              when staged; offsets count elements (em_solve_batch_ex only) */
 } em_options_t;
 
 /*

@@ -52,7 +52,7 @@ class EmOptions(C.Structure):
                 ("eps", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_float),
                 ("adapt_every", C.c_int32), ("adapt_ratio", C.c_float), ("adapt_factor", C.c_float),
                 ("fast_eta", C.c_float), ("set", C.c_int32), ("ball_center", C.c_void_p),
-                ("ball_radius", C.c_void_p), ("radius", C.c_float)]
+                ("ball_radius", C.c_void_p), ("radius", C.c_float), ("points_f16", C.c_int32)]
 
 
 _lib = None
@@ -173,10 +173,13 @@ class Handle:
         and a general set: per-coordinate bounds box_lo / box_hi (float32 device
         tensors laid out like z), or the Euclidean ball when `radius` (scalar)
         or `ball_radius` (one per instance) is given, centred at ball_center
-        (laid out like z; origin when None)."""
+        (laid out like z; origin when None).  A float16 tensor `a` is passed
+        as FP16 point storage."""
         B = int(inst.numel() * inst.element_size() // 32)
         opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every,
                        adapt_ratio, adapt_factor, 0.999, ball_center, ball_radius, radius)
+        import torch
+        opt.points_f16 = 1 if a.dtype == torch.float16 else 0
         st = self.lib.em_solve_batch_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
                                         C.byref(opt), _ptr(z), _ptr(stats))
         self._check(st, "em_solve_batch_ex")
@@ -190,6 +193,8 @@ class Handle:
         B = int(inst.numel() * inst.element_size() // 32)
         hp = inst_host.ctypes.data if hasattr(inst_host, "ctypes") else inst_host.data_ptr()
         opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, 1e-6, max_iter, tol, 1, 10.0, 2.0, eta)
+        import torch
+        opt.points_f16 = 1 if a.dtype == torch.float16 else 0
         st = self.lib.em_solve_plain_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
                                         C.c_void_p(hp), C.byref(opt), _ptr(z), _ptr(stats))
         self._check(st, "em_solve_plain_ex")
@@ -280,7 +285,7 @@ def _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adap
                      float(adapt_factor), float(eta), SET_BALL if ball else SET_BOX,
                      None if ball_center is None else ball_center.data_ptr(),
                      None if ball_radius is None else ball_radius.data_ptr(),
-                     float(0.0 if radius is None else radius))
+                     float(0.0 if radius is None else radius), 0)
 
 
 def _image_array(items):

@@ -155,6 +155,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         L.max_iter = o.max_iter;
         L.init = o.init;
         L.cls = c;
+        L.a16 = o.points_f16 ? 1 : 0;
         const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, tab[c].fn, tab[c].threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
         void *args[] = {&L};

@@ -34,6 +34,7 @@
 #pragma once
 
 #include <float.h>
+#include <hip/hip_fp16.h>
 
 #include "em_device.hpp"
 #include "emx_internal.hpp"
@@ -67,7 +68,7 @@ __host__ __device__ inline int class_of(int n, int d) {
 
 // Kernel arguments of one class launch.
 struct ClassLaunch {
-    const float *a;
+    const float *a;               // points (FP32, or FP16 when a16)
     const float *w;
     const em_instance_t *inst;
     const int32_t *list;
@@ -86,6 +87,7 @@ struct ClassLaunch {
     float adapt_factor;           // ADMM: penalty scale factor
     int32_t adapt_every;          // ADMM: 0 = fixed penalty
     int32_t max_iter, init, cls;
+    int32_t a16;                  // points stored as FP16 (widened on staging)
 };
 
 struct ClassKernel {
@@ -153,6 +155,8 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         const em_instance_t e = L.inst[b];
         const int n = uniform_int(e.n), d = uniform_int(e.d);
         const float *A = L.a + e.a_off;
+        const __half *A16 = reinterpret_cast<const __half *>(L.a) + e.a_off;
+        auto aval = [&](int64_t i) -> float { return L.a16 ? __half2float(A16[i]) : A[i]; };
         const float *Wt = L.w + e.w_off;
         float *Z = L.z + e.z_off;
         const int pitch = d | 1;
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 __syncthreads();
                 for (int i = threadIdx.x; i < cnt * d; i += S::THREADS) {
                     const int pp = i / d, jj = i - (i / d) * d;
-                    stage[pp * pitch + jj] = A[(int64_t)p0 * d + i];
+                    stage[pp * pitch + jj] = aval((int64_t)p0 * d + i);
                 }
                 __syncthreads();
                 if (pc == pw) {
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             const bool vj = RSx::valid(row, j) && cc < d;
             float zv = 0.0f, lv = BALL ? 0.0f : L.lo, hv = BALL ? 0.0f : L.hi;
             if (vj) {
-                zv = (L.init == EM_INIT_MAXW) ? A[(int64_t)best * d + cc]
+                zv = (L.init == EM_INIT_MAXW) ? aval((int64_t)best * d + cc)
                      : (L.init == EM_INIT_WMEAN) ? zw[j] : Z[cc];
                 if (BALL) {
                     if (L.ball_center) lv = L.ball_center[e.z_off + cc];

@@ -845,6 +845,7 @@ extern "C" em_status_t em_solve_plain_ex(em_handle_t h, void *stream, int64_t B,
     if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_ADMM_FAST)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");
     if (o.set == EM_SET_BALL) return fail(h, EM_ERR_UNSUPPORTED, "the ball runs in em_solve_batch_ex");
+    if (o.points_f16) return fail(h, EM_ERR_UNSUPPORTED, "FP16 points run in em_solve_batch_ex");
     if (o.set != EM_SET_BOX) return fail(h, EM_ERR_INVALID_ARG, "bad set");
     if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
         return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");

@@ -334,6 +334,34 @@ def test_weighted_penalty_boxes_ball_and_tolerance_mode():
                                   f"{st['iters'][live].mean():.1f}, converged {np.mean(st['flags'][live] == 1):.3f})")
 
 
+@pytest.mark.parametrize("solver", [ADMM, IRLS])
+def test_fp16_point_storage(solver):
+    """FP16 point storage (em_options_t.points_f16, set from a float16 tensor):
+    parity with the oracle run on the FP16-rounded points (the same input
+    bits), every shape class, fixed iterations."""
+    import torch
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    dev = gpu()
+    b = _mixed(61 + solver, 300)
+    b.a = np.clip(b.a, -1000.0, 1000.0).astype(np.float16).astype(np.float32)   # representable in FP16
+    a16 = torch.from_numpy(b.a.astype(np.float16)).to(dev)
+    w = torch.from_numpy(b.w).to(dev)
+    inst = emx.instances_tensor(b.inst, dev)
+    z = torch.zeros(b.z_size, dtype=torch.float32, device=dev)
+    st = torch.zeros((b.B, 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    hd.em_solve_batch_ex(a16, w, inst, z, st, solver=solver, init=emx.INIT_MAXW, lo=b.lo, hi=b.hi, rho=0.5,
+                         eps=1e-4, max_iter=25, tol=0.0)
+    hd.sync()
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_MAXW, eps=1e-4,
+                          solver=oracle.SOLVER_IRLS if solver == IRLS else oracle.SOLVER_ADMM)
+    _check(b, z.cpu().numpy().astype(np.float64), ref["z"], 6.0, f"batch fp16 points solver {solver} T25")
+    with pytest.raises(emx.EmxError) as e:
+        hd.em_solve_plain_ex(a16, w, inst, b.inst, z, solver=ADMM)
+    assert e.value.status == emx.EM_ERR_UNSUPPORTED
+
+
 def test_solver_routing_errors():
     import torch
     import paper_1501_03879_amd as emx
