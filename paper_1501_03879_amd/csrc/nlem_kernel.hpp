@@ -91,7 +91,12 @@ struct NlemShape {
     // to fit 64 lanes, and the extra idle slots cost more than the loads
     // save (measured), so M = 2, 3, 5, 6 read the points slot by slot.
     static constexpr bool ROWMAP = (M == 4 || M == 7);
-    static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 : 1;
+    // partial sums of ||delta||^2 from the WC waves (two buffers, by
+    // iteration parity), then one shrink factor per point (M x 64)
+    static constexpr int XN = (WC > 1) ? 2 * WC * M * 64 + M * 64 : 1;
+    // shrink factors are taken by wave w for the lane's points
+    // [w QS, min((w + 1) QS, M))
+    static constexpr int QS = (M + WC - 1) / WC;
     static_assert(TW <= 64, "tile rows are staged one column per lane");
 };
 
@@ -430,34 +435,85 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
                 }
             }
+            float s[M];
             float rd_all = rd_w;
             if constexpr (WC > 1) {
+                // The waves hold partial sums of ||delta||^2 over their
+                // coordinate slices.  Wave SW adds up the partials of its
+                // share of the lane's points, takes their shrink factors (on
+                // the first iteration their weights too, a2) and hands them
+                // to the other waves through LDS, so each point's factor is
+                // computed once per workgroup rather than once per wave.  The
+                // partials are added in wave order, as every wave would.
+                constexpr int Q0 = (SW * S::QS < M) ? SW * S::QS : M;
+                constexpr int QN = (M - Q0 < S::QS) ? (M - Q0) : S::QS;
+                float *X = xn + (t & 1) * WC * M * 64;
                 float *XS = xs + (t & 1) * WC * 4;
+                float *SV = xn + 2 * WC * M * 64;
+#pragma unroll
+                for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = nrm[q];
                 if (lane == 0) XS[SW * 4] = rd_w;
-                exchange(nrm, xn + (t & 1) * WC * M * 64);
+                __syncthreads();
                 rd_all = XS[0];
 #pragma unroll
                 for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
                 rd_all = readfirstlane(rd_all);
+                float ns[QN > 0 ? QN : 1];
+#pragma unroll
+                for (int qq = 0; qq < QN; ++qq) {
+                    ns[qq] = X[(Q0 + qq) * 64 + lane];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) ns[qq] += X[(w * M + Q0 + qq) * 64 + lane];
+                }
+                // (a branch of its own: folded into the iteration, the
+                // exponentials would run on every iteration)
+                const bool first = uniform(t == 1 && !pre);
+                if (__builtin_expect(first, 0)) {
+                    // ---- a2: NLM weights from the first iteration's
+                    // distances (the noisy start: delta = P_i - P_j)
+                    bool nonfinite = false;
+#pragma unroll
+                    for (int qq = 0; qq < QN; ++qq) {
+                        const int q = Q0 + qq;
+                        const bool valid = lam[q] >= 0.0f;   // -1: slot outside the image
+                        nonfinite |= valid && !(ns[qq] <= FLT_MAX);
+                        lam[q] = (valid ? exp2f(-ns[qq] * I.k_h) : 0.0f) * L.inv_mu;
+                    }
+                    if (lane == 0) XS[SW * 4 + 2] = __any(nonfinite) ? 1.0f : 0.0f;
+                }
+#pragma unroll
+                for (int qq = 0; qq < QN; ++qq) SV[(Q0 + qq) * 64 + lane] = shrink(ns[qq], lam[Q0 + qq]);
+                __syncthreads();
+                if (first) {
+                    float nf = XS[2];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) nf += XS[w * 4 + 2];
+                    if (uniform(nf > 0.0f)) {
+                        bad = true;
+                        break;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < M; ++q) s[q] = SV[q * 64 + lane];
+            } else {
+                // ---- a2 (one wave holds whole points): the weights from the
+                // first iteration's distances, unless the pre-pass made them
+                if (t == 1 && !pre) {
+                    float w1[M];
+                    if (!weights_from(nrm, w1)) {
+                        bad = true;
+                        break;
+                    }
+#pragma unroll
+                    for (int q = 0; q < M; ++q) lam[q] = w1[q] * L.inv_mu;
+                }
+#pragma unroll
+                for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
             }
             // dual residual of iteration t-1 (all waves hold identical sums),
             // which arms the primal residual of this iteration
             if (t > 1) rd2 = rd_all * inv_d;
-            // ---- a2: NLM weights from the first iteration's distances (the
-            // noisy start: delta = P_i - P_j), unless the pre-pass made them
-            if (t == 1 && !pre) {
-                float w1[M];
-                if (!weights_from(nrm, w1)) {
-                    bad = true;
-                    break;
-                }
-#pragma unroll
-                for (int q = 0; q < M; ++q) lam[q] = w1[q] * L.inv_mu;
-            }
             const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
-            float s[M];
-#pragma unroll
-            for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
 
             // ---- a8 (armed iterations only): lane sums of ||x_k - c||^2 with
             // x_k = v_k - e_k = a_k + (1 - s) delta, read-only on the state
