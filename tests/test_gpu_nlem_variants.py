@@ -14,7 +14,10 @@ from helpers import rel_errors, report, run_nlem
 pytestmark = pytest.mark.gpu
 D = 255.0
 # (patch radius, window radius) -> compiled coordinate-wave counts
-VARIANTS = [(3, 10, (2, 3, 4)), (3, 5, (2, 3, 4)), (3, 3, (1, 2, 3, 4)), (2, 7, (1, 2, 3)), (2, 10, (1, 2, 3))]
+# (points per lane M = 7, 2, 1, 4, 7, 5, 3, 5: the waves share each lane's
+# points for the shrink factors in every split, including waves with none)
+VARIANTS = [(3, 10, (2, 3, 4)), (3, 5, (2, 3, 4)), (3, 3, (1, 2, 3, 4)), (2, 7, (1, 2, 3)), (2, 10, (1, 2, 3)),
+            (3, 8, (2, 3, 4)), (3, 6, (2, 3, 4)), (2, 8, (1, 2, 3))]
 
 
 def _img(seed, H, W, sigma=25.0):
