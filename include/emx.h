@@ -406,6 +406,21 @@ em_status_t nlem_autotune(em_handle_t handle, void *stream, const nlem_image_t *
 em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
                       int32_t solver, int32_t *waves);
 
+/*
+ * em_kernel_timing - for measurement tools: while enabled (enable != 0),
+ * every NLEM solve launch of nlem_denoise and nlem_denoise_ex is bracketed
+ * by two HIP events on its stream, so the solve kernel's own duration can be
+ * read without the small kernels that precede it (queue reset and queue
+ * order).  Not recorded: launches into a stream that is being captured, and
+ * the multi-image graph.  Enabling or disabling discards unread timings.
+ * em_kernel_timing_read - waits for the recorded events and returns the sum
+ * of their durations (ms) and the number of launches, then clears them;
+ * read at least every 4096 launches (the next timed launch fails with
+ * UNSUPPORTED otherwise).  Errors: INVALID_ARG (NULL handle or outputs); HIP.
+ */
+em_status_t em_kernel_timing(em_handle_t handle, int32_t enable);
+em_status_t em_kernel_timing_read(em_handle_t handle, double *total_ms, int64_t *launches);
+
 /* Wait for the stream and report any asynchronous HIP error as EM_ERR_HIP. */
 em_status_t em_sync(em_handle_t handle, void *stream);
 

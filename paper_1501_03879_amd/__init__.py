@@ -100,6 +100,10 @@ def load_library():
         lib.nlem_autotune.restype = C.c_int
         lib.nlem_plan.argtypes = [vp, i32, i32, i32, C.POINTER(i32)]
         lib.nlem_plan.restype = C.c_int
+        lib.em_kernel_timing.argtypes = [vp, i32]
+        lib.em_kernel_timing.restype = C.c_int
+        lib.em_kernel_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+        lib.em_kernel_timing_read.restype = C.c_int
         lib.em_sync.argtypes = [vp, vp]
         lib.em_sync.restype = C.c_int
         lib.em_status_string.argtypes = [C.c_int]
@@ -270,6 +274,18 @@ class Handle:
         st = self.lib.nlm_denoise(self.h, _stream(stream), _ptr(img), is16, H, W, int(patch_radius),
                                   int(window_radius), float(h), _ptr(out))
         self._check(st, "nlm_denoise")
+
+    def kernel_timing(self, enable=True):
+        """Bracket every NLEM solve launch with HIP events (em_kernel_timing)."""
+        self._check(self.lib.em_kernel_timing(self.h, 1 if enable else 0), "em_kernel_timing")
+
+    def kernel_timing_read(self):
+        """(summed milliseconds, launches) of the timed NLEM solve launches since
+        the last read; waits for them."""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._check(self.lib.em_kernel_timing_read(self.h, C.byref(ms), C.byref(n)), "em_kernel_timing_read")
+        return ms.value, n.value
 
     def sync(self, stream=None):
         self._check(self.lib.em_sync(self.h, _stream(stream)), "em_sync")

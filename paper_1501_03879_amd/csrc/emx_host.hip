@@ -9,6 +9,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "emx_internal.hpp"
@@ -63,6 +64,10 @@ struct em_context {
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSideStreams] = {};
+    // em_kernel_timing: event pairs around the NLEM solve launches
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+    size_t tev_used = 0;
 };
 
 static em_status_t fail(em_context *ctx, em_status_t st, const std::string &msg) {
@@ -256,6 +261,10 @@ extern "C" em_status_t em_destroy(em_handle_t h) {
         if (h->join[i]) (void)hipEventDestroy(h->join[i]);
     }
     if (h->fork) (void)hipEventDestroy(h->fork);
+    for (auto &p : h->tev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
     delete h;
     return EM_OK;
 }
@@ -480,6 +489,35 @@ static em_status_t queue_order(em_context *h, hipStream_t s, const NlemOrderArgs
 // Queue one persistent launch per (patch radius, points per lane) group of
 // the images, each after a reset of its work-queue head (and the kernels
 // that put its pixels in longest-first order).
+// Event pairs kept for em_kernel_timing before they must be read.
+static constexpr size_t kMaxTimedLaunches = 4096;
+
+// The event pair for the next timed launch on stream s, or none: timing is
+// off, or s is being captured into a graph (events there would become graph
+// nodes).
+static em_status_t timing_pair(em_context *h, hipStream_t s, std::pair<hipEvent_t, hipEvent_t> **out) {
+    *out = nullptr;
+    if (!h->timing) return EM_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    EMX_HIP(h, hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return EM_OK;
+    if (h->tev_used == h->tev.size()) {
+        if (h->tev.size() >= kMaxTimedLaunches)
+            return fail(h, EM_ERR_UNSUPPORTED, "em_kernel_timing: read the timings (em_kernel_timing_read) "
+                                               "at least every 4096 launches");
+        std::pair<hipEvent_t, hipEvent_t> p{nullptr, nullptr};
+        EMX_HIP(h, hipEventCreate(&p.first));
+        const hipError_t e = hipEventCreate(&p.second);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(p.first);
+            return hip_fail(h, e, "hipEventCreate");
+        }
+        h->tev.push_back(p);
+    }
+    *out = &h->tev[h->tev_used];
+    return EM_OK;
+}
+
 static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const nlem_image_t *images,
                             const nlem_options_t &o) {
     auto groups = group_images(count, images);
@@ -511,8 +549,40 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
         if (ord) ws += nlem_order_bytes(total);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
         void *args[] = {&L};
+        std::pair<hipEvent_t, hipEvent_t> *tp = nullptr;
+        st = timing_pair(h, s, &tp);
+        if (st != EM_OK) return st;
+        if (tp) EMX_HIP(h, hipEventRecord(tp->first, s));
         EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
+        if (tp) {
+            EMX_HIP(h, hipEventRecord(tp->second, s));
+            ++h->tev_used;
+        }
     }
+    return EM_OK;
+}
+
+extern "C" em_status_t em_kernel_timing(em_handle_t h, int32_t enable) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    h->timing = enable != 0;
+    h->tev_used = 0;
+    return EM_OK;
+}
+
+extern "C" em_status_t em_kernel_timing_read(em_handle_t h, double *total_ms, int64_t *launches) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (!total_ms || !launches) return fail(h, EM_ERR_INVALID_ARG, "total_ms and launches must be non-NULL");
+    EMX_HIP(h, hipSetDevice(h->device));
+    double sum = 0.0;
+    for (size_t i = 0; i < h->tev_used; ++i) {
+        EMX_HIP(h, hipEventSynchronize(h->tev[i].second));
+        float ms = 0.0f;
+        EMX_HIP(h, hipEventElapsedTime(&ms, h->tev[i].first, h->tev[i].second));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)h->tev_used;
+    h->tev_used = 0;
     return EM_OK;
 }
 

@@ -32,7 +32,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("em_create", "em_destroy", "em_solve_batch", "em_solve_plain", "nlem_denoise",
                  "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_solve_batch_ex", "em_solve_plain_ex",
-                 "em_sync", "nlem_autotune", "nlem_plan",
+                 "em_sync", "nlem_autotune", "nlem_plan", "em_kernel_timing", "em_kernel_timing_read",
                  "em_status_string", "em_last_error"):
         assert must in names
 
@@ -76,6 +76,10 @@ def test_null_handle_is_rejected_without_device_work():
     assert lib.nlem_autotune(None, None, None, None, 1, None) == -1
     lib.nlem_plan.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
     assert lib.nlem_plan(None, 3, 10, 0, None) == -1
+    lib.em_kernel_timing.argtypes = [vp, C.c_int32]
+    assert lib.em_kernel_timing(None, 1) == -1
+    lib.em_kernel_timing_read.argtypes = [vp, vp, vp]
+    assert lib.em_kernel_timing_read(None, None, None) == -1
     assert lib.em_sync(None, None) == -1
     assert lib.em_destroy(None) == 0
     lib.em_create.argtypes = [C.POINTER(vp), C.c_int]
