@@ -8,10 +8,12 @@ the library's kernels.  Every pixel is one EM solve.
 
 Reported: EM solves/s (= pixels/s) of the batched persistent kernel, the
 roofline of that kernel on the FP32 FLOP model (6 flop per point-coordinate
-per iteration plus 3 per point-coordinate for the weights), and the FP64
-oracle timed on this host's cores on a bounded pixel sample.
+per iteration plus 3 per point-coordinate for the weights), em_solve_batch
+over the interior pixels' materialised windows (n = 441, d = 49 exactly),
+the plain one-launch-per-instance path on 64 of them (batched vs plain),
+and the FP64 oracle timed on this host's cores on a bounded pixel sample.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--plain N (default 64)]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--plain N (default 64)]
 """
 
 from __future__ import annotations
@@ -37,6 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip em_solve_batch over the interior pixels' materialised windows")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
     ap.add_argument("--plain", type=int, default=64,
                     help="also time the plain one-instance-per-launch path on N pixels "
@@ -356,9 +360,14 @@ def main():
                                "kernels and one NLEM kernel launch)"},
     }
 
+    if not args.no_batch:
+        res["batch_interior"] = batch_interior_rate(im, wl, dev, hd, out)
     if args.plain > 0:
         res["plain"] = plain_rate(args.plain, im, wl, dev, hd)
         res["speedup_vs_plain"] = solves_per_s / res["plain"]["solves_per_s"]
+        if "batch_interior" in res:
+            bi = res["batch_interior"]
+            bi["speedup_vs_plain"] = bi["solves_per_s"] / res["plain"]["solves_per_s"]
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(im, wl, args.cpu_seconds)
@@ -407,6 +416,65 @@ def plain_rate(npix, im, wl, dev, hd):
     dtb = time.perf_counter() - t0
     return {"solves_per_s": b.B / dt, "instances": b.B, "batched_same_instances_solves_per_s": b.B / dtb,
             "note": "n=441 d=49 interior pixels, materialised patches, init = largest weight (the centre)"}
+
+
+def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=3):
+    """em_solve_batch on every interior pixel of the image (full 21 x 21
+    windows: n = 441, d = 49) as materialised instances, the EM-solves half of
+    the metric.  Input preparation (untimed): patches gathered on the device,
+    NLM weights exp(-||P_i - P_j||^2 / h^2) in FP64 there, both stored as
+    FP32; start = the largest weight (the centre patch)."""
+    import numpy as np
+    import torch
+
+    import paper_1501_03879_amd as emx
+    from synth.pointsets import INSTANCE_DTYPE
+    H, W = im.noisy.shape
+    r, R = im.patch_radius, im.window_radius
+    k, nwin = 2 * r + 1, (2 * R + 1) ** 2
+    d = k * k
+    P = torch.from_numpy(np.pad(im.noisy.astype(np.float64), r, mode="symmetric")).to(dev)
+    patches = P.unfold(0, k, 1).unfold(1, k, 1).reshape(H * W, d)      # row-major patches
+    ys, xs = torch.meshgrid(torch.arange(R, H - R, device=dev), torch.arange(R, W - R, device=dev),
+                            indexing="ij")
+    centres = (ys * W + xs).reshape(-1)
+    dy, dx = torch.meshgrid(torch.arange(-R, R + 1, device=dev), torch.arange(-R, R + 1, device=dev),
+                            indexing="ij")
+    idx = centres[:, None] + (dy * W + dx).reshape(-1)[None, :]       # B x n, row-major window
+    B = int(idx.shape[0])
+    a64 = patches[idx]                                                # B x n x d
+    w = torch.exp(-((a64 - patches[centres][:, None, :]) ** 2).sum(-1) / (im.h * im.h)).float()
+    a = a64.float().reshape(-1)
+    del a64, patches, P
+    w = w.reshape(-1).contiguous()
+    inst = np.zeros(B, dtype=INSTANCE_DTYPE)
+    bi = np.arange(B, dtype=np.int64)
+    inst["a_off"], inst["w_off"], inst["z_off"] = bi * nwin * d, bi * nwin, bi * d
+    inst["n"], inst["d"] = nwin, d
+    it = emx.instances_tensor(inst, dev)
+    z = torch.zeros(B * d, dtype=torch.float32, device=dev)
+    st = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+    kw = dict(lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
+    hd.em_solve_batch(a, w, it, z, st, **kw)   # warm-up (workspace, code objects)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hd.em_solve_batch(a, w, it, z, st, **kw)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    iters, flags = emx.stats_view(st)[0].cpu().numpy(), emx.stats_view(st)[1].cpu().numpy()
+    centre = z.reshape(B, d)[:, (d - 1) // 2]
+    diff = float((centre - out_nlem.reshape(-1)[centres]).abs().max()) / (wl.hi - wl.lo)
+    res = {"instances": B, "n": nwin, "d": d, "ms": ms, "solves_per_s": B / (ms * 1e-3),
+           "mean_iters": float(iters.mean()), "converged_fraction": float(np.mean(flags == 1)),
+           "max_abs_diff_vs_nlem_over_range": diff,
+           "note": "em_solve_batch over the interior pixels' materialised windows (inputs in HBM); "
+                   "the NLEM kernel solves the same instances from the image tile"}
+    del a, w, z, st, it
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(im, wl, target_s):
