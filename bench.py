@@ -50,6 +50,9 @@ def parse():
                          "the PSNR table (NLM / NLEM-IRLS / NLEM-ADMM, 4 iterations), PSNR per "
                          "iteration, or the objective per iteration at sampled pixels")
     ap.add_argument("--realizations", type=int, default=10, help="noise realizations per study cell")
+    ap.add_argument("--pointsets", action="store_true",
+                    help="instead of the NLEM line, time em_solve_batch on the 1,048,576-instance "
+                         "point-set workload (n ~ U{8..512}, d in {2,3,16,49,64}) and print its own line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy (3 times): the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -255,6 +258,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.pointsets:
+        pointsets(args)
+        return
     if args.study:
         if args.gpus != 1:
             print("studies run on one GPU (--gpus 1)", file=sys.stderr)
@@ -416,6 +422,59 @@ def plain_rate(npix, im, wl, dev, hd):
     dtb = time.perf_counter() - t0
     return {"solves_per_s": b.B / dt, "instances": b.B, "batched_same_instances_solves_per_s": b.B / dtb,
             "note": "n=441 d=49 interior pixels, materialised patches, init = largest weight (the centre)"}
+
+
+def pointsets(args):
+    """em_solve_batch on the point-set workload: 1,048,576 instances, n ~
+    U{8..512}, d uniform over {2, 3, 16, 49, 64}, 20% Student-t outliers
+    scaled by 50, weights Exp(1), box [-3, 3]^d, max-weight start, mu 0.5,
+    tol 1e-4, at most 1000 iterations; inputs drawn on the device, resident
+    in HBM before the timed region.  One JSON line with the rate, the FP32
+    model throughput (6 flop per point coordinate per iteration) and the
+    per-d iteration counts."""
+    import numpy as np
+    import torch
+
+    import paper_1501_03879_amd as emx
+    import synth
+    if args.gpus != 1:
+        print("the point-set line measures one GPU (--gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    B = 1 << 20
+    a, w, inst, zs = synth.pointsets.make_pointset_batch_device(505, B, dev)
+    it = emx.instances_tensor(inst, dev)
+    z = torch.zeros(zs, dtype=torch.float32, device=dev)
+    st = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+    hd = emx.handle(0)
+    kw = dict(lo=-3.0, hi=3.0, rho=synth.configs.POINTSET_MU, max_iter=synth.configs.POINTSET_MAX_ITER,
+              tol=synth.configs.POINTSET_TOL, init=emx.INIT_MAXW)
+    for _ in range(max(1, args.warmup // 5)):
+        z.zero_()
+        hd.em_solve_batch(a, w, it, z, st, **kw)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 5))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hd.em_solve_batch(a, w, it, z, st, **kw)   # z is the max-weight start each time (init MAXW)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    iters = emx.stats_view(st)[0].cpu().numpy().astype(np.float64)
+    flags = emx.stats_view(st)[1].cpu().numpy()
+    nd = inst["n"].astype(np.float64) * inst["d"].astype(np.float64)
+    flops = float(np.sum(nd * 6.0 * iters))
+    per_d = {int(dv): {"instances": int(np.sum(inst["d"] == dv)),
+                       "mean_iters": float(iters[inst["d"] == dv].mean()),
+                       "elem_iter_share": float(np.sum((nd * iters)[inst["d"] == dv]) / np.sum(nd * iters))}
+             for dv in (2, 3, 16, 49, 64)}
+    print(json.dumps({"workload": "em_solve_batch, 1,048,576 point sets", "instances": B, "ms": ms,
+                      "solves_per_s": B / (ms * 1e-3), "mean_iters": float(iters.mean()),
+                      "converged_fraction": float(np.mean(flags == 1)),
+                      "model_tflops": flops / (ms * 1e-3) / 1e12,
+                      "frac_of_157.3": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                      "reps": reps, "per_d": per_d}), flush=True)
 
 
 def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=3):
