@@ -477,7 +477,7 @@ static int64_t group_pixels(const NlemGroup &g, const nlem_image_t *images) {
 
 // Queue the order kernels of one launch (its pixel order lands in A.order).
 static em_status_t queue_order(em_context *h, hipStream_t s, const NlemOrderArgs &A) {
-    OrderKernel k[4];
+    OrderKernel k[kOrderKernels];
     nlem_order_kernels(A, h->num_cus, k);
     for (const OrderKernel &x : k) {
         void *args[] = {const_cast<NlemOrderArgs *>(&A)};
@@ -486,9 +486,6 @@ static em_status_t queue_order(em_context *h, hipStream_t s, const NlemOrderArgs
     return EM_OK;
 }
 
-// Queue one persistent launch per (patch radius, points per lane) group of
-// the images, each after a reset of its work-queue head (and the kernels
-// that put its pixels in longest-first order).
 // Event pairs kept for em_kernel_timing before they must be read.
 static constexpr size_t kMaxTimedLaunches = 4096;
 
@@ -518,6 +515,9 @@ static em_status_t timing_pair(em_context *h, hipStream_t s, std::pair<hipEvent_
     return EM_OK;
 }
 
+// Queue one persistent launch per (patch radius, points per lane) group of
+// the images, each after a reset of its work-queue head (and the kernels
+// that put its pixels in longest-first order).
 static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const nlem_image_t *images,
                             const nlem_options_t &o) {
     auto groups = group_images(count, images);
@@ -778,7 +778,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             L.chunk = queue_chunk(g, total, cap);
             if (ord && total >= kOrderMinRounds * cap) {
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
-                OrderKernel ok[4];
+                OrderKernel ok[kOrderKernels];
                 nlem_order_kernels(A, h->num_cus, ok);
                 for (const OrderKernel &x : ok) {
                     void *oargs[] = {const_cast<NlemOrderArgs *>(&A)};

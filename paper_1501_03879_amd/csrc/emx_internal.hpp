@@ -60,7 +60,8 @@ struct OrderKernel {
 size_t nlem_order_bytes(int64_t total);
 // Arguments with the scratch laid out in `ws` (nlem_order_bytes(total) bytes).
 NlemOrderArgs nlem_order_args(const NlemLaunch &L, int pr, float lo, float hi, void *ws);
-// The four kernels to run in order on one stream: clear, count, scan, scatter.
-void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[4]);
+// The kernels to run in order on one stream: clear, count, scatter.
+constexpr int kOrderKernels = 3;
+void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[kOrderKernels]);
 
 }  // namespace emx

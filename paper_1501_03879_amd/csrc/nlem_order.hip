@@ -19,8 +19,10 @@
 
 namespace emx {
 
-// counts [0, K), offsets [K, 2K + 1), fill [2K + 1, 3K + 1)
+// counts [0, K), (unused) [K, 2K + 1), fill [2K + 1, 3K + 1)
 static constexpr int kCnt = 3 * kOrderBuckets + 1;
+// largest patch radius (the host rejects larger ones before any launch)
+static constexpr int kOrderMaxPr = EM_MAX_PATCH_RADIUS;
 
 __global__ void nlem_order_clear(NlemOrderArgs A) {
     for (int i = threadIdx.x; i < kCnt; i += blockDim.x) A.cnt[i] = 0u;
@@ -44,21 +46,26 @@ __global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
         const int iy = pix / I.W, ix = pix - (pix / I.W) * I.W;
         const float *f32 = static_cast<const float *>(I.img);
         const __half *f16 = static_cast<const __half *>(I.img);
-        auto val = [&](int dy, int dx) -> float {
-            const int64_t o = (int64_t)reflect_idx(iy + dy, I.H) * I.W + reflect_idx(ix + dx, I.W);
-            return I.is_f16 ? __half2float(f16[o]) : f32[o];
-        };
-        float m = 0.0f;
-        for (int dy = -A.pr; dy <= A.pr; ++dy)
-            for (int dx = -A.pr; dx <= A.pr; ++dx) m += val(dy, dx);
-        m *= inv_d;
-        float v = 0.0f;
-        for (int dy = -A.pr; dy <= A.pr; ++dy)
-            for (int dx = -A.pr; dx <= A.pr; ++dx) {
-                const float e = val(dy, dx) - m;
-                v = fmaf(e, e, v);
+        // reflected rows and columns of the patch, once per pixel
+        int64_t ro[2 * kOrderMaxPr + 1];
+        int co[2 * kOrderMaxPr + 1];
+        for (int k = 0; k < P; ++k) {
+            ro[k] = (int64_t)reflect_idx(iy - A.pr + k, I.H) * I.W;
+            co[k] = reflect_idx(ix - A.pr + k, I.W);
+        }
+        // one pass: the key only orders the queue, so the rounding of
+        // E[v^2] - E[v]^2 in FP32 does not matter
+        float s1 = 0.0f, s2 = 0.0f;
+        for (int ky = 0; ky < P; ++ky)
+            for (int kx = 0; kx < P; ++kx) {
+                const int64_t o = ro[ky] + co[kx];
+                const float v = I.is_f16 ? __half2float(f16[o]) : f32[o];
+                s1 += v;
+                s2 = fmaf(v, v, s2);
             }
-        const float key = sqrtf(v * inv_d) * A.scale;   // std / (hi - lo) * 2K, in [0, K]
+        const float m = s1 * inv_d;
+        const float var = fmaxf(fmaf(-m, m, s2 * inv_d), 0.0f);
+        const float key = sqrtf(var) * A.scale;   // std / (hi - lo) * 2K, in [0, K]
         const int bk = (key >= 0.0f) ? min((int)key, kOrderBuckets - 1) : kOrderBuckets - 1;  // NaN: first
         A.bucket[q] = (uint8_t)bk;
         atomicAdd(&hist[bk], 1u);
@@ -68,25 +75,34 @@ __global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
         if (hist[i]) atomicAdd(&A.cnt[i], hist[i]);
 }
 
-// Offsets with the largest bucket first.
-__global__ void nlem_order_scan(NlemOrderArgs A) {
-    if (threadIdx.x != 0) return;
-    unsigned int s = 0;
-    for (int k = kOrderBuckets - 1; k >= 0; --k) {
-        A.cnt[kOrderBuckets + k] = s;
-        s += A.cnt[k];
-    }
-    A.cnt[2 * kOrderBuckets] = s;
-}
-
-// Each block takes 256 pixels at a time: ranks within the block come from LDS
-// atomics, then one global atomic per (block, bucket) reserves the range.
-__global__ __launch_bounds__(256) void nlem_order_scatter(NlemOrderArgs A) {
+// Every block first turns the bucket counts into offsets with the largest
+// bucket first (an exclusive scan over the buckets in decreasing order, one
+// bucket per thread, repeated by each block: cheaper than a launch of its
+// own).  Then it takes 256 pixels at a time: ranks within the block come from
+// LDS atomics, and one global atomic per (block, bucket) reserves the range.
+__global__ __launch_bounds__(kOrderBuckets) void nlem_order_scatter(NlemOrderArgs A) {
+    static_assert(kOrderBuckets == 256, "one bucket per thread of a 256-thread block");
     __shared__ unsigned int lcnt[kOrderBuckets];
     __shared__ unsigned int lbase[kOrderBuckets];
+    __shared__ unsigned int offs[kOrderBuckets];
     const NlemLaunch &L = A.L;
     const int64_t total = L.prefix[L.count];
     unsigned int *fill = A.cnt + 2 * kOrderBuckets + 1;
+    {
+        const int i = threadIdx.x;             // position in decreasing bucket order
+        const int k = kOrderBuckets - 1 - i;   // its bucket
+        const unsigned int c = A.cnt[k];
+        lcnt[i] = c;
+        __syncthreads();
+        for (int off = 1; off < kOrderBuckets; off <<= 1) {   // inclusive Hillis-Steele scan
+            const unsigned int add = (i >= off) ? lcnt[i - off] : 0u;
+            __syncthreads();
+            lcnt[i] += add;
+            __syncthreads();
+        }
+        offs[k] = lcnt[i] - c;
+        __syncthreads();
+    }
     for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x; q0 < total; q0 += (int64_t)gridDim.x * blockDim.x) {
         for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) lcnt[i] = 0u;
         __syncthreads();
@@ -98,7 +114,7 @@ __global__ __launch_bounds__(256) void nlem_order_scatter(NlemOrderArgs A) {
         for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
             lbase[i] = lcnt[i] ? atomicAdd(&fill[i], lcnt[i]) : 0u;
         __syncthreads();
-        if (valid) A.order[A.cnt[kOrderBuckets + bk] + lbase[bk] + rank] = (int32_t)q;
+        if (valid) A.order[offs[bk] + lbase[bk] + rank] = (int32_t)q;
         __syncthreads();   // lcnt and lbase are reused by the next chunk
     }
 }
@@ -125,13 +141,12 @@ NlemOrderArgs nlem_order_args(const NlemLaunch &L, int pr, float lo, float hi, v
     return A;
 }
 
-void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[4]) {
+void nlem_order_kernels(const NlemOrderArgs &A, int num_cus, OrderKernel (&k)[kOrderKernels]) {
     const int64_t total = A.L.prefix[A.L.count];
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4LL * num_cus));
     k[0] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_clear), 1, 256};
     k[1] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_count), grid, 256};
-    k[2] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_scan), 1, 64};
-    k[3] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_scatter), grid, 256};
+    k[2] = OrderKernel{reinterpret_cast<const void *>(&nlem_order_scatter), grid, kOrderBuckets};
 }
 
 }  // namespace emx
