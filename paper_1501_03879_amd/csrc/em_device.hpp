@@ -103,7 +103,8 @@ __device__ __forceinline__ void reduce_scatter(const float (&x)[V], float (&out)
 // K_{s+1} = ceil(K_s / 2) values per lane: lanes whose stage bit is clear keep
 // indices [0, K_{s+1}), the others [K_{s+1}, 2 K_{s+1}).  Afterwards every lane
 // holds one wave-wide total, for coordinate RSF<V>::coord(lane) when
-// RSF<V>::valid(lane); each valid coordinate is held by exactly one lane.
+// RSF<V>::valid(lane); each valid coordinate is held by exactly one lane and
+// the other lanes return 0.
 template <int V>
 struct RSF {
     static_assert(V >= 1 && V <= 64, "RSF: 1..64 values");
@@ -150,8 +151,19 @@ __device__ __forceinline__ float rs_dpp_stage(float lo, float hi, bool upper) {
     return keep + dpp<CTRL>(send);
 }
 
+// One DPP stage of reduce_scatter_full for slot i: with an upper half
+// (i + K < Kprev) the lanes exchange halves; without one the stage is a plain
+// butterfly, which gives a valid lane the same sum (lo + partner's lo) and
+// the lanes above it, which hold no coordinate, the same value instead of 0.
+template <int CTRL, bool HALVES>
+__device__ __forceinline__ float rs_dpp_slot(float lo, float hi, bool upper) {
+    if constexpr (HALVES) return rs_dpp_stage<CTRL>(lo, hi, upper);
+    else return lo + dpp<CTRL>(lo);
+}
+
+// `own` = RSF<V>::valid(lane): lanes that hold no coordinate return 0.
 template <int V>
-__device__ __forceinline__ float reduce_scatter_full(const float (&x)[V], int lane) {
+__device__ __forceinline__ float reduce_scatter_full(const float (&x)[V], int lane, bool own) {
     using R = RSF<V>;
     constexpr int K1 = R::K(1), K2 = R::K(2), K3 = R::K(3), K4 = R::K(4), K5 = R::K(5);
     float a[K1];
@@ -163,14 +175,22 @@ __device__ __forceinline__ float reduce_scatter_full(const float (&x)[V], int la
     const bool u8 = lane & 8, u4 = lane & 4, u2 = lane & 2, u1 = lane & 1;
     float c[K3];
 #pragma unroll
-    for (int i = 0; i < K3; ++i) c[i] = rs_dpp_stage<0x128>(b[i], (i + K3 < K2) ? b[i + K3] : 0.0f, u8);  // row_ror:8
+    for (int i = 0; i < K3; ++i)   // row_ror:8
+        c[i] = (i + K3 < K2) ? rs_dpp_slot<0x128, true>(b[i], b[(i + K3) % K2], u8)
+                             : rs_dpp_slot<0x128, false>(b[i], 0.0f, u8);
     float d[K4];
 #pragma unroll
-    for (int i = 0; i < K4; ++i) d[i] = rs_dpp_stage<0x141>(c[i], (i + K4 < K3) ? c[i + K4] : 0.0f, u4);  // row_half_mirror
+    for (int i = 0; i < K4; ++i)   // row_half_mirror
+        d[i] = (i + K4 < K3) ? rs_dpp_slot<0x141, true>(c[i], c[(i + K4) % K3], u4)
+                             : rs_dpp_slot<0x141, false>(c[i], 0.0f, u4);
     float e[K5];
 #pragma unroll
-    for (int i = 0; i < K5; ++i) e[i] = rs_dpp_stage<0x4E>(d[i], (i + K5 < K4) ? d[i + K5] : 0.0f, u2);   // lane ^ 2
-    return rs_dpp_stage<0xB1>(e[0], (1 < K5) ? e[1] : 0.0f, u1);                                          // lane ^ 1
+    for (int i = 0; i < K5; ++i)   // lane ^ 2
+        e[i] = (i + K5 < K4) ? rs_dpp_slot<0x4E, true>(d[i], d[(i + K5) % K4], u2)
+                             : rs_dpp_slot<0x4E, false>(d[i], 0.0f, u2);
+    const float r = (1 < K5) ? rs_dpp_slot<0xB1, true>(e[0], e[1 % K5], u1)   // lane ^ 1
+                             : rs_dpp_slot<0xB1, false>(e[0], 0.0f, u1);
+    return own ? r : 0.0f;
 }
 
 // Reads a wave-uniform float held by lane `lane` of a VGPR into an SGPR.

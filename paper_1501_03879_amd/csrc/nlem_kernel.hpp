@@ -329,7 +329,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int q = 0; q < M; ++q) wl += wt[q];
                 const float inv_ws = 1.0f / readfirstlane(wave_sum(wl));
-                const float Ev = reduce_scatter_full<NJ>(acc, lane);   // -sum_j w_j P_j
+                const float Ev = reduce_scatter_full<NJ>(acc, lane, myv);   // -sum_j w_j P_j
                 if (myv) zr = -Ev * inv_ws;   // ADMM: the NLM patch; IRLS: it minus P_i
                 zp = zr;
                 cv[cidx] = zr;
@@ -405,7 +405,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     for (int q = 0; q < M; ++q) ac = fmaf(om[q], g[q][jj], ac);
                     acc[jj] = ac;
                 }
-                const float Ev = reduce_scatter_full<NJ>(acc, lane);   // -sum_j omega_j P_j
+                const float Ev = reduce_scatter_full<NJ>(acc, lane, myv);   // -sum_j omega_j P_j
                 const float inv_os = 1.0f / readfirstlane(wave_sum(ol));
                 // z' - P_i = P_C(P_i + raw) - P_i, exact when the box is inactive
                 const float raw = -Ev * inv_os;
@@ -572,7 +572,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int jj = 0; jj < NJ; ++jj) asm volatile("" : "+v"(g[q][jj]));
             // ---- a5: reduce over the wave; a6: z-update; a7 implicit in g and c
-            const float Ev = reduce_scatter_full<NJ>(acc, lane);
+            const float Ev = reduce_scatter_full<NJ>(acc, lane, myv);
             const float zn = clampf(fmaf(-Ev, inv_n, zr), L.lo, L.hi);
             const float dz = zn - zr;
             cv[cidx] = zn + dz;
