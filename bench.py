@@ -559,9 +559,16 @@ def cpu_baseline(im, wl, target_s):
             break
         rate = done / total_t
         npix = int(min(H * W - done, max(512, rate * (target_s - total_t))))
+    # one thread on a fixed 256-pixel sample, for the per-core rate
+    one = order[:256]
+    t0 = time.perf_counter()
+    oracle.nlem(im.noisy, im.patch_radius, im.window_radius, im.h, wl.lo, wl.hi, wl.mu,
+                wl.max_iter, wl.tol, pix=one, nthreads=1)
+    t1 = time.perf_counter() - t0
     return {"value": done / total_t, "unit": "EM solves/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} random pixels of the 256x256 image ({done / (H * W):.1%}), "
-                      f"FP64, {total_t:.1f} s"}
+                      f"FP64, {total_t:.1f} s",
+            "value_1_thread": len(one) / t1, "sample_1_thread": f"{len(one)} of the same pixels, {t1:.2f} s"}
 
 
 if __name__ == "__main__":
