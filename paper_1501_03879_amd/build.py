@@ -64,7 +64,27 @@ def build(force: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    build_client()
     return LIB
+
+
+CLIENT_SRC = os.path.join(HERE, "examples", "nlem_client.c")
+CLIENT = os.path.join(HERE, "examples", "nlem_client")
+
+
+def build_client() -> str:
+    """The C example client (examples/nlem_client.c): plain C against
+    include/emx.h and the HIP runtime, linked to libemx.so in this directory."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(rocm, "include"), "-I", os.path.join(HERE, "..", "include"),
+           CLIENT_SRC, "-o", CLIENT, "-L", os.path.dirname(LIB), "-l:" + os.path.basename(LIB),
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed for the C client:\n" + r.stdout + r.stderr)
+    return CLIENT
 
 
 if __name__ == "__main__":

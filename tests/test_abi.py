@@ -113,3 +113,18 @@ def test_instances_tensor_bytes_roundtrip():
     assert t.dtype == torch.int64 and t.shape == (17, 4)
     back = t.numpy().view(synth.pointsets.INSTANCE_DTYPE).reshape(-1)
     np.testing.assert_array_equal(back, b.inst)
+
+
+def test_c_client_links_against_the_library():
+    """The C example client is plain C on include/emx.h, linked to libemx.so
+    in the package directory; without arguments it prints its usage and
+    exits 1 before any HIP call (runs without a GPU)."""
+    import subprocess
+    from paper_1501_03879_amd import build
+    _ensure_built()
+    if not os.path.exists(build.CLIENT):
+        build.build_client()
+    r = subprocess.run([build.CLIENT], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage:" in r.stderr
+    ldd = subprocess.run(["ldd", build.CLIENT], capture_output=True, text=True, timeout=60).stdout
+    assert os.path.realpath(LIB) in {os.path.realpath(tok) for tok in ldd.split() if tok.endswith("libemx.so")}
