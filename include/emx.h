@@ -290,9 +290,11 @@ em_status_t em_solve_plain(em_handle_t handle, void *stream, int64_t B,
  * r = patch_radius in [0, EM_MAX_PATCH_RADIUS], R = window_radius in
  * [0, EM_MAX_WINDOW_RADIUS], both < min(H, W); h_param > 0.
  * stats: NULL or H*W records.  `out` must not alias `img`.
- * Scheduling: the pixels are solved in longest-first order (decreasing
- * standard deviation of the noisy patch, which tracks the iteration count);
- * the environment variable EMX_NLEM_ORDER=0 keeps raster order.  Each
+ * Scheduling: in tolerance mode (tol > 0) the pixels of a shape group at
+ * least four times as large as the resident grid are solved in longest-first
+ * order (decreasing standard deviation of the noisy patch, which tracks the
+ * iteration count); the environment variable EMX_NLEM_ORDER=0 keeps raster
+ * order.  Each
  * workgroup takes a few consecutive queue positions per atomic when pixels
  * are cheap (small windows and patches); EMX_NLEM_CHUNK=k (1..64) fixes
  * that count.  Results do not depend on either.

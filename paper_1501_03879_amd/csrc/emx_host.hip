@@ -458,13 +458,18 @@ static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
 }
 
 // Longest-first queue order (see nlem_order.hip), on unless EMX_NLEM_ORDER=0;
-// pointless without iterations (every pixel then costs the same), and for a
-// queue not much longer than the resident workgroups (nearly every pixel
-// starts at once): used from kOrderMinRounds rounds of the grid on.
-static constexpr int kOrderMinRounds = 8;
+// pointless at a fixed iteration count (tol = 0: every pixel then costs about
+// the same), and for a queue not much longer than the resident workgroups
+// (nearly every pixel starts at once, and the order kernels cost more than
+// the tail they shorten): used from kOrderMinRounds rounds of the grid on.
+// Measured on 64x64 to 320x240 images against a threshold of 8 rounds: 4
+// rounds shortened most tails (64x64 r3 R10 0.557 -> 0.372 ms, 160x120 r2 R7
+// 0.544 -> 0.375 ms) and lengthened two (128x96 r2 R7 0.236 -> 0.286 ms);
+// ordering every queue lost more often.
+static constexpr int kOrderMinRounds = 4;
 
 static bool order_enabled(const nlem_options_t &o) {
-    if (o.max_iter <= 0) return false;
+    if (o.max_iter <= 0 || !(o.tol > 0.0f)) return false;
     const char *e = getenv("EMX_NLEM_ORDER");
     return !(e && e[0] == '0' && e[1] == '\0');
 }

@@ -36,9 +36,9 @@ def _snapshot(items):
     return [(it["out"].clone(), it["stats"].clone()) for it in items]
 
 
-# the order is used for queues of at least 8 rounds of the resident grid
-# (768 workgroups for patch radius 3): the 128x131 and 96x200 images are
-# ordered, the small ones keep raster order
+# the order is used in tolerance mode for queues of at least 4 rounds of the
+# resident grid (768 workgroups for patch radius 3, window radius 10): the
+# 128x131 and 96x200 images are ordered, the small ones keep raster order
 SPECS = [(1, 128, 131, 3, 10), (2, 33, 41, 2, 7), (3, 96, 200, 3, 10), (4, 17, 90, 1, 5)]
 
 
