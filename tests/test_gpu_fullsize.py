@@ -171,3 +171,59 @@ def test_pointsets_full_batch_irls_and_weighted_sampled(solver):
     print(f"[parity] pointsets full batch {name}: mean iters {iters.mean():.1f}, converged "
           f"{np.mean(flags == 1):.4f}, max iters {iters.max()}", flush=True)
     assert e <= 1e-4
+
+
+def test_interior_pixels_as_batch_instances_sampled():
+    """em_solve_batch on every interior pixel of the 256x256 workload as a
+    materialised n = 441, d = 49 instance (bench.py's batch_interior leg, the
+    same launch): 256 sampled instances against the oracle rerun at the GPU's
+    per-instance iteration counts on the same input bits (1e-4 of 255).
+    Inputs: the window patches gathered on the device and their NLM weights
+    exp(-||P_i - P_j||^2 / h^2) computed there in FP64, both stored as FP32."""
+    import torch
+    import paper_1501_03879_amd as emx
+    dev = gpu()
+    wl = synth.nlem_256()
+    im = wl.images[0]
+    H, W = im.noisy.shape
+    r, R = im.patch_radius, im.window_radius
+    k, n = 2 * r + 1, (2 * R + 1) ** 2
+    d = k * k
+    P = torch.from_numpy(np.pad(im.noisy.astype(np.float64), r, mode="symmetric")).to(dev)
+    patches = P.unfold(0, k, 1).unfold(1, k, 1).reshape(H * W, d)
+    ys, xs = torch.meshgrid(torch.arange(R, H - R, device=dev), torch.arange(R, W - R, device=dev),
+                            indexing="ij")
+    centres = (ys * W + xs).reshape(-1)
+    dy, dx = torch.meshgrid(torch.arange(-R, R + 1, device=dev), torch.arange(-R, R + 1, device=dev),
+                            indexing="ij")
+    idx = centres[:, None] + (dy * W + dx).reshape(-1)[None, :]
+    B = int(idx.shape[0])
+    a64 = patches[idx]
+    w = torch.exp(-((a64 - patches[centres][:, None, :]) ** 2).sum(-1) / (im.h * im.h)).float().contiguous()
+    a = a64.float().contiguous()
+    del a64
+    inst = np.zeros(B, dtype=synth.pointsets.INSTANCE_DTYPE)
+    bi = np.arange(B, dtype=np.int64)
+    inst["a_off"], inst["w_off"], inst["z_off"] = bi * n * d, bi * n, bi * d
+    inst["n"], inst["d"] = n, d
+    it = emx.instances_tensor(inst, dev)
+    z = torch.zeros(B * d, dtype=torch.float32, device=dev)
+    st = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+    print(f"[parity] batch interior: {B} instances n={n} d={d}", flush=True)
+    hd = handle()
+    hd.em_solve_batch(a.reshape(-1), w.reshape(-1), it, z, st, lo=wl.lo, hi=wl.hi, rho=wl.mu,
+                      max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
+    hd.sync()
+    iters = emx.stats_view(st)[0].cpu().numpy()
+    flags = emx.stats_view(st)[1].cpu().numpy()
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(B, 256, replace=False))
+    sb = synth.pointsets.pack_instances([a[b].cpu().numpy() for b in sample],
+                                        [w[b].cpu().numpy() for b in sample], wl.lo, wl.hi)
+    ref = oracle.em_batch(sb, wl.mu, wl.max_iter, 0.0, init=oracle.INIT_MAXW, max_iter_each=iters[sample])
+    got = z.reshape(B, d)[torch.from_numpy(sample).to(dev)].cpu().numpy().reshape(-1).astype(np.float64)
+    e, rr = rel_errors(got, ref["z"], wl.hi - wl.lo)
+    report(f"batch interior {B} instances, 256 sampled (oracle at GPU iterations; mean iters "
+           f"{iters.mean():.2f}, converged {np.mean(flags == 1):.4f})", e, rr)
+    assert e <= 1e-4
+    assert np.mean(flags == 1) >= 0.999
