@@ -293,8 +293,9 @@ em_status_t em_solve_plain(em_handle_t handle, void *stream, int64_t B,
  * Scheduling: in tolerance mode (tol > 0) the pixels of a shape group at
  * least four times as large as the resident grid are solved in longest-first
  * order (decreasing standard deviation of the noisy patch, which tracks the
- * iteration count); the environment variable EMX_NLEM_ORDER=0 keeps raster
- * order.  Each
+ * iteration count for 7x7 patches; with smaller patches only groups below
+ * sixteen times the resident grid are ordered); the environment variable
+ * EMX_NLEM_ORDER=0 keeps raster order.  Each
  * workgroup takes a few consecutive queue positions per atomic when pixels
  * are cheap (small windows and patches); EMX_NLEM_CHUNK=k (1..64) fixes
  * that count.  Results do not depend on either.

@@ -467,6 +467,19 @@ static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
 // 0.544 -> 0.375 ms) and lengthened two (128x96 r2 R7 0.236 -> 0.286 ms);
 // ordering every queue lost more often.
 static constexpr int kOrderMinRounds = 4;
+// With patches of radius <= 2 (d <= 25) the standard deviation hardly
+// predicts the iteration count (correlation 0.12-0.25 on a 128x96 image,
+// against 0.84 at radius 3) and the counts have no long tail, so the order
+// only shuffles the queue: that broke up clusters of slow pixels in queues of
+// up to ~15 rounds (128x96 r2 R10 0.681 -> 0.448 ms) and cost time in longer
+// ones (320x240 r2 R7 1.078 -> 1.370 ms); such queues are ordered below
+// kOrderMaxRoundsSmallPatch rounds only.
+static constexpr int kOrderMaxRoundsSmallPatch = 16;
+
+static bool use_order(bool enabled, int pr, int64_t total, int64_t cap) {
+    if (!enabled || total < kOrderMinRounds * cap) return false;
+    return pr >= 3 || total < kOrderMaxRoundsSmallPatch * cap;
+}
 
 static bool order_enabled(const nlem_options_t &o) {
     if (o.max_iter <= 0 || !(o.tol > 0.0f)) return false;
@@ -545,7 +558,7 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
         const int64_t total = L.prefix[L.count];
         const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
         L.chunk = queue_chunk(g, total, cap);
-        if (ord && total >= kOrderMinRounds * cap) {
+        if (use_order(ord, g.pr, total, cap)) {
             const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
             st = queue_order(h, s, A);
             if (st != EM_OK) return st;
@@ -781,7 +794,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             const int64_t total = L.prefix[L.count];
             const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
             L.chunk = queue_chunk(g, total, cap);
-            if (ord && total >= kOrderMinRounds * cap) {
+            if (use_order(ord, g.pr, total, cap)) {
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
                 OrderKernel ok[kOrderKernels];
                 nlem_order_kernels(A, h->num_cus, ok);
