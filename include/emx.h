@@ -411,8 +411,8 @@ em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_r
 
 /*
  * em_kernel_timing - for measurement tools: while enabled (enable != 0),
- * every NLEM solve launch of nlem_denoise and nlem_denoise_ex is bracketed
- * by two HIP events on its stream, so the solve kernel's own duration can be
+ * every NLEM solve launch of nlem_denoise, nlem_denoise_ex and nlm_denoise
+ * (and of nlem_autotune's trials) is bracketed by two HIP events on its stream, so the solve kernel's own duration can be
  * read without the small kernels that precede it (queue reset and queue
  * order).  Not recorded: launches into a stream that is being captured, and
  * the multi-image graph.  Enabling or disabling discards unread timings.
