@@ -405,7 +405,9 @@ em_status_t nlem_autotune(em_handle_t handle, void *stream, const nlem_image_t *
                           const nlem_options_t *opt, int32_t repeats, int32_t *chosen);
 
 /* The coordinate-wave count the handle uses for a shape and solver (the
- * autotuned plan, else the built-in default).  Errors: INVALID_ARG. */
+ * autotuned plan, else the built-in default; without a plan, a shape group
+ * shorter than four rounds of the resident grid in tolerance mode runs with
+ * the most waves compiled for the shape instead).  Errors: INVALID_ARG. */
 em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
                       int32_t solver, int32_t *waves);
 

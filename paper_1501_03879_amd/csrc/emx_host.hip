@@ -309,9 +309,21 @@ static int points_per_lane(int R) {
     return kM[R];
 }
 
+// Queues shorter than this many rounds of the resident grid run, in
+// tolerance mode, with the most coordinate waves compiled for the shape: the
+// slowest pixels set the time of such a queue, and more waves per pixel
+// finish each of them sooner.  Measured on 64x64 to 160x120 images against
+// the default counts: 64x64 r2 R10 0.314 -> 0.165 ms, 64x64 r3 R7 0.491 ->
+// 0.290 ms, 128x96 r2 R5 0.228 -> 0.206 ms; at a fixed iteration count
+// (no tail) more waves were slower (64x64 r2 R5 T50 0.166 -> 0.175 ms).
+static constexpr int kFewRounds = 4;
+
 // Kernel for a shape: EMX_NLEM_WC when that variant is compiled (a manual
-// override), else the handle's autotuned plan, else the default table.
-static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solver) {
+// override), else the handle's autotuned plan, else the default table, or
+// for a short queue in tolerance mode (total pixels of the group >= 0 and
+// below kFewRounds rounds) the most coordinate waves compiled.
+static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solver, int64_t total = -1,
+                                         bool tolerance = false) {
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
         NlemKernelInfo k = nlem_kernel(pr, m, atoi(env), solver);
@@ -322,7 +334,18 @@ static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solve
         NlemKernelInfo k = nlem_kernel(pr, m, it->second, solver);
         if (k.fn) return k;
     }
-    return nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
+    NlemKernelInfo k = nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
+    if (k.fn && tolerance && total >= 0 &&
+        total < (int64_t)kFewRounds * h->num_cus * blocks_per_cu(h, k.fn, k.threads)) {
+        for (int wc = 4; wc > 0; --wc) {
+            const NlemKernelInfo x = nlem_kernel(pr, m, wc, solver);
+            if (x.fn) {
+                if (x.threads > k.threads) k = x;
+                break;
+            }
+        }
+    }
+    return k;
 }
 
 static em_status_t check_solver_params(em_context *ctx, float lo, float hi, float rho,
@@ -552,7 +575,8 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
     }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const NlemGroup &g = groups[gi];
-        NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver);
+        NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver, group_pixels(g, images),
+                                              o.max_iter > 0 && o.tol > 0.0f);
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
         const int64_t total = L.prefix[L.count];
@@ -782,7 +806,8 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         };
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const NlemGroup &g = groups[gi];
-            NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM);
+            NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM, group_pixels(g, images),
+                                                  o.max_iter > 0 && o.tol > 0.0f);
             unsigned int *counter = h->counters + gi;
             NlemLaunch L = make_launch(g, images, o, counter);
             hipGraphNode_t prev;
