@@ -465,7 +465,15 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, co
 
 // Queue positions per atomic: about 24,576 point coordinates of work per
 // pop (one pixel at d = 49, n = 441; up to 8 for small windows and patches),
-// fewer when the queue would not give every workgroup 16 chunks.
+// fewer when the queue would not give every resident workgroup enough
+// chunks.  For pixels of at least 1,024 point coordinates (every shape from
+// 3x3 patches with 11x11 windows up) at most 2 per pop and at least 5 chunks
+// per workgroup: one global counter serves about 75 M pops/s, which capped
+// medium images at one pixel per pop (400x300 r2 R5 1.76 ms, 0.99 ms with
+// 2), while larger chunks only unbalanced the end of the queue (measured
+// over 160x120 to 480x640 images with 3x3 to 7x7 patches and chunks of 1 to
+// 8: 27.6 -> 25.0 ms summed, the best choice per case summing to 24.7 ms).
+// Smaller pixels keep up to 8 per pop and 16 chunks per workgroup.
 // EMX_NLEM_CHUNK (1..64) overrides the rule.
 static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
     const char *env = getenv("EMX_NLEM_CHUNK");
@@ -476,7 +484,12 @@ static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
     const int64_t side = 2 * (int64_t)g.pr + 1;
     const int64_t elems = side * side * (int64_t)g.m * 64;   // d times the window slots
     int64_t k = std::max<int64_t>(1, std::min<int64_t>(8, 24576 / std::max<int64_t>(1, elems)));
-    while (k > 1 && total < 16 * k * cap) --k;
+    int64_t min_chunks = 16;
+    if (elems >= 1024) {
+        k = std::min<int64_t>(k, 2);
+        min_chunks = 5;
+    }
+    while (k > 1 && total < min_chunks * k * cap) --k;
     return (int)k;
 }
 
