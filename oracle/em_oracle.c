@@ -139,48 +139,152 @@ static int set_ok(int64_t d, const or_set_t *C)
 }
 
 /*
- * One instance of Algorithm 1 (EM-ADMM) in its printed form, with unscaled
- * multipliers y_k and penalty mu:
- *   loop:  r = 0
- *          for k: x_k = Psi_{w_k/mu}(z - y_k/mu, a_k);  r += x_k + y_k/mu
- *          z = P_C(r / N)                       (N = n, the points present)
- *          for k: y_k += mu (x_k - z)
- * C is the box prod_j [lo_j, hi_j] (Section 3 uses one interval for every
- * coordinate; per-coordinate bounds are the general box).
- * The loop stops after max_iter iterations, or earlier when tol > 0 and both
- *   r_pri  = sqrt(sum_k ||x_k - z||^2 / (n d))
- *   r_dual = sqrt(||z - z_prev||^2 / d)
- * are <= tol * D (the paper leaves the criterion open; this is the primal and
- * dual residual pair of the ADMM literature, checked every iteration).
+ * EM-ADMM (Section 2, Algorithm 1).
  *
- * Adaptive penalty (adapt_every > 0; the conclusion names it as future work,
- * the rule is residual balancing as in Boyd et al. 2011, Section 3.4.1):
- * after an iteration t that did not stop and with t % adapt_every == 0, with
- *   ||r|| = (sum_k ||x_k - z||^2)^(1/2),  ||s|| = mu (n ||z - z_prev||^2)^(1/2)
- * (the stacked primal and dual residuals of the consensus form):
- *   ||r|| > ratio ||s||  ->  mu = mu * factor,
- *   ||s|| > ratio ||r||  ->  mu = mu / factor,
- * keeping the unscaled y_k (so nothing else changes).  *mu_out receives the
- * final penalty (nullable).
+ * The splitting of equation (splitting) gives every term of (EM) its own copy
+ * x_k of the variable and ties the copies to one global z in C:
  *
- * a: n*d points (point-major), w: n weights, z: d values in/out (the initial
- * z is used unprojected), y: n*d multipliers in/out (NULL means start from
- * zero and discard), x_out: n*d last local variables (NULL to skip).
- * Returns the flag word; *iters, *r_pri, *r_dual receive the iteration count
- * and the residuals of the last iteration run (0 when none ran).
- * n = 0: z is left as given (EMPTY).  A negative or non-finite weight, a
- * non-finite point or initial z, or an invalid box: z is set to NaN
- * (BAD_INPUT).
+ *     minimise  sum_k w_k ||x_k - a_k||  +  i_C(z)     subject to  x_k = z  (all k),
+ *
+ * i_C the indicator of C.  With a multiplier y_k and a penalty rho_k for the
+ * constraint of point k, the augmented Lagrangian is
+ *
+ *     L = sum_k [ w_k ||x_k - a_k|| + y_k.(x_k - z) + (rho_k / 2) ||x_k - z||^2 ] + i_C(z).
+ *
+ * Algorithm 1 takes rho_k = mu for every k.  One ADMM sweep minimises L over
+ * the block of local copies (which separates into one small problem per
+ * point), then over z, and then moves every multiplier up the gradient of
+ * the dual function.  Each of these three steps, and the residuals measured
+ * after them, is a function of its own below; the solvers chain them.
+ *
+ * The multipliers are kept unscaled, as the paper writes them.  Points of a
+ * constraint with penalty zero (the weighted variant's points of weight zero)
+ * take no part: they have no term in the objective and no constraint.
  */
-static int em_solve_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
-                        const or_set_t *C, double *z, double *y, double *x_out, int64_t max_iter,
-                        double tol, int64_t adapt_every, double adapt_ratio, double adapt_factor,
-                        int64_t *iters, double *r_pri, double *r_dual, double *mu_out)
+typedef struct {
+    int64_t n, d;
+    const double *a;    /* n x d points, point-major */
+    const double *w;    /* n weights */
+    const double *pen;  /* per-constraint penalties rho_k (n), or NULL for rho_k = mu */
+    double mu;
+} admm_problem_t;
+
+static double admm_penalty(const admm_problem_t *P, int64_t k)
 {
-    *iters = 0;
-    *r_pri = 0.0;
-    *r_dual = 0.0;
-    if (mu_out) *mu_out = mu;
+    return P->pen ? P->pen[k] : P->mu;
+}
+
+static int admm_active(const admm_problem_t *P, int64_t k)
+{
+    return P->pen == NULL || P->pen[k] > 0.0;
+}
+
+/*
+ * Local block, equation (updatex).  For each point, L restricted to x_k is
+ *   w_k ||x_k - a_k|| + (rho_k / 2) ||x_k - (z - y_k / rho_k)||^2 + const,
+ * so x_k is the prox of (w_k / rho_k) ||. - a_k|| at v_k = z - y_k / rho_k:
+ * the block soft-threshold of equation (closed-form), oracle_prox above.
+ * z and y are read at their values from the previous sweep (Gauss-Seidel
+ * order: x first).
+ */
+static void admm_local_block(const admm_problem_t *P, const double *z, const double *y, double *x,
+                             double *v)
+{
+    const int64_t d = P->d;
+    for (int64_t k = 0; k < P->n; ++k) {
+        if (!admm_active(P, k)) continue;
+        const double rho = admm_penalty(P, k);
+        const double *yk = y + k * d;
+        for (int64_t j = 0; j < d; ++j) v[j] = z[j] - yk[j] / rho;
+        oracle_prox(d, v, P->a + k * d, P->w[k] / rho, x + k * d);
+    }
+}
+
+/*
+ * Global block, equation (updatez).  L restricted to z is, up to a constant,
+ *   sum_k (rho_k / 2) ||z - (x_k + y_k / rho_k)||^2 + i_C(z),
+ * an isotropic quadratic, so its minimiser over C is the projection of the
+ * rho-weighted mean of x_k + y_k / rho_k.  With rho_k = mu the weights cancel
+ * and the mean is over the N = n points present, unweighted.  When every
+ * penalty is zero there is nothing to average and z stays where it is (then
+ * projected).  `sum` is a d-vector of scratch; points are summed in order
+ * k = 1..n.
+ */
+static void admm_global_block(const admm_problem_t *P, const or_set_t *C, const double *x,
+                              const double *y, double *sum, double *z)
+{
+    const int64_t d = P->d;
+    for (int64_t j = 0; j < d; ++j) sum[j] = 0.0;
+    double total = 0.0;
+    for (int64_t k = 0; k < P->n; ++k) {
+        if (!admm_active(P, k)) continue;
+        const double rho = admm_penalty(P, k);
+        const double *xk = x + k * d, *yk = y + k * d;
+        if (P->pen) {
+            for (int64_t j = 0; j < d; ++j) sum[j] += rho * (xk[j] + yk[j] / rho);
+            total += rho;
+        } else {
+            for (int64_t j = 0; j < d; ++j) sum[j] += xk[j] + yk[j] / rho;
+        }
+    }
+    if (!P->pen) total = (double)P->n;
+    for (int64_t j = 0; j < d; ++j) sum[j] = (total > 0.0) ? sum[j] / total : z[j];
+    project_set(C, d, sum, z);
+}
+
+/*
+ * Multiplier step, equation (updatey): gradient ascent on the dual function
+ * with step rho_k, whose gradient in y_k is the constraint violation
+ * x_k - z at the new z:  y_to_k = y_from_k + rho_k (x_k - z).
+ * y_to may equal y_from.
+ */
+static void admm_multiplier_step(const admm_problem_t *P, const double *x, const double *z,
+                                 const double *y_from, double *y_to)
+{
+    const int64_t d = P->d;
+    for (int64_t k = 0; k < P->n; ++k) {
+        if (!admm_active(P, k)) continue;
+        const double rho = admm_penalty(P, k);
+        for (int64_t j = 0; j < d; ++j)
+            y_to[k * d + j] = y_from[k * d + j] + rho * (x[k * d + j] - z[j]);
+    }
+}
+
+/*
+ * Squared residuals after a sweep: primal sum_k ||x_k - z||^2 over the
+ * constraints that take part (how far the copies are from agreeing) and dual
+ * ||z - z_prev||^2 (how far z moved).  Returns the number of constraints.
+ */
+static int64_t admm_residuals(const admm_problem_t *P, const double *x, const double *z,
+                              const double *z_prev, double *sp, double *sd)
+{
+    const int64_t d = P->d;
+    int64_t m = 0;
+    *sp = 0.0;
+    *sd = 0.0;
+    for (int64_t k = 0; k < P->n; ++k) {
+        if (!admm_active(P, k)) continue;
+        ++m;
+        for (int64_t j = 0; j < d; ++j) {
+            double e = x[k * d + j] - z[j];
+            *sp += e * e;
+        }
+    }
+    for (int64_t j = 0; j < d; ++j) {
+        double e = z[j] - z_prev[j];
+        *sd += e * e;
+    }
+    return m;
+}
+
+/*
+ * Common checks: n = 0 is EMPTY (z left as given); a negative or non-finite
+ * weight, a non-finite point or starting z, or an invalid set is BAD_INPUT
+ * (z set to NaN).  Returns 0 when the instance can be solved.
+ */
+static int admm_screen(int64_t n, int64_t d, const double *a, const double *w, const or_set_t *C,
+                       double *z)
+{
     if (n == 0) return OR_EMPTY;
     int bad = !set_ok(d, C);
     for (int64_t k = 0; k < n; ++k)
@@ -193,45 +297,60 @@ static int em_solve_set(int64_t n, int64_t d, const double *a, const double *w, 
         for (int64_t j = 0; j < d; ++j) z[j] = NAN;
         return OR_BAD_INPUT;
     }
-    double D = tol_scale_set(n, d, a, C);
+    return 0;
+}
 
-    double *ybuf = y ? y : (double *)calloc((size_t)(n * d), sizeof(double));
-    double *x = (double *)malloc((size_t)(n * d) * sizeof(double));
+/*
+ * One instance of Algorithm 1 (penalty mu for every constraint).
+ *
+ * Stopping (the paper only asks for "convergence"): after each sweep,
+ *   r_pri  = sqrt(sum_k ||x_k - z||^2 / (n d)),   r_dual = sqrt(||z - z_prev||^2 / d),
+ * and the solve ends when tol > 0 and both are <= tol * D, else after
+ * max_iter sweeps.
+ *
+ * Adaptive penalty (adapt_every > 0; the conclusion names it as future work,
+ * the rule is residual balancing, Boyd et al. 2011, Section 3.4.1): after a
+ * sweep t that did not stop, with t a multiple of adapt_every, the stacked
+ * residual norms ||r|| = (sum_k ||x_k - z||^2)^(1/2) and
+ * ||s|| = mu (n ||z - z_prev||^2)^(1/2) are compared; mu is multiplied by
+ * adapt_factor when ||r|| > adapt_ratio ||s|| and divided by it when
+ * ||s|| > adapt_ratio ||r||.  The unscaled y_k are kept, so nothing else
+ * changes.  *mu_out (nullable) receives the final penalty.
+ *
+ * a: n*d points (point-major), w: n weights, z: d values in/out (the starting
+ * z is used unprojected), y: n*d multipliers in/out (NULL: start from zero,
+ * discarded), x_out: n*d last local copies (NULL to skip).  Returns the flag
+ * word; *iters, *r_pri, *r_dual receive the sweep count and the residuals of
+ * the last sweep (0 when none ran).
+ */
+static int em_solve_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                        const or_set_t *C, double *z, double *y, double *x_out, int64_t max_iter,
+                        double tol, int64_t adapt_every, double adapt_ratio, double adapt_factor,
+                        int64_t *iters, double *r_pri, double *r_dual, double *mu_out)
+{
+    *iters = 0;
+    *r_pri = 0.0;
+    *r_dual = 0.0;
+    if (mu_out) *mu_out = mu;
+    int screened = admm_screen(n, d, a, w, C, z);
+    if (screened) return screened;
+    const double D = tol_scale_set(n, d, a, C);
+
+    admm_problem_t P = {n, d, a, w, NULL, mu};
+    double *mult = y ? y : (double *)calloc((size_t)(n * d), sizeof(double));
+    double *x = (double *)calloc((size_t)(n * d), sizeof(double));
     double *v = (double *)malloc((size_t)d * sizeof(double));
-    double *r = (double *)malloc((size_t)d * sizeof(double));
-    double *zprev = (double *)malloc((size_t)d * sizeof(double));
+    double *sum = (double *)malloc((size_t)d * sizeof(double));
+    double *z_prev = (double *)malloc((size_t)d * sizeof(double));
 
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
-        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
-            const double *ak = a + k * d;
-            double *yk = ybuf + k * d;
-            double *xk = x + k * d;
-            double lambda = w[k] / mu;                    /* lambda = w_k / mu */
-            for (int64_t j = 0; j < d; ++j) v[j] = z[j] - yk[j] / mu;   /* v = z - y_k / mu */
-            oracle_prox(d, v, ak, lambda, xk);
-            for (int64_t j = 0; j < d; ++j) r[j] += xk[j] + yk[j] / mu;
-        }
-        for (int64_t j = 0; j < d; ++j) {
-            zprev[j] = z[j];
-            r[j] = r[j] / (double)n;
-        }
-        project_set(C, d, r, z);
-        for (int64_t k = 0; k < n; ++k)
-            for (int64_t j = 0; j < d; ++j)
-                ybuf[k * d + j] += mu * (x[k * d + j] - z[j]);
-
-        double sp = 0.0, sd = 0.0;
-        for (int64_t k = 0; k < n; ++k)
-            for (int64_t j = 0; j < d; ++j) {
-                double e = x[k * d + j] - z[j];
-                sp += e * e;
-            }
-        for (int64_t j = 0; j < d; ++j) {
-            double e = z[j] - zprev[j];
-            sd += e * e;
-        }
+        memcpy(z_prev, z, (size_t)d * sizeof(double));
+        admm_local_block(&P, z, mult, x, v);
+        admm_global_block(&P, C, x, mult, sum, z);
+        admm_multiplier_step(&P, x, z, mult, mult);
+        double sp, sd;
+        admm_residuals(&P, x, z, z_prev, &sp, &sd);
         *r_pri = sqrt(sp / (double)(n * d));
         *r_dual = sqrt(sd / (double)d);
         *iters = t;
@@ -240,21 +359,21 @@ static int em_solve_set(int64_t n, int64_t d, const double *a, const double *w, 
             break;
         }
         if (adapt_every > 0 && t % adapt_every == 0) {
-            double rnorm = sqrt(sp);
-            double snorm = mu * sqrt((double)n * sd);
+            const double rnorm = sqrt(sp);
+            const double snorm = P.mu * sqrt((double)n * sd);
             if (rnorm > adapt_ratio * snorm)
-                mu *= adapt_factor;
+                P.mu *= adapt_factor;
             else if (snorm > adapt_ratio * rnorm)
-                mu /= adapt_factor;
+                P.mu /= adapt_factor;
         }
     }
-    if (mu_out) *mu_out = mu;
+    if (mu_out) *mu_out = P.mu;
     if (x_out) memcpy(x_out, x, (size_t)(n * d) * sizeof(double));
-    if (!y) free(ybuf);
+    if (!y) free(mult);
     free(x);
     free(v);
-    free(r);
-    free(zprev);
+    free(sum);
+    free(z_prev);
     return flags;
 }
 
@@ -283,23 +402,15 @@ int oracle_em_solve_ball(int64_t n, int64_t d, const double *a, const double *w,
 }
 
 /*
- * The weighted-mean variant of the consensus ADMM (a different algorithm from
- * Algorithm 1, which uses one penalty mu for every constraint x_k = z): the
- * constraint of point k gets its own penalty mu_k = mu w_k, so the augmented
- * Lagrangian is
- *   sum_k w_k ||x_k - a_k|| + y_k.(x_k - z) + (mu_k / 2) ||x_k - z||^2.
- * Minimising it over each block in turn, as in Algorithm 1:
- *   x_k = Psi_{w_k / mu_k}(z - y_k / mu_k, a_k)      (threshold w_k/mu_k = 1/mu)
- *   z   = P_C( sum_k mu_k (x_k + y_k / mu_k) / sum_k mu_k )   (a weighted mean;
- *         exact over a box or a ball because the z-subproblem is an isotropic
- *         quadratic)
- *   y_k = y_k + mu_k (x_k - z).
- * A point of weight zero has no term in the objective and no penalty: it is
- * left out.  Every weight zero: z = P_C(z) (every point of C is a minimiser).
- * Residuals over the n' points of positive weight: r_pri =
- * sqrt(sum_k ||x_k - z||^2 / (n' d)) (0 when n' = 0), r_dual as for Algorithm 1;
- * the stopping rule, D and the n = 0 / bad-input rules are those of
- * oracle_em_solve.
+ * The weighted-mean variant (a different algorithm from Algorithm 1): the
+ * constraint of point k gets the penalty rho_k = mu w_k instead of mu.  The
+ * same three blocks then give a prox threshold w_k / rho_k = 1 / mu for every
+ * point and a z-update that projects the w-weighted mean of x_k + y_k / rho_k
+ * (exact over a box or a ball: the z-subproblem is an isotropic quadratic).
+ * A point of weight zero has no term and no constraint and is left out; with
+ * every weight zero z = P_C(z).  The primal residual runs over the n' points
+ * of positive weight, r_pri = sqrt(sum_k ||x_k - z||^2 / (n' d)) (0 when
+ * n' = 0); r_dual, D, stopping and the screening are those of em_solve_set.
  */
 static int em_solve_wpen_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
                              const or_set_t *C, double *z, int64_t max_iter, double tol,
@@ -308,64 +419,26 @@ static int em_solve_wpen_set(int64_t n, int64_t d, const double *a, const double
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
-    if (n == 0) return OR_EMPTY;
-    int bad = !set_ok(d, C);
-    for (int64_t k = 0; k < n; ++k)
-        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
-    for (int64_t i = 0; i < n * d; ++i)
-        if (!isfinite(a[i])) bad = 1;
-    for (int64_t j = 0; j < d; ++j)
-        if (!isfinite(z[j])) bad = 1;
-    if (bad) {
-        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
-        return OR_BAD_INPUT;
-    }
-    double D = tol_scale_set(n, d, a, C);
+    int screened = admm_screen(n, d, a, w, C, z);
+    if (screened) return screened;
+    const double D = tol_scale_set(n, d, a, C);
+    double *pen = (double *)malloc((size_t)(n + 1) * sizeof(double));
+    for (int64_t k = 0; k < n; ++k) pen[k] = (w[k] > 0.0) ? mu * w[k] : 0.0;
+    admm_problem_t P = {n, d, a, w, pen, mu};
     double *y = (double *)calloc((size_t)(n * d + 1), sizeof(double));
-    double *x = (double *)malloc((size_t)(n * d + 1) * sizeof(double));
+    double *x = (double *)calloc((size_t)(n * d + 1), sizeof(double));
     double *v = (double *)malloc((size_t)d * sizeof(double));
-    double *r = (double *)malloc((size_t)d * sizeof(double));
-    double *zprev = (double *)malloc((size_t)d * sizeof(double));
-    int64_t npos = 0;
-    double msum = 0.0;
-    for (int64_t k = 0; k < n; ++k)
-        if (w[k] > 0.0) {
-            ++npos;
-            msum += mu * w[k];
-        }
+    double *sum = (double *)malloc((size_t)d * sizeof(double));
+    double *z_prev = (double *)malloc((size_t)d * sizeof(double));
 
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
-        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
-            if (!(w[k] > 0.0)) continue;
-            const double mk = mu * w[k];                  /* mu_k = mu w_k */
-            const double *ak = a + k * d;
-            double *yk = y + k * d;
-            double *xk = x + k * d;
-            for (int64_t j = 0; j < d; ++j) v[j] = z[j] - yk[j] / mk;
-            oracle_prox(d, v, ak, w[k] / mk, xk);
-            for (int64_t j = 0; j < d; ++j) r[j] += mk * (xk[j] + yk[j] / mk);
-        }
-        for (int64_t j = 0; j < d; ++j) {
-            zprev[j] = z[j];
-            r[j] = (msum > 0.0) ? r[j] / msum : z[j];
-        }
-        project_set(C, d, r, z);
-        double sp = 0.0, sd = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
-            if (!(w[k] > 0.0)) continue;
-            const double mk = mu * w[k];
-            for (int64_t j = 0; j < d; ++j) {
-                double e = x[k * d + j] - z[j];
-                y[k * d + j] += mk * e;
-                sp += e * e;
-            }
-        }
-        for (int64_t j = 0; j < d; ++j) {
-            double e = z[j] - zprev[j];
-            sd += e * e;
-        }
+        memcpy(z_prev, z, (size_t)d * sizeof(double));
+        admm_local_block(&P, z, y, x, v);
+        admm_global_block(&P, C, x, y, sum, z);
+        admm_multiplier_step(&P, x, z, y, y);
+        double sp, sd;
+        const int64_t npos = admm_residuals(&P, x, z, z_prev, &sp, &sd);
         *r_pri = (npos > 0) ? sqrt(sp / (double)(npos * d)) : 0.0;
         *r_dual = sqrt(sd / (double)d);
         *iters = t;
@@ -374,11 +447,12 @@ static int em_solve_wpen_set(int64_t n, int64_t d, const double *a, const double
             break;
         }
     }
+    free(pen);
     free(y);
     free(x);
     free(v);
-    free(r);
-    free(zprev);
+    free(sum);
+    free(z_prev);
     return flags;
 }
 
@@ -420,24 +494,28 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
 }
 
 /*
- * Accelerated ADMM, the second extension the conclusion names ([Goldstein2012]:
- * "fast ADMM with restart" for weakly convex problems), applied to the
- * splitting (splitting) with u = (x_k), v = z, constraint x_k - z = 0 and
- * penalty mu.  With predictor values z_hat, y_hat (z_hat = z0, y_hat = 0 at
- * the start, alpha = 1, c_prev = +inf):
- *   x_k   = Psi_{w_k/mu}(z_hat - y_hat_k / mu, a_k)
- *   z     = P_C( mean_k (x_k + y_hat_k / mu) )
- *   y_k   = y_hat_k + mu (x_k - z)
- *   c     = mu ( sum_k ||x_k - z||^2 + n ||z - z_hat||^2 )
- *         (= ||y - y_hat||^2 / mu + mu ||B (z - z_hat)||^2 of the reference)
- *   if c < eta c_prev:  alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2,
- *                       beta = (alpha - 1) / alpha',
- *                       z_hat = z + beta (z - z_prev), y_hat = y + beta (y - y_prev)
- *   else (restart):     alpha' = 1, z_hat = z_prev, y_hat = y_prev,
- *                       c = c_prev / eta
- * where z_prev, y_prev are the previous iteration's z, y (the starting z and
- * zero before the first).  Residuals and stopping as for oracle_em_solve
- * (r_dual from z - z_prev).  eta = 0.999 in the reference.
+ * Accelerated ADMM, the second extension the conclusion names: fast ADMM with
+ * restart for weakly convex problems [Goldstein2012], applied to the same
+ * splitting (first block the local copies x_k, second block z, constraint
+ * x_k - z = 0, penalty mu).
+ *
+ * The sweeps are those of Algorithm 1 except that the local and global blocks
+ * start from predicted values z_hat, y_hat instead of the last z, y:
+ *   x     = local block at (z_hat, y_hat),
+ *   z     = global block from (x, y_hat),
+ *   y     = y_hat + mu (x - z)                       (multiplier step from y_hat).
+ * The progress measure of the sweep is
+ *   c = mu sum_k ||x_k - z||^2 + mu n ||z - z_hat||^2
+ * (the squared multiplier change over mu plus mu times the squared change of
+ * B z with B the stacked -I blocks).  When c < eta c_prev the next
+ * predictions extrapolate along the last step with Nesterov's weight: alpha'
+ * = (1 + sqrt(1 + 4 alpha^2)) / 2, beta = (alpha - 1) / alpha', z_hat = z +
+ * beta (z - z_prev), y_hat = y + beta (y - y_prev), and c_prev = c.  Otherwise
+ * the sweep is restarted from the previous iterate: z_hat = z_prev, y_hat =
+ * y_prev, alpha' = 1, and c_prev becomes c_prev / eta.  Initially z_hat = z_prev
+ * = z0, y_hat = y_prev = 0, alpha = 1 and c_prev = +inf (so the first sweep
+ * takes the momentum branch with beta = 0).
+ * Residuals and stopping as for em_solve_set (r_dual from z - z_prev).
  * *restarts (nullable) receives the number of restarts.
  */
 int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w, double mu,
@@ -449,58 +527,37 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
     *r_pri = 0.0;
     *r_dual = 0.0;
     if (restarts) *restarts = 0;
-    if (n == 0) return OR_EMPTY;
     or_set_t C = {lo, hi, NULL, 0.0};
-    int bad = !set_ok(d, &C);
-    for (int64_t k = 0; k < n; ++k)
-        if (!isfinite(w[k]) || w[k] < 0.0) bad = 1;
-    for (int64_t i = 0; i < n * d; ++i)
-        if (!isfinite(a[i])) bad = 1;
-    for (int64_t j = 0; j < d; ++j)
-        if (!isfinite(z[j])) bad = 1;
-    if (bad) {
-        for (int64_t j = 0; j < d; ++j) z[j] = NAN;
-        return OR_BAD_INPUT;
-    }
-    double D = tol_scale_set(n, d, a, &C);
-    size_t nd = (size_t)(n * d);
+    int screened = admm_screen(n, d, a, w, &C, z);
+    if (screened) return screened;
+    const double D = tol_scale_set(n, d, a, &C);
+    admm_problem_t P = {n, d, a, w, NULL, mu};
+    const size_t nd = (size_t)(n * d);
     double *y = (double *)calloc(nd, sizeof(double));
-    double *yp = (double *)calloc(nd, sizeof(double));
-    double *yh = (double *)calloc(nd, sizeof(double));
-    double *x = (double *)malloc(nd * sizeof(double));
+    double *y_prev = (double *)calloc(nd, sizeof(double));
+    double *y_hat = (double *)calloc(nd, sizeof(double));
+    double *x = (double *)calloc(nd, sizeof(double));
     double *v = (double *)malloc((size_t)d * sizeof(double));
-    double *r = (double *)malloc((size_t)d * sizeof(double));
-    double *zp = (double *)malloc((size_t)d * sizeof(double));
-    double *zh = (double *)malloc((size_t)d * sizeof(double));
-    memcpy(zp, z, (size_t)d * sizeof(double));
-    memcpy(zh, z, (size_t)d * sizeof(double));
+    double *sum = (double *)malloc((size_t)d * sizeof(double));
+    double *z_prev = (double *)malloc((size_t)d * sizeof(double));
+    double *z_hat = (double *)malloc((size_t)d * sizeof(double));
+    memcpy(z_prev, z, (size_t)d * sizeof(double));
+    memcpy(z_hat, z, (size_t)d * sizeof(double));
     double alpha = 1.0, c_prev = INFINITY;
 
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
-        for (int64_t j = 0; j < d; ++j) r[j] = 0.0;
-        for (int64_t k = 0; k < n; ++k) {
-            const double *yk = yh + k * d;
-            double *xk = x + k * d;
-            for (int64_t j = 0; j < d; ++j) v[j] = zh[j] - yk[j] / mu;
-            oracle_prox(d, v, a + k * d, w[k] / mu, xk);
-            for (int64_t j = 0; j < d; ++j) r[j] += xk[j] + yk[j] / mu;
-        }
-        double sd = 0.0, sh = 0.0, sp = 0.0;
+        memcpy(z_prev, z, (size_t)d * sizeof(double));
+        memcpy(y_prev, y, nd * sizeof(double));
+        admm_local_block(&P, z_hat, y_hat, x, v);
+        admm_global_block(&P, &C, x, y_hat, sum, z);
+        admm_multiplier_step(&P, x, z, y_hat, y);
+        double sp, sd;
+        admm_residuals(&P, x, z, z_prev, &sp, &sd);
+        double sh = 0.0;
         for (int64_t j = 0; j < d; ++j) {
-            double zn = clamp_box(r[j] / (double)n, lo[j], hi[j]);
-            double e = zn - z[j];
-            sd += e * e;
-            double eh = zn - zh[j];
-            sh += eh * eh;
-            zp[j] = z[j];          /* previous iterate */
-            z[j] = zn;
-        }
-        for (int64_t i = 0; i < n * d; ++i) {
-            yp[i] = y[i];
-            y[i] = yh[i] + mu * (x[i] - z[i % d]);
-            double e = x[i] - z[i % d];
-            sp += e * e;
+            double e = z[j] - z_hat[j];
+            sh += e * e;
         }
         *r_pri = sqrt(sp / (double)(n * d));
         *r_dual = sqrt(sd / (double)d);
@@ -509,30 +566,30 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
             flags = OR_CONVERGED;
             break;
         }
-        double c = mu * (sp + (double)n * sh);
+        const double c = mu * (sp + (double)n * sh);
         if (c < eta * c_prev) {
-            double alpha_n = 0.5 * (1.0 + sqrt(1.0 + 4.0 * alpha * alpha));
-            double beta = (alpha - 1.0) / alpha_n;
-            for (int64_t j = 0; j < d; ++j) zh[j] = z[j] + beta * (z[j] - zp[j]);
-            for (int64_t i = 0; i < n * d; ++i) yh[i] = y[i] + beta * (y[i] - yp[i]);
-            alpha = alpha_n;
+            const double alpha_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * alpha * alpha));
+            const double beta = (alpha - 1.0) / alpha_next;
+            for (int64_t j = 0; j < d; ++j) z_hat[j] = z[j] + beta * (z[j] - z_prev[j]);
+            for (size_t i = 0; i < nd; ++i) y_hat[i] = y[i] + beta * (y[i] - y_prev[i]);
+            alpha = alpha_next;
             c_prev = c;
         } else {
-            for (int64_t j = 0; j < d; ++j) zh[j] = zp[j];
-            for (int64_t i = 0; i < n * d; ++i) yh[i] = yp[i];
+            memcpy(z_hat, z_prev, (size_t)d * sizeof(double));
+            memcpy(y_hat, y_prev, nd * sizeof(double));
             alpha = 1.0;
             c_prev = c_prev / eta;
             if (restarts) ++*restarts;
         }
     }
     free(y);
-    free(yp);
-    free(yh);
+    free(y_prev);
+    free(y_hat);
     free(x);
     free(v);
-    free(r);
-    free(zp);
-    free(zh);
+    free(sum);
+    free(z_prev);
+    free(z_hat);
     return flags;
 }
 

@@ -187,6 +187,36 @@ def test_worked_example_iterations_two_to_six(orc):
     assert r["iters"] > 6 and abs(r["z"][0] - 1.0) <= 0.05
 
 
+def test_worked_example_iterations_seven_to_twelve(orc):
+    """The same example past the tie.  From t = 7 on the middle point is
+    within lambda = 1 of v (so x_2 = a_2 = 1) and the outer two are not
+    (x_1 = v_1 - 1, x_3 = v_3 + 1).  With v_k = z - y_k that gives
+      x_1 + y_1 = z - 1,  x_2 + y_2 = 1 + y_2,  x_3 + y_3 = z + 1,
+      z' = (2 z + 1 + y_2) / 3,   y_2' = y_2 + 1 - z',
+      y_1' = z - 1 - z',          y_3' = z + 1 - z',
+    a two-variable recursion worked out by hand, started from z = 1,
+    y = (-2/3, -2/3, 4/3) after t = 6: z = 7/9, 19/27, 61/81, 211/243,
+    721/729, 2347/2187: the iterates oscillate towards the median 1, and the
+    primal residual is no longer zero (x_2 = 1 differs from z').  The branch
+    conditions are checked along the way in exact arithmetic."""
+    from fractions import Fraction as Fr
+    a = np.array([[0.0], [1.0], [5.0]])
+    z, y = Fr(1), [Fr(-2, 3), Fr(-2, 3), Fr(4, 3)]
+    for t in range(7, 13):
+        v = [z - yk for yk in y]
+        assert abs(v[0] - 0) > 1 and abs(v[1] - 1) <= 1 and abs(v[2] - 5) > 1
+        zn = (2 * z + 1 + y[1]) / 3
+        x = [v[0] - 1, Fr(1), v[2] + 1]
+        y = [z - 1 - zn, y[1] + 1 - zn, z + 1 - zn]
+        z = zn
+        r = orc.em_solve(a, [1, 1, 1], 1.0, 0.0, 10.0, [3.0], max_iter=t)
+        assert abs(r["z"][0] - float(z)) <= 1e-14, (t, r["z"][0], z)
+        np.testing.assert_allclose(r["y"].ravel(), [float(q) for q in y], rtol=0, atol=1e-13)
+        rp = np.sqrt(sum(float(xk - z) ** 2 for xk in x) / 3)
+        assert abs(r["r_pri"] - rp) <= 1e-14
+    assert z == Fr(2347, 2187)
+
+
 # --------------------------------------------------- converged solutions
 
 def _solve(orc, a, w, lo=-INF, hi=INF, mu=None, z0=None, iters=20000):
