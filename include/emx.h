@@ -74,6 +74,10 @@ enum {
     EM_EMPTY = 4,     /* n = 0: z left as given */
     EM_BAD_INPUT = 8  /* negative/non-finite weight or non-finite point: z set to NaN */
 };
+/* Accelerated ADMM (EM_SOLVER_ADMM_FAST): flags >> EM_RESTART_SHIFT is the
+ * number of restarts the solve took (capped at 2^23 - 1); the low byte holds
+ * the bits above.  Other solvers leave the upper bits zero. */
+#define EM_RESTART_SHIFT 8
 
 /* Starting value of z for em_solve_batch / em_solve_plain. */
 typedef enum {
@@ -249,7 +253,9 @@ em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
  *     y_hat = y + beta (y - y_prev);
  *   otherwise restart: z_hat = z_prev, y_hat = y_prev, alpha = 1,
  *     c_prev = c_prev / fast_eta
- * (alpha = 1 and c_prev = +inf at the start).  Residuals and stopping as for
+ * (alpha = 1 and c_prev = +inf at the start; no decision is taken after the
+ * last allowed sweep, and stats.flags >> EM_RESTART_SHIFT counts the
+ * restarts).  Residuals and stopping as for
  * em_solve_batch, evaluated every iteration.  Its momentum needs the previous
  * multipliers, a second n x d state, which this path keeps in device memory.
  * Other solvers and the ball return EM_ERR_UNSUPPORTED; arguments and errors

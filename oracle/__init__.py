@@ -82,7 +82,7 @@ def _load():
                                            C.c_double, C.c_double, C.c_double, C.c_double, fp, fp, fp, fp,
                                            C.c_int64, i32p, C.c_double, C.c_int, C.c_int64,
                                            C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_double,
-                                           C.c_int]
+                                           i32p, C.c_int]
         lib.oracle_em_batch_ex.restype = C.c_int
         lib.oracle_em_batch.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p,
                                         C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
@@ -277,7 +277,8 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     optional float32 per-coordinate bounds indexed like z; ball_radius
     (float32, one per instance) selects the ball constraint with centres
     ball_center (float32 indexed like z, None = origin).  Returns z (float64,
-    concatenated), iters, flags, residuals and the final penalties."""
+    concatenated), iters, flags, residuals, the final penalties and the
+    accelerated ADMM's restart counts."""
     inst = batch.inst
     B = int(inst.shape[0])
     a = np.ascontiguousarray(batch.a, dtype=np.float32)
@@ -297,6 +298,7 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     rp = np.zeros(B)
     rd = np.zeros(B)
     mf = np.zeros(B)
+    rs = np.zeros(B, np.int32)
     mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
     _load().oracle_em_batch_ex(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
                                _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
@@ -306,8 +308,9 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
                                _p(mie, C.c_int32), float(tol), int(init), int(adapt_every),
                                float(adapt_ratio), float(adapt_factor), _p(z, C.c_double),
                                _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
-                               _p(rd, C.c_double), _p(mf, C.c_double), float(eta), int(nthreads))
-    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf)
+                               _p(rd, C.c_double), _p(mf, C.c_double), float(eta),
+                               _p(rs, C.c_int32), int(nthreads))
+    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf, restarts=rs)
 
 
 def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: float,

@@ -516,7 +516,10 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
  * = z0, y_hat = y_prev = 0, alpha = 1 and c_prev = +inf (so the first sweep
  * takes the momentum branch with beta = 0).
  * Residuals and stopping as for em_solve_set (r_dual from z - z_prev).
- * *restarts (nullable) receives the number of restarts.
+ * *restarts (nullable) receives the number of restarts.  No decision is
+ * taken after the last allowed sweep (nothing follows it), so a solve that
+ * stops at sweep T, by the tolerance or by max_iter = T, reports the
+ * decisions of sweeps 1..T-1.
  */
 int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w, double mu,
                          const double *lo, const double *hi, double *z, int64_t max_iter,
@@ -566,6 +569,7 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
             flags = OR_CONVERGED;
             break;
         }
+        if (t == max_iter) break;   /* the decision would change nothing */
         const double c = mu * (sp + (double)n * sh);
         if (c < eta * c_prev) {
             const double alpha_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * alpha * alpha));
@@ -779,7 +783,8 @@ int oracle_max_threads(void)
  * centres ball_center (nullable = origin, indexed like z; solvers 0, 1 and 4).
  * Otherwise box_lo / box_hi (nullable, float32, indexed like
  * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
- * mu_out (nullable): the final penalty per instance.
+ * mu_out (nullable): the final penalty per instance; restarts_out (nullable):
+ * the accelerated ADMM's restart count per instance.
  */
 int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t *a_off,
                        const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
@@ -789,7 +794,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
                        const int32_t *max_iter_each, double tol, int init, int64_t adapt_every,
                        double adapt_ratio, double adapt_factor, double *z, int32_t *iters,
                        int32_t *flags, double *r_pri, double *r_dual, double *mu_out, double eta,
-                       int nthreads)
+                       int32_t *restarts_out, int nthreads)
 {
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -824,7 +829,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
                 zb[j] = s / (W > 0.0 ? W : (double)n);
             }
         }
-        int64_t it = 0;
+        int64_t it = 0, rs = 0;
         double rp = 0.0, rd = 0.0, mf = mu;
         int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
         int f;
@@ -833,7 +838,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         else if (solver == 4)
             f = em_solve_wpen_set(n, d, ab, wb, mu, &C, zb, mi, tol, &it, &rp, &rd);
         else if (solver == 3)
-            f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, NULL);
+            f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, &rs);
         else
             f = em_solve_set(n, d, ab, wb, mu, &C, zb, NULL, NULL, mi, tol, adapt_every, adapt_ratio,
                              adapt_factor, &it, &rp, &rd, &mf);
@@ -842,6 +847,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         if (r_pri) r_pri[b] = rp;
         if (r_dual) r_dual[b] = rd;
         if (mu_out) mu_out[b] = mf;
+        if (restarts_out) restarts_out[b] = (int32_t)rs;
         free(ab);
         free(wb);
         free(lv);
@@ -860,7 +866,7 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
 {
     return oracle_em_batch_ex(B, a, w, a_off, w_off, z_off, n_arr, d_arr, 0, mu, 1.0, lo, hi, NULL,
                               NULL, NULL, NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z,
-                              iters, flags, r_pri, r_dual, NULL, 0.999, nthreads);
+                              iters, flags, r_pri, r_dual, NULL, 0.999, NULL, nthreads);
 }
 
 /* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */

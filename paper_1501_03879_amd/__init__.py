@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("EMX_LIBRARY") or os.path.join(HERE, "libemx.so")
 
 EM_OK, EM_ERR_INVALID_ARG, EM_ERR_UNSUPPORTED, EM_ERR_OUT_OF_MEMORY, EM_ERR_HIP = 0, -1, -2, -3, -4
 CONVERGED, MAXITER, EMPTY, BAD_INPUT = 1, 2, 4, 8
+RESTART_SHIFT = 8   # accelerated ADMM: flags >> RESTART_SHIFT = restarts
 INIT_GIVEN, INIT_MAXW, INIT_WMEAN = 0, 1, 2
 SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST, SOLVER_ADMM_WEIGHTED = 0, 1, 2, 3, 4
 SET_BOX, SET_BALL = 0, 1

@@ -184,8 +184,11 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
 //     n ||z - z_hat||^2) decides between momentum
 //     (z_hat = z + beta (z - z_prev), u_hat = u + beta (u - u_prev),
 //     beta = (alpha - 1) / alpha', alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2) and
-//     a restart (z_hat = z_prev, u_hat = u_prev, alpha = 1, c_prev /= eta).
-//     u = y / mu throughout (mu is fixed).
+//     a restart (z_hat = z_prev, u_hat = u_prev, alpha = 1, c_prev /= eta),
+//     except after the last allowed sweep; the restart count goes to the
+//     flags word.  u = y / mu throughout (mu is fixed).
+constexpr int kMaxRestartCount = (1 << 23) - 1;
+
 struct PlainArgs {
     const float *a;
     const float *w;
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
     const float *UH = FAST ? P.uh : P.u;   // the multipliers the prox and the mean use
     const float *ZH = FAST ? zh : zs;
     float alpha = 1.0f, c_prev = INFINITY;
-    int iters = 0, flags = EM_MAXITER;
+    int iters = 0, flags = EM_MAXITER, restarts = 0;
     float rpri = 0.0f, rdual = 0.0f;
     for (int t = 1; t <= P.max_iter; ++t) {
         // x_k = prox_{w_k/mu}(z_hat - u_hat_k, a_k)
@@ -364,6 +367,7 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
         }
         if constexpr (FAST) {
             const float sh2 = block_sum256(shl, red);
+            if (t == P.max_iter) break;   // no sweep follows: the decision would change nothing
             const float c = P.mu * (sp + (float)n * sh2);
             if (c < P.eta * c_prev) {
                 const float an = 0.5f * (1.0f + sqrtf(1.0f + 4.0f * alpha * alpha));
@@ -377,12 +381,15 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
                 for (int i = tid; i < n * d; i += 256) P.uh[i] = P.up[i];
                 alpha = 1.0f;
                 c_prev = c_prev / P.eta;
+                ++restarts;
             }
             __syncthreads();
         }
     }
     if (tid < d) Z[tid] = zs[tid];
-    if (tid == 0 && P.stats) P.stats[P.b] = em_stats_t{iters, flags, rpri, rdual};
+    if (tid == 0 && P.stats)
+        P.stats[P.b] = em_stats_t{iters, flags | (FAST ? min(restarts, kMaxRestartCount) << EM_RESTART_SHIFT : 0),
+                                  rpri, rdual};
 }
 
 em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,

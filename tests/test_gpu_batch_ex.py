@@ -172,19 +172,31 @@ def _per_instance_errors(batch, got, ref, D):
     return np.array(out)
 
 
+def _fast_parity(b, got, st, ref, D, name):
+    """Every instance: the GPU took exactly as many restarts as the FP64
+    oracle (the restart test c < eta c_prev is a decision on floating-point
+    values, so this is checked, not assumed) and its z is within 1e-4 D of
+    the oracle's."""
+    import paper_1501_03879_amd as emx
+    err = _per_instance_errors(b, got, ref["z"], D)
+    rs_gpu = st["flags"] >> emx.RESTART_SHIFT
+    same = rs_gpu == ref["restarts"]
+    print(f"[parity] {name}: max_rel={err.max():.3e} over all {b.B} instances; restarts "
+          f"{int(rs_gpu.sum())} (gpu) vs {int(ref['restarts'].sum())} (oracle), "
+          f"{int((~same).sum())} instances differ", flush=True)
+    assert np.all(same), np.flatnonzero(~same)
+    assert err.max() <= 1e-4, (np.argmax(err), err.max())
+    return err
+
+
 def test_fast_admm_plain_fixed_iterations():
-    """The restart test (c < eta c_prev) is a decision on floating-point
-    values; the number of instances on which FP32 and FP64 take a different
-    branch is reported (and must be a small minority); all others match the
-    oracle to the bar."""
     b = _mixed(31, 60)
     got, st = run_plain_ex(b, solver=FAST, max_iter=30, tol=0.0, init=oracle.INIT_MAXW, mu=2.0)
     ref = oracle.em_batch(b, 2.0, 30, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM)
-    err = _per_instance_errors(b, got, ref["z"], 6.0)
-    ok = err <= 1e-4
-    print(f"[parity] plain fast-ADMM T30 mu=2: max_rel={err[ok].max():.3e} over {ok.sum()} of {b.B} "
-          f"instances; {(~ok).sum()} took another restart branch", flush=True)
-    assert ok.mean() >= 0.95
+    _fast_parity(b, got, st, ref, 6.0, "plain fast-ADMM T30 mu=2")
+    live = np.array([e["n"] > 0 for e in b.inst])
+    assert np.all((st["flags"][live] & 0xff) == oracle.MAXITER)
+    assert ref["restarts"].sum() > 0   # the restart branch is exercised
 
 
 def test_fast_admm_plain_tolerance_mode_beats_plain_admm():
@@ -193,13 +205,11 @@ def test_fast_admm_plain_tolerance_mode_beats_plain_admm():
     _, st0 = run_plain_ex(b, solver=ADMM, max_iter=3000, tol=1e-4, init=oracle.INIT_MAXW, mu=5.0)
     ref = oracle.em_batch(b, 5.0, 3000, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM,
                           max_iter_each=st["iters"])
-    err = _per_instance_errors(b, got, ref["z"], 6.0)
-    ok = err <= 1e-4
+    _fast_parity(b, got, st, ref, 6.0, "plain fast-ADMM tol mu=5")
     print(f"[parity] plain fast-ADMM tol mu=5: mean iters {st['iters'].mean():.1f} vs plain ADMM "
-          f"{st0['iters'].mean():.1f}; max_rel={err[ok].max():.3e} on {ok.sum()} of {b.B}", flush=True)
-    assert ok.mean() >= 0.9
+          f"{st0['iters'].mean():.1f}", flush=True)
     assert st["iters"].mean() * 2 < st0["iters"].mean()
-    assert np.mean(st["flags"] == 1) >= 0.95
+    assert np.mean((st["flags"] & 0xff) == oracle.CONVERGED) >= 0.95
 
 
 def test_plain_admm_per_coordinate_boxes():

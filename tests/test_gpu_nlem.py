@@ -73,35 +73,43 @@ def test_constant_image():
     assert np.all(st["flags"] == 1)
 
 
-def test_256_tolerance_mode_sampled():
+def test_256_tolerance_mode_every_pixel():
     """The 256x256 sigma-20 image at d=49, n<=441, tol 1e-4, <=200 iterations:
-    whole image on the GPU; 1536 sampled pixels (corners, borders, interior)
-    recomputed by the oracle at the GPU's iteration counts."""
+    every one of the 65,536 pixels recomputed by the oracle at the GPU's
+    per-pixel iteration count (reading R18), max-abs and RMS error reported."""
     wl = synth.nlem_256()
     im = wl.images[0]
     got, st = run_nlem(im.noisy, 3, 10, im.h, wl.mu, wl.max_iter, wl.tol)
     H, W = im.noisy.shape
-    rng = np.random.default_rng(0)
-    border = [i for i in range(H * W) if min(i // W, i % W, H - 1 - i // W, W - 1 - i % W) < 10]
-    pix = np.unique(np.concatenate([[0, W - 1, (H - 1) * W, H * W - 1],
-                                    rng.choice(border, 512, replace=False),
-                                    rng.choice(H * W, 1020, replace=False)]))
-    ref = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, 0.0, pix=pix,
-                      max_iter_each=st["iters"][pix])
-    emax, erms = rel_errors(got[pix], ref["out"], D)
-    report("nlem 256x256 tol-mode (sampled, oracle at GPU iterations)", emax, erms)
+    ref = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, 0.0,
+                      max_iter_each=st["iters"])
+    emax, erms = rel_errors(got, ref["out"], D)
+    report(f"nlem 256x256 tol-mode, all {H * W} pixels, oracle at GPU iterations", emax, erms)
     assert emax <= 1e-4
     # the stop was legitimate: residuals at the GPU's count are within tol (FP32 slack 5%)
     tau = wl.tol * D
     ok = (ref["r_pri"] <= 1.05 * tau) & (ref["r_dual"] <= 1.05 * tau)
-    conv = st["flags"][pix] == 1
+    conv = st["flags"] == 1
     assert np.all(ok[conv])
-    # and not late: compare with the oracle's own stopping iteration
-    own = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, wl.tol, pix=pix)
-    diff = st["iters"][pix] - own["iters"]
-    print(f"[parity] iteration count gpu - oracle: mean {diff.mean():.3f}, "
-          f"|diff|<=1 for {np.mean(np.abs(diff) <= 1):.3f}", flush=True)
-    assert np.mean(np.abs(diff) <= 1) >= 0.95
+    # and not late: the GPU evaluates the primal residual only after an
+    # iteration whose dual residual was within tol, so it stops at the
+    # oracle's iteration or one later (R18); FP32 rounding of a residual that
+    # sits at the threshold can move that decision
+    own = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, wl.tol)
+    diff = st["iters"] - own["iters"]
+    vals, cnts = np.unique(diff, return_counts=True)
+    print(f"[parity] iteration count gpu - oracle over all pixels: "
+          f"{dict(zip(vals.tolist(), cnts.tolist()))}", flush=True)
+    off = np.flatnonzero((diff < 0) | (diff > 1))
+    if off.size:
+        # the oracle's residuals at its own stop and one iteration before, relative to tol D
+        prev = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, 0.0, pix=off,
+                           max_iter_each=np.maximum(own["iters"][off] - 1, 0))
+        for q, i in enumerate(off[:20]):
+            print(f"  pixel {i}: gpu {st['iters'][i]} oracle {own['iters'][i]}; oracle at its stop "
+                  f"r_pri/tau {own['r_pri'][i] / tau:.4f} r_dual/tau {own['r_dual'][i] / tau:.4f}; "
+                  f"one before r_dual/tau {prev['r_dual'][q] / tau:.4f}", flush=True)
+    assert np.mean((diff >= 0) & (diff <= 1)) >= 0.999
     assert np.mean(st["flags"] == 1) >= 0.99
 
 

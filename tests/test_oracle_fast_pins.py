@@ -74,8 +74,9 @@ def test_momentum_sweeps_three_and_four_exact(orc):
 
 
 def test_restart_returns_to_the_previous_iterate_exact(orc):
-    """Same instance.  At t = 5 the progress measure c5 (~0.10010) is not below
-    eta c4 (~0.09999): restart.  The next sweep then starts from the previous
+    """Same instance.  After t = 5 the progress measure c5 (~0.10010) is not
+    below eta c4 (~0.09999): restart (counted when a sixth sweep is allowed;
+    no decision follows the last allowed sweep).  The next sweep then starts from the previous
     iterate, z_hat = z4 and y_hat = y4 (not z5, y5), with the same branch
     pattern, so z6 = (2 z4 + 3 + y4_2) / 3 where
       y4_2 = y_hat4_2 + 3 - z4,  y_hat4_2 = (-10 + 2 beta_2 + 2 beta_3 (1 + beta_2)) / 27."""
@@ -84,9 +85,9 @@ def test_restart_returns_to_the_previous_iterate_exact(orc):
     z4 = (229 - 8 * b2 - 8 * b3 * (1 + b2)) / 81
     yh4 = (-10 + 2 * b2 + 2 * b3 * (1 + b2)) / 27
     y4 = yh4 + 3 - z4
-    r5 = _run(orc, [1.0, 3.0, 5.0], [2.0, 2.0, 2.0], 1.0, 4.0, 5)
-    assert r5["restarts"] == 1
+    assert _run(orc, [1.0, 3.0, 5.0], [2.0, 2.0, 2.0], 1.0, 4.0, 5)["restarts"] == 0
     r6 = _run(orc, [1.0, 3.0, 5.0], [2.0, 2.0, 2.0], 1.0, 4.0, 6)
+    assert r6["restarts"] == 1
     assert abs(r6["z"][0] - (2 * z4 + 3 + y4) / 3) <= 1e-14, r6["z"][0]
 
 
@@ -103,18 +104,21 @@ def test_restart_on_the_appendix_example(orc):
     about 1.39)."""
     b2 = nesterov_betas(2)[1]
     a, w = [0.0, 1.0, 5.0], [1.0, 1.0, 1.0]
-    for T, want, rs in ((1, 8 / 3, 0), (2, 7 / 3, 0), (3, 2 - b2 / 3, 1)):
+    for T, want in ((1, 8 / 3), (2, 7 / 3), (3, 2 - b2 / 3)):
         r = _run(orc, a, w, 1.0, 3.0, T, lo=0.0, hi=10.0)
         assert abs(r["z"][0] - want) <= 1e-14, (T, r["z"][0])
-        assert r["restarts"] == rs, (T, r["restarts"])
+        assert r["restarts"] == 0, (T, r["restarts"])
     r = _run(orc, a, w, 1.0, 3.0, 4, lo=0.0, hi=10.0)
     assert abs(r["z"][0] - 2.0) <= 1e-14, r["z"][0]
+    assert r["restarts"] == 1
 
 
 @pytest.mark.parametrize("eta", [0.5, 0.999])
 def test_restart_threshold_scales_with_eta(orc, eta):
-    """c3 = c2 exactly on the appendix example, so the restart at t = 3 happens
-    for any eta < 1; after it c_prev = c2 / eta."""
-    r = orc.em_solve_fast([[0.0], [1.0], [5.0]], [1.0, 1.0, 1.0], 1.0, 0.0, 10.0, [3.0],
-                          max_iter=3, tol=0.0, eta=eta)
-    assert r["restarts"] == 1
+    """c3 = c2 exactly on the appendix example, so the restart after t = 3
+    happens for any eta < 1 (seen with max_iter = 4: no decision follows the
+    last allowed sweep, which has nothing after it)."""
+    for T, rs in ((3, 0), (4, 1)):
+        r = orc.em_solve_fast([[0.0], [1.0], [5.0]], [1.0, 1.0, 1.0], 1.0, 0.0, 10.0, [3.0],
+                              max_iter=T, tol=0.0, eta=eta)
+        assert r["restarts"] == rs
