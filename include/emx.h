@@ -93,6 +93,7 @@ typedef enum {
 #define EM_MAX_N 512           /* largest point count n per instance */
 #define EM_MAX_PATCH_RADIUS 3  /* nlem: patch side 2r+1 <= 7 (d <= 49) */
 #define EM_MAX_WINDOW_RADIUS 10/* nlem: window side 2R+1 <= 21 (n <= 441) */
+#define EM_NOALLOC_MAX_PIXELS (1 << 22) /* nlem_denoise_noalloc: largest H * W */
 
 /*
  * One instance of a batch, in device memory (32 bytes).  Points a_k are
@@ -313,6 +314,28 @@ em_status_t nlem_denoise(em_handle_t handle, void *stream, const void *img, int3
                          int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
                          float h_param, float lo, float hi, float rho, int32_t max_iter,
                          float tol, float *out, em_stats_t *stats);
+
+/*
+ * nlem_denoise_noalloc - nlem_denoise for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, semantics, kernels and
+ * results as nlem_denoise (bit for bit), but the work-queue head and the
+ * longest-first order scratch live in a static device array of the library
+ * (256 + 5 * EM_NOALLOC_MAX_PIXELS + 4096 bytes, about 20 MiB), which every
+ * GPU the library runs on holds until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocating call (em_kernel_timing does not
+ * cover it).  The array is shared by every call on the same GPU and keeps
+ * the last call's contents; the call clears what must start at zero with
+ * kernels on `stream`.  Calls that overlap on one GPU (concurrent streams,
+ * several handles or host threads) race on the array and give wrong
+ * results: serialise them.
+ * Errors: as nlem_denoise; UNSUPPORTED also when H * W > EM_NOALLOC_MAX_PIXELS
+ * or the device index is 64 or more.
+ */
+em_status_t nlem_denoise_noalloc(em_handle_t handle, void *stream, const void *img, int32_t img_is_f16,
+                                 int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                                 float h_param, float lo, float hi, float rho, int32_t max_iter,
+                                 float tol, float *out, em_stats_t *stats);
 
 /* One image of an nlem_denoise_multi call (host memory; pointers are device). */
 typedef struct {

@@ -25,6 +25,7 @@ SOLVER_ADMM, SOLVER_IRLS, SOLVER_ADMM_ADAPTIVE, SOLVER_ADMM_FAST, SOLVER_ADMM_WE
 SET_BOX, SET_BALL = 0, 1
 NLEM_INIT_NOISY, NLEM_INIT_NLM = 0, 1
 MAX_D, MAX_N, MAX_PATCH_RADIUS, MAX_WINDOW_RADIUS = 64, 512, 3, 10
+NOALLOC_MAX_PIXELS = 1 << 22   # nlem_denoise_noalloc: largest H * W
 
 # the 16-byte per-instance / per-pixel result record (em_stats_t)
 STATS_FIELDS = ("iters", "flags", "r_pri", "r_dual")
@@ -90,6 +91,8 @@ def load_library():
         lib.nlem_denoise.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, f32, f32, i32, f32,
                                      vp, vp]
         lib.nlem_denoise.restype = C.c_int
+        lib.nlem_denoise_noalloc.argtypes = lib.nlem_denoise.argtypes
+        lib.nlem_denoise_noalloc.restype = C.c_int
         lib.nlem_denoise_multi.argtypes = [vp, vp, i32, C.POINTER(NlemImage), f32, f32, f32, i32, f32]
         lib.nlem_denoise_multi.restype = C.c_int
         lib.nlem_denoise_ex.argtypes = [vp, vp, i32, C.POINTER(NlemImage), C.POINTER(NlemOptions)]
@@ -226,6 +229,19 @@ class Handle:
                                    float(hi), float(rho), int(max_iter), float(tol), _ptr(out),
                                    _ptr(stats))
         self._check(st, "nlem_denoise")
+
+    def nlem_denoise_noalloc(self, img, out, stats=None, *, patch_radius, window_radius, h, lo=0.0,
+                             hi=255.0, rho=1e-3, max_iter=200, tol=1e-4, stream=None):
+        """nlem_denoise with the library's static scratch instead of handle
+        workspace (no device allocation; H * W <= NOALLOC_MAX_PIXELS)."""
+        import torch
+        H, W = int(img.shape[0]), int(img.shape[1])
+        is16 = 1 if img.dtype == torch.float16 else 0
+        st = self.lib.nlem_denoise_noalloc(self.h, _stream(stream), _ptr(img), is16, H, W,
+                                           int(patch_radius), int(window_radius), float(h),
+                                           float(lo), float(hi), float(rho), int(max_iter),
+                                           float(tol), _ptr(out), _ptr(stats))
+        self._check(st, "nlem_denoise_noalloc")
 
     def nlem_denoise_multi(self, items, *, lo=0.0, hi=255.0, rho=1e-3, max_iter=200, tol=1e-4,
                            stream=None):

@@ -14,7 +14,7 @@ namespace emx {
 
 int blocks_per_cu(em_context *ctx, const void *fn, int threads);
 int ctx_num_cus(em_context *ctx);
-em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg);
+em_status_t ctx_error(em_context *ctx, em_status_t st, const char *msg);
 em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what);
 unsigned int *ctx_counters(em_context *ctx, int n);
 em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, int n);

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -51,7 +52,7 @@ struct em_context {
     int plan_epoch = 0;                 // bumped when a plan changes (invalidates the multi graph)
     unsigned int *counters = nullptr;  // kNumCounters work-queue heads
     int num_counters = 0;
-    std::string last_error;
+    char last_error[512] = {0};         // message of the last failed call (fixed storage)
     std::map<const void *, int> occupancy;
     MultiGraph multi;
     // batch workspace (grown on demand)
@@ -64,20 +65,24 @@ struct em_context {
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSideStreams] = {};
+    // nlem_denoise_noalloc: this device's address of the static scratch array
+    // (set by em_create; null when the device index is beyond kScratchDevices)
+    void *noalloc = nullptr;
     // em_kernel_timing: event pairs around the NLEM solve launches
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
     size_t tev_used = 0;
 };
 
-static em_status_t fail(em_context *ctx, em_status_t st, const std::string &msg) {
-    if (ctx) ctx->last_error = msg;
+// Error messages go to the handle's fixed buffer (no allocation on any path).
+static em_status_t fail(em_context *ctx, em_status_t st, const char *msg) {
+    if (ctx) snprintf(ctx->last_error, sizeof(ctx->last_error), "%s", msg);
     return st;
 }
 
 static em_status_t hip_fail(em_context *ctx, hipError_t e, const char *what) {
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    return fail(ctx, EM_ERR_HIP, m);
+    if (ctx) snprintf(ctx->last_error, sizeof(ctx->last_error), "%s: %s", what, hipGetErrorString(e));
+    return EM_ERR_HIP;
 }
 
 #define EMX_HIP(ctx, call)                                  \
@@ -88,14 +93,19 @@ static em_status_t hip_fail(em_context *ctx, hipError_t e, const char *what) {
 
 namespace emx {
 
-int blocks_per_cu(em_context *ctx, const void *fn, int threads) {
+// Resident workgroups per CU of a kernel, cached per handle; with
+// cache = false a kernel not yet cached is measured without being added
+// (no host allocation: the entry point that allocates nothing uses this).
+int blocks_per_cu(em_context *ctx, const void *fn, int threads, bool cache) {
     auto it = ctx->occupancy.find(fn);
     if (it != ctx->occupancy.end()) return it->second;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, 0) != hipSuccess || nb < 1) nb = 1;
-    ctx->occupancy[fn] = nb;
+    if (cache) ctx->occupancy[fn] = nb;
     return nb;
 }
+
+int blocks_per_cu(em_context *ctx, const void *fn, int threads) { return blocks_per_cu(ctx, fn, threads, true); }
 
 int ctx_num_cus(em_context *ctx) { return ctx->num_cus; }
 
@@ -116,7 +126,7 @@ em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fo
 }
 int ctx_device(em_context *ctx) { return ctx->device; }
 
-em_status_t ctx_error(em_context *ctx, em_status_t st, const std::string &msg) { return fail(ctx, st, msg); }
+em_status_t ctx_error(em_context *ctx, em_status_t st, const char *msg) { return fail(ctx, st, msg); }
 
 em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what) { return hip_fail(ctx, e, what); }
 
@@ -209,6 +219,42 @@ static void append_plan_cache(const em_context *ctx, int pr, int m, int solver, 
 
 static constexpr int kNumCounters = 256;
 
+// ---------------------------------------------------------------------------
+// Scratch of nlem_denoise_noalloc: a static device array, one copy per GPU,
+// held until the process ends.  Layout: the work-queue head (first 256
+// bytes), then the longest-first order scratch of up to
+// EM_NOALLOC_MAX_PIXELS pixels (nlem_order_bytes).  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in symbol):
+// em_create looks up its device address once per device with the device
+// current and every use goes through that address.
+// ---------------------------------------------------------------------------
+static constexpr size_t kScratchHeadBytes = 256;
+static constexpr size_t kScratchBytes =
+    kScratchHeadBytes + (size_t)EM_NOALLOC_MAX_PIXELS * (sizeof(int32_t) + 1) + 4096;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kScratchDevices = 64;
+static void *g_scratch_addr[kScratchDevices] = {};
+static std::mutex g_scratch_mu;
+
+// The device address of `scratch` on `device` (the current device), looked
+// up on the first call for that device.  *addr = null for device indices
+// beyond kScratchDevices.
+static hipError_t scratch_address(int device, void **addr) {
+    *addr = nullptr;
+    if (device < 0 || device >= kScratchDevices) return hipSuccess;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *addr = g_scratch_addr[device];
+    return hipSuccess;
+}
+
 extern "C" em_status_t em_create(em_handle_t *handle, int device) {
     if (!handle) return EM_ERR_INVALID_ARG;
     *handle = nullptr;
@@ -232,6 +278,10 @@ extern "C" em_status_t em_create(em_handle_t *handle, int device) {
         if (colon != std::string::npos) ctx->arch = a.substr(0, colon);
     }
     load_plan_cache(ctx);
+    if (scratch_address(device, &ctx->noalloc) != hipSuccess) {
+        delete ctx;
+        return EM_ERR_HIP;
+    }
     if (hipMalloc(&ctx->counters, kNumCounters * sizeof(unsigned int)) != hipSuccess) {
         delete ctx;
         return EM_ERR_OUT_OF_MEMORY;
@@ -280,7 +330,7 @@ extern "C" const char *em_status_string(em_status_t s) {
     return "EM_ERR_UNKNOWN";
 }
 
-extern "C" const char *em_last_error(em_handle_t h) { return h ? h->last_error.c_str() : ""; }
+extern "C" const char *em_last_error(em_handle_t h) { return h ? h->last_error : ""; }
 
 extern "C" em_status_t em_sync(em_handle_t h, void *stream) {
     if (!h) return EM_ERR_INVALID_ARG;
@@ -323,7 +373,7 @@ static constexpr int kFewRounds = 4;
 // for a short queue in tolerance mode (total pixels of the group >= 0 and
 // below kFewRounds rounds) the most coordinate waves compiled.
 static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solver, int64_t total = -1,
-                                         bool tolerance = false) {
+                                         bool tolerance = false, bool cache = true) {
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
         NlemKernelInfo k = nlem_kernel(pr, m, atoi(env), solver);
@@ -336,7 +386,7 @@ static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solve
     }
     NlemKernelInfo k = nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
     if (k.fn && tolerance && total >= 0 &&
-        total < (int64_t)kFewRounds * h->num_cus * blocks_per_cu(h, k.fn, k.threads)) {
+        total < (int64_t)kFewRounds * h->num_cus * blocks_per_cu(h, k.fn, k.threads, cache)) {
         for (int wc = 4; wc > 0; --wc) {
             const NlemKernelInfo x = nlem_kernel(pr, m, wc, solver);
             if (x.fn) {
@@ -654,6 +704,55 @@ extern "C" em_status_t nlem_denoise(em_handle_t h, void *stream, const void *img
     if (st != EM_OK) return st;
     EMX_HIP(h, hipSetDevice(h->device));
     return nlem_run(h, static_cast<hipStream_t>(stream), 1, &im, o);
+}
+
+extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const void *img, int32_t img_is_f16,
+                                            int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
+                                            float h_param, float lo, float hi, float rho, int32_t max_iter,
+                                            float tol, float *out, em_stats_t *stats) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    nlem_image_t im{img, out, stats, H, W, patch_radius, window_radius, h_param, img_is_f16};
+    em_status_t st = check_image(h, im);
+    if (st != EM_OK) return st;
+    const nlem_options_t o = admm_options(lo, hi, rho, max_iter, tol);
+    st = check_options(h, &o);
+    if (st != EM_OK) return st;
+    const int64_t total = (int64_t)H * W;
+    if (total > (int64_t)EM_NOALLOC_MAX_PIXELS)
+        return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: H * W above EM_NOALLOC_MAX_PIXELS");
+    if (!h->noalloc) return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: no scratch for this device index");
+    EMX_HIP(h, hipSetDevice(h->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const NlemGroup g{patch_radius, points_per_lane(window_radius), {}};   // no images listed: no allocation
+    const NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM, total,
+                                                max_iter > 0 && tol > 0.0f, /*cache=*/false);
+    if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape");
+    char *scr = static_cast<char *>(h->noalloc);
+    unsigned int *counter = reinterpret_cast<unsigned int *>(scr);
+    NlemLaunch L;
+    memset(&L, 0, sizeof(L));
+    fill_common(L, o);
+    L.count = 1;
+    L.img[0] = make_desc(im);
+    L.prefix[0] = 0;
+    L.prefix[1] = total;
+    L.counter = counter;
+    st = ctx_reset_counters(h, s, counter, 1);
+    if (st != EM_OK) return st;
+    const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads, /*cache=*/false);
+    L.chunk = queue_chunk(g, total, cap);
+    if (use_order(order_enabled(o), g.pr, total, cap)) {
+        if (kScratchHeadBytes + nlem_order_bytes(total) > kScratchBytes)
+            return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: order scratch too small");
+        const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, scr + kScratchHeadBytes);
+        st = queue_order(h, s, A);   // its first kernel clears the bucket counters
+        if (st != EM_OK) return st;
+        L.order = A.order;
+    }
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
+    void *args[] = {&L};
+    EMX_HIP(h, hipLaunchKernel(k.fn, dim3(grid), dim3(k.threads), args, 0, s));
+    return EM_OK;
 }
 
 extern "C" em_status_t nlem_denoise_ex(em_handle_t h, void *stream, int32_t count,
