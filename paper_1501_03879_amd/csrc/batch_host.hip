@@ -3,6 +3,7 @@
 // baseline (literal Algorithm 1 with the iterates in device memory).
 #include <float.h>
 
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -27,9 +28,9 @@ em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fo
 // and class): a million instances over twenty counters would otherwise
 // serialise on the hot ones.
 __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t *inst, int64_t B, float *z,
-                                                            em_stats_t *stats, unsigned int *counts) {
-    __shared__ unsigned int hist[kNumClasses];
-    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x) hist[i] = 0u;
+                                                            em_stats_t *stats, unsigned int *counts, int wide) {
+    __shared__ unsigned int hist[kNumAllClasses];
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b < B) {
@@ -41,22 +42,22 @@ __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t 
                 for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
             if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
         } else {
-            atomicAdd(&hist[class_of(e.n, e.d)], 1u);
+            atomicAdd(&hist[class_of(e.n, e.d, wide != 0)], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x)
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x)
         if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
 __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *offsets) {
     if (threadIdx.x == 0) {
         unsigned int s = 0;
-        for (int c = 0; c < kNumClasses; ++c) {
+        for (int c = 0; c < kNumAllClasses; ++c) {
             offsets[c] = s;
             s += counts[c];
         }
-        offsets[kNumClasses] = s;
+        offsets[kNumAllClasses] = s;
     }
 }
 
@@ -64,10 +65,10 @@ __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *of
 // (block, class) reserves the block's range of the class list.
 __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_t *inst, int64_t B,
                                                               const unsigned int *offsets, unsigned int *fill,
-                                                              int32_t *list) {
-    __shared__ unsigned int lcnt[kNumClasses];
-    __shared__ unsigned int lbase[kNumClasses];
-    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x) lcnt[i] = 0u;
+                                                              int32_t *list, int wide) {
+    __shared__ unsigned int lcnt[kNumAllClasses];
+    __shared__ unsigned int lbase[kNumAllClasses];
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) lcnt[i] = 0u;
     __syncthreads();
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int c = -1;
@@ -75,15 +76,21 @@ __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_
     if (b < B) {
         const em_instance_t e = inst[b];
         if (e.n > 0 && e.n <= EM_MAX_N && e.d >= 1 && e.d <= EM_MAX_D) {
-            c = class_of(e.n, e.d);
+            c = class_of(e.n, e.d, wide != 0);
             rank = atomicAdd(&lcnt[c], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kNumClasses; i += blockDim.x)
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x)
         lbase[i] = lcnt[i] ? atomicAdd(&fill[i], lcnt[i]) : 0u;
     __syncthreads();
     if (c >= 0) list[offsets[c] + lbase[c] + rank] = (int32_t)b;
+}
+
+// EMX_BATCH_WIDE=0 keeps every instance on the generic classes (for comparison).
+static bool wide_disabled() {
+    const char *e = getenv("EMX_BATCH_WIDE");
+    return e && e[0] == '0' && e[1] == '\0';
 }
 
 em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
@@ -93,16 +100,18 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     int32_t *list = static_cast<int32_t *>(ctx_workspace(ctx, (size_t)B * sizeof(int32_t), &st));
     if (!list) return st;
     // counters: [0, K) class counts, [K, 2K+1) offsets, [2K+1, 3K+1) fill, [3K+1, 4K+1) queue heads
-    unsigned int *cnt = ctx_counters(ctx, 4 * kNumClasses + 1);
+    constexpr int K = kNumAllClasses;
+    unsigned int *cnt = ctx_counters(ctx, 4 * K + 1);
     if (!cnt) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
-    unsigned int *counts = cnt, *offsets = cnt + kNumClasses, *fill = cnt + 2 * kNumClasses + 1,
-                 *heads = cnt + 3 * kNumClasses + 1;
-    st = ctx_reset_counters(ctx, s, cnt, 4 * kNumClasses + 1);
+    unsigned int *counts = cnt, *offsets = cnt + K, *fill = cnt + 2 * K + 1, *heads = cnt + 3 * K + 1;
+    st = ctx_reset_counters(ctx, s, cnt, 4 * K + 1);
     if (st != EM_OK) return st;
+    // fixed-penalty EM-ADMM over a box: d > 16, n <= 448 go to the sliced kernel
+    const int wide = (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX && !wide_disabled()) ? 1 : 0;
     const unsigned nb = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts);
+    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, wide);
     hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
-    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list);
+    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, wide);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
     const bool ball = o.set == EM_SET_BALL;
@@ -116,8 +125,9 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     const bool vbox = ball || o.box_lo != nullptr;
     // The classes run concurrently on the caller's stream and the handle's
     // side streams (fork after the classification, join before returning), so
-    // one class's tail overlaps the others' work.  Class c goes to stream
-    // c mod 4: the four n-classes of a d-family land on different streams.
+    // one class's tail overlaps the others' work.  The launched classes go to
+    // the four streams in turn: neighbouring n-classes of a d-family land on
+    // different streams.
     hipStream_t *side;
     hipEvent_t fork, *join;
     st = ctx_side_streams(ctx, &side, &fork, &join);
@@ -125,8 +135,12 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     e = hipEventRecord(fork, s);
     for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the class streams");
-    for (int c = 0; c < kNumClasses; ++c) {
-        const int si = c % (kSideStreams + 1);
+    const ClassKernel *wtab = batch_wide_table();
+    int launched = 0;
+    for (int c = 0; c < K; ++c) {
+        if (c >= kNumClasses ? !wide : (wide && class_unused_with_wide(c))) continue;
+        const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
+        const int si = launched++ % (kSideStreams + 1);
         hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L;
         memset(&L, 0, sizeof(L));
@@ -156,10 +170,10 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         L.init = o.init;
         L.cls = c;
         L.a16 = o.points_f16 ? 1 : 0;
-        const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, tab[c].fn, tab[c].threads);
+        const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, ck.fn, ck.threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
         void *args[] = {&L};
-        e = hipLaunchKernel(tab[c].fn, dim3(grid), dim3(tab[c].threads), args, 0, cs);
+        e = hipLaunchKernel(ck.fn, dim3(grid), dim3(ck.threads), args, 0, cs);
         if (e != hipSuccess) return ctx_hip_error(ctx, e, "batch class launch");
     }
     for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) {

@@ -66,6 +66,31 @@ __host__ __device__ inline int class_of(int n, int d) {
     return 4 + (wc - 1) * 4 + k;
 }
 
+// Classes of the sliced EM-ADMM kernel (batch_wide.hpp; fixed penalty over a
+// box): d in (16, 64] and n <= 448 go to 13-coordinate slices over
+// WC = ceil(d / 13) in [2, 5] waves with M = ceil(n / 64) in [1, 7] points
+// per lane.  Their ids follow the kNumClasses classes above.
+constexpr int kWideNJ = 13;
+constexpr int kWideMaxM = 7;
+constexpr int kWideMinWC = 2, kWideMaxWC = 5;
+constexpr int kNumWideClasses = (kWideMaxWC - kWideMinWC + 1) * kWideMaxM;
+constexpr int kNumAllClasses = kNumClasses + kNumWideClasses;
+
+__host__ __device__ inline int class_of(int n, int d, bool wide) {
+    if (wide && d > 16 && n <= 64 * kWideMaxM) {
+        const int wc = (d + kWideNJ - 1) / kWideNJ;
+        const int m = (n + 63) / 64;
+        return kNumClasses + (wc - kWideMinWC) * kWideMaxM + (m - 1);
+    }
+    return class_of(n, d);
+}
+
+// With the sliced classes in use, the classes above that only take d > 16 and
+// n <= 256 never receive an instance.
+__host__ __device__ constexpr bool class_unused_with_wide(int c) {
+    return c >= 8 && c < kNumClasses && (c - 4) % 4 != 3;
+}
+
 // Kernel arguments of one class launch.
 struct ClassLaunch {
     const float *a;               // points (FP32, or FP16 when a16)
@@ -229,6 +254,9 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             } else {
                 best = uniform_int((int)pmin);
             }
+            // no weight >= 0 at all leaves no candidate: the instance is bad
+            // (NaN z below) and the clamp only keeps the read inside it
+            best = min(max(best, 0), n - 1);
         }
 
         // ---- WMEAN init: sum_k w_k a_k / sum_k w_k, the weights scaled by their
@@ -958,5 +986,6 @@ const ClassKernel *batch_class_table_admm_ball();
 const ClassKernel *batch_class_table_irls_ball();
 const ClassKernel *batch_class_table_wpen();
 const ClassKernel *batch_class_table_wpen_ball();
+const ClassKernel *batch_wide_table();   // kNumWideClasses entries
 
 }  // namespace emx

@@ -1,0 +1,29 @@
+// Shape classes of the batched EM-ADMM for d in (16, 64] and n <= 448
+// (fixed penalty, box): 13-coordinate slices, WC = ceil(d / 13) waves,
+// M = ceil(n / 64) points per lane.
+#include "batch_wide.hpp"
+
+namespace emx {
+
+// Waves per SIMD the launch bound asks for (its second argument): as many as
+// the registers of M points allow (state and points of a 13-coordinate
+// slice take ~26 M VGPRs, the rest ~70).
+constexpr int wide_waves_per_simd(int m) { return m <= 1 ? 6 : m <= 2 ? 4 : m <= 3 ? 3 : 2; }
+
+template <int C>
+constexpr ClassKernel wide_kernel() {
+    constexpr int wc = kWideMinWC + C / kWideMaxM;
+    constexpr int m = 1 + C % kWideMaxM;
+    return ClassKernel{
+        reinterpret_cast<const void *>(&batch_wide_kernel<kWideNJ, m, wc, wide_waves_per_simd(m)>), 64 * wc};
+}
+
+template <int... C>
+const ClassKernel *wide_table(std::integer_sequence<int, C...>) {
+    static const ClassKernel t[kNumWideClasses] = {wide_kernel<C>()...};
+    return t;
+}
+
+const ClassKernel *batch_wide_table() { return wide_table(std::make_integer_sequence<int, kNumWideClasses>{}); }
+
+}  // namespace emx

@@ -1,0 +1,350 @@
+// Batched EM-ADMM (Algorithm 1 of arXiv:1501.03879) for point sets of
+// d in (16, 64] and n <= 448 with a fixed penalty over a box: one workgroup
+// of WC waves per instance, the instance's coordinates cut into slices of NJ
+// (wave cw owns coordinates [cw NJ, cw NJ + NJ)), its points into M per lane
+// (lane l owns points l + 64 q, q < M).  Slices and point slots are sized to
+// the instance (d = 49: 4 x 13 coordinates, n = 441: 7 x 64 slots), so the
+// points and the iteration state fill the registers of four waves and two
+// instances share a CU.
+//
+//  * Staging: 64 points at a time go through LDS (one row of d values per
+//    lane group, coalesced), every lane then takes its slice of its point.
+//  * Iteration (same iterates as Algorithm 1; see the NLEM kernel for the
+//    reduced form): with g = e - a per point coordinate and c = 2 z^t -
+//    z^{t-1},
+//      pass 1:  delta = g + c,  partial ||delta||^2 over the slice
+//      the WC partials summed through LDS, s = min(1, lambda / nu)
+//      pass 2:  E += s delta,  g = s delta - a
+//      a full 64-lane reduce-scatter leaves E of one slice coordinate per
+//      lane; that lane updates z = clamp(z - E / n, lo_j, hi_j) and hands
+//      c to the wave through LDS.
+//  * Stop: primal and dual residuals <= tol D, the primal one evaluated on
+//    iterations after one whose dual residual was within tol D (and on the
+//    last allowed one) and tested right after them.
+#pragma once
+
+#include <float.h>
+#include <hip/hip_fp16.h>
+
+#include "batch_kernel.hpp"
+
+namespace emx {
+
+template <int NJ, int M, int WC>
+struct WideShape {
+    static constexpr int THREADS = 64 * WC;
+    static constexpr int STAGE = 64 * 65;       // 64 points x pitch (d | 1) <= 65
+    static constexpr int XN = 2 * WC * M * 64;  // norm partials, two buffers by iteration parity
+};
+
+template <int NJ, int M, int WC, int WAVES_PER_SIMD>
+__global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(ClassLaunch L) {
+    using S = WideShape<NJ, M, WC>;
+    using RSx = RSF<NJ>;
+    __shared__ float stage[S::STAGE];
+    __shared__ float xn[S::XN];
+    __shared__ float xs[3 * WC * 4];   // per-wave residual partials: two buffers + the armed test
+    __shared__ float cvec[WC * 128];   // per wave: c of the slice [0, NJ); private slots [64, 128)
+    __shared__ unsigned int item_s;
+    __shared__ int flag_s[4];
+
+    const int lane = threadIdx.x & 63;
+    const int cw = uniform_int(threadIdx.x >> 6);
+    const bool holds = (RSx::mask() >> lane) & 1;   // lane holds a slice coordinate after the reduce-scatter
+    const int myc = RSx::coord(lane);
+    float *cv = cvec + cw * 128;
+    const int cidx = holds ? myc : 64 + lane;
+    const unsigned int cbeg = L.offsets[L.cls];
+    const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
+    const bool vbox = L.box_lo != nullptr;
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            item_s = atomicAdd(L.counter, 1u);
+            flag_s[0] = 0;  // a point or weight is bad
+            flag_s[1] = 0;  // max |a| (float bits, non-negative)
+            flag_s[2] = 0;  // the starting z or the box is bad
+            flag_s[3] = 0;  // widest box interval (float bits, non-negative)
+        }
+        __syncthreads();
+        const unsigned int it = (unsigned int)uniform_int((int)item_s);
+        if (it >= ccount) break;
+        const int b = uniform_int(L.list[cbeg + it]);
+        const em_instance_t e = L.inst[b];
+        const int n = uniform_int(e.n), d = uniform_int(e.d);
+        const float *A = L.a + e.a_off;
+        const __half *A16 = reinterpret_cast<const __half *>(L.a) + e.a_off;
+        const float *Wt = L.w + e.w_off;
+        float *Z = L.z + e.z_off;
+        const int pitch = d | 1;
+        const int j0 = cw * NJ;                  // first coordinate of the slice
+        const int cj = j0 + myc;                 // the coordinate this lane owns after the reduce-scatter
+        const bool own = holds && cj < d;
+
+        // ---- stage the points (64 at a time through LDS; wave w copies rows
+        // w, w + WC, ... one value per lane) and keep the lane's slice as -a
+        float na[M][NJ];
+        float lam[M];
+        bool bad_l = false;
+        float amax = 0.0f;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int p0 = q * 64;
+            const int cnt = max(0, min(64, n - p0));
+            if (q > 0) __syncthreads();   // the previous chunk has been read
+            for (int r = cw; r < cnt; r += WC) {
+                if (lane < d) {
+                    const int64_t src = (int64_t)(p0 + r) * d + lane;
+                    stage[r * pitch + lane] = L.a16 ? __half2float(A16[src]) : A[src];
+                }
+            }
+            __syncthreads();
+            const int p = p0 + lane;
+            const bool vp = p < n;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int j = j0 + jj;
+                const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
+                bad_l |= !(fabsf(v) <= FLT_MAX);
+                amax = fmaxf(amax, fabsf(v));
+                na[q][jj] = -v;
+            }
+            const float wv = vp ? Wt[p] : 0.0f;
+            bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
+            lam[q] = vp ? wv : -1.0f;   // the weight for now (-1: no point)
+        }
+        const float wamax = wave_max(amax);
+        if (__any(bad_l) && lane == 0) flag_s[0] = 1;
+        if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
+
+        // ---- starting z of the owned coordinate
+        float zr = 0.0f;
+        if (L.init == EM_INIT_MAXW) {
+            // the point of largest weight, lowest index on ties (every wave
+            // holds all the weights, so no exchange is needed)
+            float wb = -1.0f;
+            int pb = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+                if (lam[q] > wb) wb = lam[q], pb = q * 64 + lane;
+            const float wm = wave_max(wb);
+            const float cand = (wb == wm) ? (float)pb : 3.0e38f;
+            // (no weight >= 0 at all leaves no candidate: the instance is bad
+            // and the clamp only keeps the read inside it)
+            const int best = min(uniform_int((int)(-wave_max(-cand))), n - 1);
+            if (own) zr = L.a16 ? __half2float(A16[(int64_t)best * d + cj]) : A[(int64_t)best * d + cj];
+        } else if (L.init == EM_INIT_WMEAN) {
+            // sum_k w_k a_k / sum_k w_k, weights scaled by their largest value and
+            // points by 1/n (no overflow); every weight zero: equal weights
+            float wl = 0.0f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) wl = fmaxf(wl, lam[q]);
+            const float wmx = readfirstlane(wave_max(wl));
+            const bool uni = !(wmx > 0.0f);
+            const float sw = uni ? 0.0f : 1.0f / wmx;
+            const float inv_n = 1.0f / (float)n;
+            float cq[M];
+            float cs = 0.0f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) {
+                cq[q] = (lam[q] >= 0.0f) ? (uni ? 1.0f : lam[q] * sw) * inv_n : 0.0f;
+                cs += cq[q];
+            }
+            float acc[NJ];
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                float ac = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) ac = fmaf(-cq[q], na[q][jj], ac);   // na = -a
+                acc[jj] = ac;
+            }
+            const float sum = reduce_scatter_full<NJ>(acc, lane, holds);
+            const float Cs = readfirstlane(wave_sum(cs));
+            if (own) zr = sum * (1.0f / Cs);
+        } else {
+            if (own) zr = Z[cj];
+        }
+        float blo = 0.0f, bhi = 0.0f;
+        bool zbad = false;
+        float wid = 0.0f;
+        if (own) {
+            blo = vbox ? L.box_lo[e.z_off + cj] : L.lo;
+            bhi = vbox ? L.box_hi[e.z_off + cj] : L.hi;
+            zbad = !(fabsf(zr) <= FLT_MAX) || !(blo <= bhi);
+            wid = bhi - blo;
+            if (!(wid >= 0.0f)) wid = 0.0f;
+        }
+        const float wwid = wave_max(wid);
+        if (__any(zbad) && lane == 0) flag_s[2] = 1;
+        if (lane == 0) atomicMax(&flag_s[3], __float_as_int(wwid));
+        cv[cidx] = zr;   // c = z; slots of coordinates >= d hold 0 (zr = 0, never updated)
+        __syncthreads();
+        const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
+        const float wmax = readfirstlane(__int_as_float(flag_s[3]));
+        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f)
+                                 ? wmax : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
+        const float tau = L.tol * Dscale;
+        const float tau2 = tau * tau;
+        const float arm2 = (L.arm * tau) * (L.arm * tau);
+        __syncthreads();   // flags are reset by the next pop
+
+        int iters = 0, flags = EM_MAXITER;
+        float rp2 = 0.0f, rd2 = 0.0f;
+        if (bad_all) {
+            flags = EM_BAD_INPUT;
+        } else {
+            const float inv_mu = 1.0f / L.mu;
+#pragma unroll
+            for (int q = 0; q < M; ++q) lam[q] = (lam[q] >= 0.0f) ? lam[q] * inv_mu : 0.0f;
+            float g[M][NJ];
+#pragma unroll
+            for (int q = 0; q < M; ++q)
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) g[q][jj] = na[q][jj];
+            const float inv_n = 1.0f / (float)n;
+            const float fn = (float)n;
+            const float inv_d = 1.0f / (float)d;
+            const float inv_nd = 1.0f / (fn * (float)d);
+            const int max_iter = L.max_iter;
+            float zp = zr;      // z^{t-1}
+            float Ep = 0.0f;    // E^t
+            float rd_w = 0.0f, rp_w = 0.0f;
+            bool done = false;
+            for (int t = 1; t <= max_iter; ++t) {
+                // ---- pass 1: delta = g + c, partial ||delta||^2
+                float nrm[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) nrm[q] = kNu2Floor;
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    const float c = cv[jj];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        g[q][jj] += c;
+                        nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                    }
+                }
+                // ---- the slices' partials summed (in wave order, identical in
+                // every wave), with the dual residual of iteration t-1
+                float rd_all = rd_w;
+                if constexpr (WC > 1) {
+                    float *X = xn + (t & 1) * WC * M * 64;
+                    float *XS = xs + (t & 1) * WC * 4;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) X[(cw * M + q) * 64 + lane] = nrm[q];
+                    if (lane == 0) XS[cw * 4] = rd_w;
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        float sum = X[q * 64 + lane];
+#pragma unroll
+                        for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
+                        nrm[q] = sum;
+                    }
+                    rd_all = XS[0];
+#pragma unroll
+                    for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
+                    rd_all = readfirstlane(rd_all);
+                }
+                if (t > 1) rd2 = rd_all * inv_d;
+                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
+                float s[M];
+#pragma unroll
+                for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
+                // ---- armed iterations: lane sums of ||x_k - c||^2 with
+                // x_k = a_k + (1 - s) delta (absent points and padded
+                // coordinates give exactly 0)
+                float rp_lane = 0.0f;
+                if (armed) {
+                    float rq[M];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rq[q] = 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj < NJ; ++jj) {
+                        const float c = cv[jj];
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            const float y = fmaf(1.0f - s[q], g[q][jj], -(na[q][jj] + c));
+                            rq[q] = fmaf(y, y, rq[q]);
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rp_lane += rq[q];
+                }
+                // ---- pass 2: E = sum_k s delta, g = s delta - a
+                float acc[NJ];
+#pragma unroll
+                for (int jj = 0; jj < NJ; ++jj) {
+                    float ac = 0.0f;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) {
+                        const float dl = g[q][jj];
+                        ac = fmaf(s[q], dl, ac);
+                        g[q][jj] = fmaf(s[q], dl, na[q][jj]);
+                    }
+                    acc[jj] = ac;
+                }
+                // keep the new state materialised here (not sunk past the reductions)
+#pragma unroll
+                for (int q = 0; q < M; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < NJ; ++jj) asm volatile("" : "+v"(g[q][jj]));
+                // ---- reduce-scatter; z-update of the owned coordinate
+                const float Ev = reduce_scatter_full<NJ>(acc, lane, holds);
+                const float zn = own ? clampf(fmaf(-Ev, inv_n, zr), blo, bhi) : 0.0f;
+                const float dz = zn - zr;
+                cv[cidx] = zn + dz;
+                rd_w = readfirstlane(wave_sum(dz * dz));
+                const float cz = (2.0f * zr - zp) - zn;   // c - z' (0 on lanes without a coordinate)
+                zp = zr;
+                zr = zn;
+                if (armed) {
+                    // sum_k ||x_k - z'||^2 = sum_k ||x_k - c||^2 + 2 (c - z') . sum_k (x_k - c)
+                    // + n ||c - z'||^2, with sum_k (x_k - c) = E^t - E^{t+1}
+                    const float rpx = own ? cz * fmaf(fn, cz, 2.0f * (Ep - Ev)) : 0.0f;
+                    rp_w = readfirstlane(wave_sum(rp_lane + rpx));
+                    float rd_t = rd_w, rp_t = rp_w;
+                    if constexpr (WC > 1) {
+                        float *XS = xs + 2 * WC * 4;   // its own slot: armed iterations only
+                        if (lane == 0) {
+                            XS[cw * 4 + 0] = rd_w;
+                            XS[cw * 4 + 1] = rp_w;
+                        }
+                        __syncthreads();
+                        rd_t = XS[0];
+                        rp_t = XS[1];
+#pragma unroll
+                        for (int w = 1; w < WC; ++w) {
+                            rd_t += XS[w * 4 + 0];
+                            rp_t += XS[w * 4 + 1];
+                        }
+                        rd_t = readfirstlane(rd_t);
+                        rp_t = readfirstlane(rp_t);
+                    }
+                    rd2 = rd_t * inv_d;
+                    rp2 = fmaxf(rp_t, 0.0f) * inv_nd;
+                    if (uniform(tau2 > 0.0f && rp2 <= tau2 && rd2 <= tau2)) {
+                        flags = EM_CONVERGED;
+                        iters = t;
+                        done = true;
+                        break;
+                    }
+                }
+                Ep = Ev;
+            }
+            if (!done) iters = max_iter;   // the last iteration was armed and tested
+        }
+        // ---- write z and the statistics
+        if (own) Z[cj] = bad_all ? __builtin_nanf("") : zr;
+        if (cw == 0 && lane == 0 && L.stats != nullptr) {
+            em_stats_t st;
+            st.iters = bad_all ? 0 : iters;
+            st.flags = flags;
+            st.r_pri = bad_all ? 0.0f : sqrtf(rp2);
+            st.r_dual = bad_all ? 0.0f : sqrtf(rd2);
+            L.stats[b] = st;
+        }
+    }
+}
+
+}  // namespace emx
