@@ -6,16 +6,20 @@
 namespace emx {
 
 // Waves per SIMD the launch bound asks for (its second argument): as many as
-// the registers of M points allow (state and points of a 13-coordinate
-// slice take ~26 M VGPRs, the rest ~70).
-constexpr int wide_waves_per_simd(int m) { return m <= 1 ? 6 : m <= 2 ? 4 : m <= 3 ? 3 : 2; }
+// the registers allow: ~26 M VGPRs for the state and points of M points of a
+// 13-coordinate slice, 64 / WC for a chunk's staging loads, ~60 for the rest.
+constexpr int wide_waves_per_simd(int m, int wc) {
+    const int regs = 26 * m + 60 + 64 / wc;
+    const int w = 512 / regs;
+    return w > 6 ? 6 : (w < 2 ? 2 : w);
+}
 
 template <int C>
 constexpr ClassKernel wide_kernel() {
     constexpr int wc = kWideMinWC + C / kWideMaxM;
     constexpr int m = 1 + C % kWideMaxM;
     return ClassKernel{
-        reinterpret_cast<const void *>(&batch_wide_kernel<kWideNJ, m, wc, wide_waves_per_simd(m)>), 64 * wc};
+        reinterpret_cast<const void *>(&batch_wide_kernel<kWideNJ, m, wc, wide_waves_per_simd(m, wc)>), 64 * wc};
 }
 
 template <int... C>

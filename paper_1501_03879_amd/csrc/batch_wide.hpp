@@ -8,7 +8,9 @@
 // instances share a CU.
 //
 //  * Staging: 64 points at a time go through LDS (one row of d values per
-//    lane group, coalesced), every lane then takes its slice of its point.
+//    load, coalesced; a chunk's loads all issued at once and the next
+//    chunk's in flight while this one is read back), every lane then takes
+//    its slice of its point.
 //  * Iteration (same iterates as Algorithm 1; see the NLEM kernel for the
 //    reduced form): with g = e - a per point coordinate and c = 2 z^t -
 //    z^{t-1},
@@ -36,6 +38,56 @@ struct WideShape {
     static constexpr int STAGE = 64 * 65;       // 64 points x pitch (d | 1) <= 65
     static constexpr int XN = 2 * WC * M * 64;  // norm partials, two buffers by iteration parity
 };
+
+// Stage one instance's points (FP32 or FP16 storage, T) into registers: the
+// workgroup's waves load whole rows of d values (wave cw rows cw + WC k of
+// each 64-point chunk, one value per lane, coalesced), the loads of up to LA
+// chunks in flight at once (all of them for WC >= 4), the next chunk issued
+// as soon as one has been read back; chunk by chunk the rows go through LDS
+// and every lane keeps its slice of its point as -a.  Loads past the instance
+// read its element 0 (no branches, so nothing waits early); those rows are
+// staged but never read back.
+template <int NJ, int M, int WC, typename T>
+__device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, int lane, int j0, float *stage,
+                                             float (&na)[M][NJ], float &amax, bool &bad) {
+    constexpr int RK = (64 + WC - 1) / WC;                 // rows per wave and chunk
+    constexpr int LA0 = 112 / RK;                          // ~112 VGPRs of loads in flight
+    constexpr int LA = LA0 < 1 ? 1 : (LA0 > M ? M : LA0);
+    const int pitch = d | 1;
+    const int step = WC * d;
+    T raw[LA][RK];
+    auto issue = [&](int q) {
+        const int off0 = (q * 64 + cw) * d + lane;
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            const int r = cw + WC * k;
+            const bool v = r < 64 && q * 64 + r < n && lane < d;
+            raw[q % LA][k] = A[v ? off0 + k * step : 0];
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < LA; ++q) issue(q);
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        if (q > 0) __syncthreads();   // the previous chunk has been read back
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            const int r = cw + WC * k;
+            if (r < 64 && lane < d) stage[r * pitch + lane] = (float)raw[q % LA][k];
+        }
+        if (q + LA < M) issue(q + LA);
+        __syncthreads();
+        const bool vp = q * 64 + lane < n;
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            const int j = j0 + jj;
+            const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
+            bad |= !(fabsf(v) <= FLT_MAX);
+            amax = fmaxf(amax, fabsf(v));
+            na[q][jj] = -v;
+        }
+    }
+}
 
 template <int NJ, int M, int WC, int WAVES_PER_SIMD>
 __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(ClassLaunch L) {
@@ -76,48 +128,24 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
         const __half *A16 = reinterpret_cast<const __half *>(L.a) + e.a_off;
         const float *Wt = L.w + e.w_off;
         float *Z = L.z + e.z_off;
-        const int pitch = d | 1;
         const int j0 = cw * NJ;                  // first coordinate of the slice
         const int cj = j0 + myc;                 // the coordinate this lane owns after the reduce-scatter
         const bool own = holds && cj < d;
 
-        // ---- stage the points (64 at a time through LDS; wave w copies rows
-        // w, w + WC, ... one value per lane) and keep the lane's slice as -a
-        float na[M][NJ];
+        // ---- weights of the lane's points, and (largest-weight start) the
+        // chosen point, before the points: their loads overlap the staging
         float lam[M];
         bool bad_l = false;
-        float amax = 0.0f;
 #pragma unroll
         for (int q = 0; q < M; ++q) {
-            const int p0 = q * 64;
-            const int cnt = max(0, min(64, n - p0));
-            if (q > 0) __syncthreads();   // the previous chunk has been read
-            for (int r = cw; r < cnt; r += WC) {
-                if (lane < d) {
-                    const int64_t src = (int64_t)(p0 + r) * d + lane;
-                    stage[r * pitch + lane] = L.a16 ? __half2float(A16[src]) : A[src];
-                }
-            }
-            __syncthreads();
-            const int p = p0 + lane;
-            const bool vp = p < n;
-#pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) {
-                const int j = j0 + jj;
-                const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
-                bad_l |= !(fabsf(v) <= FLT_MAX);
-                amax = fmaxf(amax, fabsf(v));
-                na[q][jj] = -v;
-            }
-            const float wv = vp ? Wt[p] : 0.0f;
+            // unconditional loads (slots past n read weight 0, then drop it):
+            // no branch, so all of them are in flight together
+            const int p = q * 64 + lane;
+            const float wr = Wt[min(p, n - 1)];
+            const float wv = (p < n) ? wr : 0.0f;
             bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
-            lam[q] = vp ? wv : -1.0f;   // the weight for now (-1: no point)
+            lam[q] = (p < n) ? wv : -1.0f;   // the weight for now (-1: no point)
         }
-        const float wamax = wave_max(amax);
-        if (__any(bad_l) && lane == 0) flag_s[0] = 1;
-        if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
-
-        // ---- starting z of the owned coordinate
         float zr = 0.0f;
         if (L.init == EM_INIT_MAXW) {
             // the point of largest weight, lowest index on ties (every wave
@@ -133,7 +161,31 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
             // and the clamp only keeps the read inside it)
             const int best = min(uniform_int((int)(-wave_max(-cand))), n - 1);
             if (own) zr = L.a16 ? __half2float(A16[(int64_t)best * d + cj]) : A[(int64_t)best * d + cj];
-        } else if (L.init == EM_INIT_WMEAN) {
+        } else if (L.init == EM_INIT_GIVEN) {
+            if (own) zr = Z[cj];
+        }
+        float blo = L.lo, bhi = L.hi;
+        if (own && vbox) {
+            blo = L.box_lo[e.z_off + cj];
+            bhi = L.box_hi[e.z_off + cj];
+        }
+
+        // ---- stage the points, 64 at a time through LDS: wave w copies rows
+        // w, w + WC, ... of a chunk (one row of d values per load, all of a
+        // chunk's loads issued together, the next chunk's loads in flight
+        // while this one is read back); every lane then keeps its slice of
+        // its point as -a
+        float na[M][NJ];
+        float amax = 0.0f;
+        if (L.a16)
+            stage_points<NJ, M, WC>(A16, n, d, cw, lane, j0, stage, na, amax, bad_l);
+        else
+            stage_points<NJ, M, WC>(A, n, d, cw, lane, j0, stage, na, amax, bad_l);
+        const float wamax = wave_max(amax);
+        if (__any(bad_l) && lane == 0) flag_s[0] = 1;
+        if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
+
+        if (L.init == EM_INIT_WMEAN) {
             // sum_k w_k a_k / sum_k w_k, weights scaled by their largest value and
             // points by 1/n (no overflow); every weight zero: equal weights
             float wl = 0.0f;
@@ -161,15 +213,10 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
             const float sum = reduce_scatter_full<NJ>(acc, lane, holds);
             const float Cs = readfirstlane(wave_sum(cs));
             if (own) zr = sum * (1.0f / Cs);
-        } else {
-            if (own) zr = Z[cj];
         }
-        float blo = 0.0f, bhi = 0.0f;
         bool zbad = false;
         float wid = 0.0f;
         if (own) {
-            blo = vbox ? L.box_lo[e.z_off + cj] : L.lo;
-            bhi = vbox ? L.box_hi[e.z_off + cj] : L.hi;
             zbad = !(fabsf(zr) <= FLT_MAX) || !(blo <= bhi);
             wid = bhi - blo;
             if (!(wid >= 0.0f)) wid = 0.0f;
