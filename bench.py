@@ -1,19 +1,26 @@
-"""Benchmark: Non-Local Euclidean Medians on one MI355X.
+"""Benchmark: Non-Local Euclidean Medians and the batched Euclidean-median
+solver on one MI355X.
 
 One step = nlem_denoise over the whole 256 x 256 synthetic image (sigma 20,
 patch 7x7 so d = 49, window 21x21 so n <= 441, h = 10 sigma, box [0, 255],
 mu = 1e-3, primal/dual residual 1e-4 relative to 255 or 200 iterations):
 staging, weights, per-pixel EM-ADMM and the centre-pixel output all run in
-the library's kernels.  Every pixel is one EM solve.
+the library's kernels; `value` is its rate in Mpixel/s.
 
-Reported: EM solves/s (= pixels/s) of the batched persistent kernel, the
-roofline of that kernel on the FP32 FLOP model (6 flop per point-coordinate
-per iteration plus 3 per point-coordinate for the weights), em_solve_batch
-over the interior pixels' materialised windows (n = 441, d = 49 exactly),
-the plain one-launch-per-instance path on 64 of them (batched vs plain),
-and the FP64 oracle timed on this host's cores on a bounded pixel sample.
+Also in the line: em_solves_per_s_n441_d49, em_solve_batch over the 55,696
+interior pixels' materialised windows (n = 441, d = 49 exactly), with the
+plain one-instance-per-launch path on the same instances (speedup_vs_plain)
+and FP64-oracle error on sampled instances; the roofline of the NLEM kernel
+on the FP32 FLOP model (6 flop per point coordinate per iteration plus 3
+per point coordinate for the weights); one sub-record per workload in
+`configs` (64 x 64 with 50 fixed iterations, the 256 x 256 step, 512 x 512
+mixed noise with FP32 and FP16 storage, 16 images in one graph, 1,048,576
+point sets), each with its time, rate, model TFLOP/s and max-abs / RMS
+error against the FP64 oracle at the GPU's iteration counts; and the
+oracle itself timed on this host's cores (cpu_baseline), whose outputs
+cover every pixel of the step's image.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--plain N (default 64)]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-configs] [--plain 0|1]
 """
 
 from __future__ import annotations
@@ -41,10 +48,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip em_solve_batch over the interior pixels' materialised windows")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads' sub-records (64x64, 512x512 FP32/FP16, 16 images, "
+                         "point sets)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time")
-    ap.add_argument("--plain", type=int, default=64,
-                    help="also time the plain one-instance-per-launch path on N pixels "
-                         "(speedup_vs_plain in the line; 0 skips it)")
+    ap.add_argument("--plain", type=int, default=1,
+                    help="also time the plain one-instance-per-launch path on the same n=441, d=49 "
+                         "instances (speedup_vs_plain in the line; 0 skips it)")
     ap.add_argument("--study", choices=["psnr", "evolution", "objective"], default=None,
                     help="instead of the timing line, run a denoising-quality study on the GPU: "
                          "the PSNR table (NLM / NLEM-IRLS / NLEM-ADMM, 4 iterations), PSNR per "
@@ -53,6 +63,9 @@ def parse():
     ap.add_argument("--pointsets", action="store_true",
                     help="instead of the NLEM line, time em_solve_batch on the 1,048,576-instance "
                          "point-set workload (n ~ U{8..512}, d in {2,3,16,49,64}) and print its own line")
+    ap.add_argument("--batch-interior", action="store_true",
+                    help="instead of the NLEM line, time only em_solve_batch over the 55,696 interior "
+                         "pixels of the 256x256 image as materialised n=441, d=49 instances (its own line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy (3 times): the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -253,6 +266,154 @@ def window_sizes(H, W, R):
     return (ny[:, None] * nx[None, :]).reshape(-1)
 
 
+def _events_ms(fn, reps):
+    """Mean time of fn() over reps calls, from HIP events on the current stream
+    (the library's calls run on it; their side streams join back into it)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _err(got, ref, D):
+    import numpy as np
+    e = np.abs(np.asarray(got, np.float64) - np.asarray(ref, np.float64)) / D
+    return {"max_abs_over_range": float(e.max()) if e.size else 0.0,
+            "rms_over_range": float(np.sqrt(np.mean(e ** 2))) if e.size else 0.0}
+
+
+def _rate_record(ms, flops, **extra):
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"ms": ms, "model_tflops": tf, "frac_of_157.3": tf / FP32_PEAK_TFLOPS, **extra}
+
+
+def nlem_image_config(hd, dev, img_np, pr, wr, h, wl, fp16, reps, oracle_pix, rng, oracle_images=None):
+    """nlem_denoise on one image: time per call, Mpixel/s, the 6-flop model
+    throughput (+3 flop per point coordinate for the weights) and, on
+    `oracle_pix` sampled pixels (all when it is >= the pixel count), the FP64
+    oracle's error at the GPU's per-pixel iteration counts; oracle_images maps
+    a label to the image the oracle is fed (default: the image itself)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_03879_amd as emx
+    H, W = img_np.shape
+    d = (2 * pr + 1) ** 2
+    t = torch.from_numpy(img_np).to(dev)
+    if fp16:
+        t = t.half()
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    st = torch.zeros((H * W, 4), dtype=torch.int32, device=dev)
+
+    def call():
+        hd.nlem_denoise(t, out, st, patch_radius=pr, window_radius=wr, h=h, lo=wl.lo, hi=wl.hi, rho=wl.mu,
+                        max_iter=wl.max_iter, tol=wl.tol)
+    for _ in range(3):
+        call()
+    ms = _events_ms(call, reps)
+    iters = emx.stats_view(st)[0].cpu().numpy().astype(np.int64)
+    n = window_sizes(H, W, wr).astype(np.int64)
+    flops = 6.0 * float(np.sum(n * d * iters)) + 3.0 * float(np.sum(n * d))
+    got = out.cpu().numpy().reshape(-1)
+    pix = np.arange(H * W) if oracle_pix >= H * W else np.sort(rng.choice(H * W, oracle_pix, replace=False))
+    errs = {}
+    for label, im in (oracle_images or {"oracle": img_np}).items():
+        r = oracle.nlem(im, pr, wr, h, wl.lo, wl.hi, wl.mu, wl.max_iter, 0.0, pix=pix,
+                        max_iter_each=iters[pix])
+        errs[label] = {"pixels": int(pix.size), **_err(got[pix], r["out"], wl.hi - wl.lo)}
+    return _rate_record(ms, flops, mpixel_per_s=H * W / (ms * 1e-3) / 1e6, mean_iters=float(iters.mean()),
+                        reps=reps, oracle_error=errs)
+
+
+def multi_config(hd, dev, reps, per_image, rng):
+    """The 16-image workload as one cached nlem_denoise_multi graph."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_03879_amd as emx
+    import synth
+    wl = synth.nlem_multi_image()
+    items = []
+    for im in wl.images:
+        t = torch.from_numpy(im.noisy).to(dev)
+        items.append(dict(img=t, out=torch.zeros_like(t), patch_radius=im.patch_radius,
+                          window_radius=im.window_radius, h=im.h,
+                          stats=torch.zeros((im.noisy.size, 4), dtype=torch.int32, device=dev)))
+
+    def call():
+        hd.nlem_denoise_multi(items, lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol)
+    for _ in range(2):
+        call()
+    ms = _events_ms(call, reps)
+    flops, px, got_all, ref_all = 0.0, 0, [], []
+    for im, it in zip(wl.images, items):
+        H, W = im.noisy.shape
+        d = (2 * im.patch_radius + 1) ** 2
+        iters = emx.stats_view(it["stats"])[0].cpu().numpy().astype(np.int64)
+        n = window_sizes(H, W, im.window_radius).astype(np.int64)
+        flops += 6.0 * float(np.sum(n * d * iters)) + 3.0 * float(np.sum(n * d))
+        px += H * W
+        pix = np.sort(rng.choice(H * W, per_image, replace=False))
+        r = oracle.nlem(im.noisy, im.patch_radius, im.window_radius, im.h, wl.lo, wl.hi, wl.mu, wl.max_iter,
+                        0.0, pix=pix, max_iter_each=iters[pix])
+        got_all.append(it["out"].cpu().numpy().reshape(-1)[pix])
+        ref_all.append(r["out"])
+    return _rate_record(ms, flops, mpixel_per_s=px / (ms * 1e-3) / 1e6, images=len(wl.images), pixels=px,
+                        reps=reps, oracle_error={"pixels": int(per_image * len(wl.images)),
+                                                 **_err(np.concatenate(got_all), np.concatenate(ref_all), 255.0)})
+
+
+def pointsets_config(hd, dev, reps, per_d, rng):
+    """em_solve_batch on the 1,048,576 point sets (drawn on the device)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_1501_03879_amd as emx
+    import synth
+    B = 1 << 20
+    a, w, inst, zs = synth.pointsets.make_pointset_batch_device(505, B, dev)
+    it = emx.instances_tensor(inst, dev)
+    z = torch.zeros(zs, dtype=torch.float32, device=dev)
+    st = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+    mu, T, tol = synth.configs.POINTSET_MU, synth.configs.POINTSET_MAX_ITER, synth.configs.POINTSET_TOL
+
+    def call():
+        hd.em_solve_batch(a, w, it, z, st, lo=-3.0, hi=3.0, rho=mu, max_iter=T, tol=tol, init=emx.INIT_MAXW)
+    call()
+    ms = _events_ms(call, reps)
+    iters = emx.stats_view(st)[0].cpu().numpy().astype(np.int64)
+    flags = emx.stats_view(st)[1].cpu().numpy()
+    nd = inst["n"].astype(np.float64) * inst["d"].astype(np.float64)
+    flops = 6.0 * float(np.sum(nd * iters))
+    sample = np.concatenate([rng.choice(np.flatnonzero(inst["d"] == dv), per_d, replace=False)
+                             for dv in (2, 3, 16, 49, 64)])
+    pts, ws = [], []
+    for b in sample:
+        e = inst[b]
+        n, d = int(e["n"]), int(e["d"])
+        pts.append(a[e["a_off"]:e["a_off"] + n * d].view(n, d).cpu().numpy())
+        ws.append(w[e["w_off"]:e["w_off"] + n].cpu().numpy())
+    sub = synth.pointsets.pack_instances(pts, ws, -3.0, 3.0)
+    ref = oracle.em_batch(sub, mu, T, 0.0, init=oracle.INIT_MAXW, max_iter_each=iters[sample])
+    zc = z.cpu().numpy()
+    got = np.concatenate([zc[inst[b]["z_off"]:inst[b]["z_off"] + inst[b]["d"]] for b in sample])
+    res = _rate_record(ms, flops, solves_per_s=B / (ms * 1e-3), instances=B, mean_iters=float(iters.mean()),
+                       converged_fraction=float(np.mean(flags == 1)),
+                       maxiter_instances=int(np.sum(flags == 2)), reps=reps,
+                       oracle_error={"instances": int(sample.size), **_err(got, ref["z"], 6.0)})
+    del a, w, z, st, it
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -260,6 +421,17 @@ def main():
         return
     if args.pointsets:
         pointsets(args)
+        return
+    if args.batch_interior:
+        import torch
+
+        import paper_1501_03879_amd as emx
+        import synth
+        wl = synth.nlem_256()
+        r = batch_interior_rate(wl.images[0], wl, torch.device("cuda:0"), emx.handle(0), None,
+                                reps=max(1, min(args.steps, 20)))
+        print(json.dumps({"workload": "em_solve_batch, the 256x256 image's interior pixels as n=441, "
+                                      "d=49 instances", **r}), flush=True)
         return
     if args.study:
         if args.gpus != 1:
@@ -332,8 +504,8 @@ def main():
 
     res = {
         "metric": METRIC,
-        "value": solves_per_s,
-        "unit": "EM solves/s",
+        "value": solves_per_s / 1e6,
+        "unit": "Mpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -347,6 +519,10 @@ def main():
                                f"h=200 box [0,255] mu={wl.mu} tol={wl.tol} max_iter={wl.max_iter}",
                    "pixels": H * W, "patch_radius": pr, "window_radius": wr},
         "mpixel_per_s": solves_per_s / 1e6,
+        "nlem_solves_per_s_all_pixels": solves_per_s,
+        "nlem_solves_note": "one EM solve per pixel, border pixels included (their windows are "
+                            "truncated: n from 121 to 441, mean 423.2); the rate at n=441, d=49 "
+                            "exactly is em_solves_per_s_n441_d49",
         "mean_iters": float(iters.mean()),
         "converged_fraction": float(np.mean(flags == 1)),
         "elem_iters_per_s": elem_iters / (ms * 1e-3),
@@ -366,63 +542,40 @@ def main():
                                "kernels and one NLEM kernel launch)"},
     }
 
+    rng = np.random.default_rng(12)
     if not args.no_batch:
-        res["batch_interior"] = batch_interior_rate(im, wl, dev, hd, out)
-    if args.plain > 0:
-        res["plain"] = plain_rate(args.plain, im, wl, dev, hd)
-        res["speedup_vs_plain"] = solves_per_s / res["plain"]["solves_per_s"]
-        if "batch_interior" in res:
-            bi = res["batch_interior"]
-            bi["speedup_vs_plain"] = bi["solves_per_s"] / res["plain"]["solves_per_s"]
-
+        bi = batch_interior_rate(im, wl, dev, hd, out, plain=args.plain != 0, oracle_instances=1024)
+        res["em_solves_per_s_n441_d49"] = bi["solves_per_s"]
+        res["batch_interior"] = bi
+        if "plain" in bi:
+            res["speedup_vs_plain"] = bi["speedup_vs_plain"]
+    if not args.no_configs:
+        cfg = {}
+        sm = synth.nlem_small()
+        s_im = sm.images[0]
+        cfg["small_64x64_r2_R5_T50"] = nlem_image_config(
+            hd, dev, s_im.noisy, s_im.patch_radius, s_im.window_radius, s_im.h, sm, False, 20, 1 << 30, rng)
+        cfg["nlem_256x256_d49"] = {"ms": ms, "model_tflops": tflops_step,
+                                   "frac_of_157.3": tflops_step / FP32_PEAK_TFLOPS,
+                                   "mpixel_per_s": solves_per_s / 1e6, "mean_iters": float(iters.mean()),
+                                   "note": "the timed step above; oracle error over every pixel in "
+                                           "cpu_baseline.oracle_error"}
+        for f16 in (False, True):
+            mw = synth.nlem_512_mixed(fp16_storage=f16)
+            m_im = mw.images[0]
+            refs = {"oracle": m_im.noisy}
+            if f16:
+                refs = {"oracle_fp32_image": m_im.noisy,
+                        "oracle_fp16_rounded_image": m_im.noisy.astype(np.float16).astype(np.float32)}
+            cfg["mixed_512x512_" + ("fp16" if f16 else "fp32")] = nlem_image_config(
+                hd, dev, m_im.noisy, 3, 10, m_im.h, mw, f16, 5, 4096, rng, refs)
+        cfg["multi_16_images_graph"] = multi_config(hd, dev, 3, 256, rng)
+        cfg["pointsets_1m"] = pointsets_config(hd, dev, 3, 512, rng)
+        res["configs"] = cfg
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(im, wl, args.cpu_seconds,
                                            out.cpu().numpy().reshape(-1).astype(np.float64), iters)
     print(json.dumps(res), flush=True)
-
-
-def plain_rate(npix, im, wl, dev, hd):
-    """The plain path (em_solve_plain: one kernel launch per pixel, iterates in
-    device memory) on the first `npix` interior pixels' materialised patches
-    and NLM weights (built on the host in float64, stored as float32)."""
-    import numpy as np
-    import torch
-
-    import paper_1501_03879_amd as emx
-    import synth
-    img = im.noisy.astype(np.float64)
-    H, W = img.shape
-    P = np.pad(img, 3, mode="symmetric")
-    pts, ws = [], []
-    rng = np.random.default_rng(1)
-    for _ in range(npix):
-        iy, ix = rng.integers(10, H - 10), rng.integers(10, W - 10)
-        a = np.array([P[y:y + 7, x:x + 7].reshape(-1) for y in range(iy - 10, iy + 11)
-                      for x in range(ix - 10, ix + 11)])
-        c = P[iy:iy + 7, ix:ix + 7].reshape(-1)
-        pts.append(a.astype(np.float32))
-        ws.append(np.exp(-np.sum((a - c) ** 2, axis=1) / im.h ** 2).astype(np.float32))
-    b = synth.pointsets.pack_instances(pts, ws, 0.0, 255.0)
-    a = torch.from_numpy(b.a).to(dev)
-    w = torch.from_numpy(b.w).to(dev)
-    inst = emx.instances_tensor(b.inst, dev)
-    z = torch.zeros(b.z_size, device=dev)
-    st = torch.zeros((b.B, 4), dtype=torch.int32, device=dev)
-    kw = dict(lo=0.0, hi=255.0, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
-    hd.em_solve_plain(a, w, inst, b.inst, z, st, **kw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hd.em_solve_plain(a, w, inst, b.inst, z, st, **kw)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    hd.em_solve_batch(a, w, inst, z, st, **kw)   # warm-up (workspace, code objects)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    hd.em_solve_batch(a, w, inst, z, st, **kw)
-    torch.cuda.synchronize()
-    dtb = time.perf_counter() - t0
-    return {"solves_per_s": b.B / dt, "instances": b.B, "batched_same_instances_solves_per_s": b.B / dtb,
-            "note": "n=441 d=49 interior pixels, materialised patches, init = largest weight (the centre)"}
 
 
 def pointsets(args):
@@ -478,16 +631,22 @@ def pointsets(args):
                       "reps": reps, "per_d": per_d}), flush=True)
 
 
-def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=3):
+def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_instances=0):
     """em_solve_batch on every interior pixel of the image (full 21 x 21
     windows: n = 441, d = 49) as materialised instances, the EM-solves half of
     the metric.  Input preparation (untimed): patches gathered on the device,
     NLM weights exp(-||P_i - P_j||^2 / h^2) in FP64 there, both stored as
-    FP32; start = the largest weight (the centre patch)."""
+    FP32; start = the largest weight (the centre patch).  With plain=True the
+    same instances also go through em_solve_plain (one launch per instance),
+    timed with HIP events; oracle_instances > 0: that many sampled instances
+    are solved by the FP64 oracle at the GPU's iteration counts (every
+    coordinate of z compared)."""
     import numpy as np
     import torch
 
+    import oracle
     import paper_1501_03879_amd as emx
+    import synth
     from synth.pointsets import INSTANCE_DTYPE
     H, W = im.noisy.shape
     r, R = im.patch_radius, im.window_radius
@@ -517,21 +676,44 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=3):
     kw = dict(lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
     hd.em_solve_batch(a, w, it, z, st, **kw)   # warm-up (workspace, code objects)
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        hd.em_solve_batch(a, w, it, z, st, **kw)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = _events_ms(lambda: hd.em_solve_batch(a, w, it, z, st, **kw), reps)
     iters, flags = emx.stats_view(st)[0].cpu().numpy(), emx.stats_view(st)[1].cpu().numpy()
     centre = z.reshape(B, d)[:, (d - 1) // 2]
-    diff = float((centre - out_nlem.reshape(-1)[centres]).abs().max()) / (wl.hi - wl.lo)
-    res = {"instances": B, "n": nwin, "d": d, "ms": ms, "solves_per_s": B / (ms * 1e-3),
-           "mean_iters": float(iters.mean()), "converged_fraction": float(np.mean(flags == 1)),
+    diff = (None if out_nlem is None else
+            float((centre - out_nlem.reshape(-1)[centres]).abs().max()) / (wl.hi - wl.lo))
+    flops = 6.0 * nwin * d * float(np.sum(iters.astype(np.float64)))
+    res = {"instances": B, "n": nwin, "d": d, "solves_per_s": B / (ms * 1e-3),
+           **_rate_record(ms, flops), "mean_iters": float(iters.mean()),
+           "converged_fraction": float(np.mean(flags == 1)),
            "max_abs_diff_vs_nlem_over_range": diff,
-           "note": "em_solve_batch over the interior pixels' materialised windows (inputs in HBM); "
-                   "the NLEM kernel solves the same instances from the image tile"}
+           "note": "em_solve_batch over the interior pixels' materialised windows (inputs in HBM, "
+                   "weights computed outside the timed region); the NLEM kernel solves the same "
+                   "instances from the image tile"}
+    if oracle_instances > 0:
+        rng = np.random.default_rng(5)
+        sample = np.sort(rng.choice(B, min(oracle_instances, B), replace=False))
+        ah = a.view(B, nwin, d)[torch.from_numpy(sample).to(dev)].cpu().numpy()
+        wh = w.view(B, nwin)[torch.from_numpy(sample).to(dev)].cpu().numpy()
+        sub = synth.pointsets.pack_instances(list(ah), list(wh), wl.lo, wl.hi)
+        ref = oracle.em_batch(sub, wl.mu, wl.max_iter, 0.0, init=oracle.INIT_MAXW,
+                              max_iter_each=iters[sample])
+        got = z.view(B, d)[torch.from_numpy(sample).to(dev)].cpu().numpy().reshape(-1)
+        res["oracle_error"] = {"instances": int(sample.size), **_err(got, ref["z"], wl.hi - wl.lo)}
+    if plain:
+        zp = torch.zeros_like(z)
+        stp = torch.zeros_like(st)
+        pk = dict(kw)
+        hd.em_solve_plain(a[:nwin * d * 64], w[:nwin * 64], emx.instances_tensor(inst[:64], dev), inst[:64],
+                          zp, stp, **pk)   # warm-up
+        torch.cuda.synchronize()
+        pms = _events_ms(lambda: hd.em_solve_plain(a, w, it, inst, zp, stp, **pk), 1)
+        same = bool(torch.equal(zp, z))
+        res["plain"] = {"ms": pms, "solves_per_s": B / (pms * 1e-3), "instances": B,
+                        "bitwise_equal_to_batched": same,
+                        "note": "em_solve_plain on the same instances: the batched class kernel launched as "
+                                "one workgroup per instance, back to back on one stream (HIP events)"}
+        res["speedup_vs_plain"] = res["solves_per_s"] / res["plain"]["solves_per_s"]
+        del zp, stp
     del a, w, z, st, it
     torch.cuda.empty_cache()
     return res

@@ -87,6 +87,49 @@ __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_
     if (c >= 0) list[offsets[c] + lbase[c] + rank] = (int32_t)b;
 }
 
+// The class kernels of a solver and set.
+static const ClassKernel *class_table(const em_options_t &o) {
+    const bool ball = o.set == EM_SET_BALL;
+    return (o.solver == EM_SOLVER_IRLS) ? (ball ? batch_class_table_irls_ball() : batch_class_table_irls())
+           : (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? batch_class_table_adapt()
+           : (o.solver == EM_SOLVER_ADMM_WEIGHTED) ? (ball ? batch_class_table_wpen_ball() : batch_class_table_wpen())
+                                                   : (ball ? batch_class_table_admm_ball() : batch_class_table_admm());
+}
+
+// Arguments of a class launch (queue fields and `single` left to the caller).
+static ClassLaunch class_launch(const float *a, const float *w, const em_instance_t *inst, const em_options_t &o,
+                                float *z, em_stats_t *stats, int c) {
+    const bool ball = o.set == EM_SET_BALL;
+    const bool vbox = ball || o.box_lo != nullptr;
+    ClassLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.a = a;
+    L.w = w;
+    L.inst = inst;
+    L.z = z;
+    L.stats = stats;
+    L.box_lo = ball ? nullptr : o.box_lo;
+    L.box_hi = ball ? nullptr : o.box_hi;
+    L.ball_center = ball ? o.ball_center : nullptr;
+    L.ball_radius = ball ? o.ball_radius : nullptr;
+    L.radius = o.radius;
+    L.lo = vbox ? 0.0f : o.lo;   // padded coordinates clamp to 0 when the box is per coordinate
+    L.hi = vbox ? 0.0f : o.hi;
+    L.mu = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
+    L.tol = o.tol;
+    L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
+    L.eps = o.eps;
+    L.adapt_every = (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? o.adapt_every : 0;
+    L.adapt_ratio2 = o.adapt_ratio * o.adapt_ratio;
+    L.adapt_factor = o.adapt_factor;
+    L.max_iter = o.max_iter;
+    L.init = o.init;
+    L.cls = c;
+    L.a16 = o.points_f16 ? 1 : 0;
+    L.single = -1;
+    return L;
+}
+
 // EMX_BATCH_WIDE=0 keeps every instance on the generic classes (for comparison).
 static bool wide_disabled() {
     const char *e = getenv("EMX_BATCH_WIDE");
@@ -114,15 +157,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, wide);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
-    const bool ball = o.set == EM_SET_BALL;
-    const ClassKernel *tab = (o.solver == EM_SOLVER_IRLS)
-                                 ? (ball ? batch_class_table_irls_ball() : batch_class_table_irls())
-                             : (o.solver == EM_SOLVER_ADMM_ADAPTIVE)
-                                 ? batch_class_table_adapt()
-                             : (o.solver == EM_SOLVER_ADMM_WEIGHTED)
-                                 ? (ball ? batch_class_table_wpen_ball() : batch_class_table_wpen())
-                                 : (ball ? batch_class_table_admm_ball() : batch_class_table_admm());
-    const bool vbox = ball || o.box_lo != nullptr;
+    const ClassKernel *tab = class_table(o);
     // The classes run concurrently on the caller's stream and the handle's
     // side streams (fork after the classification, join before returning), so
     // one class's tail overlaps the others' work.  The launched classes go to
@@ -142,34 +177,10 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
         const int si = launched++ % (kSideStreams + 1);
         hipStream_t cs = (si == 0) ? s : side[si - 1];
-        ClassLaunch L;
-        memset(&L, 0, sizeof(L));
-        L.a = a;
-        L.w = w;
-        L.inst = inst;
+        ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
         L.list = list;
         L.offsets = offsets;
         L.counter = heads + c;
-        L.z = z;
-        L.stats = stats;
-        L.box_lo = ball ? nullptr : o.box_lo;
-        L.box_hi = ball ? nullptr : o.box_hi;
-        L.ball_center = ball ? o.ball_center : nullptr;
-        L.ball_radius = ball ? o.ball_radius : nullptr;
-        L.radius = o.radius;
-        L.lo = vbox ? 0.0f : o.lo;   // padded coordinates clamp to 0 when the box is per coordinate
-        L.hi = vbox ? 0.0f : o.hi;
-        L.mu = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
-        L.tol = o.tol;
-        L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
-        L.eps = o.eps;
-        L.adapt_every = (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? o.adapt_every : 0;
-        L.adapt_ratio2 = o.adapt_ratio * o.adapt_ratio;
-        L.adapt_factor = o.adapt_factor;
-        L.max_iter = o.max_iter;
-        L.init = o.init;
-        L.cls = c;
-        L.a16 = o.points_f16 ? 1 : 0;
         const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, ck.fn, ck.threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
         void *args[] = {&L};
@@ -186,12 +197,17 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
 
 // ------------------------------------------------------------------ plain
 
-// One instance per launch with the iterates in device memory: the simple
-// baseline for the batched solver, and the home of the accelerated variant
-// (its momentum needs the previous multipliers, a second n x d state).
+// The plain path, one instance per launch:
+//  * EM-ADMM: the batched solver's own class kernels, each launched as a
+//    single workgroup on a single instance (no work queue, no other instance
+//    on the chip), so batched / plain measures what batching and the
+//    persistent queue add, with the same per-instance code.
+//  * The accelerated ADMM (its momentum needs the previous multipliers, a
+//    second n x d state) runs here only, iterates in device memory, one
+//    256-thread workgroup per instance (plain_solve_kernel<true>).
 //   FAST = false: literal Algorithm 1 (thread per point for the prox and the
 //     multiplier update, thread per coordinate for the mean), residuals
-//     every iteration.
+//     every iteration (not used by the library).
 //   FAST = true: fast ADMM with restart ([Goldstein2012], weakly convex
 //     case) on the same splitting: the prox and the mean use the predictors
 //     z_hat, u_hat; after the update, c = mu (sum_k ||x_k - z||^2 +
@@ -406,10 +422,42 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
                                   rpri, rdual};
 }
 
+// EM-ADMM one instance per launch through the class kernels; empty and
+// malformed instances are finished by the classification kernel on that
+// instance alone (EMPTY, or BAD_INPUT with z = NaN).
+static em_status_t plain_admm(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
+                              const em_instance_t *inst, const em_instance_t *inst_host, const em_options_t &o,
+                              float *z, em_stats_t *stats) {
+    const bool wide = o.set == EM_SET_BOX && !wide_disabled();
+    const ClassKernel *tab = class_table(o);
+    const ClassKernel *wtab = batch_wide_table();
+    unsigned int *scratch = ctx_counters(ctx, kNumAllClasses);   // class counts of the finishing kernel
+    if (!scratch) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
+    for (int64_t b = 0; b < B; ++b) {
+        const em_instance_t &e = inst_host[b];
+        if (e.n <= 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
+            hipLaunchKernelGGL(batch_classify_count, dim3(1), dim3(256), 0, s, inst + b, (int64_t)1, z,
+                               stats ? stats + b : nullptr, scratch, 0);
+            continue;
+        }
+        const int c = class_of(e.n, e.d, wide);
+        const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
+        ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
+        L.single = b;
+        void *args[] = {&L};
+        const hipError_t err = hipLaunchKernel(ck.fn, dim3(1), dim3(ck.threads), args, 0, s);
+        if (err != hipSuccess) return ctx_hip_error(ctx, err, "plain launch");
+    }
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return ctx_hip_error(ctx, err, "plain launch");
+    return EM_OK;
+}
+
 em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
                         const em_instance_t *inst, const em_instance_t *inst_host, const em_options_t &o,
                         float *z, em_stats_t *stats) {
     const bool fast = o.solver == EM_SOLVER_ADMM_FAST;
+    if (!fast) return plain_admm(ctx, s, B, a, w, inst, inst_host, o, z, stats);
     int64_t maxnd = 1;
     for (int64_t b = 0; b < B; ++b) {
         const int64_t n = inst_host[b].n, d = inst_host[b].d;
@@ -441,10 +489,7 @@ em_status_t plain_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     P.init = o.init;
     for (int64_t b = 0; b < B; ++b) {
         P.b = b;
-        if (fast)
-            hipLaunchKernelGGL(plain_solve_kernel<true>, dim3(1), dim3(256), 0, s, P);
-        else
-            hipLaunchKernelGGL(plain_solve_kernel<false>, dim3(1), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(plain_solve_kernel<true>, dim3(1), dim3(256), 0, s, P);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "plain launch");

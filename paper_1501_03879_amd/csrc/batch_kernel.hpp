@@ -113,6 +113,7 @@ struct ClassLaunch {
     int32_t adapt_every;          // ADMM: 0 = fixed penalty
     int32_t max_iter, init, cls;
     int32_t a16;                  // points stored as FP16 (widened on staging)
+    int64_t single;               // >= 0: solve only this instance (one workgroup, no queue)
 };
 
 struct ClassKernel {
@@ -161,13 +162,17 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     float *zb = zvec + wave * DS;       // per wave: z of the slice, for a penalty rescale
     float *Bl_s = Bv + wave * 2 * H2 * 4;  // per wave: the box (ball: centre) in the reduced layout
     float *Bh_s = Bl_s + H2 * 4;
-    const unsigned int cbeg = L.offsets[L.cls];
-    const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
+    // one instance per launch (L.single >= 0: the plain path) or the class's
+    // work queue
+    const bool one = L.single >= 0;
+    const unsigned int cbeg = one ? 0u : L.offsets[L.cls];
+    const unsigned int ccount = one ? 1u : L.offsets[L.cls + 1] - cbeg;
+    unsigned int taken = 0;   // thread 0, single-instance mode: instances taken
     const bool vbox = L.box_lo != nullptr;
 
     for (;;) {
         if (threadIdx.x == 0) {
-            item_s = atomicAdd(L.counter, 1u);
+            item_s = one ? taken++ : atomicAdd(L.counter, 1u);
             flag_s[0] = 0;  // a point or weight is bad
             flag_s[1] = 0;  // max |a| (float bits, non-negative)
             flag_s[2] = 0;  // the starting z or the box is bad
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         __syncthreads();
         const unsigned int it = (unsigned int)uniform_int((int)item_s);
         if (it >= ccount) break;
-        const int b = uniform_int(L.list[cbeg + it]);
+        const int b = one ? (int)L.single : uniform_int(L.list[cbeg + it]);
         const em_instance_t e = L.inst[b];
         const int n = uniform_int(e.n), d = uniform_int(e.d);
         const float *A = L.a + e.a_off;
