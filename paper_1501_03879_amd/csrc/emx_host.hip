@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "emx_internal.hpp"
+#include "nlem_group.hpp"
 #include "nlem_table.hpp"
 
 namespace emx {
@@ -350,15 +351,6 @@ extern "C" em_status_t em_sync(em_handle_t h, void *stream) {
 // already within kArmFactor * tol * D (both must be within tol * D to stop).
 static constexpr float kArmFactor = 1.0f;
 
-// Points per lane M for a window radius (n = (2R+1)^2 <= 64 M): the
-// smallest M, except R = 9, which takes M = 7 for the kernels' row mapping
-// (3 runs of 7 columns x 19 rows; measured 4-5% faster than M = 6 slot by
-// slot).  M = 4 (R = 7) and M = 7 (R = 9, 10) use the row mapping.
-static int points_per_lane(int R) {
-    static const int kM[EM_MAX_WINDOW_RADIUS + 1] = {1, 1, 1, 1, 2, 2, 3, 4, 5, 7, 7};
-    return kM[R];
-}
-
 // Queues shorter than this many rounds of the resident grid run, in
 // tolerance mode, with the most coordinate waves compiled for the shape: the
 // slowest pixels set the time of such a queue, and more waves per pixel
@@ -473,27 +465,6 @@ static em_status_t check_options(em_context *ctx, const nlem_options_t *o) {
     if (st != EM_OK) return st;
     if (!std::isfinite(o->lo) || !std::isfinite(o->hi)) return fail(ctx, EM_ERR_INVALID_ARG, "nlem needs a finite box");
     return EM_OK;
-}
-
-struct NlemGroup {
-    int pr, m;
-    std::vector<int> images;
-};
-
-static std::vector<NlemGroup> group_images(int32_t count, const nlem_image_t *images) {
-    std::vector<NlemGroup> groups;
-    for (int i = 0; i < count; ++i) {
-        const int pr = images[i].patch_radius, m = points_per_lane(images[i].window_radius);
-        NlemGroup *g = nullptr;
-        for (auto &x : groups)
-            if (x.pr == pr && x.m == m && (int)x.images.size() < kMaxImagesPerLaunch) g = &x;
-        if (!g) {
-            groups.push_back(NlemGroup{pr, m, {}});
-            g = &groups.back();
-        }
-        g->images.push_back(i);
-    }
-    return groups;
 }
 
 static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, const nlem_options_t &o,
@@ -723,7 +694,7 @@ extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const v
     if (!h->noalloc) return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: no scratch for this device index");
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const NlemGroup g{patch_radius, points_per_lane(window_radius), {}};   // no images listed: no allocation
+    const NlemGroup g{patch_radius, points_per_lane(window_radius), {}, 0};   // no images listed: no allocation
     const NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM, total,
                                                 max_iter > 0 && tol > 0.0f, /*cache=*/false);
     if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape");
