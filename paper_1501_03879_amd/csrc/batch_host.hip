@@ -87,6 +87,16 @@ __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_
     if (c >= 0) list[offsets[c] + lbase[c] + rank] = (int32_t)b;
 }
 
+// Far outliers: the fixed-penalty EM-ADMM over a box defers an instance whose
+// largest |a| exceeds kOutlierK D sqrt(n) to kernels that carry the prox
+// displacement e itself (ClassLaunch, batch_wide.hpp).  With g = e - a the
+// computed primal residual has a floor of about 3e-4 tol (max |a| / D) /
+// sqrt(n) (measured on the 91 of 1,048,576 point sets that ended at max_iter
+// that way, max |a| / D from 2.9e4 to 7.5e5); below the bound it stays under
+// 0.12 tol.  On the point-set workload 0.9% of the instances (1.3% of the
+// work) are deferred.
+constexpr float kOutlierK = 300.0f;
+
 // The class kernels of a solver and set.
 static const ClassKernel *class_table(const em_options_t &o) {
     const bool ball = o.set == EM_SET_BALL;
@@ -127,6 +137,7 @@ static ClassLaunch class_launch(const float *a, const float *w, const em_instanc
     L.cls = c;
     L.a16 = o.points_f16 ? 1 : 0;
     L.single = -1;
+    L.outlier = kOutlierK;
     return L;
 }
 
@@ -138,19 +149,25 @@ static bool wide_disabled() {
 
 em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
                         const em_instance_t *inst, const em_options_t &o, float *z, em_stats_t *stats) {
-    // workspace: list[B] int32
+    // fixed-penalty EM-ADMM over a box: d > 16, n <= 448 go to the sliced
+    // kernel, far-outlier instances to the deferred lists
+    const int wide = (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX && !wide_disabled()) ? 1 : 0;
+    const bool defer = o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX;
+    // workspace: list[B] int32, then (deferral) the deferred lists of B each
     em_status_t st;
-    int32_t *list = static_cast<int32_t *>(ctx_workspace(ctx, (size_t)B * sizeof(int32_t), &st));
+    int32_t *list = static_cast<int32_t *>(
+        ctx_workspace(ctx, (size_t)B * sizeof(int32_t) * (defer ? 1 + kDeferLists : 1), &st));
     if (!list) return st;
-    // counters: [0, K) class counts, [K, 2K+1) offsets, [2K+1, 3K+1) fill, [3K+1, 4K+1) queue heads
+    // counters: [0, K) class counts, [K, 2K+1) offsets, [2K+1, 3K+1) fill, [3K+1, 4K+1) queue heads,
+    // then the deferred lists' {0, count} pairs and queue heads
     constexpr int K = kNumAllClasses;
-    unsigned int *cnt = ctx_counters(ctx, 4 * K + 1);
+    constexpr int NC = 4 * K + 1 + 3 * kDeferLists;
+    unsigned int *cnt = ctx_counters(ctx, NC);
     if (!cnt) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
     unsigned int *counts = cnt, *offsets = cnt + K, *fill = cnt + 2 * K + 1, *heads = cnt + 3 * K + 1;
-    st = ctx_reset_counters(ctx, s, cnt, 4 * K + 1);
+    unsigned int *defer_q = cnt + 4 * K + 1, *defer_heads = defer_q + 2 * kDeferLists;
+    st = ctx_reset_counters(ctx, s, cnt, NC);
     if (st != EM_OK) return st;
-    // fixed-penalty EM-ADMM over a box: d > 16, n <= 448 go to the sliced kernel
-    const int wide = (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX && !wide_disabled()) ? 1 : 0;
     const unsigned nb = (unsigned)((B + 255) / 256);
     hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, wide);
     hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
@@ -181,6 +198,11 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         L.list = list;
         L.offsets = offsets;
         L.counter = heads + c;
+        if (defer) {
+            L.defer_list = list + B;
+            L.defer_stride = B;
+            L.defer_q = defer_q;
+        }
         const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, ck.fn, ck.threads);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
         void *args[] = {&L};
@@ -192,6 +214,22 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         if (e == hipSuccess) e = hipStreamWaitEvent(s, join[i], 0);
     }
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "join of the class streams");
+    if (defer) {
+        // the deferred far-outlier instances, after every class kernel (an empty
+        // list costs one launch whose workgroups exit at once)
+        const ClassKernel *dtab = batch_deferred_table();
+        for (int k = 0; k < kDeferLists; ++k) {
+            ClassLaunch L = class_launch(a, w, inst, o, z, stats, 0);
+            L.list = list + (int64_t)(k + 1) * B;
+            L.offsets = defer_q + 2 * k;
+            L.counter = defer_heads + k;
+            const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, dtab[k].fn, dtab[k].threads);
+            const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
+            void *args[] = {&L};
+            e = hipLaunchKernel(dtab[k].fn, dim3(grid), dim3(dtab[k].threads), args, 0, s);
+            if (e != hipSuccess) return ctx_hip_error(ctx, e, "deferred launch");
+        }
+    }
     return EM_OK;
 }
 

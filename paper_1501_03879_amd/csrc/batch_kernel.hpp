@@ -114,7 +114,23 @@ struct ClassLaunch {
     int32_t max_iter, init, cls;
     int32_t a16;                  // points stored as FP16 (widened on staging)
     int64_t single;               // >= 0: solve only this instance (one workgroup, no queue)
+    // Far outliers (fixed-penalty EM-ADMM over a box): an instance whose
+    // largest |a| exceeds outlier * D * sqrt(n) is not solved by the class
+    // kernel but appended to deferred list k (k = 0: d <= 16; 1: d > 16), at
+    // defer_list + k * defer_stride, its count at defer_q[2 k + 1]
+    // (defer_q[2 k] stays 0); null defer_q: no deferral
+    float outlier;
+    int32_t *defer_list;
+    int64_t defer_stride;
+    unsigned int *defer_q;
 };
+
+// Append instance b to its deferred list (thread 0 of the workgroup).
+__device__ __forceinline__ void defer_instance(const ClassLaunch &L, int b, int n, int d) {
+    const int k = (d <= 16) ? 0 : 1;
+    const unsigned int pos = atomicAdd(&L.defer_q[2 * k + 1], 1u);
+    L.defer_list[k * L.defer_stride + pos] = b;
+}
 
 struct ClassKernel {
     const void *fn;
@@ -135,6 +151,9 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
     constexpr bool BALL = SET == 1;
     constexpr bool ADAPT = SOLVER == 2;   // adaptive penalty (a separate kernel: it needs registers)
     constexpr bool WPEN = SOLVER == 4;    // penalty mu w_k per constraint (weighted-mean z-update)
+    // SOLVER 5: EM-ADMM carrying the prox displacement e itself instead of
+    // g = e - a (far-outlier instances deferred by SOLVER 0, see ClassLaunch)
+    constexpr bool ES = SOLVER == 5;
     using S = BatchShape<DS, M, WC, WP>;
     using RSx = RS<DS>;
     constexpr int H2 = S::H2;
@@ -363,12 +382,19 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         const float rad = BALL ? (L.ball_radius ? readfirstlane(L.ball_radius[b]) : L.radius) : 0.0f;
         const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0 || (BALL && !(rad >= 0.0f)));
         const float wmax = BALL ? 2.0f * rad : readfirstlane(__int_as_float(flag_s[3]));
-        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f)
-                                 ? wmax : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
+        const float amax_all = readfirstlane(__int_as_float(flag_s[1]));
+        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f) ? wmax : fmaxf(1.0f, amax_all);
         const float tau = L.tol * Dscale;
         const float tau2 = tau * tau;
         const float arm2 = (L.arm * tau) * (L.arm * tau);
         __syncthreads();  // flags are reset by the next pop
+        if constexpr (SOLVER == 0 && !BALL) {
+            if (L.defer_q != nullptr && !bad_all &&
+                uniform(amax_all > L.outlier * Dscale * sqrtf((float)n))) {
+                if (threadIdx.x == 0) defer_instance(L, b, n, d);
+                continue;
+            }
+        }
 
         // Ball projection factor min(1, radius / ||m - center||) from the lane's
         // row partial sum of (m_j - center_j)^2 (identical on the row's lanes);
@@ -682,7 +708,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
 #pragma unroll
             for (int q = 0; q < M; ++q)
 #pragma unroll
-                for (int jj = 0; jj < DS; ++jj) g[q][jj] = na[q][jj];
+                for (int jj = 0; jj < DS; ++jj) g[q][jj] = ES ? 0.0f : na[q][jj];
             const float inv_d = 1.0f / (float)d;
             const float inv_nd = (fn > 0.0f) ? 1.0f / (fn * (float)d) : 0.0f;
             const int max_iter = L.max_iter;
@@ -700,9 +726,20 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                     const float cj = cv[jj];
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
-                        g[q][jj] += cj;
-                        nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                        if constexpr (ES) {
+                            const float dl = (g[q][jj] + cj) + na[q][jj];
+                            nrm[q] = fmaf(dl, dl, nrm[q]);
+                        } else {
+                            g[q][jj] += cj;
+                            nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                        }
                     }
+                }
+                if constexpr (ES) {   // pass 2 recomputes delta (do not hold it across the exchange)
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int jj = 0; jj < DS; ++jj) asm volatile("" : "+v"(g[q][jj]));
                 }
                 float rd_all = rd_w;
                 if constexpr (WC > 1 || WP > 1) {
@@ -797,7 +834,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                 // Absent points and padded coordinates give exactly 0 (g stays -a).
                 float rp_lane = 0.0f;
                 float Ys[H2];   // WPEN, armed: sum_k (x_k - c) in the reduced layout
-                if (armed) {
+                if (!ES && armed) {
                     float ysum[DS];   // WPEN: lane sums of x_k - c (points of weight zero give 0)
                     float rq[M];
 #pragma unroll
@@ -823,16 +860,54 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
 #pragma unroll
                 for (int q = 0; q < M; ++q) sw[q] = WPEN ? s[q] * wq[q] : s[q];
                 float acc[DS];
+                if constexpr (ES) {
+                    // delta = (e + c) - a again; e = s delta; armed: x_k - c = e - s delta
+                    float rq[M];
 #pragma unroll
-                for (int jj = 0; jj < DS; ++jj) {
-                    float ac = 0.0f;
+                    for (int q = 0; q < M; ++q) rq[q] = 0.0f;
+                    if (armed) {
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        const float dl = g[q][jj];
-                        ac = fmaf(sw[q], dl, ac);
-                        g[q][jj] = fmaf(s[q], dl, na[q][jj]);
+                        for (int jj = 0; jj < DS; ++jj) {
+                            const float cj = cv[jj];
+                            float ac = 0.0f;
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                const float dl = (g[q][jj] + cj) + na[q][jj];
+                                const float y = fmaf(-s[q], dl, g[q][jj]);
+                                rq[q] = fmaf(y, y, rq[q]);
+                                ac = fmaf(sw[q], dl, ac);
+                                g[q][jj] = s[q] * dl;
+                            }
+                            acc[jj] = ac;
+                        }
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < DS; ++jj) {
+                            const float cj = cv[jj];
+                            float ac = 0.0f;
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                const float dl = (g[q][jj] + cj) + na[q][jj];
+                                ac = fmaf(sw[q], dl, ac);
+                                g[q][jj] = s[q] * dl;
+                            }
+                            acc[jj] = ac;
+                        }
                     }
-                    acc[jj] = ac;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rp_lane += rq[q];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < DS; ++jj) {
+                        float ac = 0.0f;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            const float dl = g[q][jj];
+                            ac = fmaf(sw[q], dl, ac);
+                            g[q][jj] = fmaf(s[q], dl, na[q][jj]);
+                        }
+                        acc[jj] = ac;
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < M; ++q)
@@ -992,5 +1067,10 @@ const ClassKernel *batch_class_table_irls_ball();
 const ClassKernel *batch_class_table_wpen();
 const ClassKernel *batch_class_table_wpen_ball();
 const ClassKernel *batch_wide_table();   // kNumWideClasses entries
+// The kernels that solve the deferred far-outlier lists 0 and 1 (fixed-penalty
+// EM-ADMM over a box carrying e): d <= 16 (one 16-coordinate slice) and
+// d <= 64 (four), both n <= 512 (2 x 4 points per lane).
+constexpr int kDeferLists = 2;
+const ClassKernel *batch_deferred_table();
 
 }  // namespace emx

@@ -30,4 +30,12 @@ const ClassKernel *wide_table(std::integer_sequence<int, C...>) {
 
 const ClassKernel *batch_wide_table() { return wide_table(std::make_integer_sequence<int, kNumWideClasses>{}); }
 
+// Kernels of the deferred far-outlier lists (EM-ADMM carrying e, generic
+// shapes of batch_kernel.hpp: the carried state takes more registers than the
+// sliced shapes have to spare).
+const ClassKernel *batch_deferred_table() {
+    static const ClassKernel t[kDeferLists] = {class_kernel<7, 5, 0>(), class_kernel<19, 5, 0>()};
+    return t;
+}
+
 }  // namespace emx

@@ -89,7 +89,13 @@ __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, i
     }
 }
 
-template <int NJ, int M, int WC, int WAVES_PER_SIMD>
+// ES: carry the prox displacement e itself instead of g = e - a (as the
+// generic kernel's SOLVER 5 for deferred far-outlier instances, see
+// ClassLaunch): delta = (e + c) - a in both passes and x_k - c = e - s delta
+// on armed iterations, 7 operations per point coordinate instead of 4,
+// without the floor that a large |a| puts under the primal residual computed
+// from g.  The class kernels use ES = false and defer such instances.
+template <int NJ, int M, int WC, int WAVES_PER_SIMD, bool ES = false>
 __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(ClassLaunch L) {
     using S = WideShape<NJ, M, WC>;
     using RSx = RSF<NJ>;
@@ -232,12 +238,19 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
         __syncthreads();
         const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
         const float wmax = readfirstlane(__int_as_float(flag_s[3]));
-        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f)
-                                 ? wmax : fmaxf(1.0f, readfirstlane(__int_as_float(flag_s[1])));
+        const float amax_all = readfirstlane(__int_as_float(flag_s[1]));
+        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f) ? wmax : fmaxf(1.0f, amax_all);
         const float tau = L.tol * Dscale;
         const float tau2 = tau * tau;
         const float arm2 = (L.arm * tau) * (L.arm * tau);
         __syncthreads();   // flags are reset by the next pop
+        if constexpr (!ES) {
+            if (L.defer_q != nullptr && !bad_all &&
+                uniform(amax_all > L.outlier * Dscale * sqrtf((float)n))) {
+                if (threadIdx.x == 0) defer_instance(L, b, n, d);
+                continue;
+            }
+        }
 
         int iters = 0, flags = EM_MAXITER;
         float rp2 = 0.0f, rd2 = 0.0f;
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
 #pragma unroll
             for (int q = 0; q < M; ++q)
 #pragma unroll
-                for (int jj = 0; jj < NJ; ++jj) g[q][jj] = na[q][jj];
+                for (int jj = 0; jj < NJ; ++jj) g[q][jj] = ES ? 0.0f : na[q][jj];
             const float inv_n = 1.0f / (float)n;
             const float fn = (float)n;
             const float inv_d = 1.0f / (float)d;
@@ -271,9 +284,20 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                     const float c = cv[jj];
 #pragma unroll
                     for (int q = 0; q < M; ++q) {
-                        g[q][jj] += c;
-                        nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                        if constexpr (ES) {
+                            const float dl = (g[q][jj] + c) + na[q][jj];
+                            nrm[q] = fmaf(dl, dl, nrm[q]);
+                        } else {
+                            g[q][jj] += c;
+                            nrm[q] = fmaf(g[q][jj], g[q][jj], nrm[q]);
+                        }
                     }
+                }
+                if constexpr (ES) {   // pass 2 recomputes delta (do not hold it across the exchange)
+#pragma unroll
+                    for (int q = 0; q < M; ++q)
+#pragma unroll
+                        for (int jj = 0; jj < NJ; ++jj) asm volatile("" : "+v"(g[q][jj]));
                 }
                 // ---- the slices' partials summed (in wave order, identical in
                 // every wave), with the dual residual of iteration t-1
@@ -306,7 +330,7 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                 // x_k = a_k + (1 - s) delta (absent points and padded
                 // coordinates give exactly 0)
                 float rp_lane = 0.0f;
-                if (armed) {
+                if (!ES && armed) {
                     float rq[M];
 #pragma unroll
                     for (int q = 0; q < M; ++q) rq[q] = 0.0f;
@@ -322,18 +346,56 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
 #pragma unroll
                     for (int q = 0; q < M; ++q) rp_lane += rq[q];
                 }
-                // ---- pass 2: E = sum_k s delta, g = s delta - a
+                // ---- pass 2: E = sum_k s delta, g = s delta - a (ES: delta again,
+                // e = s delta, armed: lane sums of ||e - s delta||^2)
                 float acc[NJ];
+                if constexpr (ES) {
+                    float rq[M];
 #pragma unroll
-                for (int jj = 0; jj < NJ; ++jj) {
-                    float ac = 0.0f;
+                    for (int q = 0; q < M; ++q) rq[q] = 0.0f;
+                    if (armed) {
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        const float dl = g[q][jj];
-                        ac = fmaf(s[q], dl, ac);
-                        g[q][jj] = fmaf(s[q], dl, na[q][jj]);
+                        for (int jj = 0; jj < NJ; ++jj) {
+                            const float c = cv[jj];
+                            float ac = 0.0f;
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                const float dl = (g[q][jj] + c) + na[q][jj];
+                                const float y = fmaf(-s[q], dl, g[q][jj]);
+                                rq[q] = fmaf(y, y, rq[q]);
+                                ac = fmaf(s[q], dl, ac);
+                                g[q][jj] = s[q] * dl;
+                            }
+                            acc[jj] = ac;
+                        }
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < NJ; ++jj) {
+                            const float c = cv[jj];
+                            float ac = 0.0f;
+#pragma unroll
+                            for (int q = 0; q < M; ++q) {
+                                const float dl = (g[q][jj] + c) + na[q][jj];
+                                ac = fmaf(s[q], dl, ac);
+                                g[q][jj] = s[q] * dl;
+                            }
+                            acc[jj] = ac;
+                        }
                     }
-                    acc[jj] = ac;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) rp_lane += rq[q];
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < NJ; ++jj) {
+                        float ac = 0.0f;
+#pragma unroll
+                        for (int q = 0; q < M; ++q) {
+                            const float dl = g[q][jj];
+                            ac = fmaf(s[q], dl, ac);
+                            g[q][jj] = fmaf(s[q], dl, na[q][jj]);
+                        }
+                        acc[jj] = ac;
+                    }
                 }
                 // keep the new state materialised here (not sunk past the reductions)
 #pragma unroll
