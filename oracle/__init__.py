@@ -82,7 +82,7 @@ def _load():
                                            C.c_double, C.c_double, C.c_double, C.c_double, fp, fp, fp, fp,
                                            C.c_int64, i32p, C.c_double, C.c_int, C.c_int64,
                                            C.c_double, C.c_double, dp, i32p, i32p, dp, dp, dp, C.c_double,
-                                           i32p, C.c_int]
+                                           i32p, C.c_int, C.c_double, i32p]
         lib.oracle_em_batch_ex.restype = C.c_int
         lib.oracle_em_batch.argtypes = [C.c_int64, fp, fp, i64p, i64p, i64p, i32p, i32p,
                                         C.c_double, C.c_double, C.c_double, C.c_int64, i32p,
@@ -269,7 +269,7 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
              max_iter_each=None, nthreads: int = 0, solver: int = SOLVER_ADMM, eps: float = 1e-6,
              box_lo=None, box_hi=None, adapt_every: int = 0, adapt_ratio: float = 10.0,
              adapt_factor: float = 2.0, eta: float = 0.999, ball_center=None,
-             ball_radius=None) -> dict:
+             ball_radius=None, tie_band: float = 2e-6) -> dict:
     """Batch of instances (a ``synth.PointSetBatch`` or anything with a, w, inst,
     z_size, lo, hi).  solver: SOLVER_ADMM (adapt_every > 0: adaptive penalty),
     SOLVER_IRLS, SOLVER_FAST_ADMM (restart parameter eta) or SOLVER_WPEN (the
@@ -278,7 +278,9 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     (float32, one per instance) selects the ball constraint with centres
     ball_center (float32 indexed like z, None = origin).  Returns z (float64,
     concatenated), iters, flags, residuals, the final penalties and the
-    accelerated ADMM's restart counts."""
+    accelerated ADMM's restart counts and its near-tie decisions (ties: those
+    with |c - thr| <= tie_band thr, thr = eta (1 - 2^-16) c_prev, where a run
+    in a lower precision may take either branch)."""
     inst = batch.inst
     B = int(inst.shape[0])
     a = np.ascontiguousarray(batch.a, dtype=np.float32)
@@ -299,6 +301,7 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
     rd = np.zeros(B)
     mf = np.zeros(B)
     rs = np.zeros(B, np.int32)
+    ti = np.zeros(B, np.int32)
     mie = None if max_iter_each is None else np.ascontiguousarray(max_iter_each, dtype=np.int32)
     _load().oracle_em_batch_ex(B, _p(a, C.c_float), _p(w, C.c_float), _p(a_off, C.c_int64),
                                _p(w_off, C.c_int64), _p(z_off, C.c_int64), _p(n, C.c_int32),
@@ -309,8 +312,8 @@ def em_batch(batch, mu: float, max_iter: int, tol: float, init: int = INIT_MAXW,
                                float(adapt_ratio), float(adapt_factor), _p(z, C.c_double),
                                _p(iters, C.c_int32), _p(flags, C.c_int32), _p(rp, C.c_double),
                                _p(rd, C.c_double), _p(mf, C.c_double), float(eta),
-                               _p(rs, C.c_int32), int(nthreads))
-    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf, restarts=rs)
+                               _p(rs, C.c_int32), int(nthreads), float(tie_band), _p(ti, C.c_int32))
+    return dict(z=z, iters=iters, flags=flags, r_pri=rp, r_dual=rd, mu=mf, restarts=rs, ties=ti)
 
 
 def nlem(img, patch_radius: int, window_radius: int, h: float, lo: float, hi: float,

@@ -507,7 +507,8 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
  * The progress measure of the sweep is
  *   c = mu sum_k ||x_k - z||^2 + mu n ||z - z_hat||^2
  * (the squared multiplier change over mu plus mu times the squared change of
- * B z with B the stacked -I blocks).  When c < eta c_prev the next
+ * B z with B the stacked -I blocks).  When c < eta' c_prev, with eta' = eta
+ * (1 - 2^-16), the next
  * predictions extrapolate along the last step with Nesterov's weight: alpha'
  * = (1 + sqrt(1 + 4 alpha^2)) / 2, beta = (alpha - 1) / alpha', z_hat = z +
  * beta (z - z_prev), y_hat = y + beta (y - y_prev), and c_prev = c.  Otherwise
@@ -515,21 +516,34 @@ int oracle_em_solve(int64_t n, int64_t d, const double *a, const double *w,
  * y_prev, alpha' = 1, and c_prev becomes c_prev / eta.  Initially z_hat = z_prev
  * = z0, y_hat = y_prev = 0, alpha = 1 and c_prev = +inf (so the first sweep
  * takes the momentum branch with beta = 0).
+ * The guard factor 1 - 2^-16 is this implementation's reading of the test
+ * c < eta c_prev of [Goldstein2012]: once the iterate stalls (e.g. z held at
+ * a bound of the box with every prox returning its own point) each sweep
+ * repeats the same c, and after a restart the test compares c with
+ * eta (c_prev / eta) = c, an exact tie that exact arithmetic sends to the
+ * restart branch and that rounding sends either way; with the guard the tie
+ * is 1.5e-5 c on the restart side, wider than the rounding of an FP32 run.
+ * Only decisions with c within that band below eta c_prev change branch.
  * Residuals and stopping as for em_solve_set (r_dual from z - z_prev).
- * *restarts (nullable) receives the number of restarts.  No decision is
+ * *restarts (nullable) receives the number of restarts.  *ties (nullable,
+ * batch entry only) counts the decisions with a finite c_prev and
+ * |c - eta' c_prev| <= tie_band eta' c_prev: there c and the threshold agree
+ * to within the rounding of a lower-precision run of the same sweeps, so
+ * either branch is a correct run.  No decision is
  * taken after the last allowed sweep (nothing follows it), so a solve that
  * stops at sweep T, by the tolerance or by max_iter = T, reports the
  * decisions of sweeps 1..T-1.
  */
-int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w, double mu,
-                         const double *lo, const double *hi, double *z, int64_t max_iter,
-                         double tol, double eta, int64_t *iters, double *r_pri, double *r_dual,
-                         int64_t *restarts)
+static int em_solve_fast_set(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                             const double *lo, const double *hi, double *z, int64_t max_iter,
+                             double tol, double eta, double tie_band, int64_t *iters,
+                             double *r_pri, double *r_dual, int64_t *restarts, int64_t *ties)
 {
     *iters = 0;
     *r_pri = 0.0;
     *r_dual = 0.0;
     if (restarts) *restarts = 0;
+    if (ties) *ties = 0;
     or_set_t C = {lo, hi, NULL, 0.0};
     int screened = admm_screen(n, d, a, w, &C, z);
     if (screened) return screened;
@@ -547,6 +561,7 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
     memcpy(z_prev, z, (size_t)d * sizeof(double));
     memcpy(z_hat, z, (size_t)d * sizeof(double));
     double alpha = 1.0, c_prev = INFINITY;
+    const double eta_g = eta * (1.0 - 0x1p-16);
 
     int flags = OR_MAXITER;
     for (int64_t t = 1; t <= max_iter; ++t) {
@@ -571,7 +586,9 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
         }
         if (t == max_iter) break;   /* the decision would change nothing */
         const double c = mu * (sp + (double)n * sh);
-        if (c < eta * c_prev) {
+        const double thr = eta_g * c_prev;
+        if (ties && isfinite(c_prev) && fabs(c - thr) <= tie_band * thr) ++*ties;
+        if (c < thr) {
             const double alpha_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * alpha * alpha));
             const double beta = (alpha - 1.0) / alpha_next;
             for (int64_t j = 0; j < d; ++j) z_hat[j] = z[j] + beta * (z[j] - z_prev[j]);
@@ -595,6 +612,15 @@ int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w,
     free(z_prev);
     free(z_hat);
     return flags;
+}
+
+int oracle_em_solve_fast(int64_t n, int64_t d, const double *a, const double *w, double mu,
+                         const double *lo, const double *hi, double *z, int64_t max_iter,
+                         double tol, double eta, int64_t *iters, double *r_pri, double *r_dual,
+                         int64_t *restarts)
+{
+    return em_solve_fast_set(n, d, a, w, mu, lo, hi, z, max_iter, tol, eta, 0.0, iters, r_pri,
+                             r_dual, restarts, NULL);
 }
 
 /*
@@ -784,7 +810,8 @@ int oracle_max_threads(void)
  * Otherwise box_lo / box_hi (nullable, float32, indexed like
  * z) give per-coordinate bounds; otherwise [lo, hi] for every coordinate.
  * mu_out (nullable): the final penalty per instance; restarts_out (nullable):
- * the accelerated ADMM's restart count per instance.
+ * the accelerated ADMM's restart count per instance; ties_out (nullable): its
+ * count of decisions within tie_band (relative) of the threshold.
  */
 int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t *a_off,
                        const int64_t *w_off, const int64_t *z_off, const int32_t *n_arr,
@@ -794,7 +821,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
                        const int32_t *max_iter_each, double tol, int init, int64_t adapt_every,
                        double adapt_ratio, double adapt_factor, double *z, int32_t *iters,
                        int32_t *flags, double *r_pri, double *r_dual, double *mu_out, double eta,
-                       int32_t *restarts_out, int nthreads)
+                       int32_t *restarts_out, int nthreads, double tie_band, int32_t *ties_out)
 {
     set_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -829,7 +856,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
                 zb[j] = s / (W > 0.0 ? W : (double)n);
             }
         }
-        int64_t it = 0, rs = 0;
+        int64_t it = 0, rs = 0, ti = 0;
         double rp = 0.0, rd = 0.0, mf = mu;
         int64_t mi = max_iter_each ? max_iter_each[b] : max_iter;
         int f;
@@ -838,7 +865,8 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         else if (solver == 4)
             f = em_solve_wpen_set(n, d, ab, wb, mu, &C, zb, mi, tol, &it, &rp, &rd);
         else if (solver == 3)
-            f = oracle_em_solve_fast(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, &it, &rp, &rd, &rs);
+            f = em_solve_fast_set(n, d, ab, wb, mu, lv, hv, zb, mi, tol, eta, tie_band, &it, &rp, &rd,
+                                  &rs, &ti);
         else
             f = em_solve_set(n, d, ab, wb, mu, &C, zb, NULL, NULL, mi, tol, adapt_every, adapt_ratio,
                              adapt_factor, &it, &rp, &rd, &mf);
@@ -848,6 +876,7 @@ int oracle_em_batch_ex(int64_t B, const float *a, const float *w, const int64_t 
         if (r_dual) r_dual[b] = rd;
         if (mu_out) mu_out[b] = mf;
         if (restarts_out) restarts_out[b] = (int32_t)rs;
+        if (ties_out) ties_out[b] = (int32_t)ti;
         free(ab);
         free(wb);
         free(lv);
@@ -866,7 +895,7 @@ int oracle_em_batch(int64_t B, const float *a, const float *w, const int64_t *a_
 {
     return oracle_em_batch_ex(B, a, w, a_off, w_off, z_off, n_arr, d_arr, 0, mu, 1.0, lo, hi, NULL,
                               NULL, NULL, NULL, max_iter, max_iter_each, tol, init, 0, 10.0, 2.0, z,
-                              iters, flags, r_pri, r_dual, NULL, 0.999, NULL, nthreads);
+                              iters, flags, r_pri, r_dual, NULL, 0.999, NULL, nthreads, 0.0, NULL);
 }
 
 /* Symmetric (edge-repeating) reflection of index i into [0, N); needs |overhang| <= N. */

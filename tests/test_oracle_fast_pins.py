@@ -122,3 +122,44 @@ def test_restart_threshold_scales_with_eta(orc, eta):
         r = orc.em_solve_fast([[0.0], [1.0], [5.0]], [1.0, 1.0, 1.0], 1.0, 0.0, 10.0, [3.0],
                               max_iter=T, tol=0.0, eta=eta)
         assert r["restarts"] == rs
+
+
+def test_stalled_iterate_exact_tie_goes_to_restart(orc):
+    """Points 5 and 6 with weights 1e6 (lambda = 1e6, every prox returns its
+    own point), mu = 1, box [0, 1], z0 = 1.  Every sweep has x = a and z = 1
+    (the mean of x + y_hat is above 1), so c = (5 - 1)^2 + (6 - 1)^2 = 41 on
+    every sweep while y drifts by a - 1.  With eta' = eta (1 - 2^-16):
+      t = 1: c = 41 < eta' inf: momentum (beta_1 = 0), c_prev = 41.
+      t = 2: 41 >= eta' 41: restart (margin 1e-3), c_prev = 41 / eta.
+      t = 3: 41 against eta' (41 / eta) = 41 (1 - 2^-16): the exact tie of
+        the unguarded test, now 1.5e-5 on the restart side: restart,
+        c_prev = 41 / eta^2 (z_hat, y_hat from the start of sweep 3).
+      t = 4: 41 < eta' 41 / eta^2: momentum (margin 1e-3), c_prev = 41.
+      t = 5: as t = 2: restart.
+    Restarts after T sweeps (decisions 1 .. T - 1): 0, 1, 2, 2, 3 for
+    T = 2 .. 6.  The batch entry's tie count sees the t = 3 decision with a
+    band of 2e-5 and none with the default 2e-6; the decisions worked out by
+    hand for the other instances of this file (sweeps 1 .. 3) count nothing."""
+    import numpy as np
+    from synth.pointsets import pack_instances
+    pts = [np.array([[5.0], [6.0]], np.float32), np.array([[1.0], [3.0], [5.0]], np.float32),
+           np.array([[0.0], [1.0], [5.0]], np.float32)]
+    ws = [np.array([1e6, 1e6], np.float32), np.full(3, 2.0, np.float32), np.ones(3, np.float32)]
+    b = pack_instances(pts, ws, 0.0, 1.0)
+    lo = np.array([0.0, -10.0, 0.0], np.float32)
+    hi = np.array([1.0, 10.0, 10.0], np.float32)
+    z0 = np.array([1.0, 4.0, 3.0])
+
+    def run(T, band=2e-6):
+        return orc.em_batch(b, 1.0, T, 0.0, init=orc.INIT_GIVEN, z0=z0, solver=orc.SOLVER_FAST_ADMM,
+                            box_lo=lo, box_hi=hi, tie_band=band)
+
+    for T, rs in ((2, 0), (3, 1), (4, 2), (5, 2), (6, 3)):
+        r = run(T)
+        assert r["z"][0] == 1.0 and r["restarts"][0] == rs, (T, r["restarts"])
+        assert r["ties"][0] == 0
+        if T <= 4:
+            assert r["ties"][1] == 0 and r["ties"][2] == 0, (T, r["ties"])
+    assert run(4, 2e-5)["ties"][0] == 1
+    assert run(3, 2e-5)["ties"][0] == 0
+    assert run(6, 1.0)["ties"][0] == 4   # decisions 2 .. 5 (t = 1 compares with an infinite c_prev)
