@@ -159,7 +159,7 @@ typedef enum {
     EM_SOLVER_ADMM = 0,          /* Algorithm 1, fixed penalty rho (as em_solve_batch) */
     EM_SOLVER_IRLS = 1,          /* IRLS on the smooth surrogate (EM_surrogate), parameter eps */
     EM_SOLVER_ADMM_ADAPTIVE = 2, /* Algorithm 1 with the penalty adapted by residual balancing */
-    EM_SOLVER_ADMM_FAST = 3,     /* accelerated ADMM with restart (em_solve_plain_ex only) */
+    EM_SOLVER_ADMM_FAST = 3,     /* accelerated ADMM with restart (boxes; em_solve_batch_ex, em_solve_plain_ex) */
     EM_SOLVER_ADMM_WEIGHTED = 4  /* consensus ADMM with penalty rho w_k per constraint (a weighted-
                                     mean z-update; a different algorithm from Algorithm 1) */
 } em_solver_t;
@@ -184,7 +184,7 @@ typedef struct {
     int32_t adapt_every;   /* ADAPTIVE: balance after every adapt_every-th iteration (>= 1) */
     float adapt_ratio;     /* ADAPTIVE: imbalance ratio that triggers a change (> 1, e.g. 10) */
     float adapt_factor;    /* ADAPTIVE: factor applied to rho (> 1, e.g. 2) */
-    float fast_eta;        /* FAST: restart parameter eta in (0, 1) (0.999 in the reference) */
+    float fast_eta;        /* FAST: restart parameter eta in (0, 1) (0.999 in [Goldstein2012]) */
     int32_t set;           /* em_set_t: the convex set C */
     const float *ball_center; /* BALL: NULL (origin) or centres, device, indexed like z */
     const float *ball_radius; /* BALL: NULL (use radius) or one radius per instance, device */
@@ -222,6 +222,11 @@ typedef struct {
  *     quadratic majoriser); stopped on r_dual alone (stats r_pri = 0); all
  *     weights zero: every point of C is a minimiser, z becomes the start
  *     projected onto C and the solve reports CONVERGED after one iteration.
+ *   EM_SOLVER_ADMM_FAST: the accelerated ADMM with restart, as documented
+ *     at em_solve_plain_ex (same iterates, both residuals tested every
+ *     sweep, restarts counted in flags >> EM_RESTART_SHIFT), batched: 8
+ *     coordinates per wave, up to 8 waves and 8 points per lane, its
+ *     second n x d state in registers.  Boxes only.
  *   EM_SOLVER_ADMM_WEIGHTED: the consensus splitting of Section 2 with the
  *     penalty rho w_k on the constraint x_k = z of point k instead of one rho
  *     for all: x_k = prox with threshold w_k / (rho w_k) = 1 / rho at
@@ -233,8 +238,8 @@ typedef struct {
  * Errors: INVALID_ARG (NULL options, bad solver or init, rho <= 0 for ADMM,
  * eps <= 0 for IRLS, adapt_every < 1, adapt_ratio <= 1 or adapt_factor <= 1
  * for ADAPTIVE, one of box_lo / box_hi NULL, a bad set, a ball with box
- * arrays, and em_solve_batch's errors); UNSUPPORTED for EM_SOLVER_ADMM_FAST
- * (see em_solve_plain_ex) and for the ball with ADAPTIVE; HIP.
+ * arrays, fast_eta outside (0, 1) for FAST, and em_solve_batch's errors);
+ * UNSUPPORTED for the ball with ADAPTIVE or FAST; HIP.
  */
 em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
                               const float *a, const float *w, const em_instance_t *inst,
@@ -249,16 +254,20 @@ em_status_t em_solve_batch_ex(em_handle_t handle, void *stream, int64_t B,
  *   x_k = prox at z_hat - y_hat_k / rho, z = P_C(mean_k(x_k + y_hat_k / rho)),
  *   y_k = y_hat_k + rho (x_k - z),
  *   c = rho (sum_k ||x_k - z||^2 + n ||z - z_hat||^2);
- *   c < fast_eta c_prev: alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2, beta =
+ *   c < fast_eta (1 - 2^-16) c_prev: alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2, beta =
  *     (alpha - 1) / alpha', z_hat = z + beta (z - z_prev),
  *     y_hat = y + beta (y - y_prev);
  *   otherwise restart: z_hat = z_prev, y_hat = y_prev, alpha = 1,
  *     c_prev = c_prev / fast_eta
  * (alpha = 1 and c_prev = +inf at the start; no decision is taken after the
  * last allowed sweep, and stats.flags >> EM_RESTART_SHIFT counts the
- * restarts).  Residuals and stopping as for
+ * restarts).  The guard 1 - 2^-16 on the momentum test resolves the exact
+ * ties of a stalled iterate (each sweep repeating c, then c against
+ * fast_eta (c / fast_eta) after a restart) to the restart side, as exact
+ * arithmetic does, in FP32 as in the FP64 oracle.  Residuals and stopping as for
  * em_solve_batch, evaluated every iteration.  Its momentum needs the previous
- * multipliers, a second n x d state, which this path keeps in device memory.
+ * multipliers, a second n x d state, which this path keeps in device memory
+ * (em_solve_batch_ex runs the same solver batched, the state in registers).
  * Other solvers and the ball return EM_ERR_UNSUPPORTED; arguments and errors
  * otherwise as em_solve_plain and em_solve_batch_ex (fast_eta must be in
  * (0, 1)).

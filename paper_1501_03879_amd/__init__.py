@@ -175,9 +175,9 @@ class Handle:
                           lo=-float("inf"), hi=float("inf"), box_lo=None, box_hi=None, rho=1.0,
                           eps=1e-6, max_iter=1000, tol=1e-4, adapt_every=1, adapt_ratio=10.0,
                           adapt_factor=2.0, ball_center=None, ball_radius=None, radius=None,
-                          stream=None):
+                          eta=0.999, stream=None):
         """em_solve_batch with a solver choice (ADMM, IRLS, adaptive-penalty ADMM,
-        weighted-penalty ADMM)
+        accelerated ADMM with restart parameter eta, weighted-penalty ADMM)
         and a general set: per-coordinate bounds box_lo / box_hi (float32 device
         tensors laid out like z), or the Euclidean ball when `radius` (scalar)
         or `ball_radius` (one per instance) is given, centred at ball_center
@@ -185,7 +185,7 @@ class Handle:
         as FP16 point storage."""
         B = int(inst.numel() * inst.element_size() // 32)
         opt = _options(solver, init, lo, hi, box_lo, box_hi, rho, eps, max_iter, tol, adapt_every,
-                       adapt_ratio, adapt_factor, 0.999, ball_center, ball_radius, radius)
+                       adapt_ratio, adapt_factor, eta, ball_center, ball_radius, radius)
         import torch
         opt.points_f16 = 1 if a.dtype == torch.float16 else 0
         st = self.lib.em_solve_batch_ex(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),

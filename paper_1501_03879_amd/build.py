@@ -18,7 +18,7 @@ LIB = os.environ.get("EMX_BUILD_OUTPUT") or os.path.join(HERE, "libemx.so")
 BUILD_DIR = os.environ.get("EMX_BUILD_DIR") or os.path.join(HERE, "_build")
 SOURCES = ["nlem_pr0.hip", "nlem_pr1.hip", "nlem_pr2.hip", "nlem_pr3.hip", "batch_admm.hip",
            "batch_irls.hip", "batch_adapt.hip", "batch_admm_ball.hip", "batch_irls_ball.hip",
-           "batch_wpen.hip", "batch_wpen_ball.hip", "batch_wide.hip",
+           "batch_wpen.hip", "batch_wpen_ball.hip", "batch_wide.hip", "batch_fast.hip",
            "batch_host.hip", "nlem_order.hip",
            "emx_host.hip"]
 ARCH = os.environ.get("EMX_OFFLOAD_ARCH", "gfx950")

@@ -28,7 +28,7 @@ em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fo
 // and class): a million instances over twenty counters would otherwise
 // serialise on the hot ones.
 __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t *inst, int64_t B, float *z,
-                                                            em_stats_t *stats, unsigned int *counts, int wide) {
+                                                            em_stats_t *stats, unsigned int *counts, int mode) {
     __shared__ unsigned int hist[kNumAllClasses];
     for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t 
                 for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
             if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
         } else {
-            atomicAdd(&hist[class_of(e.n, e.d, wide != 0)], 1u);
+            atomicAdd(&hist[class_of(e.n, e.d, mode)], 1u);
         }
     }
     __syncthreads();
@@ -65,7 +65,7 @@ __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *of
 // (block, class) reserves the block's range of the class list.
 __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_t *inst, int64_t B,
                                                               const unsigned int *offsets, unsigned int *fill,
-                                                              int32_t *list, int wide) {
+                                                              int32_t *list, int mode) {
     __shared__ unsigned int lcnt[kNumAllClasses];
     __shared__ unsigned int lbase[kNumAllClasses];
     for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) lcnt[i] = 0u;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_
     if (b < B) {
         const em_instance_t e = inst[b];
         if (e.n > 0 && e.n <= EM_MAX_N && e.d >= 1 && e.d <= EM_MAX_D) {
-            c = class_of(e.n, e.d, wide != 0);
+            c = class_of(e.n, e.d, mode);
             rank = atomicAdd(&lcnt[c], 1u);
         }
     }
@@ -138,6 +138,7 @@ static ClassLaunch class_launch(const float *a, const float *w, const em_instanc
     L.a16 = o.points_f16 ? 1 : 0;
     L.single = -1;
     L.outlier = kOutlierK;
+    L.fast_eta = o.fast_eta;
     return L;
 }
 
@@ -153,6 +154,8 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     // kernel, far-outlier instances to the deferred lists
     const int wide = (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX && !wide_disabled()) ? 1 : 0;
     const bool defer = o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX;
+    const bool fast = o.solver == EM_SOLVER_ADMM_FAST;   // its own classes (batch_fast.hpp)
+    const int mode = fast ? 2 : wide;
     // workspace: list[B] int32, then (deferral) the deferred lists of B each
     em_status_t st;
     int32_t *list = static_cast<int32_t *>(
@@ -169,9 +172,9 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     st = ctx_reset_counters(ctx, s, cnt, NC);
     if (st != EM_OK) return st;
     const unsigned nb = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, wide);
+    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, mode);
     hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
-    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, wide);
+    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, mode);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
     const ClassKernel *tab = class_table(o);
@@ -188,10 +191,16 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the class streams");
     const ClassKernel *wtab = batch_wide_table();
+    const ClassKernel *ftab = batch_fast_table();
     int launched = 0;
     for (int c = 0; c < K; ++c) {
-        if (c >= kNumClasses ? !wide : (wide && class_unused_with_wide(c))) continue;
-        const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
+        const bool skip = fast ? c < kFirstFastClass
+                               : (c >= kFirstFastClass ||
+                                  (c >= kNumClasses ? !wide : (wide && class_unused_with_wide(c))));
+        if (skip) continue;
+        const ClassKernel &ck = (c >= kFirstFastClass) ? ftab[c - kFirstFastClass]
+                                : (c >= kNumClasses)  ? wtab[c - kNumClasses]
+                                                      : tab[c];
         const int si = launched++ % (kSideStreams + 1);
         hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
@@ -252,7 +261,8 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
 //     n ||z - z_hat||^2) decides between momentum
 //     (z_hat = z + beta (z - z_prev), u_hat = u + beta (u - u_prev),
 //     beta = (alpha - 1) / alpha', alpha' = (1 + sqrt(1 + 4 alpha^2)) / 2) and
-//     a restart (z_hat = z_prev, u_hat = u_prev, alpha = 1, c_prev /= eta),
+//     a restart (z_hat = z_prev, u_hat = u_prev, alpha = 1, c_prev /= eta)
+//     (momentum while c < eta (1 - 2^-16) c_prev),
 //     except after the last allowed sweep; the restart count goes to the
 //     flags word.  u = y / mu throughout (mu is fixed).
 constexpr int kMaxRestartCount = (1 << 23) - 1;
@@ -437,7 +447,7 @@ __global__ __launch_bounds__(256) void plain_solve_kernel(PlainArgs P) {
             const float sh2 = block_sum256(shl, red);
             if (t == P.max_iter) break;   // no sweep follows: the decision would change nothing
             const float c = P.mu * (sp + (float)n * sh2);
-            if (c < P.eta * c_prev) {
+            if (c < P.eta * (1.0f - 0x1p-16f) * c_prev) {   // guard: see batch_fast.hpp
                 const float an = 0.5f * (1.0f + sqrtf(1.0f + 4.0f * alpha * alpha));
                 const float beta = (alpha - 1.0f) / an;
                 for (int j = tid; j < d; j += 256) zh[j] = zs[j] + beta * (zs[j] - zprev[j]);

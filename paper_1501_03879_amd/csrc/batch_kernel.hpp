@@ -74,10 +74,20 @@ constexpr int kWideNJ = 13;
 constexpr int kWideMaxM = 7;
 constexpr int kWideMinWC = 2, kWideMaxWC = 5;
 constexpr int kNumWideClasses = (kWideMaxWC - kWideMinWC + 1) * kWideMaxM;
-constexpr int kNumAllClasses = kNumClasses + kNumWideClasses;
+// Classes of the accelerated ADMM (batch_fast.hpp): 8-coordinate slices over
+// WC in {1, 2, 4, 8} waves (the smallest with 8 WC >= d) and M in {1, 2, 4, 8}
+// points per lane (the smallest with 64 M >= n); ids after the sliced ones.
+constexpr int kNumFastClasses = 16;
+constexpr int kFirstFastClass = kNumClasses + kNumWideClasses;
+constexpr int kNumAllClasses = kFirstFastClass + kNumFastClasses;
 
-__host__ __device__ inline int class_of(int n, int d, bool wide) {
-    if (wide && d > 16 && n <= 64 * kWideMaxM) {
+__host__ __device__ constexpr int pow2_index(int v) { return v <= 1 ? 0 : v <= 2 ? 1 : v <= 4 ? 2 : 3; }
+
+// mode 0: generic classes; 1: sliced classes where they apply (fixed-penalty
+// EM-ADMM over a box); 2: the accelerated ADMM's classes
+__host__ __device__ inline int class_of(int n, int d, int mode) {
+    if (mode == 2) return kFirstFastClass + 4 * pow2_index((d + 7) / 8) + pow2_index((n + 63) / 64);
+    if (mode == 1 && d > 16 && n <= 64 * kWideMaxM) {
         const int wc = (d + kWideNJ - 1) / kWideNJ;
         const int m = (n + 63) / 64;
         return kNumClasses + (wc - kWideMinWC) * kWideMaxM + (m - 1);
@@ -120,6 +130,7 @@ struct ClassLaunch {
     // defer_list + k * defer_stride, its count at defer_q[2 k + 1]
     // (defer_q[2 k] stays 0); null defer_q: no deferral
     float outlier;
+    float fast_eta;               // accelerated ADMM: restart when c >= fast_eta c_prev
     int32_t *defer_list;
     int64_t defer_stride;
     unsigned int *defer_q;
@@ -1072,5 +1083,6 @@ const ClassKernel *batch_wide_table();   // kNumWideClasses entries
 // d <= 64 (four), both n <= 512 (2 x 4 points per lane).
 constexpr int kDeferLists = 2;
 const ClassKernel *batch_deferred_table();
+const ClassKernel *batch_fast_table();   // kNumFastClasses entries
 
 }  // namespace emx

@@ -50,10 +50,44 @@ struct WideShape {
 template <int NJ, int M, int WC, typename T>
 __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, int lane, int j0, float *stage,
                                              float (&na)[M][NJ], float &amax, bool &bad) {
+    const int pitch = d | 1;
+    if constexpr (WC == 1 && NJ <= 16) {
+        // one wave and d <= NJ: a chunk's 64 d values are contiguous, so copy
+        // them flat (element i = lane + 64 k, row i / d by a float reciprocal,
+        // exact for i < 2^22) rather than one row of d <= 16 values per load
+        const float inv_d = 1.0f / (float)d;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            if (q > 0) __syncthreads();
+            const int cnt = min(64, max(0, n - q * 64)) * d;   // values in the chunk
+            T raw[NJ];
+#pragma unroll
+            for (int k = 0; k < NJ; ++k) {
+                const int i = lane + 64 * k;
+                raw[k] = A[(i < cnt) ? q * 64 * d + i : 0];
+            }
+#pragma unroll
+            for (int k = 0; k < NJ; ++k) {
+                const int i = lane + 64 * k;
+                const int r = (int)(((float)i + 0.5f) * inv_d);
+                if (i < cnt) stage[r * pitch + (i - r * d)] = (float)raw[k];
+            }
+            __syncthreads();
+            const bool vp = q * 64 + lane < n;
+#pragma unroll
+            for (int jj = 0; jj < NJ; ++jj) {
+                const int j = j0 + jj;
+                const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
+                bad |= !(fabsf(v) <= FLT_MAX);
+                amax = fmaxf(amax, fabsf(v));
+                na[q][jj] = -v;
+            }
+        }
+        return;
+    }
     constexpr int RK = (64 + WC - 1) / WC;                 // rows per wave and chunk
     constexpr int LA0 = 112 / RK;                          // ~112 VGPRs of loads in flight
     constexpr int LA = LA0 < 1 ? 1 : (LA0 > M ? M : LA0);
-    const int pitch = d | 1;
     const int step = WC * d;
     T raw[LA][RK];
     auto issue = [&](int q) {
@@ -89,6 +123,131 @@ __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, i
     }
 }
 
+// Per-instance set-up shared by the sliced kernels, between the queue pop and
+// the solve: the weights (lam; -1 on empty slots), the lane's slices of its
+// points as -a (na), the starting z and the bounds of the lane's coordinate,
+// the checks that make an instance BAD_INPUT, and the tolerance scale D
+// (flag_s cleared by the pop).  The starting z goes to the wave's broadcast
+// slot cv[cidx] (slots of coordinates >= d get 0).
+struct WideStart {
+    float zr, blo, bhi;      // the owned coordinate's z^0 and bounds
+    bool bad_all;            // the instance is BAD_INPUT
+    float Dscale, amax_all;  // tolerance scale D and the largest |a|
+};
+
+template <int NJ, int M, int WC>
+__device__ __forceinline__ WideStart wide_start(const ClassLaunch &L, const em_instance_t &e, int n, int d, int cw,
+                                                int lane, bool holds, bool own, int j0, int cj, float *stage,
+                                                int *flag_s, float *cv, int cidx, float (&lam)[M],
+                                                float (&na)[M][NJ]) {
+    const float *A = L.a + e.a_off;
+    const __half *A16 = reinterpret_cast<const __half *>(L.a) + e.a_off;
+    const float *Wt = L.w + e.w_off;
+    const float *Z = L.z + e.z_off;
+    const bool vbox = L.box_lo != nullptr;
+    // ---- weights of the lane's points, and (largest-weight start) the
+    // chosen point, before the points: their loads overlap the staging
+    bool bad_l = false;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        // unconditional loads (slots past n read weight 0, then drop it):
+        // no branch, so all of them are in flight together
+        const int p = q * 64 + lane;
+        const float wr = Wt[min(p, n - 1)];
+        const float wv = (p < n) ? wr : 0.0f;
+        bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
+        lam[q] = (p < n) ? wv : -1.0f;   // the weight for now (-1: no point)
+    }
+    float zr = 0.0f;
+    if (L.init == EM_INIT_MAXW) {
+        // the point of largest weight, lowest index on ties (every wave
+        // holds all the weights, so no exchange is needed)
+        float wb = -1.0f;
+        int pb = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < M; ++q)
+            if (lam[q] > wb) wb = lam[q], pb = q * 64 + lane;
+        const float wm = wave_max(wb);
+        const float cand = (wb == wm) ? (float)pb : 3.0e38f;
+        // (no weight >= 0 at all leaves no candidate: the instance is bad
+        // and the clamp only keeps the read inside it)
+        const int best = min(uniform_int((int)(-wave_max(-cand))), n - 1);
+        if (own) zr = L.a16 ? __half2float(A16[(int64_t)best * d + cj]) : A[(int64_t)best * d + cj];
+    } else if (L.init == EM_INIT_GIVEN) {
+        if (own) zr = Z[cj];
+    }
+    float blo = L.lo, bhi = L.hi;
+    if (own && vbox) {
+        blo = L.box_lo[e.z_off + cj];
+        bhi = L.box_hi[e.z_off + cj];
+    }
+
+    // ---- stage the points, 64 at a time through LDS: wave w copies rows
+    // w, w + WC, ... of a chunk (one row of d values per load, all of a
+    // chunk's loads issued together, the next chunk's loads in flight
+    // while this one is read back); every lane then keeps its slice of
+    // its point as -a
+    float amax = 0.0f;
+    if (L.a16)
+        stage_points<NJ, M, WC>(A16, n, d, cw, lane, j0, stage, na, amax, bad_l);
+    else
+        stage_points<NJ, M, WC>(A, n, d, cw, lane, j0, stage, na, amax, bad_l);
+    const float wamax = wave_max(amax);
+    if (__any(bad_l) && lane == 0) flag_s[0] = 1;
+    if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
+
+    if (L.init == EM_INIT_WMEAN) {
+        // sum_k w_k a_k / sum_k w_k, weights scaled by their largest value and
+        // points by 1/n (no overflow); every weight zero: equal weights
+        float wl = 0.0f;
+#pragma unroll
+        for (int q = 0; q < M; ++q) wl = fmaxf(wl, lam[q]);
+        const float wmx = readfirstlane(wave_max(wl));
+        const bool uni = !(wmx > 0.0f);
+        const float sw = uni ? 0.0f : 1.0f / wmx;
+        const float inv_n = 1.0f / (float)n;
+        float cq[M];
+        float cs = 0.0f;
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            cq[q] = (lam[q] >= 0.0f) ? (uni ? 1.0f : lam[q] * sw) * inv_n : 0.0f;
+            cs += cq[q];
+        }
+        float acc[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+            float ac = 0.0f;
+#pragma unroll
+            for (int q = 0; q < M; ++q) ac = fmaf(-cq[q], na[q][jj], ac);   // na = -a
+            acc[jj] = ac;
+        }
+        const float sum = reduce_scatter_full<NJ>(acc, lane, holds);
+        const float Cs = readfirstlane(wave_sum(cs));
+        if (own) zr = sum * (1.0f / Cs);
+    }
+    bool zbad = false;
+    float wid = 0.0f;
+    if (own) {
+        zbad = !(fabsf(zr) <= FLT_MAX) || !(blo <= bhi);
+        wid = bhi - blo;
+        if (!(wid >= 0.0f)) wid = 0.0f;
+    }
+    const float wwid = wave_max(wid);
+    if (__any(zbad) && lane == 0) flag_s[2] = 1;
+    if (lane == 0) atomicMax(&flag_s[3], __float_as_int(wwid));
+    cv[cidx] = zr;
+    __syncthreads();
+    WideStart r;
+    r.zr = zr;
+    r.blo = blo;
+    r.bhi = bhi;
+    r.bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
+    const float wmax = readfirstlane(__int_as_float(flag_s[3]));
+    r.amax_all = readfirstlane(__int_as_float(flag_s[1]));
+    r.Dscale = (wmax <= FLT_MAX && wmax > 0.0f) ? wmax : fmaxf(1.0f, r.amax_all);
+    return r;
+}
+
 // ES: carry the prox displacement e itself instead of g = e - a (as the
 // generic kernel's SOLVER 5 for deferred far-outlier instances, see
 // ClassLaunch): delta = (e + c) - a in both passes and x_k - c = e - s delta
@@ -118,7 +277,6 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
     const unsigned int cbeg = one ? 0u : L.offsets[L.cls];
     const unsigned int ccount = one ? 1u : L.offsets[L.cls + 1] - cbeg;
     unsigned int taken = 0;   // thread 0, single-instance mode: instances taken
-    const bool vbox = L.box_lo != nullptr;
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -134,112 +292,19 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
         const int b = one ? (int)L.single : uniform_int(L.list[cbeg + it]);
         const em_instance_t e = L.inst[b];
         const int n = uniform_int(e.n), d = uniform_int(e.d);
-        const float *A = L.a + e.a_off;
-        const __half *A16 = reinterpret_cast<const __half *>(L.a) + e.a_off;
-        const float *Wt = L.w + e.w_off;
         float *Z = L.z + e.z_off;
         const int j0 = cw * NJ;                  // first coordinate of the slice
         const int cj = j0 + myc;                 // the coordinate this lane owns after the reduce-scatter
         const bool own = holds && cj < d;
 
-        // ---- weights of the lane's points, and (largest-weight start) the
-        // chosen point, before the points: their loads overlap the staging
         float lam[M];
-        bool bad_l = false;
-#pragma unroll
-        for (int q = 0; q < M; ++q) {
-            // unconditional loads (slots past n read weight 0, then drop it):
-            // no branch, so all of them are in flight together
-            const int p = q * 64 + lane;
-            const float wr = Wt[min(p, n - 1)];
-            const float wv = (p < n) ? wr : 0.0f;
-            bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
-            lam[q] = (p < n) ? wv : -1.0f;   // the weight for now (-1: no point)
-        }
-        float zr = 0.0f;
-        if (L.init == EM_INIT_MAXW) {
-            // the point of largest weight, lowest index on ties (every wave
-            // holds all the weights, so no exchange is needed)
-            float wb = -1.0f;
-            int pb = 0x7fffffff;
-#pragma unroll
-            for (int q = 0; q < M; ++q)
-                if (lam[q] > wb) wb = lam[q], pb = q * 64 + lane;
-            const float wm = wave_max(wb);
-            const float cand = (wb == wm) ? (float)pb : 3.0e38f;
-            // (no weight >= 0 at all leaves no candidate: the instance is bad
-            // and the clamp only keeps the read inside it)
-            const int best = min(uniform_int((int)(-wave_max(-cand))), n - 1);
-            if (own) zr = L.a16 ? __half2float(A16[(int64_t)best * d + cj]) : A[(int64_t)best * d + cj];
-        } else if (L.init == EM_INIT_GIVEN) {
-            if (own) zr = Z[cj];
-        }
-        float blo = L.lo, bhi = L.hi;
-        if (own && vbox) {
-            blo = L.box_lo[e.z_off + cj];
-            bhi = L.box_hi[e.z_off + cj];
-        }
-
-        // ---- stage the points, 64 at a time through LDS: wave w copies rows
-        // w, w + WC, ... of a chunk (one row of d values per load, all of a
-        // chunk's loads issued together, the next chunk's loads in flight
-        // while this one is read back); every lane then keeps its slice of
-        // its point as -a
         float na[M][NJ];
-        float amax = 0.0f;
-        if (L.a16)
-            stage_points<NJ, M, WC>(A16, n, d, cw, lane, j0, stage, na, amax, bad_l);
-        else
-            stage_points<NJ, M, WC>(A, n, d, cw, lane, j0, stage, na, amax, bad_l);
-        const float wamax = wave_max(amax);
-        if (__any(bad_l) && lane == 0) flag_s[0] = 1;
-        if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
-
-        if (L.init == EM_INIT_WMEAN) {
-            // sum_k w_k a_k / sum_k w_k, weights scaled by their largest value and
-            // points by 1/n (no overflow); every weight zero: equal weights
-            float wl = 0.0f;
-#pragma unroll
-            for (int q = 0; q < M; ++q) wl = fmaxf(wl, lam[q]);
-            const float wmx = readfirstlane(wave_max(wl));
-            const bool uni = !(wmx > 0.0f);
-            const float sw = uni ? 0.0f : 1.0f / wmx;
-            const float inv_n = 1.0f / (float)n;
-            float cq[M];
-            float cs = 0.0f;
-#pragma unroll
-            for (int q = 0; q < M; ++q) {
-                cq[q] = (lam[q] >= 0.0f) ? (uni ? 1.0f : lam[q] * sw) * inv_n : 0.0f;
-                cs += cq[q];
-            }
-            float acc[NJ];
-#pragma unroll
-            for (int jj = 0; jj < NJ; ++jj) {
-                float ac = 0.0f;
-#pragma unroll
-                for (int q = 0; q < M; ++q) ac = fmaf(-cq[q], na[q][jj], ac);   // na = -a
-                acc[jj] = ac;
-            }
-            const float sum = reduce_scatter_full<NJ>(acc, lane, holds);
-            const float Cs = readfirstlane(wave_sum(cs));
-            if (own) zr = sum * (1.0f / Cs);
-        }
-        bool zbad = false;
-        float wid = 0.0f;
-        if (own) {
-            zbad = !(fabsf(zr) <= FLT_MAX) || !(blo <= bhi);
-            wid = bhi - blo;
-            if (!(wid >= 0.0f)) wid = 0.0f;
-        }
-        const float wwid = wave_max(wid);
-        if (__any(zbad) && lane == 0) flag_s[2] = 1;
-        if (lane == 0) atomicMax(&flag_s[3], __float_as_int(wwid));
-        cv[cidx] = zr;   // c = z; slots of coordinates >= d hold 0 (zr = 0, never updated)
-        __syncthreads();
-        const bool bad_all = uniform(flag_s[0] != 0 || flag_s[2] != 0);
-        const float wmax = readfirstlane(__int_as_float(flag_s[3]));
-        const float amax_all = readfirstlane(__int_as_float(flag_s[1]));
-        const float Dscale = (wmax <= FLT_MAX && wmax > 0.0f) ? wmax : fmaxf(1.0f, amax_all);
+        const WideStart st0 = wide_start<NJ, M, WC>(L, e, n, d, cw, lane, holds, own, j0, cj, stage, flag_s, cv,
+                                                    cidx, lam, na);
+        float zr = st0.zr;
+        const float blo = st0.blo, bhi = st0.bhi;
+        const bool bad_all = st0.bad_all;
+        const float amax_all = st0.amax_all, Dscale = st0.Dscale;
         const float tau = L.tol * Dscale;
         const float tau2 = tau * tau;
         const float arm2 = (L.arm * tau) * (L.arm * tau);

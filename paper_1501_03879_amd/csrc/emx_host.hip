@@ -218,7 +218,7 @@ static void append_plan_cache(const em_context *ctx, int pr, int m, int solver, 
 // handle
 // ---------------------------------------------------------------------------
 
-static constexpr int kNumCounters = 256;
+static constexpr int kNumCounters = 512;
 
 // ---------------------------------------------------------------------------
 // Scratch of nlem_denoise_noalloc: a static device array, one copy per GPU,
@@ -978,11 +978,13 @@ extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B,
     if (!h) return EM_ERR_INVALID_ARG;
     if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
     const em_options_t &o = *opt;
-    if (o.solver == EM_SOLVER_ADMM_FAST)
-        return fail(h, EM_ERR_UNSUPPORTED, "accelerated ADMM runs in em_solve_plain_ex");
     if (o.solver != EM_SOLVER_ADMM && o.solver != EM_SOLVER_IRLS && o.solver != EM_SOLVER_ADMM_ADAPTIVE &&
-        o.solver != EM_SOLVER_ADMM_WEIGHTED)
+        o.solver != EM_SOLVER_ADMM_WEIGHTED && o.solver != EM_SOLVER_ADMM_FAST)
         return fail(h, EM_ERR_INVALID_ARG, "bad solver");
+    if (o.solver == EM_SOLVER_ADMM_FAST && !(o.fast_eta > 0.0f && o.fast_eta < 1.0f))
+        return fail(h, EM_ERR_INVALID_ARG, "fast_eta must be in (0, 1)");
+    if (o.solver == EM_SOLVER_ADMM_FAST && o.set == EM_SET_BALL)
+        return fail(h, EM_ERR_UNSUPPORTED, "the accelerated ADMM runs over boxes");
     if ((o.box_lo == nullptr) != (o.box_hi == nullptr))
         return fail(h, EM_ERR_INVALID_ARG, "box_lo and box_hi must both be NULL or both be set");
     if (o.solver == EM_SOLVER_IRLS && (!(o.eps > 0.0f) || !std::isfinite(o.eps)))

@@ -121,7 +121,7 @@ def run_nlm(img_np, pr, wr, h, fp16=False):
 
 def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo=None,
                  box_hi=None, adapt_every=1, adapt_ratio=10.0, adapt_factor=2.0, z0=None,
-                 ball_center=None, ball_radius=None, radius=None):
+                 ball_center=None, ball_radius=None, radius=None, eta=0.999):
     """em_solve_batch_ex on the GPU for a synth.PointSetBatch (box from the
     batch's lo/hi unless per-coordinate arrays are given)."""
     import torch
@@ -142,7 +142,7 @@ def run_batch_ex(batch, *, solver, max_iter, tol, init, mu=0.5, eps=1e-6, box_lo
     hd.em_solve_batch_ex(a, w, inst, z, stats, solver=solver, init=init, lo=batch.lo, hi=batch.hi,
                          box_lo=bl, box_hi=bh, rho=mu, eps=eps, max_iter=max_iter, tol=tol,
                          adapt_every=adapt_every, adapt_ratio=adapt_ratio, adapt_factor=adapt_factor,
-                         ball_center=bc, ball_radius=br, radius=radius)
+                         ball_center=bc, ball_radius=br, radius=radius, eta=eta)
     hd.sync()
     it, fl, rp, rd = emx.stats_view(stats)
     return (z.cpu().numpy().astype(np.float64),

@@ -173,18 +173,23 @@ def _per_instance_errors(batch, got, ref, D):
 
 
 def _fast_parity(b, got, st, ref, D, name):
-    """Every instance: the GPU took exactly as many restarts as the FP64
-    oracle (the restart test c < eta c_prev is a decision on floating-point
-    values, so this is checked, not assumed) and its z is within 1e-4 D of
-    the oracle's."""
+    """Every instance: z within 1e-4 D of the oracle's, and exactly as many
+    restarts as the FP64 oracle took (the restart test c < eta c_prev is a
+    decision on floating-point values, so this is checked, not assumed),
+    except on instances where the oracle met a near-tie decision (c within
+    2e-6 of the guarded threshold eta (1 - 2^-16) c_prev, ref["ties"]):
+    there FP32 does not resolve c against the threshold and either branch is
+    a correct run, so only the z bar applies."""
     import paper_1501_03879_amd as emx
     err = _per_instance_errors(b, got, ref["z"], D)
     rs_gpu = st["flags"] >> emx.RESTART_SHIFT
     same = rs_gpu == ref["restarts"]
+    tie = ref["ties"] > 0
     print(f"[parity] {name}: max_rel={err.max():.3e} over all {b.B} instances; restarts "
           f"{int(rs_gpu.sum())} (gpu) vs {int(ref['restarts'].sum())} (oracle), "
-          f"{int((~same).sum())} instances differ", flush=True)
-    assert np.all(same), np.flatnonzero(~same)
+          f"{int((~same).sum())} instances differ, {int((~same & tie).sum())} of them at a near-tie "
+          f"({int(tie.sum())} instances with one)", flush=True)
+    assert np.all(same | tie), np.flatnonzero(~same & ~tie)
     assert err.max() <= 1e-4, (np.argmax(err), err.max())
     return err
 
@@ -210,6 +215,80 @@ def test_fast_admm_plain_tolerance_mode_beats_plain_admm():
           f"{st0['iters'].mean():.1f}", flush=True)
     assert st["iters"].mean() * 2 < st0["iters"].mean()
     assert np.mean((st["flags"] & 0xff) == oracle.CONVERGED) >= 0.95
+
+
+def test_fast_admm_batched_fixed_iterations():
+    """The batched accelerated ADMM (8-coordinate slices, every class: n in
+    [1, 512], d in 1..64) against the oracle at 30 sweeps, every instance,
+    restart counts included."""
+    b = _mixed(34, 400)
+    got, st = run_batch_ex(b, solver=FAST, max_iter=30, tol=0.0, init=oracle.INIT_MAXW, mu=2.0)
+    ref = oracle.em_batch(b, 2.0, 30, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM)
+    _fast_parity(b, got, st, ref, 6.0, "batched fast-ADMM T30 mu=2")
+    live = np.array([e["n"] > 0 for e in b.inst])
+    assert np.all((st["flags"][live] & 0xff) == oracle.MAXITER)
+    assert np.all(st["iters"][live] == 30)
+    assert ref["restarts"].sum() > 0
+
+
+def test_fast_admm_batched_tolerance_mode_and_saving():
+    """The point-set distribution at tol 1e-4 with mu = 5 (a penalty far from
+    the best one): every instance within 1e-4 of the oracle run to the GPU's
+    sweep count, the same restarts, and the sweeps saved against the batched
+    Algorithm 1 at the same penalty."""
+    b = synth.make_pointset_batch(505, 512)
+    got, st = run_batch_ex(b, solver=FAST, max_iter=3000, tol=1e-4, init=oracle.INIT_MAXW, mu=5.0)
+    _, st0 = run_batch_ex(b, solver=ADMM, max_iter=3000, tol=1e-4, init=oracle.INIT_MAXW, mu=5.0)
+    ref = oracle.em_batch(b, 5.0, 3000, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM,
+                          max_iter_each=st["iters"])
+    _fast_parity(b, got, st, ref, 6.0, "batched fast-ADMM tol mu=5")
+    own = oracle.em_batch(b, 5.0, 3000, 1e-4, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM)
+    print(f"[parity] batched fast-ADMM tol mu=5: mean sweeps {st['iters'].mean():.1f} (oracle's own stop "
+          f"{own['iters'].mean():.1f}) vs batched ADMM {st0['iters'].mean():.1f}; converged "
+          f"{np.mean((st['flags'] & 0xff) == oracle.CONVERGED):.3f}", flush=True)
+    # both residuals are tested every sweep, as the oracle does: the same stop
+    # up to FP32 rounding of a residual at the threshold
+    assert np.count_nonzero(st["iters"] != own["iters"]) <= max(1, b.B // 100)
+    assert st["iters"].mean() * 2 < st0["iters"].mean()
+    assert np.mean((st["flags"] & 0xff) == oracle.CONVERGED) >= 0.99
+
+
+def test_fast_admm_batched_boxes_starts_and_bad_instances():
+    """Per-coordinate boxes with the given and the weighted-mean starts, FP16
+    points, and a NaN point (BAD_INPUT) among good instances."""
+    import torch
+    b = _mixed(35, 120)
+    lo, hi = _boxes(b, 36)
+    z0 = np.random.default_rng(37).uniform(-1.0, 1.0, b.z_size).astype(np.float32)
+    for init in (oracle.INIT_GIVEN, oracle.INIT_WMEAN):
+        got, st = run_batch_ex(b, solver=FAST, max_iter=25, tol=0.0, init=init, mu=1.0, box_lo=lo, box_hi=hi,
+                               z0=z0 if init == oracle.INIT_GIVEN else None)
+        ref = oracle.em_batch(b, 1.0, 25, 0.0, init=init, z0=z0 if init == oracle.INIT_GIVEN else None,
+                              solver=oracle.SOLVER_FAST_ADMM, box_lo=lo, box_hi=hi)
+        _fast_parity(b, got, st, ref, 3.0, f"batched fast-ADMM boxes init={init} T25")
+    a16 = b.a.astype(np.float16)
+    b16 = synth.pointsets.PointSetBatch(a=a16.astype(np.float32), w=b.w, inst=b.inst, z_size=b.z_size,
+                                         lo=b.lo, hi=b.hi)
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    dev = gpu()
+    z = torch.zeros(b.z_size, dtype=torch.float32, device=dev)
+    stt = torch.zeros((b.B, 4), dtype=torch.int32, device=dev)
+    handle().em_solve_batch_ex(torch.from_numpy(a16).to(dev), torch.from_numpy(b.w).to(dev),
+                               emx.instances_tensor(b.inst, dev), z, stt, solver=FAST, init=oracle.INIT_MAXW,
+                               lo=b.lo, hi=b.hi, rho=1.0, max_iter=25, tol=0.0)
+    handle().sync()
+    it, fl, rp, rd = emx.stats_view(stt)
+    st16 = dict(iters=it.cpu().numpy(), flags=fl.cpu().numpy())
+    ref = oracle.em_batch(b16, 1.0, 25, 0.0, init=oracle.INIT_MAXW, solver=oracle.SOLVER_FAST_ADMM)
+    _fast_parity(b16, z.cpu().numpy().astype(np.float64), st16, ref, 6.0, "batched fast-ADMM fp16 points")
+    bad = synth.pointsets.pack_instances([b.points(0).copy(), b.points(1)], [b.weights(0), b.weights(1)],
+                                         -3.0, 3.0)
+    bad.a[0] = np.nan
+    gotb, stb = run_batch_ex(bad, solver=FAST, max_iter=10, tol=0.0, init=oracle.INIT_MAXW, mu=1.0)
+    assert stb["flags"][0] == oracle.BAD_INPUT
+    assert np.all(np.isnan(gotb[:bad.inst[0]["d"]]))
+    assert (stb["flags"][1] & 0xff) == oracle.MAXITER
 
 
 def test_plain_admm_per_coordinate_boxes():
@@ -383,9 +462,13 @@ def test_solver_routing_errors():
     inst = emx.instances_tensor(b.inst, dev)
     z = torch.zeros(b.z_size, device=dev)
     hd = handle()
-    with pytest.raises(emx.EmxError) as e:
-        hd.em_solve_batch_ex(a, w, inst, z, solver=FAST)
+    with pytest.raises(emx.EmxError) as e:   # the accelerated ADMM runs over boxes only
+        hd.em_solve_batch_ex(a, w, inst, z, solver=FAST, radius=1.0)
     assert e.value.status == emx.EM_ERR_UNSUPPORTED
+    for eta in (0.0, 1.0, float("nan")):
+        with pytest.raises(emx.EmxError) as e:
+            hd.em_solve_batch_ex(a, w, inst, z, solver=FAST, eta=eta)
+        assert e.value.status == emx.EM_ERR_INVALID_ARG
     for solver in (IRLS, WPEN):
         with pytest.raises(emx.EmxError) as e:
             hd.em_solve_plain_ex(a, w, inst, b.inst, z, solver=solver)
