@@ -73,6 +73,9 @@ __global__ __launch_bounds__(64 * WC, fast_waves_per_simd(M)) void batch_fast_ke
     const int cidx = holds ? myc : 64 + lane;
     const unsigned int cbeg = L.offsets[L.cls];
     const unsigned int ccount = L.offsets[L.cls + 1] - cbeg;
+    // workgroups beyond the class's instance count would only find the queue
+    // empty: they leave before the atomic, so an empty class costs its dispatch
+    if (blockIdx.x >= ccount) return;
 
     for (;;) {
         if (threadIdx.x == 0) {

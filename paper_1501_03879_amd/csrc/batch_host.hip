@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 
 #include "batch_kernel.hpp"
@@ -148,6 +149,35 @@ static bool wide_disabled() {
     return e && e[0] == '0' && e[1] == '\0';
 }
 
+// Largest point-coordinate count an instance of class c can have.
+static int64_t class_capacity(int c) {
+    if (c >= kFirstFastClass) {
+        const int k = c - kFirstFastClass;
+        return (int64_t)(64 << (k % 4)) * (8 << (k / 4));
+    }
+    if (c >= kNumClasses) {
+        const int k = c - kNumClasses;
+        return (int64_t)(64 * (1 + k % kWideMaxM)) * (kWideNJ * (kWideMinWC + k / kWideMaxM));
+    }
+    const ClassShape sh = class_shape(c);
+    return (int64_t)(64 * sh.m * sh.wp) * (sh.ds * sh.wc);
+}
+
+// Class launch order: largest instances first, so that on a batch of one
+// heavy shape its kernel is among the first four launched (one per stream)
+// instead of queued behind the dispatches of empty classes; each class's
+// counts are only known on the device.
+static const int *class_launch_order() {
+    static const std::array<int, kNumAllClasses> order = [] {
+        std::array<int, kNumAllClasses> o{};
+        for (int c = 0; c < kNumAllClasses; ++c) o[c] = c;
+        std::stable_sort(o.begin(), o.end(),
+                         [](int x, int y) { return class_capacity(x) > class_capacity(y); });
+        return o;
+    }();
+    return order.data();
+}
+
 em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *a, const float *w,
                         const em_instance_t *inst, const em_options_t &o, float *z, em_stats_t *stats) {
     // fixed-penalty EM-ADMM over a box: d > 16, n <= 448 go to the sliced
@@ -181,8 +211,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     // The classes run concurrently on the caller's stream and the handle's
     // side streams (fork after the classification, join before returning), so
     // one class's tail overlaps the others' work.  The launched classes go to
-    // the four streams in turn: neighbouring n-classes of a d-family land on
-    // different streams.
+    // the four streams in turn, largest shapes first.
     hipStream_t *side;
     hipEvent_t fork, *join;
     st = ctx_side_streams(ctx, &side, &fork, &join);
@@ -192,8 +221,10 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the class streams");
     const ClassKernel *wtab = batch_wide_table();
     const ClassKernel *ftab = batch_fast_table();
+    const int *order = class_launch_order();
     int launched = 0;
-    for (int c = 0; c < K; ++c) {
+    for (int oi = 0; oi < K; ++oi) {
+        const int c = order[oi];
         const bool skip = fast ? c < kFirstFastClass
                                : (c >= kFirstFastClass ||
                                   (c >= kNumClasses ? !wide : (wide && class_unused_with_wide(c))));
@@ -250,8 +281,9 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
 //    on the chip), so batched / plain measures what batching and the
 //    persistent queue add, with the same per-instance code.
 //  * The accelerated ADMM (its momentum needs the previous multipliers, a
-//    second n x d state) runs here only, iterates in device memory, one
-//    256-thread workgroup per instance (plain_solve_kernel<true>).
+//    second n x d state): iterates in device memory, one 256-thread
+//    workgroup per instance (plain_solve_kernel<true>); em_solve_batch_ex
+//    runs it batched with the state in registers (batch_fast.hpp).
 //   FAST = false: literal Algorithm 1 (thread per point for the prox and the
 //     multiplier update, thread per coordinate for the mean), residuals
 //     every iteration (not used by the library).

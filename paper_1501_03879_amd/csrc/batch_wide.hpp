@@ -276,6 +276,9 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
     const bool one = L.single >= 0;
     const unsigned int cbeg = one ? 0u : L.offsets[L.cls];
     const unsigned int ccount = one ? 1u : L.offsets[L.cls + 1] - cbeg;
+    // workgroups beyond the class's instance count would only find the queue
+    // empty: they leave before the atomic, so an empty class costs its dispatch
+    if (blockIdx.x >= ccount) return;
     unsigned int taken = 0;   // thread 0, single-instance mode: instances taken
 
     for (;;) {
