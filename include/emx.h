@@ -44,9 +44,10 @@
  *        r_dual = sqrt( ||z^t - z^{t-1}||^2 / d ),
  *    stop when both are <= tol * D, where D = hi - lo for a finite box and
  *    max(1, max_k ||a_k||_inf) otherwise.  The primal residual is only
- *    evaluated on iterations that follow one with r_dual <= tol D (and on
- *    the last allowed iteration), so a solve may end one iteration later
- *    than a solver that evaluates both every iteration.  tol = 0 runs
+ *    evaluated on iterations that follow one with r_dual <= tol D (times a
+ *    plan's arm factor >= 1; nlem_plan_t, em_batch_plan_t) and on the last
+ *    allowed iteration, so a solve may end one iteration later than a solver
+ *    that evaluates both every iteration.  tol = 0 runs
  *    exactly max_iter iterations; max_iter = 0 returns the starting z.
  *  - Arithmetic is FP32 (image storage may be FP16, widened on load).
  */
@@ -426,28 +427,124 @@ em_status_t nlm_denoise(em_handle_t handle, void *stream, const void *img, int32
                         int32_t H, int32_t W, int32_t patch_radius, int32_t window_radius,
                         float h_param, float *out);
 
+/* Where the values of a plan come from. */
+typedef enum {
+    EM_PLAN_BUILTIN = 0,  /* the built-in table and rules */
+    EM_PLAN_TUNED = 1,    /* measured by an autotune call on this handle */
+    EM_PLAN_CACHE = 2,    /* loaded from the EMX_AUTOTUNE_CACHE file when the handle was created */
+    EM_PLAN_SET = 3       /* given by the caller (nlem_plan_set, em_batch_plan_set) */
+} em_plan_source_t;
+
 /*
- * nlem_autotune - time every compiled coordinate-wave count (waves per pixel
- * over the patch coordinates) for this image's shape and solver, `repeats`
- * runs each after one warm-up, on `stream` (synchronously), and keep the
- * fastest as the handle's plan for (patch radius, window class, solver).
- * nlem_denoise, nlem_denoise_ex and nlem_denoise_multi use the plan from
- * then on (the environment variable EMX_NLEM_WC still overrides).  When
- * EMX_AUTOTUNE_CACHE names a file, the choice is appended to it and every
+ * The schedule of the NLEM solve kernel for one shape (patch radius, window
+ * class, solver, image storage): its tile shape and the schedule of its
+ * persistent work queue.  Every choice gives a correct solve: waves changes
+ * the summation order (results agree to FP32 rounding), chunk and order only
+ * which workgroup solves which pixel when, and arm_factor only on which
+ * iteration the primal residual is evaluated (a solve stops at the first
+ * evaluated iteration with both residuals within tol D, at most one iteration
+ * after an evaluation on every iteration would have stopped it).
+ */
+typedef struct {
+    int32_t waves;       /* coordinate waves per pixel (a compiled count, 1..4) */
+    int32_t chunk;       /* queue positions per atomic pop, 1..64; 0 = the built-in size rule */
+    int32_t order;       /* longest-first pixel order (tolerance mode): -1 = the built-in rule,
+                            0 = off, 1 = on */
+    float arm_factor;    /* the primal residual is evaluated on iterations that follow one with
+                            r_dual <= arm_factor tol D, and on the last one; >= 1, 1 = built-in */
+    int32_t source;      /* em_plan_source_t; ignored by nlem_plan_set */
+} nlem_plan_t;
+
+/*
+ * nlem_autotune - measure schedules for this image's shape, solver and
+ * storage on `stream` (synchronously, `repeats` timed runs of each candidate
+ * after one warm-up) and keep the fastest as the handle's plan: first every
+ * compiled coordinate-wave count with the built-in queue rules, then, with
+ * the best count, queue chunks 1, 2, 4 and 8, then (tolerance mode) the
+ * queue order off and on, then (tolerance mode, EM-ADMM) arm factors 1.5, 2
+ * and 3; a candidate after the wave count replaces the plan only when it is
+ * more than 1% faster.  nlem_denoise, nlem_denoise_ex and nlem_denoise_multi
+ * use the plan from then on (for a launch of several images, the plan of its
+ * shape with FP16 storage when every image in it is FP16); the environment
+ * variables EMX_NLEM_WC, EMX_NLEM_CHUNK and EMX_NLEM_ORDER still override.
+ * When EMX_AUTOTUNE_CACHE names a file, the plan is appended to it and every
  * later em_create on the same architecture loads it.  The image's out and
- * stats are written by the trials (the last variant's results).
- * chosen: NULL or receives the chosen count.
+ * stats are written by the trials (the last candidate's results).
+ * chosen: NULL or receives the chosen coordinate-wave count.
  * Errors: as nlem_denoise_ex for one image, INVALID_ARG for repeats < 1; HIP.
  */
 em_status_t nlem_autotune(em_handle_t handle, void *stream, const nlem_image_t *image,
                           const nlem_options_t *opt, int32_t repeats, int32_t *chosen);
 
-/* The coordinate-wave count the handle uses for a shape and solver (the
- * autotuned plan, else the built-in default; without a plan, a shape group
- * shorter than four rounds of the resident grid in tolerance mode runs with
- * the most waves compiled for the shape instead).  Errors: INVALID_ARG. */
+/* The coordinate-wave count the handle uses for a shape and solver with FP32
+ * storage (the plan's, else the built-in default; without a plan, a shape
+ * group shorter than four rounds of the resident grid in tolerance mode runs
+ * with the most waves compiled for the shape instead).  Errors: INVALID_ARG. */
 em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
                       int32_t solver, int32_t *waves);
+
+/* The whole plan of a shape, solver and storage (img_is_f16): the handle's
+ * plan with its source, or the built-in values (waves = the default count,
+ * chunk 0, order -1, arm_factor 1, source EM_PLAN_BUILTIN).
+ * Errors: INVALID_ARG (NULL arguments, bad shape or solver). */
+em_status_t nlem_plan_get(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
+                          int32_t solver, int32_t img_is_f16, nlem_plan_t *plan);
+
+/* Set the handle's plan of a shape, solver and storage (source becomes
+ * EM_PLAN_SET; not written to the cache file), or with plan = NULL return
+ * it to the built-in values.  Errors: INVALID_ARG (bad shape or solver,
+ * waves not compiled for the shape, chunk outside 0..64, order outside
+ * -1..1, arm_factor not finite or below 1). */
+em_status_t nlem_plan_set(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
+                          int32_t solver, int32_t img_is_f16, const nlem_plan_t *plan);
+
+/*
+ * The schedule of the batched fixed-penalty EM-ADMM (em_solve_batch and
+ * em_solve_batch_ex with EM_SOLVER_ADMM over a box, and the plain path,
+ * which follows the same routing): for each of the 28 sliced classes (d in
+ * (16, 64], n <= 448; class k = 7 (ceil(d / 13) - 2) + ceil(n / 64) - 1:
+ * 13-coordinate slices over ceil(d / 13) waves, ceil(n / 64) points per lane)
+ * whether its instances run there or in the generic classes (16-coordinate
+ * slices over ceil(d / 16) waves, 1, 2 or 4 points per lane and one or two
+ * point waves), and the arm factor of the primal residual (as nlem_plan_t).
+ * Far-outlier deferral is unaffected.
+ */
+typedef struct {
+    uint64_t generic_classes;  /* bit k set: sliced class k is routed to the generic classes */
+    float arm_factor;          /* >= 1, 1 = built-in */
+    int32_t source;            /* em_plan_source_t; ignored by em_batch_plan_set */
+} em_batch_plan_t;
+
+/*
+ * em_batch_autotune - measure the batched fixed-penalty EM-ADMM on this batch
+ * (arguments as em_solve_batch_ex; opt->solver must be EM_SOLVER_ADMM over a
+ * box) and keep the fastest schedule as the handle's plan for its point
+ * storage (opt->points_f16): after the built-in plan, each sliced class that
+ * holds instances of the batch (largest first) is tried in the generic
+ * classes, then arm factors 1.5, 2 and 3 (tolerance mode); a change is kept
+ * when more than 1% faster.  `repeats` timed calls per candidate after one
+ * warm-up, synchronously on `stream`; z and stats hold the last candidate's
+ * results.  The plan is appended to the EMX_AUTOTUNE_CACHE file as for
+ * nlem_autotune.  chosen: NULL or receives the plan.
+ * Errors: as em_solve_batch_ex; INVALID_ARG for repeats < 1; UNSUPPORTED for
+ * other solvers or sets; HIP.
+ */
+em_status_t em_batch_autotune(em_handle_t handle, void *stream, int64_t B, const float *a,
+                              const float *w, const em_instance_t *inst, const em_options_t *opt,
+                              float *z, em_stats_t *stats, int32_t repeats, em_batch_plan_t *chosen);
+
+/* The batch plan for point storage points_f16 (the handle's, else the
+ * built-in: no class routed, arm_factor 1).  solver must be EM_SOLVER_ADMM.
+ * Errors: INVALID_ARG. */
+em_status_t em_batch_plan_get(em_handle_t handle, int32_t solver, int32_t points_f16,
+                              em_batch_plan_t *plan);
+
+/* Set the batch plan for point storage points_f16 (source EM_PLAN_SET), or
+ * with plan = NULL return to the built-in one.  Errors: INVALID_ARG (solver
+ * other than EM_SOLVER_ADMM, bits above the 28 classes, arm_factor not finite
+ * or below 1). */
+em_status_t em_batch_plan_set(em_handle_t handle, int32_t solver, int32_t points_f16,
+                              const em_batch_plan_t *plan);
 
 /*
  * em_kernel_timing - for measurement tools: while enabled (enable != 0),

@@ -48,6 +48,29 @@ class NlemOptions(C.Structure):
                 ("rho", C.c_float), ("eps", C.c_float), ("max_iter", C.c_int32), ("tol", C.c_float)]
 
 
+PLAN_BUILTIN, PLAN_TUNED, PLAN_CACHE, PLAN_SET = 0, 1, 2, 3
+PLAN_SOURCES = ("builtin", "tuned", "cache", "set")
+
+
+class NlemPlan(C.Structure):
+    """nlem_plan_t: schedule of the NLEM solve kernel for one shape."""
+    _fields_ = [("waves", C.c_int32), ("chunk", C.c_int32), ("order", C.c_int32),
+                ("arm_factor", C.c_float), ("source", C.c_int32)]
+
+    def as_dict(self):
+        return dict(waves=self.waves, chunk=self.chunk, order=self.order,
+                    arm_factor=float(self.arm_factor), source=PLAN_SOURCES[self.source])
+
+
+class BatchPlan(C.Structure):
+    """em_batch_plan_t: sliced classes routed to the generic kernels, arm factor."""
+    _fields_ = [("generic_classes", C.c_uint64), ("arm_factor", C.c_float), ("source", C.c_int32)]
+
+    def as_dict(self):
+        return dict(generic_classes=int(self.generic_classes), arm_factor=float(self.arm_factor),
+                    source=PLAN_SOURCES[self.source])
+
+
 class EmOptions(C.Structure):
     _fields_ = [("solver", C.c_int32), ("init", C.c_int32), ("lo", C.c_float), ("hi", C.c_float),
                 ("box_lo", C.c_void_p), ("box_hi", C.c_void_p), ("rho", C.c_float),
@@ -104,6 +127,17 @@ def load_library():
         lib.nlem_autotune.restype = C.c_int
         lib.nlem_plan.argtypes = [vp, i32, i32, i32, C.POINTER(i32)]
         lib.nlem_plan.restype = C.c_int
+        lib.nlem_plan_get.argtypes = [vp, i32, i32, i32, i32, C.POINTER(NlemPlan)]
+        lib.nlem_plan_get.restype = C.c_int
+        lib.nlem_plan_set.argtypes = [vp, i32, i32, i32, i32, C.POINTER(NlemPlan)]
+        lib.nlem_plan_set.restype = C.c_int
+        lib.em_batch_autotune.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(EmOptions), vp, vp, i32,
+                                          C.POINTER(BatchPlan)]
+        lib.em_batch_autotune.restype = C.c_int
+        lib.em_batch_plan_get.argtypes = [vp, i32, i32, C.POINTER(BatchPlan)]
+        lib.em_batch_plan_get.restype = C.c_int
+        lib.em_batch_plan_set.argtypes = [vp, i32, i32, C.POINTER(BatchPlan)]
+        lib.em_batch_plan_set.restype = C.c_int
         lib.em_kernel_timing.argtypes = [vp, i32]
         lib.em_kernel_timing.restype = C.c_int
         lib.em_kernel_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
@@ -282,6 +316,52 @@ class Handle:
         self._check(self.lib.nlem_plan(self.h, int(patch_radius), int(window_radius), int(solver),
                                        C.byref(waves)), "nlem_plan")
         return waves.value
+
+    def nlem_plan_get(self, patch_radius, window_radius, solver=SOLVER_ADMM, f16=False):
+        """The whole plan (dict: waves, chunk, order, arm_factor, source)."""
+        p = NlemPlan()
+        self._check(self.lib.nlem_plan_get(self.h, int(patch_radius), int(window_radius), int(solver),
+                                           1 if f16 else 0, C.byref(p)), "nlem_plan_get")
+        return p.as_dict()
+
+    def nlem_plan_set(self, patch_radius, window_radius, plan=None, solver=SOLVER_ADMM, f16=False):
+        """Set the plan (dict with waves, chunk, order, arm_factor) or, with
+        plan=None, return to the built-in one."""
+        p = None if plan is None else NlemPlan(int(plan["waves"]), int(plan.get("chunk", 0)),
+                                               int(plan.get("order", -1)),
+                                               float(plan.get("arm_factor", 1.0)), 0)
+        self._check(self.lib.nlem_plan_set(self.h, int(patch_radius), int(window_radius), int(solver),
+                                           1 if f16 else 0, None if p is None else C.byref(p)),
+                    "nlem_plan_set")
+
+    def em_batch_autotune(self, a, w, inst, z, stats=None, *, lo, hi, rho, max_iter, tol,
+                          init=INIT_MAXW, box_lo=None, box_hi=None, repeats=2, stream=None):
+        """Tune the batched fixed-penalty EM-ADMM over a box on this batch;
+        returns the chosen plan (dict)."""
+        import torch
+        B = int(inst.numel() * inst.element_size() // 32)
+        opt = _options(SOLVER_ADMM, init, lo, hi, box_lo, box_hi, rho, 1e-6, max_iter, tol, 1, 10.0,
+                       2.0, 0.999)
+        opt.points_f16 = 1 if a.dtype == torch.float16 else 0
+        p = BatchPlan()
+        st = self.lib.em_batch_autotune(self.h, _stream(stream), B, _ptr(a), _ptr(w), _ptr(inst),
+                                        C.byref(opt), _ptr(z), _ptr(stats), int(repeats), C.byref(p))
+        self._check(st, "em_batch_autotune")
+        return p.as_dict()
+
+    def em_batch_plan_get(self, f16=False, solver=SOLVER_ADMM):
+        p = BatchPlan()
+        self._check(self.lib.em_batch_plan_get(self.h, int(solver), 1 if f16 else 0, C.byref(p)),
+                    "em_batch_plan_get")
+        return p.as_dict()
+
+    def em_batch_plan_set(self, plan=None, f16=False, solver=SOLVER_ADMM):
+        """Set the batch plan (dict with generic_classes, arm_factor) or, with
+        plan=None, return to the built-in one."""
+        p = None if plan is None else BatchPlan(int(plan.get("generic_classes", 0)),
+                                                float(plan.get("arm_factor", 1.0)), 0)
+        self._check(self.lib.em_batch_plan_set(self.h, int(solver), 1 if f16 else 0,
+                                               None if p is None else C.byref(p)), "em_batch_plan_set")
 
     def nlm_denoise(self, img, out, *, patch_radius, window_radius, h, stream=None):
         """Non-Local Means: img H x W float32/float16, out H x W float32."""

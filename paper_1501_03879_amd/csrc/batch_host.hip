@@ -23,13 +23,15 @@ em_status_t ctx_reset_counters(em_context *ctx, hipStream_t s, unsigned int *c, 
 void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fork, hipEvent_t **join);
+BatchPlanView ctx_batch_plan(em_context *ctx, const em_options_t &o);
 
 // Classify: counts per class; empty / malformed instances finished here.
 // Counts go through a per-block LDS histogram (one global atomic per block
 // and class): a million instances over twenty counters would otherwise
 // serialise on the hot ones.
 __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t *inst, int64_t B, float *z,
-                                                            em_stats_t *stats, unsigned int *counts, int mode) {
+                                                            em_stats_t *stats, unsigned int *counts, int mode,
+                                                            uint64_t generic_mask) {
     __shared__ unsigned int hist[kNumAllClasses];
     for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
@@ -43,8 +45,24 @@ __global__ __launch_bounds__(256) void batch_classify_count(const em_instance_t 
                 for (int j = 0; j < e.d; ++j) z[e.z_off + j] = __builtin_nanf("");
             if (stats) stats[b] = em_stats_t{0, EM_BAD_INPUT, 0.0f, 0.0f};
         } else {
-            atomicAdd(&hist[class_of(e.n, e.d, mode)], 1u);
+            atomicAdd(&hist[class_of(e.n, e.d, mode, generic_mask)], 1u);
         }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x)
+        if (hist[i]) atomicAdd(&counts[i], hist[i]);
+}
+
+// Class counts only (sliced classes, nothing routed back), for the autotuner.
+__global__ __launch_bounds__(256) void batch_classify_count_only(const em_instance_t *inst, int64_t B,
+                                                                 unsigned int *counts) {
+    __shared__ unsigned int hist[kNumAllClasses];
+    for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) {
+        const em_instance_t e = inst[b];
+        if (e.n > 0 && e.n <= EM_MAX_N && e.d >= 1 && e.d <= EM_MAX_D) atomicAdd(&hist[class_of(e.n, e.d, 1)], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x)
@@ -66,7 +84,7 @@ __global__ void batch_classify_scan(const unsigned int *counts, unsigned int *of
 // (block, class) reserves the block's range of the class list.
 __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_t *inst, int64_t B,
                                                               const unsigned int *offsets, unsigned int *fill,
-                                                              int32_t *list, int mode) {
+                                                              int32_t *list, int mode, uint64_t generic_mask) {
     __shared__ unsigned int lcnt[kNumAllClasses];
     __shared__ unsigned int lbase[kNumAllClasses];
     for (int i = threadIdx.x; i < kNumAllClasses; i += blockDim.x) lcnt[i] = 0u;
@@ -77,7 +95,7 @@ __global__ __launch_bounds__(256) void batch_classify_scatter(const em_instance_
     if (b < B) {
         const em_instance_t e = inst[b];
         if (e.n > 0 && e.n <= EM_MAX_N && e.d >= 1 && e.d <= EM_MAX_D) {
-            c = class_of(e.n, e.d, mode);
+            c = class_of(e.n, e.d, mode, generic_mask);
             rank = atomicAdd(&lcnt[c], 1u);
         }
     }
@@ -128,7 +146,7 @@ static ClassLaunch class_launch(const float *a, const float *w, const em_instanc
     L.hi = vbox ? 0.0f : o.hi;
     L.mu = (o.solver == EM_SOLVER_IRLS) ? 1.0f : o.rho;
     L.tol = o.tol;
-    L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= tol D
+    L.arm = 1.0f;  // primal residual evaluated after an iteration with r_dual <= arm tol D (set by the caller)
     L.eps = o.eps;
     L.adapt_every = (o.solver == EM_SOLVER_ADMM_ADAPTIVE) ? o.adapt_every : 0;
     L.adapt_ratio2 = o.adapt_ratio * o.adapt_ratio;
@@ -186,6 +204,8 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     const bool defer = o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX;
     const bool fast = o.solver == EM_SOLVER_ADMM_FAST;   // its own classes (batch_fast.hpp)
     const int mode = fast ? 2 : wide;
+    const BatchPlanView plan = ctx_batch_plan(ctx, o);   // routing and arm factor of a plan
+    const uint64_t gmask = wide ? plan.generic_mask : 0;
     // workspace: list[B] int32, then (deferral) the deferred lists of B each
     em_status_t st;
     int32_t *list = static_cast<int32_t *>(
@@ -202,9 +222,10 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     st = ctx_reset_counters(ctx, s, cnt, NC);
     if (st != EM_OK) return st;
     const unsigned nb = (unsigned)((B + 255) / 256);
-    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, mode);
+    hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, mode, gmask);
     hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
-    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, mode);
+    hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, mode,
+                       gmask);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "classify launch");
     const ClassKernel *tab = class_table(o);
@@ -225,9 +246,11 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     int launched = 0;
     for (int oi = 0; oi < K; ++oi) {
         const int c = order[oi];
+        // (with sliced classes routed back by a plan, every generic class may receive instances)
         const bool skip = fast ? c < kFirstFastClass
                                : (c >= kFirstFastClass ||
-                                  (c >= kNumClasses ? !wide : (wide && class_unused_with_wide(c))));
+                                  (c >= kNumClasses ? !wide || ((gmask >> (c - kNumClasses)) & 1u)
+                                                    : (wide && gmask == 0 && class_unused_with_wide(c))));
         if (skip) continue;
         const ClassKernel &ck = (c >= kFirstFastClass) ? ftab[c - kFirstFastClass]
                                 : (c >= kNumClasses)  ? wtab[c - kNumClasses]
@@ -235,6 +258,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         const int si = launched++ % (kSideStreams + 1);
         hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
+        L.arm = plan.arm;
         L.list = list;
         L.offsets = offsets;
         L.counter = heads + c;
@@ -260,6 +284,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         const ClassKernel *dtab = batch_deferred_table();
         for (int k = 0; k < kDeferLists; ++k) {
             ClassLaunch L = class_launch(a, w, inst, o, z, stats, 0);
+            L.arm = plan.arm;
             L.list = list + (int64_t)(k + 1) * B;
             L.offsets = defer_q + 2 * k;
             L.counter = defer_heads + k;
@@ -270,6 +295,25 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
             if (e != hipSuccess) return ctx_hip_error(ctx, e, "deferred launch");
         }
     }
+    return EM_OK;
+}
+
+// Instances per sliced class of the fixed-penalty EM-ADMM over a box (the
+// classification of batch_solve with no class routed back, counts copied to
+// the host; synchronous on s).  For the autotuner.
+em_status_t batch_wide_counts(em_context *ctx, hipStream_t s, int64_t B, const em_instance_t *inst,
+                              unsigned int (&wide_counts)[kNumWideClasses]) {
+    unsigned int *cnt = ctx_counters(ctx, kNumAllClasses);
+    if (!cnt) return ctx_error(ctx, EM_ERR_UNSUPPORTED, "counter pool too small");
+    em_status_t st = ctx_reset_counters(ctx, s, cnt, kNumAllClasses);
+    if (st != EM_OK) return st;
+    const unsigned nb = (unsigned)((B + 255) / 256);
+    hipLaunchKernelGGL(batch_classify_count_only, dim3(nb), dim3(256), 0, s, inst, B, cnt);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(wide_counts, cnt + kNumClasses, sizeof(wide_counts),
+                                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return ctx_hip_error(ctx, e, "class counts");
     return EM_OK;
 }
 
@@ -509,6 +553,7 @@ static em_status_t plain_admm(em_context *ctx, hipStream_t s, int64_t B, const f
                               const em_instance_t *inst, const em_instance_t *inst_host, const em_options_t &o,
                               float *z, em_stats_t *stats) {
     const bool wide = o.set == EM_SET_BOX && !wide_disabled();
+    const BatchPlanView plan = ctx_batch_plan(ctx, o);   // the batched path's routing and arm factor
     const ClassKernel *tab = class_table(o);
     const ClassKernel *wtab = batch_wide_table();
     unsigned int *scratch = ctx_counters(ctx, kNumAllClasses);   // class counts of the finishing kernel
@@ -517,12 +562,13 @@ static em_status_t plain_admm(em_context *ctx, hipStream_t s, int64_t B, const f
         const em_instance_t &e = inst_host[b];
         if (e.n <= 0 || e.n > EM_MAX_N || e.d < 1 || e.d > EM_MAX_D) {
             hipLaunchKernelGGL(batch_classify_count, dim3(1), dim3(256), 0, s, inst + b, (int64_t)1, z,
-                               stats ? stats + b : nullptr, scratch, 0);
+                               stats ? stats + b : nullptr, scratch, 0, (uint64_t)0);
             continue;
         }
-        const int c = class_of(e.n, e.d, wide);
+        const int c = class_of(e.n, e.d, wide, wide ? plan.generic_mask : 0);
         const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
+        L.arm = plan.arm;
         L.single = b;
         void *args[] = {&L};
         const hipError_t err = hipLaunchKernel(ck.fn, dim3(1), dim3(ck.threads), args, 0, s);

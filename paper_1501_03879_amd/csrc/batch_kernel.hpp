@@ -67,13 +67,10 @@ __host__ __device__ inline int class_of(int n, int d) {
 }
 
 // Classes of the sliced EM-ADMM kernel (batch_wide.hpp; fixed penalty over a
-// box): d in (16, 64] and n <= 448 go to 13-coordinate slices over
-// WC = ceil(d / 13) in [2, 5] waves with M = ceil(n / 64) in [1, 7] points
-// per lane.  Their ids follow the kNumClasses classes above.
-constexpr int kWideNJ = 13;
-constexpr int kWideMaxM = 7;
-constexpr int kWideMinWC = 2, kWideMaxWC = 5;
-constexpr int kNumWideClasses = (kWideMaxWC - kWideMinWC + 1) * kWideMaxM;
+// box; shapes in emx_internal.hpp, where a batch plan numbers them too): d in
+// (16, 64] and n <= 448 go to 13-coordinate slices over WC = ceil(d / 13) in
+// [2, 5] waves with M = ceil(n / 64) in [1, 7] points per lane.  Their ids
+// follow the kNumClasses classes above.
 // Classes of the accelerated ADMM (batch_fast.hpp): 8-coordinate slices over
 // WC in {1, 2, 4, 8} waves (the smallest with 8 WC >= d) and M in {1, 2, 4, 8}
 // points per lane (the smallest with 64 M >= n); ids after the sliced ones.
@@ -84,13 +81,15 @@ constexpr int kNumAllClasses = kFirstFastClass + kNumFastClasses;
 __host__ __device__ constexpr int pow2_index(int v) { return v <= 1 ? 0 : v <= 2 ? 1 : v <= 4 ? 2 : 3; }
 
 // mode 0: generic classes; 1: sliced classes where they apply (fixed-penalty
-// EM-ADMM over a box); 2: the accelerated ADMM's classes
-__host__ __device__ inline int class_of(int n, int d, int mode) {
+// EM-ADMM over a box), except those whose bit k = class - kNumClasses is set
+// in generic_mask (a plan's routing); 2: the accelerated ADMM's classes
+__host__ __device__ inline int class_of(int n, int d, int mode, uint64_t generic_mask = 0) {
     if (mode == 2) return kFirstFastClass + 4 * pow2_index((d + 7) / 8) + pow2_index((n + 63) / 64);
     if (mode == 1 && d > 16 && n <= 64 * kWideMaxM) {
         const int wc = (d + kWideNJ - 1) / kWideNJ;
         const int m = (n + 63) / 64;
-        return kNumClasses + (wc - kWideMinWC) * kWideMaxM + (m - 1);
+        const int k = (wc - kWideMinWC) * kWideMaxM + (m - 1);
+        if (!((generic_mask >> k) & 1u)) return kNumClasses + k;
     }
     return class_of(n, d);
 }
@@ -130,7 +129,7 @@ struct ClassLaunch {
     // defer_list + k * defer_stride, its count at defer_q[2 k + 1]
     // (defer_q[2 k] stays 0); null defer_q: no deferral
     float outlier;
-    float fast_eta;               // accelerated ADMM: restart when c >= fast_eta c_prev
+    float fast_eta;               // accelerated ADMM: restart when c >= fast_eta (1 - 2^-16) c_prev
     int32_t *defer_list;
     int64_t defer_stride;
     unsigned int *defer_q;

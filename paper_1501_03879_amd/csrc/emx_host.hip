@@ -2,6 +2,7 @@
 // handle-owned workspace, persistent-grid sizing and kernel dispatch.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -26,6 +27,8 @@ em_status_t batch_solve(em_context *ctx, hipStream_t stream, int64_t B, const fl
 em_status_t plain_solve(em_context *ctx, hipStream_t stream, int64_t B, const float *a,
                         const float *w, const em_instance_t *inst, const em_instance_t *inst_host,
                         const em_options_t &o, float *z, em_stats_t *stats);
+em_status_t batch_wide_counts(em_context *ctx, hipStream_t s, int64_t B, const em_instance_t *inst,
+                              unsigned int (&wide_counts)[kNumWideClasses]);
 
 __global__ void reset_counters_kernel(unsigned int *c, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,14 +45,30 @@ struct MultiGraph {
     void *ws = nullptr;   // the graph's own queue-order scratch (kept with the graph)
 };
 
-// Autotuned NLEM plans: (patch radius, points per lane, solver) -> coordinate waves.
-using PlanKey = std::tuple<int, int, int>;
+// NLEM plans: (patch radius, points per lane, solver, FP16 storage) -> the
+// solve kernel's schedule (nlem_plan_t without its source).
+using PlanKey = std::tuple<int, int, int, int>;
+struct NlemPlan {
+    int wc = 0;         // coordinate waves
+    int chunk = 0;      // queue positions per pop; 0 = the size rule
+    int order = -1;     // longest-first order: -1 = the rule, 0 = off, 1 = on
+    float arm = 1.0f;   // residual arm factor (>= 1)
+    int source = EM_PLAN_BUILTIN;
+};
+// Batch plans: (solver, FP16 points) -> routing of the sliced classes and arm factor.
+using BatchPlanKey = std::pair<int, int>;
+struct BatchPlan {
+    uint64_t mask = 0;
+    float arm = 1.0f;
+    int source = EM_PLAN_BUILTIN;
+};
 
 struct em_context {
     int device = 0;
     int num_cus = 0;
     std::string arch;                   // gcnArchName of the device (cache key)
-    std::map<PlanKey, int> plans;       // measured by nlem_autotune or loaded from the cache
+    std::map<PlanKey, NlemPlan> plans;  // measured by nlem_autotune, loaded from the cache or set
+    std::map<BatchPlanKey, BatchPlan> batch_plans;   // em_batch_autotune / cache / em_batch_plan_set
     int plan_epoch = 0;                 // bumped when a plan changes (invalidates the multi graph)
     unsigned int *counters = nullptr;  // kNumCounters work-queue heads
     int num_counters = 0;
@@ -131,6 +150,16 @@ em_status_t ctx_error(em_context *ctx, em_status_t st, const char *msg) { return
 
 em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what) { return hip_fail(ctx, e, what); }
 
+// The batch plan of a call: the handle's plan for the fixed-penalty EM-ADMM
+// over a box and its point storage, else the built-in one.
+BatchPlanView ctx_batch_plan(em_context *ctx, const em_options_t &o) {
+    if (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX) {
+        auto it = ctx->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, o.points_f16 ? 1 : 0});
+        if (it != ctx->batch_plans.end()) return BatchPlanView{it->second.mask, it->second.arm};
+    }
+    return BatchPlanView{0, 1.0f};
+}
+
 // Work-queue heads: a fixed pool owned by the handle.
 unsigned int *ctx_counters(em_context *ctx, int n) {
     if (n > ctx->num_counters) return nullptr;
@@ -187,31 +216,75 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
 }  // namespace emx
 
 // ---------------------------------------------------------------------------
-// autotune cache: text lines "nlem <arch> <patch radius> <points per lane>
-// <solver> <coordinate waves>" in the file named by EMX_AUTOTUNE_CACHE
+// autotune cache: text lines in the file named by EMX_AUTOTUNE_CACHE,
+//   nlem2 <arch> <patch radius> <points per lane> <solver> <fp16> <waves> <chunk> <order> <arm>
+//   batch <arch> <solver> <fp16> <routed classes, hex> <arm>
+// and, from before the queue and arm fields existed,
+//   nlem <arch> <patch radius> <points per lane> <solver> <waves>
+// (both storages, built-in queue rules).  Later lines win; lines for another
+// architecture, an uncompiled variant, values out of range or that do not
+// parse are skipped.
 // ---------------------------------------------------------------------------
+
+static bool plan_values_ok(int chunk, int order, float arm) {
+    return chunk >= 0 && chunk <= 64 && order >= -1 && order <= 1 && std::isfinite(arm) && arm >= 1.0f;
+}
+
+static constexpr uint64_t kAllWideClasses = ((uint64_t)1 << kNumWideClasses) - 1;
 
 static void load_plan_cache(em_context *ctx) {
     const char *path = getenv("EMX_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    char kind[16], arch[64];
-    int pr, m, solver, wc;
-    while (fscanf(f, "%15s %63s %d %d %d %d", kind, arch, &pr, &m, &solver, &wc) == 6) {
-        if (strcmp(kind, "nlem") == 0 && ctx->arch == arch && nlem_kernel(pr, m, wc, solver).fn)
-            ctx->plans[PlanKey{pr, m, solver}] = wc;   // later lines win
+    char line[256];
+    while (fgets(line, sizeof(line), f)) {
+        char kind[16], arch[64];
+        int pr, m, solver, f16, wc, chunk, order;
+        float arm;
+        unsigned long long mask;
+        if (sscanf(line, "%15s %63s", kind, arch) != 2 || ctx->arch != arch) continue;
+        if (strcmp(kind, "nlem2") == 0 &&
+            sscanf(line, "%*s %*s %d %d %d %d %d %d %d %f", &pr, &m, &solver, &f16, &wc, &chunk, &order,
+                   &arm) == 8) {
+            if ((f16 == 0 || f16 == 1) && nlem_kernel(pr, m, wc, solver).fn && plan_values_ok(chunk, order, arm))
+                ctx->plans[PlanKey{pr, m, solver, f16}] = NlemPlan{wc, chunk, order, arm, EM_PLAN_CACHE};
+        } else if (strcmp(kind, "nlem") == 0 &&
+                   sscanf(line, "%*s %*s %d %d %d %d", &pr, &m, &solver, &wc) == 4) {
+            if (nlem_kernel(pr, m, wc, solver).fn)
+                for (int x = 0; x < 2; ++x)
+                    ctx->plans[PlanKey{pr, m, solver, x}] = NlemPlan{wc, 0, -1, 1.0f, EM_PLAN_CACHE};
+        } else if (strcmp(kind, "batch") == 0 &&
+                   sscanf(line, "%*s %*s %d %d %llx %f", &solver, &f16, &mask, &arm) == 4) {
+            if (solver == EM_SOLVER_ADMM && (f16 == 0 || f16 == 1) && (mask & ~kAllWideClasses) == 0 &&
+                plan_values_ok(0, -1, arm))
+                ctx->batch_plans[BatchPlanKey{solver, f16}] = BatchPlan{(uint64_t)mask, arm, EM_PLAN_CACHE};
+        }
     }
     fclose(f);
 }
 
-static void append_plan_cache(const em_context *ctx, int pr, int m, int solver, int wc) {
+static void append_cache_line(const char *text) {
     const char *path = getenv("EMX_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "nlem %s %d %d %d %d\n", ctx->arch.c_str(), pr, m, solver, wc);
+    fputs(text, f);
     fclose(f);
+}
+
+static void append_plan_cache(const em_context *ctx, const PlanKey &k, const NlemPlan &p) {
+    char line[256];
+    snprintf(line, sizeof(line), "nlem2 %s %d %d %d %d %d %d %d %.9g\n", ctx->arch.c_str(), std::get<0>(k),
+             std::get<1>(k), std::get<2>(k), std::get<3>(k), p.wc, p.chunk, p.order, (double)p.arm);
+    append_cache_line(line);
+}
+
+static void append_batch_plan_cache(const em_context *ctx, const BatchPlanKey &k, const BatchPlan &p) {
+    char line[256];
+    snprintf(line, sizeof(line), "batch %s %d %d %llx %.9g\n", ctx->arch.c_str(), k.first, k.second,
+             (unsigned long long)p.mask, (double)p.arm);
+    append_cache_line(line);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,34 +433,53 @@ static constexpr float kArmFactor = 1.0f;
 // (no tail) more waves were slower (64x64 r2 R5 T50 0.166 -> 0.175 ms).
 static constexpr int kFewRounds = 4;
 
-// Kernel for a shape: EMX_NLEM_WC when that variant is compiled (a manual
-// override), else the handle's autotuned plan, else the default table, or
-// for a short queue in tolerance mode (total pixels of the group >= 0 and
-// below kFewRounds rounds) the most coordinate waves compiled.
-static NlemKernelInfo select_nlem_kernel(em_context *h, int pr, int m, int solver, int64_t total = -1,
-                                         bool tolerance = false, bool cache = true) {
+// The schedule of one NLEM launch: kernel (coordinate waves), queue
+// positions per pop (0 = the size rule), queue order (-1 = the rule, 0 = off,
+// 1 = on) and residual arm factor.
+struct NlemSchedule {
+    NlemKernelInfo k;
+    int chunk;
+    int order;
+    float arm;
+};
+
+static const NlemPlan *find_plan(const em_context *h, int pr, int m, int solver, int f16) {
+    auto it = h->plans.find(PlanKey{pr, m, solver, f16 ? 1 : 0});
+    return it == h->plans.end() ? nullptr : &it->second;
+}
+
+// Schedule for a shape, field by field: the environment override
+// (EMX_NLEM_WC when that variant is compiled; EMX_NLEM_CHUNK and
+// EMX_NLEM_ORDER act in queue_chunk and order_enabled), else the handle's
+// plan, else the built-in default; without an override or plan, a short
+// queue in tolerance mode (total pixels of the group >= 0 and below
+// kFewRounds rounds) runs with the most coordinate waves compiled.
+static NlemSchedule nlem_schedule(em_context *h, int pr, int m, int solver, int f16, int64_t total = -1,
+                                  bool tolerance = false, bool cache = true) {
+    const NlemPlan *plan = find_plan(h, pr, m, solver, f16);
+    NlemSchedule r{NlemKernelInfo{nullptr, 0}, plan ? plan->chunk : 0, plan ? plan->order : -1,
+                   plan ? plan->arm : kArmFactor};
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
-        NlemKernelInfo k = nlem_kernel(pr, m, atoi(env), solver);
-        if (k.fn) return k;
+        r.k = nlem_kernel(pr, m, atoi(env), solver);
+        if (r.k.fn) return r;
     }
-    auto it = h->plans.find(PlanKey{pr, m, solver});
-    if (it != h->plans.end()) {
-        NlemKernelInfo k = nlem_kernel(pr, m, it->second, solver);
-        if (k.fn) return k;
+    if (plan) {
+        r.k = nlem_kernel(pr, m, plan->wc, solver);
+        if (r.k.fn) return r;
     }
-    NlemKernelInfo k = nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
-    if (k.fn && tolerance && total >= 0 &&
-        total < (int64_t)kFewRounds * h->num_cus * blocks_per_cu(h, k.fn, k.threads, cache)) {
+    r.k = nlem_kernel(pr, m, nlem_default_wc(pr, m, solver), solver);
+    if (r.k.fn && tolerance && total >= 0 &&
+        total < (int64_t)kFewRounds * h->num_cus * blocks_per_cu(h, r.k.fn, r.k.threads, cache)) {
         for (int wc = 4; wc > 0; --wc) {
             const NlemKernelInfo x = nlem_kernel(pr, m, wc, solver);
             if (x.fn) {
-                if (x.threads > k.threads) k = x;
+                if (x.threads > r.k.threads) r.k = x;
                 break;
             }
         }
     }
-    return k;
+    return r;
 }
 
 static em_status_t check_solver_params(em_context *ctx, float lo, float hi, float rho,
@@ -495,13 +587,14 @@ static NlemLaunch make_launch(const NlemGroup &g, const nlem_image_t *images, co
 // over 160x120 to 480x640 images with 3x3 to 7x7 patches and chunks of 1 to
 // 8: 27.6 -> 25.0 ms summed, the best choice per case summing to 24.7 ms).
 // Smaller pixels keep up to 8 per pop and 16 chunks per workgroup.
-// EMX_NLEM_CHUNK (1..64) overrides the rule.
-static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap) {
+// EMX_NLEM_CHUNK (1..64), then a plan's chunk, override the rule.
+static int queue_chunk(const NlemGroup &g, int64_t total, int64_t cap, int plan_chunk) {
     const char *env = getenv("EMX_NLEM_CHUNK");
     if (env && *env) {
         const int v = atoi(env);
         if (v >= 1 && v <= 64) return v;
     }
+    if (plan_chunk >= 1 && plan_chunk <= 64) return plan_chunk;
     const int64_t side = 2 * (int64_t)g.pr + 1;
     const int64_t elems = side * side * (int64_t)g.m * 64;   // d times the window slots
     int64_t k = std::max<int64_t>(1, std::min<int64_t>(8, 24576 / std::max<int64_t>(1, elems)));
@@ -533,8 +626,11 @@ static constexpr int kOrderMinRounds = 4;
 // kOrderMaxRoundsSmallPatch rounds only.
 static constexpr int kOrderMaxRoundsSmallPatch = 16;
 
-static bool use_order(bool enabled, int pr, int64_t total, int64_t cap) {
-    if (!enabled || total < kOrderMinRounds * cap) return false;
+// plan_order: a plan's choice (0 off, 1 on) or -1 for the rule below.
+static bool use_order(bool enabled, int pr, int64_t total, int64_t cap, int plan_order) {
+    if (!enabled || plan_order == 0) return false;
+    if (plan_order == 1) return true;
+    if (total < kOrderMinRounds * cap) return false;
     return pr >= 3 || total < kOrderMaxRoundsSmallPatch * cap;
 }
 
@@ -548,6 +644,13 @@ static int64_t group_pixels(const NlemGroup &g, const nlem_image_t *images) {
     int64_t t = 0;
     for (int i : g.images) t += (int64_t)images[i].H * images[i].W;
     return t;
+}
+
+// A launch takes the plan of FP16 storage when every image in it is FP16.
+static int group_f16(const NlemGroup &g, const nlem_image_t *images) {
+    for (int i : g.images)
+        if (!images[i].img_is_f16) return 0;
+    return g.images.empty() ? 0 : 1;
 }
 
 // Queue the order kernels of one launch (its pixel order lands in A.order).
@@ -609,14 +712,16 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
     }
     for (size_t gi = 0; gi < groups.size(); ++gi) {
         const NlemGroup &g = groups[gi];
-        NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, o.solver, group_pixels(g, images),
-                                              o.max_iter > 0 && o.tol > 0.0f);
+        const NlemSchedule sc = nlem_schedule(h, g.pr, g.m, o.solver, group_f16(g, images),
+                                              group_pixels(g, images), o.max_iter > 0 && o.tol > 0.0f);
+        const NlemKernelInfo k = sc.k;
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
+        L.tau_arm = sc.arm * L.tau;
         const int64_t total = L.prefix[L.count];
         const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
-        L.chunk = queue_chunk(g, total, cap);
-        if (use_order(ord, g.pr, total, cap)) {
+        L.chunk = queue_chunk(g, total, cap, sc.chunk);
+        if (use_order(ord, g.pr, total, cap, sc.order)) {
             const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
             st = queue_order(h, s, A);
             if (st != EM_OK) return st;
@@ -695,14 +800,16 @@ extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const v
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const NlemGroup g{patch_radius, points_per_lane(window_radius), {}, 0};   // no images listed: no allocation
-    const NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM, total,
-                                                max_iter > 0 && tol > 0.0f, /*cache=*/false);
+    const NlemSchedule sc = nlem_schedule(h, g.pr, g.m, NLEM_SOLVER_ADMM, img_is_f16 ? 1 : 0, total,
+                                          max_iter > 0 && tol > 0.0f, /*cache=*/false);
+    const NlemKernelInfo k = sc.k;
     if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape");
     char *scr = static_cast<char *>(h->noalloc);
     unsigned int *counter = reinterpret_cast<unsigned int *>(scr);
     NlemLaunch L;
     memset(&L, 0, sizeof(L));
     fill_common(L, o);
+    L.tau_arm = sc.arm * L.tau;
     L.count = 1;
     L.img[0] = make_desc(im);
     L.prefix[0] = 0;
@@ -711,8 +818,8 @@ extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const v
     st = ctx_reset_counters(h, s, counter, 1);
     if (st != EM_OK) return st;
     const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads, /*cache=*/false);
-    L.chunk = queue_chunk(g, total, cap);
-    if (use_order(order_enabled(o), g.pr, total, cap)) {
+    L.chunk = queue_chunk(g, total, cap, sc.chunk);
+    if (use_order(order_enabled(o), g.pr, total, cap, sc.order)) {
         if (kScratchHeadBytes + nlem_order_bytes(total) > kScratchBytes)
             return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: order scratch too small");
         const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, scr + kScratchHeadBytes);
@@ -755,6 +862,33 @@ extern "C" em_status_t nlm_denoise(em_handle_t h, void *stream, const void *img,
     return nlem_run(h, static_cast<hipStream_t>(stream), 1, &im, o);
 }
 
+// Mean time (ms) of `repeats` calls of fn on stream s after one warm-up call
+// (synchronous).
+template <class F>
+static em_status_t time_calls(em_context *h, hipStream_t s, int repeats, F fn, float *ms) {
+    em_status_t st = fn();   // warm-up (workspace, occupancy queries, code objects)
+    if (st != EM_OK) return st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    EMX_HIP(h, hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < repeats && st == EM_OK && e == hipSuccess; ++r) st = fn();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != EM_OK) return st;
+    if (e != hipSuccess) return hip_fail(h, e, "autotune timing");
+    *ms = t / (float)repeats;
+    return EM_OK;
+}
+
+// A candidate after the first stage replaces the best plan only when it is
+// faster by more than this fraction (run-to-run noise is ~0.5% here).
+static constexpr float kTuneMargin = 0.01f;
+
 extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_image_t *image,
                                      const nlem_options_t *opt, int32_t repeats, int32_t *chosen) {
     if (!h) return EM_ERR_INVALID_ARG;
@@ -767,55 +901,107 @@ extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_ima
     EMX_HIP(h, hipSetDevice(h->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int pr = image->patch_radius, m = points_per_lane(image->window_radius);
-    const PlanKey key{pr, m, opt->solver};
-    hipEvent_t e0, e1;
-    EMX_HIP(h, hipEventCreate(&e0));
-    EMX_HIP(h, hipEventCreate(&e1));
-    int best = 0;
+    const PlanKey key{pr, m, opt->solver, image->img_is_f16 ? 1 : 0};
+    const bool tolerance = opt->max_iter > 0 && opt->tol > 0.0f;
+    const auto prev = h->plans.find(key);
+    const bool had = prev != h->plans.end();
+    const NlemPlan old = had ? prev->second : NlemPlan{};
+    auto run = [&]() { return nlem_run(h, s, 1, image, *opt); };
+    NlemPlan best;
     float best_ms = 0.0f;
-    for (int wc = 1; wc <= 4; ++wc) {
-        if (!nlem_kernel(pr, m, wc, opt->solver).fn) continue;
-        h->plans[key] = wc;
-        st = nlem_run(h, s, 1, image, *opt);   // warm-up (and occupancy query)
-        if (st != EM_OK) break;
-        hipError_t e = hipEventRecord(e0, s);
-        for (int r = 0; r < repeats && st == EM_OK && e == hipSuccess; ++r) st = nlem_run(h, s, 1, image, *opt);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
+    auto trial = [&](const NlemPlan &p, float margin) -> em_status_t {
+        h->plans[key] = p;
         float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            st = hip_fail(h, e, "autotune timing");
-            break;
-        }
-        if (st != EM_OK) break;
-        if (best == 0 || ms < best_ms) {
-            best = wc;
+        const em_status_t r = time_calls(h, s, repeats, run, &ms);
+        if (r == EM_OK && (best.wc == 0 || ms < (1.0f - margin) * best_ms)) {
+            best = p;
             best_ms = ms;
         }
+        return r;
+    };
+    // 1: the tile shape (every compiled coordinate-wave count, built-in queue rules)
+    for (int wc = 1; wc <= 4 && st == EM_OK; ++wc)
+        if (nlem_kernel(pr, m, wc, opt->solver).fn) st = trial(NlemPlan{wc, 0, -1, 1.0f, EM_PLAN_TUNED}, 0.0f);
+    // 2: queue positions per pop; 3: queue order; 4: residual arm factor
+    const int chunks[] = {1, 2, 4, 8};
+    for (int c : chunks) {
+        if (st != EM_OK || best.wc == 0) break;
+        NlemPlan p = best;
+        p.chunk = c;
+        st = trial(p, kTuneMargin);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != EM_OK || best == 0) {
-        h->plans.erase(key);
+    for (int ord = 0; tolerance && ord <= 1 && st == EM_OK && best.wc != 0; ++ord) {
+        NlemPlan p = best;
+        p.order = ord;
+        st = trial(p, kTuneMargin);
+    }
+    const float arms[] = {1.5f, 2.0f, 3.0f};
+    for (float a : arms) {
+        if (!tolerance || opt->solver != NLEM_SOLVER_ADMM || st != EM_OK || best.wc == 0) break;
+        NlemPlan p = best;
+        p.arm = a;
+        st = trial(p, kTuneMargin);
+    }
+    if (st != EM_OK || best.wc == 0) {
+        if (had) h->plans[key] = old;
+        else h->plans.erase(key);
         return st != EM_OK ? st : fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
     }
+    best.source = EM_PLAN_TUNED;
     h->plans[key] = best;
     ++h->plan_epoch;
-    append_plan_cache(h, pr, m, opt->solver, best);
-    if (chosen) *chosen = best;
+    append_plan_cache(h, key, best);
+    if (chosen) *chosen = best.wc;
+    return EM_OK;
+}
+
+static em_status_t check_plan_shape(em_context *h, int32_t pr, int32_t wr, int32_t solver) {
+    if (pr < 0 || pr > EM_MAX_PATCH_RADIUS || wr < 0 || wr > EM_MAX_WINDOW_RADIUS ||
+        (solver != NLEM_SOLVER_ADMM && solver != NLEM_SOLVER_IRLS))
+        return fail(h, EM_ERR_INVALID_ARG, "bad shape or solver");
     return EM_OK;
 }
 
 extern "C" em_status_t nlem_plan(em_handle_t h, int32_t patch_radius, int32_t window_radius,
                                  int32_t solver, int32_t *waves) {
     if (!h || !waves) return EM_ERR_INVALID_ARG;
-    if (patch_radius < 0 || patch_radius > EM_MAX_PATCH_RADIUS || window_radius < 0 ||
-        window_radius > EM_MAX_WINDOW_RADIUS || (solver != NLEM_SOLVER_ADMM && solver != NLEM_SOLVER_IRLS))
-        return fail(h, EM_ERR_INVALID_ARG, "bad shape or solver");
+    em_status_t st = check_plan_shape(h, patch_radius, window_radius, solver);
+    if (st != EM_OK) return st;
     const int m = points_per_lane(window_radius);
-    auto it = h->plans.find(PlanKey{patch_radius, m, solver});
-    *waves = (it != h->plans.end()) ? it->second : nlem_default_wc(patch_radius, m, solver);
+    const NlemPlan *p = find_plan(h, patch_radius, m, solver, 0);
+    *waves = p ? p->wc : nlem_default_wc(patch_radius, m, solver);
+    return EM_OK;
+}
+
+extern "C" em_status_t nlem_plan_get(em_handle_t h, int32_t patch_radius, int32_t window_radius,
+                                     int32_t solver, int32_t img_is_f16, nlem_plan_t *plan) {
+    if (!h || !plan) return EM_ERR_INVALID_ARG;
+    em_status_t st = check_plan_shape(h, patch_radius, window_radius, solver);
+    if (st != EM_OK) return st;
+    const int m = points_per_lane(window_radius);
+    const NlemPlan *p = find_plan(h, patch_radius, m, solver, img_is_f16);
+    const NlemPlan b = p ? *p : NlemPlan{nlem_default_wc(patch_radius, m, solver), 0, -1, 1.0f, EM_PLAN_BUILTIN};
+    *plan = nlem_plan_t{b.wc, b.chunk, b.order, b.arm, b.source};
+    return EM_OK;
+}
+
+extern "C" em_status_t nlem_plan_set(em_handle_t h, int32_t patch_radius, int32_t window_radius,
+                                     int32_t solver, int32_t img_is_f16, const nlem_plan_t *plan) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    em_status_t st = check_plan_shape(h, patch_radius, window_radius, solver);
+    if (st != EM_OK) return st;
+    const int m = points_per_lane(window_radius);
+    const PlanKey key{patch_radius, m, solver, img_is_f16 ? 1 : 0};
+    if (!plan) {
+        h->plans.erase(key);
+    } else {
+        if (!nlem_kernel(patch_radius, m, plan->waves, solver).fn)
+            return fail(h, EM_ERR_INVALID_ARG, "waves: no compiled kernel of that count for the shape");
+        if (!plan_values_ok(plan->chunk, plan->order, plan->arm_factor))
+            return fail(h, EM_ERR_INVALID_ARG, "chunk 0..64, order -1..1 and a finite arm_factor >= 1");
+        h->plans[key] = NlemPlan{plan->waves, plan->chunk, plan->order, plan->arm_factor, EM_PLAN_SET};
+    }
+    ++h->plan_epoch;
     return EM_OK;
 }
 
@@ -889,10 +1075,16 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         };
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const NlemGroup &g = groups[gi];
-            NlemKernelInfo k = select_nlem_kernel(h, g.pr, g.m, NLEM_SOLVER_ADMM, group_pixels(g, images),
-                                                  o.max_iter > 0 && o.tol > 0.0f);
+            const NlemSchedule sc = nlem_schedule(h, g.pr, g.m, NLEM_SOLVER_ADMM, group_f16(g, images),
+                                                  group_pixels(g, images), o.max_iter > 0 && o.tol > 0.0f);
+            const NlemKernelInfo k = sc.k;
+            if (!k.fn) {
+                (void)hipGraphDestroy(graph);
+                return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape");
+            }
             unsigned int *counter = h->counters + gi;
             NlemLaunch L = make_launch(g, images, o, counter);
+            L.tau_arm = sc.arm * L.tau;
             hipGraphNode_t prev;
             int one = 1;
             void *rargs[] = {&counter, &one};
@@ -901,8 +1093,8 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             if (st != EM_OK) return st;
             const int64_t total = L.prefix[L.count];
             const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
-            L.chunk = queue_chunk(g, total, cap);
-            if (use_order(ord, g.pr, total, cap)) {
+            L.chunk = queue_chunk(g, total, cap, sc.chunk);
+            if (use_order(ord, g.pr, total, cap, sc.order)) {
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
                 OrderKernel ok[kOrderKernels];
                 nlem_order_kernels(A, h->num_cus, ok);
@@ -1007,6 +1199,101 @@ extern "C" em_status_t em_solve_batch_ex(em_handle_t h, void *stream, int64_t B,
     if (B == 0) return EM_OK;
     EMX_HIP(h, hipSetDevice(h->device));
     return batch_solve(h, static_cast<hipStream_t>(stream), B, a, w, inst, o, z, stats);
+}
+
+extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B, const float *a,
+                                         const float *w, const em_instance_t *inst, const em_options_t *opt,
+                                         float *z, em_stats_t *stats, int32_t repeats, em_batch_plan_t *chosen) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (!opt) return fail(h, EM_ERR_INVALID_ARG, "options must be non-NULL");
+    if (repeats < 1) return fail(h, EM_ERR_INVALID_ARG, "repeats must be >= 1");
+    if (opt->solver != EM_SOLVER_ADMM || opt->set != EM_SET_BOX)
+        return fail(h, EM_ERR_UNSUPPORTED, "em_batch_autotune: the fixed-penalty EM-ADMM over a box");
+    const BatchPlanKey key{EM_SOLVER_ADMM, opt->points_f16 ? 1 : 0};
+    const auto prev = h->batch_plans.find(key);
+    const bool had = prev != h->batch_plans.end();
+    const BatchPlan old = had ? prev->second : BatchPlan{};
+    h->batch_plans.erase(key);
+    // validates the arguments like any call, before anything is timed
+    em_status_t st = em_solve_batch_ex(h, stream, B, a, w, inst, opt, z, stats);
+    if (st != EM_OK || B == 0) {
+        if (had) h->batch_plans[key] = old;
+        if (st == EM_OK && chosen) *chosen = em_batch_plan_t{old.mask, old.arm, old.source};
+        return st;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned int counts[kNumWideClasses];
+    st = batch_wide_counts(h, s, B, inst, counts);
+    auto run = [&]() { return em_solve_batch_ex(h, stream, B, a, w, inst, opt, z, stats); };
+    BatchPlan best;
+    float best_ms = 0.0f;
+    bool have = false;
+    auto trial = [&](const BatchPlan &p, float margin) -> em_status_t {
+        h->batch_plans[key] = p;
+        float ms = 0.0f;
+        const em_status_t r = time_calls(h, s, repeats, run, &ms);
+        if (r == EM_OK && (!have || ms < (1.0f - margin) * best_ms)) {
+            best = p;
+            best_ms = ms;
+            have = true;
+        }
+        return r;
+    };
+    if (st == EM_OK) st = trial(BatchPlan{0, 1.0f, EM_PLAN_TUNED}, 0.0f);
+    // each populated sliced class in the generic classes, largest first
+    int order[kNumWideClasses];
+    int npop = 0;
+    for (int k = 0; k < kNumWideClasses; ++k)
+        if (counts[k] > 0) order[npop++] = k;
+    std::sort(order, order + npop, [&](int x, int y) { return counts[x] > counts[y]; });
+    for (int i = 0; i < npop && st == EM_OK; ++i) {
+        BatchPlan p = best;
+        p.mask |= (uint64_t)1 << order[i];
+        st = trial(p, kTuneMargin);
+    }
+    const float arms[] = {1.5f, 2.0f, 3.0f};
+    for (float arm : arms) {
+        if (!(opt->tol > 0.0f) || opt->max_iter <= 0 || st != EM_OK) break;
+        BatchPlan p = best;
+        p.arm = arm;
+        st = trial(p, kTuneMargin);
+    }
+    if (st != EM_OK || !have) {
+        if (had) h->batch_plans[key] = old;
+        else h->batch_plans.erase(key);
+        return st != EM_OK ? st : fail(h, EM_ERR_HIP, "em_batch_autotune: no timing");
+    }
+    best.source = EM_PLAN_TUNED;
+    h->batch_plans[key] = best;
+    append_batch_plan_cache(h, key, best);
+    if (chosen) *chosen = em_batch_plan_t{best.mask, best.arm, best.source};
+    return EM_OK;
+}
+
+extern "C" em_status_t em_batch_plan_get(em_handle_t h, int32_t solver, int32_t points_f16,
+                                         em_batch_plan_t *plan) {
+    if (!h || !plan) return EM_ERR_INVALID_ARG;
+    if (solver != EM_SOLVER_ADMM) return fail(h, EM_ERR_INVALID_ARG, "batch plans are for EM_SOLVER_ADMM");
+    auto it = h->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, points_f16 ? 1 : 0});
+    const BatchPlan b = (it != h->batch_plans.end()) ? it->second : BatchPlan{};
+    *plan = em_batch_plan_t{b.mask, b.arm, b.source};
+    return EM_OK;
+}
+
+extern "C" em_status_t em_batch_plan_set(em_handle_t h, int32_t solver, int32_t points_f16,
+                                         const em_batch_plan_t *plan) {
+    if (!h) return EM_ERR_INVALID_ARG;
+    if (solver != EM_SOLVER_ADMM) return fail(h, EM_ERR_INVALID_ARG, "batch plans are for EM_SOLVER_ADMM");
+    const BatchPlanKey key{EM_SOLVER_ADMM, points_f16 ? 1 : 0};
+    if (!plan) {
+        h->batch_plans.erase(key);
+        return EM_OK;
+    }
+    if ((plan->generic_classes & ~kAllWideClasses) != 0)
+        return fail(h, EM_ERR_INVALID_ARG, "generic_classes: bits above the sliced classes");
+    if (!plan_values_ok(0, -1, plan->arm_factor)) return fail(h, EM_ERR_INVALID_ARG, "arm_factor must be finite and >= 1");
+    h->batch_plans[key] = BatchPlan{plan->generic_classes, plan->arm_factor, EM_PLAN_SET};
+    return EM_OK;
 }
 
 extern "C" em_status_t em_solve_plain(em_handle_t h, void *stream, int64_t B, const float *a,

@@ -32,7 +32,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("em_create", "em_destroy", "em_solve_batch", "em_solve_plain", "nlem_denoise",
                  "nlem_denoise_multi", "nlem_denoise_ex", "nlm_denoise", "em_solve_batch_ex", "em_solve_plain_ex",
-                 "em_sync", "nlem_autotune", "nlem_plan", "em_kernel_timing", "em_kernel_timing_read",
+                 "em_sync", "nlem_autotune", "nlem_plan", "nlem_plan_get", "nlem_plan_set", "em_batch_autotune",
+                 "em_batch_plan_get", "em_batch_plan_set", "em_kernel_timing", "em_kernel_timing_read",
                  "em_status_string", "em_last_error"):
         assert must in names
 
@@ -50,6 +51,8 @@ def test_struct_sizes_match_the_header():
     assert C.sizeof(emx.NlemImage) == 8 * 3 + 4 * 6          # nlem_image_t
     assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
     assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8 + 8 + 8 * 2 + 8   # em_options_t
+    assert C.sizeof(emx.NlemPlan) == 4 * 5                   # nlem_plan_t
+    assert C.sizeof(emx.BatchPlan) == 8 + 4 + 4              # em_batch_plan_t
 
 
 def test_null_handle_is_rejected_without_device_work():
@@ -76,6 +79,16 @@ def test_null_handle_is_rejected_without_device_work():
     assert lib.nlem_autotune(None, None, None, None, 1, None) == -1
     lib.nlem_plan.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
     assert lib.nlem_plan(None, 3, 10, 0, None) == -1
+    lib.nlem_plan_get.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    assert lib.nlem_plan_get(None, 3, 10, 0, 0, None) == -1
+    lib.nlem_plan_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp]
+    assert lib.nlem_plan_set(None, 3, 10, 0, 0, None) == -1
+    lib.em_batch_autotune.argtypes = [vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
+    assert lib.em_batch_autotune(None, None, 1, None, None, None, None, None, None, 1, None) == -1
+    lib.em_batch_plan_get.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    assert lib.em_batch_plan_get(None, 0, 0, None) == -1
+    lib.em_batch_plan_set.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    assert lib.em_batch_plan_set(None, 0, 0, None) == -1
     lib.em_kernel_timing.argtypes = [vp, C.c_int32]
     assert lib.em_kernel_timing(None, 1) == -1
     lib.em_kernel_timing_read.argtypes = [vp, vp, vp]
