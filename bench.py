@@ -18,9 +18,13 @@ mixed noise with FP32 and FP16 storage, 16 images in one graph, 1,048,576
 point sets), each with its time, rate, model TFLOP/s and max-abs / RMS
 error against the FP64 oracle at the GPU's iteration counts; and the
 oracle itself timed on this host's cores (cpu_baseline), whose outputs
-cover every pixel of the step's image.
+cover every pixel of the step's image.  Before the warm-up, the built-in
+schedules are timed and the autotuners (nlem_autotune, em_batch_autotune)
+pick the plans the timed steps run; `plan` and `batch_interior.plan`
+record both, with the plans' source (--tune 0 keeps the built-in plans).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch] [--no-configs] [--plain 0|1]
+                    [--tune 0|1]
 """
 
 from __future__ import annotations
@@ -66,6 +70,10 @@ def parse():
     ap.add_argument("--batch-interior", action="store_true",
                     help="instead of the NLEM line, time only em_solve_batch over the 55,696 interior "
                          "pixels of the 256x256 image as materialised n=441, d=49 instances (its own line)")
+    ap.add_argument("--tune", type=int, default=1,
+                    help="tune the NLEM and batch schedules (nlem_autotune, em_batch_autotune) during the "
+                         "untimed warm-up and time the tuned plans, after timing the built-in ones; "
+                         "0 keeps the built-in plans")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device-to-device copy (3 times): the known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters")
@@ -88,9 +96,10 @@ def copy_calibration():
     print(f"copy calibration: 3 copies of {src.numel() * 4} bytes", flush=True)
 
 
-def profiled_traffic():
+def profiled_traffic(waves):
     """HBM bytes per launch of the NLEM kernel from the committed rocprofv3
-    counter summary, or None when the kernel sources changed since."""
+    counter summary, or None when the kernel sources changed since or the
+    plan runs another coordinate-wave count than the profiled kernel."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "nlem_256x256_d49_counters.md")
@@ -104,7 +113,8 @@ def profiled_traffic():
     h = hashlib.sha256(src.encode()).hexdigest()[:16]
     m_h = re.search(r"kernel_source_sha256_16: (\w+)", text)
     m_t = re.search(r"traffic_bytes_per_launch: (\d+)", text)
-    if not m_h or not m_t or m_h.group(1) != h:
+    m_k = re.search(r"nlem_solve_kernel<3, 7, (\d), 0>", text)
+    if not m_h or not m_t or m_h.group(1) != h or not m_k or int(m_k.group(1)) != waves:
         return None
     return float(m_t.group(1))
 
@@ -429,7 +439,7 @@ def main():
         import synth
         wl = synth.nlem_256()
         r = batch_interior_rate(wl.images[0], wl, torch.device("cuda:0"), emx.handle(0), None,
-                                reps=max(1, min(args.steps, 20)))
+                                reps=max(1, min(args.steps, 20)), tune=args.tune != 0)
         print(json.dumps({"workload": "em_solve_batch, the 256x256 image's interior pixels as n=441, "
                                       "d=49 instances", **r}), flush=True)
         return
@@ -469,6 +479,24 @@ def main():
         hd.nlem_denoise(img, out, stats, patch_radius=pr, window_radius=wr, h=im.h, lo=wl.lo,
                         hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol)
 
+    # schedule: the built-in plan is timed, then nlem_autotune keeps the
+    # fastest plan of its search (both untimed for the line); the timed steps
+    # run the plan in force
+    plan = {"nlem_builtin": hd.nlem_plan_get(pr, wr)}
+    if args.tune:
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        plan["nlem_builtin_ms_per_step"] = _events_ms(step, 20)
+        t_tune = time.perf_counter()
+        hd.nlem_autotune(dict(img=img, out=out, stats=stats, patch_radius=pr, window_radius=wr, h=im.h),
+                         lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, repeats=5)
+        hd.sync()
+        plan["tune_s"] = time.perf_counter() - t_tune
+    plan["nlem"] = hd.nlem_plan_get(pr, wr)
+    plan["nlem_same_as_builtin"] = all(plan["nlem"][k] == plan["nlem_builtin"][k]
+                                       for k in ("waves", "chunk", "order", "arm_factor"))
+    waves = plan["nlem"]["waves"]
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -525,14 +553,15 @@ def main():
                             "exactly is em_solves_per_s_n441_d49",
         "mean_iters": float(iters.mean()),
         "converged_fraction": float(np.mean(flags == 1)),
+        "plan": plan,
         "elem_iters_per_s": elem_iters / (ms * 1e-3),
         "host_wall_s": wall,
         "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
                      "frac_nonpacked_fma_peak": tflops / FP32_NONPACKED_TFLOPS,
-                     "flops_per_launch": flops, "traffic": profiled_traffic(),
-                     "kernel": f"nlem_solve_kernel, patch radius {pr}, {hd.nlem_plan(pr, wr)} "
-                               f"coordinate waves", "kernel_ms": kernel_ms,
+                     "flops_per_launch": flops, "traffic": profiled_traffic(waves),
+                     "kernel": f"nlem_solve_kernel<{pr}, 7, {waves}, 0> ({waves} coordinate waves, "
+                               f"plan {plan['nlem']['source']})", "kernel_ms": kernel_ms,
                      "achieved_per_step": tflops_step,
                      "timing": "achieved: flops per launch / the NLEM kernel's mean duration, from "
                                "HIP events the library records around each NLEM launch on the "
@@ -544,7 +573,8 @@ def main():
 
     rng = np.random.default_rng(12)
     if not args.no_batch:
-        bi = batch_interior_rate(im, wl, dev, hd, out, plain=args.plain != 0, oracle_instances=1024)
+        bi = batch_interior_rate(im, wl, dev, hd, out, plain=args.plain != 0, oracle_instances=1024,
+                                 tune=args.tune != 0)
         res["em_solves_per_s_n441_d49"] = bi["solves_per_s"]
         res["batch_interior"] = bi
         if "plain" in bi:
@@ -631,7 +661,7 @@ def pointsets(args):
                       "reps": reps, "per_d": per_d}), flush=True)
 
 
-def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_instances=0):
+def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_instances=0, tune=False):
     """em_solve_batch on every interior pixel of the image (full 21 x 21
     windows: n = 441, d = 49) as materialised instances, the EM-solves half of
     the metric.  Input preparation (untimed): patches gathered on the device,
@@ -640,7 +670,8 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_i
     same instances also go through em_solve_plain (one launch per instance),
     timed with HIP events; oracle_instances > 0: that many sampled instances
     are solved by the FP64 oracle at the GPU's iteration counts (every
-    coordinate of z compared)."""
+    coordinate of z compared).  tune=True: the built-in plan is timed, then
+    em_batch_autotune picks the plan the timed calls use (both reported)."""
     import numpy as np
     import torch
 
@@ -676,6 +707,17 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_i
     kw = dict(lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter, tol=wl.tol, init=emx.INIT_MAXW)
     hd.em_solve_batch(a, w, it, z, st, **kw)   # warm-up (workspace, code objects)
     torch.cuda.synchronize()
+    plan = {"batch_builtin": hd.em_batch_plan_get()}
+    if tune:
+        plan["batch_builtin_ms"] = _events_ms(lambda: hd.em_solve_batch(a, w, it, z, st, **kw), reps)
+        t_tune = time.perf_counter()
+        hd.em_batch_autotune(a, w, it, z, st, lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter,
+                             tol=wl.tol, init=emx.INIT_MAXW, repeats=3)
+        hd.sync()
+        plan["tune_s"] = time.perf_counter() - t_tune
+    plan["batch"] = hd.em_batch_plan_get()
+    plan["batch_same_as_builtin"] = all(plan["batch"][k] == plan["batch_builtin"][k]
+                                        for k in ("generic_classes", "arm_factor"))
     ms = _events_ms(lambda: hd.em_solve_batch(a, w, it, z, st, **kw), reps)
     iters, flags = emx.stats_view(st)[0].cpu().numpy(), emx.stats_view(st)[1].cpu().numpy()
     centre = z.reshape(B, d)[:, (d - 1) // 2]
@@ -688,7 +730,8 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_i
            "max_abs_diff_vs_nlem_over_range": diff,
            "note": "em_solve_batch over the interior pixels' materialised windows (inputs in HBM, "
                    "weights computed outside the timed region); the NLEM kernel solves the same "
-                   "instances from the image tile"}
+                   "instances from the image tile",
+           "plan": plan}
     if oracle_instances > 0:
         rng = np.random.default_rng(5)
         sample = np.sort(rng.choice(B, min(oracle_instances, B), replace=False))

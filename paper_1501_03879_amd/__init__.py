@@ -299,8 +299,10 @@ class Handle:
 
     def nlem_autotune(self, item, *, solver=SOLVER_ADMM, init=NLEM_INIT_NOISY, lo=0.0, hi=255.0,
                       rho=1e-3, eps=1e-6, max_iter=200, tol=1e-4, repeats=2, stream=None):
-        """Time the compiled coordinate-wave counts on one image (a dict as
-        for nlem_denoise_ex) and keep the fastest; returns the chosen count."""
+        """Search the schedule of this image's shape (coordinate waves, queue
+        chunk, queue order, residual arm factor) on the image (a dict as for
+        nlem_denoise_ex) and keep the fastest plan; returns its coordinate-wave
+        count (the whole plan: nlem_plan_get)."""
         arr = _image_array([item])
         opt = NlemOptions(int(solver), int(init), float(lo), float(hi), float(rho), float(eps),
                           int(max_iter), float(tol))
