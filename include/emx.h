@@ -47,7 +47,8 @@
  *    evaluated on iterations that follow one with r_dual <= tol D (times a
  *    plan's arm factor >= 1; nlem_plan_t, em_batch_plan_t) and on the last
  *    allowed iteration, so a solve may end one iteration later than a solver
- *    that evaluates both every iteration.  tol = 0 runs
+ *    that evaluates both every iteration (up to check_every iterations later
+ *    under a plan that checks only every check_every-th iteration).  tol = 0 runs
  *    exactly max_iter iterations; max_iter = 0 returns the starting z.
  *  - Arithmetic is FP32 (image storage may be FP16, widened on load).
  */
@@ -440,10 +441,11 @@ typedef enum {
  * class, solver, image storage): its tile shape and the schedule of its
  * persistent work queue.  Every choice gives a correct solve: waves changes
  * the summation order (results agree to FP32 rounding), chunk and order only
- * which workgroup solves which pixel when, and arm_factor only on which
- * iteration the primal residual is evaluated (a solve stops at the first
- * evaluated iteration with both residuals within tol D, at most one iteration
- * after an evaluation on every iteration would have stopped it).
+ * which workgroup solves which pixel when, and arm_factor and check_every
+ * only on which iterations the primal residual is evaluated (a solve stops at
+ * the first evaluated iteration with both residuals within tol D: at most one
+ * iteration after an evaluation on every iteration would have stopped it with
+ * check_every = 1, at most check_every iterations after it otherwise).
  */
 typedef struct {
     int32_t waves;       /* coordinate waves per pixel (a compiled count, 1..4) */
@@ -452,6 +454,8 @@ typedef struct {
                             0 = off, 1 = on */
     float arm_factor;    /* the primal residual is evaluated on iterations that follow one with
                             r_dual <= arm_factor tol D, and on the last one; >= 1, 1 = built-in */
+    int32_t check_every; /* ... and only on iterations t that are multiples of check_every
+                            (1, 2, 4 or 8; 1 = built-in) */
     int32_t source;      /* em_plan_source_t; ignored by nlem_plan_set */
 } nlem_plan_t;
 
@@ -462,8 +466,8 @@ typedef struct {
  * compiled coordinate-wave count with the built-in queue rules, then, with
  * the best count, queue chunks 1, 2, 4 and 8, then (tolerance mode) the
  * queue order off and on, then (tolerance mode, EM-ADMM) arm factors 1.5, 2
- * and 3; a candidate after the wave count replaces the plan only when it is
- * more than 1% faster.  nlem_denoise, nlem_denoise_ex and nlem_denoise_multi
+ * and 3 and residual-check intervals 2, 4 and 8; a candidate after the wave
+ * count replaces the plan only when it is more than 1% faster.  nlem_denoise, nlem_denoise_ex and nlem_denoise_multi
  * use the plan from then on (for a launch of several images, the plan of its
  * shape with FP16 storage when every image in it is FP16); the environment
  * variables EMX_NLEM_WC, EMX_NLEM_CHUNK and EMX_NLEM_ORDER still override.
@@ -485,7 +489,7 @@ em_status_t nlem_plan(em_handle_t handle, int32_t patch_radius, int32_t window_r
 
 /* The whole plan of a shape, solver and storage (img_is_f16): the handle's
  * plan with its source, or the built-in values (waves = the default count,
- * chunk 0, order -1, arm_factor 1, source EM_PLAN_BUILTIN).
+ * chunk 0, order -1, arm_factor 1, check_every 1, source EM_PLAN_BUILTIN).
  * Errors: INVALID_ARG (NULL arguments, bad shape or solver). */
 em_status_t nlem_plan_get(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
                           int32_t solver, int32_t img_is_f16, nlem_plan_t *plan);
@@ -494,7 +498,7 @@ em_status_t nlem_plan_get(em_handle_t handle, int32_t patch_radius, int32_t wind
  * EM_PLAN_SET; not written to the cache file), or with plan = NULL return
  * it to the built-in values.  Errors: INVALID_ARG (bad shape or solver,
  * waves not compiled for the shape, chunk outside 0..64, order outside
- * -1..1, arm_factor not finite or below 1). */
+ * -1..1, arm_factor not finite or below 1, check_every not 1, 2, 4 or 8). */
 em_status_t nlem_plan_set(em_handle_t handle, int32_t patch_radius, int32_t window_radius,
                           int32_t solver, int32_t img_is_f16, const nlem_plan_t *plan);
 
@@ -506,12 +510,13 @@ em_status_t nlem_plan_set(em_handle_t handle, int32_t patch_radius, int32_t wind
  * 13-coordinate slices over ceil(d / 13) waves, ceil(n / 64) points per lane)
  * whether its instances run there or in the generic classes (16-coordinate
  * slices over ceil(d / 16) waves, 1, 2 or 4 points per lane and one or two
- * point waves), and the arm factor of the primal residual (as nlem_plan_t).
- * Far-outlier deferral is unaffected.
+ * point waves), and the arm factor and check interval of the primal residual
+ * (as nlem_plan_t).  Far-outlier deferral is unaffected.
  */
 typedef struct {
     uint64_t generic_classes;  /* bit k set: sliced class k is routed to the generic classes */
     float arm_factor;          /* >= 1, 1 = built-in */
+    int32_t check_every;       /* 1, 2, 4 or 8; 1 = built-in */
     int32_t source;            /* em_plan_source_t; ignored by em_batch_plan_set */
 } em_batch_plan_t;
 
@@ -521,8 +526,8 @@ typedef struct {
  * box) and keep the fastest schedule as the handle's plan for its point
  * storage (opt->points_f16): after the built-in plan, each sliced class that
  * holds instances of the batch (largest first) is tried in the generic
- * classes, then arm factors 1.5, 2 and 3 (tolerance mode); a change is kept
- * when more than 1% faster.  `repeats` timed calls per candidate after one
+ * classes, then arm factors 1.5, 2 and 3 and check intervals 2, 4 and 8
+ * (tolerance mode); a change is kept when more than 1% faster.  `repeats` timed calls per candidate after one
  * warm-up, synchronously on `stream`; z and stats hold the last candidate's
  * results.  The plan is appended to the EMX_AUTOTUNE_CACHE file as for
  * nlem_autotune.  chosen: NULL or receives the plan.
@@ -534,7 +539,8 @@ em_status_t em_batch_autotune(em_handle_t handle, void *stream, int64_t B, const
                               float *z, em_stats_t *stats, int32_t repeats, em_batch_plan_t *chosen);
 
 /* The batch plan for point storage points_f16 (the handle's, else the
- * built-in: no class routed, arm_factor 1).  solver must be EM_SOLVER_ADMM.
+ * built-in: no class routed, arm_factor 1, check_every 1).  solver must be
+ * EM_SOLVER_ADMM.
  * Errors: INVALID_ARG. */
 em_status_t em_batch_plan_get(em_handle_t handle, int32_t solver, int32_t points_f16,
                               em_batch_plan_t *plan);
@@ -542,7 +548,7 @@ em_status_t em_batch_plan_get(em_handle_t handle, int32_t solver, int32_t points
 /* Set the batch plan for point storage points_f16 (source EM_PLAN_SET), or
  * with plan = NULL return to the built-in one.  Errors: INVALID_ARG (solver
  * other than EM_SOLVER_ADMM, bits above the 28 classes, arm_factor not finite
- * or below 1). */
+ * or below 1, check_every not 1, 2, 4 or 8). */
 em_status_t em_batch_plan_set(em_handle_t handle, int32_t solver, int32_t points_f16,
                               const em_batch_plan_t *plan);
 

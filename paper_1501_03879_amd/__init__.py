@@ -55,20 +55,22 @@ PLAN_SOURCES = ("builtin", "tuned", "cache", "set")
 class NlemPlan(C.Structure):
     """nlem_plan_t: schedule of the NLEM solve kernel for one shape."""
     _fields_ = [("waves", C.c_int32), ("chunk", C.c_int32), ("order", C.c_int32),
-                ("arm_factor", C.c_float), ("source", C.c_int32)]
+                ("arm_factor", C.c_float), ("check_every", C.c_int32), ("source", C.c_int32)]
 
     def as_dict(self):
         return dict(waves=self.waves, chunk=self.chunk, order=self.order,
-                    arm_factor=float(self.arm_factor), source=PLAN_SOURCES[self.source])
+                    arm_factor=float(self.arm_factor), check_every=self.check_every,
+                    source=PLAN_SOURCES[self.source])
 
 
 class BatchPlan(C.Structure):
     """em_batch_plan_t: sliced classes routed to the generic kernels, arm factor."""
-    _fields_ = [("generic_classes", C.c_uint64), ("arm_factor", C.c_float), ("source", C.c_int32)]
+    _fields_ = [("generic_classes", C.c_uint64), ("arm_factor", C.c_float), ("check_every", C.c_int32),
+                ("source", C.c_int32)]
 
     def as_dict(self):
         return dict(generic_classes=int(self.generic_classes), arm_factor=float(self.arm_factor),
-                    source=PLAN_SOURCES[self.source])
+                    check_every=self.check_every, source=PLAN_SOURCES[self.source])
 
 
 class EmOptions(C.Structure):
@@ -327,11 +329,12 @@ class Handle:
         return p.as_dict()
 
     def nlem_plan_set(self, patch_radius, window_radius, plan=None, solver=SOLVER_ADMM, f16=False):
-        """Set the plan (dict with waves, chunk, order, arm_factor) or, with
-        plan=None, return to the built-in one."""
+        """Set the plan (dict with waves, chunk, order, arm_factor, check_every)
+        or, with plan=None, return to the built-in one."""
         p = None if plan is None else NlemPlan(int(plan["waves"]), int(plan.get("chunk", 0)),
                                                int(plan.get("order", -1)),
-                                               float(plan.get("arm_factor", 1.0)), 0)
+                                               float(plan.get("arm_factor", 1.0)),
+                                               int(plan.get("check_every", 1)), 0)
         self._check(self.lib.nlem_plan_set(self.h, int(patch_radius), int(window_radius), int(solver),
                                            1 if f16 else 0, None if p is None else C.byref(p)),
                     "nlem_plan_set")
@@ -358,10 +361,11 @@ class Handle:
         return p.as_dict()
 
     def em_batch_plan_set(self, plan=None, f16=False, solver=SOLVER_ADMM):
-        """Set the batch plan (dict with generic_classes, arm_factor) or, with
-        plan=None, return to the built-in one."""
+        """Set the batch plan (dict with generic_classes, arm_factor,
+        check_every) or, with plan=None, return to the built-in one."""
         p = None if plan is None else BatchPlan(int(plan.get("generic_classes", 0)),
-                                                float(plan.get("arm_factor", 1.0)), 0)
+                                                float(plan.get("arm_factor", 1.0)),
+                                                int(plan.get("check_every", 1)), 0)
         self._check(self.lib.em_batch_plan_set(self.h, int(solver), 1 if f16 else 0,
                                                None if p is None else C.byref(p)), "em_batch_plan_set")
 

@@ -259,6 +259,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
         L.arm = plan.arm;
+        L.check_mask = plan.check - 1;
         L.list = list;
         L.offsets = offsets;
         L.counter = heads + c;
@@ -285,6 +286,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         for (int k = 0; k < kDeferLists; ++k) {
             ClassLaunch L = class_launch(a, w, inst, o, z, stats, 0);
             L.arm = plan.arm;
+            L.check_mask = plan.check - 1;
             L.list = list + (int64_t)(k + 1) * B;
             L.offsets = defer_q + 2 * k;
             L.counter = defer_heads + k;
@@ -569,6 +571,7 @@ static em_status_t plain_admm(em_context *ctx, hipStream_t s, int64_t B, const f
         const ClassKernel &ck = (c >= kNumClasses) ? wtab[c - kNumClasses] : tab[c];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
         L.arm = plan.arm;
+        L.check_mask = plan.check - 1;
         L.single = b;
         void *args[] = {&L};
         const hipError_t err = hipLaunchKernel(ck.fn, dim3(1), dim3(ck.threads), args, 0, s);

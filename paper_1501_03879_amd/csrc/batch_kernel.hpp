@@ -116,6 +116,7 @@ struct ClassLaunch {
     const float *ball_radius;     // SET = 1: radii (one per instance) or null (radius below)
     float radius;
     float lo, hi, mu, tol, arm;
+    int32_t check_mask;           // primal residual only on iterations t with (t & check_mask) == 0 (or the last)
     float eps;                    // IRLS
     float adapt_ratio2;           // ADMM: (residual ratio)^2 that triggers a penalty change
     float adapt_factor;           // ADMM: penalty scale factor
@@ -838,7 +839,8 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
                         }
                     }
                 }
-                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2) ||
+                const bool armed = uniform((t == max_iter) ||
+                                           (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0) ||
                                            (ADAPT && t % every == 0));
                 float s[M];
 #pragma unroll

@@ -390,7 +390,8 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                     rd_all = readfirstlane(rd_all);
                 }
                 if (t > 1) rd2 = rd_all * inv_d;
-                const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
+                const bool armed = uniform((t == max_iter) ||
+                                           (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
                 float s[M];
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);

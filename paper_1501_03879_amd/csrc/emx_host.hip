@@ -53,6 +53,7 @@ struct NlemPlan {
     int chunk = 0;      // queue positions per pop; 0 = the size rule
     int order = -1;     // longest-first order: -1 = the rule, 0 = off, 1 = on
     float arm = 1.0f;   // residual arm factor (>= 1)
+    int check = 1;      // residual-check interval (1, 2, 4 or 8)
     int source = EM_PLAN_BUILTIN;
 };
 // Batch plans: (solver, FP16 points) -> routing of the sliced classes and arm factor.
@@ -60,6 +61,7 @@ using BatchPlanKey = std::pair<int, int>;
 struct BatchPlan {
     uint64_t mask = 0;
     float arm = 1.0f;
+    int check = 1;
     int source = EM_PLAN_BUILTIN;
 };
 
@@ -155,9 +157,9 @@ em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what) { ret
 BatchPlanView ctx_batch_plan(em_context *ctx, const em_options_t &o) {
     if (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX) {
         auto it = ctx->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, o.points_f16 ? 1 : 0});
-        if (it != ctx->batch_plans.end()) return BatchPlanView{it->second.mask, it->second.arm};
+        if (it != ctx->batch_plans.end()) return BatchPlanView{it->second.mask, it->second.arm, it->second.check};
     }
-    return BatchPlanView{0, 1.0f};
+    return BatchPlanView{0, 1.0f, 1};
 }
 
 // Work-queue heads: a fixed pool owned by the handle.
@@ -217,8 +219,9 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
 
 // ---------------------------------------------------------------------------
 // autotune cache: text lines in the file named by EMX_AUTOTUNE_CACHE,
-//   nlem2 <arch> <patch radius> <points per lane> <solver> <fp16> <waves> <chunk> <order> <arm>
-//   batch <arch> <solver> <fp16> <routed classes, hex> <arm>
+//   nlem2 <arch> <patch radius> <points per lane> <solver> <fp16> <waves> <chunk> <order> <arm> <check>
+//   batch <arch> <solver> <fp16> <routed classes, hex> <arm> <check>
+// (a missing check field reads as 1)
 // and, from before the queue and arm fields existed,
 //   nlem <arch> <patch radius> <points per lane> <solver> <waves>
 // (both storages, built-in queue rules).  Later lines win; lines for another
@@ -226,8 +229,9 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
 // parse are skipped.
 // ---------------------------------------------------------------------------
 
-static bool plan_values_ok(int chunk, int order, float arm) {
-    return chunk >= 0 && chunk <= 64 && order >= -1 && order <= 1 && std::isfinite(arm) && arm >= 1.0f;
+static bool plan_values_ok(int chunk, int order, float arm, int check) {
+    return chunk >= 0 && chunk <= 64 && order >= -1 && order <= 1 && std::isfinite(arm) && arm >= 1.0f &&
+           (check == 1 || check == 2 || check == 4 || check == 8);
 }
 
 static constexpr uint64_t kAllWideClasses = ((uint64_t)1 << kNumWideClasses) - 1;
@@ -240,25 +244,26 @@ static void load_plan_cache(em_context *ctx) {
     char line[256];
     while (fgets(line, sizeof(line), f)) {
         char kind[16], arch[64];
-        int pr, m, solver, f16, wc, chunk, order;
+        int pr, m, solver, f16, wc, chunk, order, check = 1;
         float arm;
         unsigned long long mask;
         if (sscanf(line, "%15s %63s", kind, arch) != 2 || ctx->arch != arch) continue;
         if (strcmp(kind, "nlem2") == 0 &&
-            sscanf(line, "%*s %*s %d %d %d %d %d %d %d %f", &pr, &m, &solver, &f16, &wc, &chunk, &order,
-                   &arm) == 8) {
-            if ((f16 == 0 || f16 == 1) && nlem_kernel(pr, m, wc, solver).fn && plan_values_ok(chunk, order, arm))
-                ctx->plans[PlanKey{pr, m, solver, f16}] = NlemPlan{wc, chunk, order, arm, EM_PLAN_CACHE};
+            sscanf(line, "%*s %*s %d %d %d %d %d %d %d %f %d", &pr, &m, &solver, &f16, &wc, &chunk, &order,
+                   &arm, &check) >= 8) {
+            if ((f16 == 0 || f16 == 1) && nlem_kernel(pr, m, wc, solver).fn &&
+                plan_values_ok(chunk, order, arm, check))
+                ctx->plans[PlanKey{pr, m, solver, f16}] = NlemPlan{wc, chunk, order, arm, check, EM_PLAN_CACHE};
         } else if (strcmp(kind, "nlem") == 0 &&
                    sscanf(line, "%*s %*s %d %d %d %d", &pr, &m, &solver, &wc) == 4) {
             if (nlem_kernel(pr, m, wc, solver).fn)
                 for (int x = 0; x < 2; ++x)
-                    ctx->plans[PlanKey{pr, m, solver, x}] = NlemPlan{wc, 0, -1, 1.0f, EM_PLAN_CACHE};
+                    ctx->plans[PlanKey{pr, m, solver, x}] = NlemPlan{wc, 0, -1, 1.0f, 1, EM_PLAN_CACHE};
         } else if (strcmp(kind, "batch") == 0 &&
-                   sscanf(line, "%*s %*s %d %d %llx %f", &solver, &f16, &mask, &arm) == 4) {
+                   sscanf(line, "%*s %*s %d %d %llx %f %d", &solver, &f16, &mask, &arm, &check) >= 4) {
             if (solver == EM_SOLVER_ADMM && (f16 == 0 || f16 == 1) && (mask & ~kAllWideClasses) == 0 &&
-                plan_values_ok(0, -1, arm))
-                ctx->batch_plans[BatchPlanKey{solver, f16}] = BatchPlan{(uint64_t)mask, arm, EM_PLAN_CACHE};
+                plan_values_ok(0, -1, arm, check))
+                ctx->batch_plans[BatchPlanKey{solver, f16}] = BatchPlan{(uint64_t)mask, arm, check, EM_PLAN_CACHE};
         }
     }
     fclose(f);
@@ -275,15 +280,16 @@ static void append_cache_line(const char *text) {
 
 static void append_plan_cache(const em_context *ctx, const PlanKey &k, const NlemPlan &p) {
     char line[256];
-    snprintf(line, sizeof(line), "nlem2 %s %d %d %d %d %d %d %d %.9g\n", ctx->arch.c_str(), std::get<0>(k),
-             std::get<1>(k), std::get<2>(k), std::get<3>(k), p.wc, p.chunk, p.order, (double)p.arm);
+    snprintf(line, sizeof(line), "nlem2 %s %d %d %d %d %d %d %d %.9g %d\n", ctx->arch.c_str(),
+             std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), p.wc, p.chunk, p.order,
+             (double)p.arm, p.check);
     append_cache_line(line);
 }
 
 static void append_batch_plan_cache(const em_context *ctx, const BatchPlanKey &k, const BatchPlan &p) {
     char line[256];
-    snprintf(line, sizeof(line), "batch %s %d %d %llx %.9g\n", ctx->arch.c_str(), k.first, k.second,
-             (unsigned long long)p.mask, (double)p.arm);
+    snprintf(line, sizeof(line), "batch %s %d %d %llx %.9g %d\n", ctx->arch.c_str(), k.first, k.second,
+             (unsigned long long)p.mask, (double)p.arm, p.check);
     append_cache_line(line);
 }
 
@@ -441,6 +447,7 @@ struct NlemSchedule {
     int chunk;
     int order;
     float arm;
+    int check;   // residual-check interval
 };
 
 static const NlemPlan *find_plan(const em_context *h, int pr, int m, int solver, int f16) {
@@ -458,7 +465,7 @@ static NlemSchedule nlem_schedule(em_context *h, int pr, int m, int solver, int 
                                   bool tolerance = false, bool cache = true) {
     const NlemPlan *plan = find_plan(h, pr, m, solver, f16);
     NlemSchedule r{NlemKernelInfo{nullptr, 0}, plan ? plan->chunk : 0, plan ? plan->order : -1,
-                   plan ? plan->arm : kArmFactor};
+                   plan ? plan->arm : kArmFactor, plan ? plan->check : 1};
     const char *env = getenv("EMX_NLEM_WC");
     if (env && *env) {
         r.k = nlem_kernel(pr, m, atoi(env), solver);
@@ -718,6 +725,7 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
         if (!k.fn) return fail(h, EM_ERR_UNSUPPORTED, "no compiled kernel for this shape and solver");
         NlemLaunch L = make_launch(g, images, o, h->counters + gi);
         L.tau_arm = sc.arm * L.tau;
+        L.check_mask = sc.check - 1;
         const int64_t total = L.prefix[L.count];
         const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
         L.chunk = queue_chunk(g, total, cap, sc.chunk);
@@ -810,6 +818,7 @@ extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const v
     memset(&L, 0, sizeof(L));
     fill_common(L, o);
     L.tau_arm = sc.arm * L.tau;
+    L.check_mask = sc.check - 1;
     L.count = 1;
     L.img[0] = make_desc(im);
     L.prefix[0] = 0;
@@ -921,7 +930,7 @@ extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_ima
     };
     // 1: the tile shape (every compiled coordinate-wave count, built-in queue rules)
     for (int wc = 1; wc <= 4 && st == EM_OK; ++wc)
-        if (nlem_kernel(pr, m, wc, opt->solver).fn) st = trial(NlemPlan{wc, 0, -1, 1.0f, EM_PLAN_TUNED}, 0.0f);
+        if (nlem_kernel(pr, m, wc, opt->solver).fn) st = trial(NlemPlan{wc, 0, -1, 1.0f, 1, EM_PLAN_TUNED}, 0.0f);
     // 2: queue positions per pop; 3: queue order; 4: residual arm factor
     const int chunks[] = {1, 2, 4, 8};
     for (int c : chunks) {
@@ -940,6 +949,14 @@ extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_ima
         if (!tolerance || opt->solver != NLEM_SOLVER_ADMM || st != EM_OK || best.wc == 0) break;
         NlemPlan p = best;
         p.arm = a;
+        st = trial(p, kTuneMargin);
+    }
+    // 5: residual-check interval
+    const int checks[] = {2, 4, 8};
+    for (int c : checks) {
+        if (!tolerance || opt->solver != NLEM_SOLVER_ADMM || st != EM_OK || best.wc == 0) break;
+        NlemPlan p = best;
+        p.check = c;
         st = trial(p, kTuneMargin);
     }
     if (st != EM_OK || best.wc == 0) {
@@ -980,8 +997,8 @@ extern "C" em_status_t nlem_plan_get(em_handle_t h, int32_t patch_radius, int32_
     if (st != EM_OK) return st;
     const int m = points_per_lane(window_radius);
     const NlemPlan *p = find_plan(h, patch_radius, m, solver, img_is_f16);
-    const NlemPlan b = p ? *p : NlemPlan{nlem_default_wc(patch_radius, m, solver), 0, -1, 1.0f, EM_PLAN_BUILTIN};
-    *plan = nlem_plan_t{b.wc, b.chunk, b.order, b.arm, b.source};
+    const NlemPlan b = p ? *p : NlemPlan{nlem_default_wc(patch_radius, m, solver), 0, -1, 1.0f, 1, EM_PLAN_BUILTIN};
+    *plan = nlem_plan_t{b.wc, b.chunk, b.order, b.arm, b.check, b.source};
     return EM_OK;
 }
 
@@ -997,9 +1014,11 @@ extern "C" em_status_t nlem_plan_set(em_handle_t h, int32_t patch_radius, int32_
     } else {
         if (!nlem_kernel(patch_radius, m, plan->waves, solver).fn)
             return fail(h, EM_ERR_INVALID_ARG, "waves: no compiled kernel of that count for the shape");
-        if (!plan_values_ok(plan->chunk, plan->order, plan->arm_factor))
-            return fail(h, EM_ERR_INVALID_ARG, "chunk 0..64, order -1..1 and a finite arm_factor >= 1");
-        h->plans[key] = NlemPlan{plan->waves, plan->chunk, plan->order, plan->arm_factor, EM_PLAN_SET};
+        if (!plan_values_ok(plan->chunk, plan->order, plan->arm_factor, plan->check_every))
+            return fail(h, EM_ERR_INVALID_ARG,
+                        "chunk 0..64, order -1..1, a finite arm_factor >= 1 and check_every 1, 2, 4 or 8");
+        h->plans[key] = NlemPlan{plan->waves, plan->chunk, plan->order, plan->arm_factor, plan->check_every,
+                                 EM_PLAN_SET};
     }
     ++h->plan_epoch;
     return EM_OK;
@@ -1085,6 +1104,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             unsigned int *counter = h->counters + gi;
             NlemLaunch L = make_launch(g, images, o, counter);
             L.tau_arm = sc.arm * L.tau;
+            L.check_mask = sc.check - 1;
             hipGraphNode_t prev;
             int one = 1;
             void *rargs[] = {&counter, &one};
@@ -1218,7 +1238,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
     em_status_t st = em_solve_batch_ex(h, stream, B, a, w, inst, opt, z, stats);
     if (st != EM_OK || B == 0) {
         if (had) h->batch_plans[key] = old;
-        if (st == EM_OK && chosen) *chosen = em_batch_plan_t{old.mask, old.arm, old.source};
+        if (st == EM_OK && chosen) *chosen = em_batch_plan_t{old.mask, old.arm, old.check, old.source};
         return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1239,7 +1259,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
         }
         return r;
     };
-    if (st == EM_OK) st = trial(BatchPlan{0, 1.0f, EM_PLAN_TUNED}, 0.0f);
+    if (st == EM_OK) st = trial(BatchPlan{0, 1.0f, 1, EM_PLAN_TUNED}, 0.0f);
     // each populated sliced class in the generic classes, largest first
     int order[kNumWideClasses];
     int npop = 0;
@@ -1258,6 +1278,13 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
         p.arm = arm;
         st = trial(p, kTuneMargin);
     }
+    const int checks[] = {2, 4, 8};
+    for (int c : checks) {
+        if (!(opt->tol > 0.0f) || opt->max_iter <= 0 || st != EM_OK) break;
+        BatchPlan p = best;
+        p.check = c;
+        st = trial(p, kTuneMargin);
+    }
     if (st != EM_OK || !have) {
         if (had) h->batch_plans[key] = old;
         else h->batch_plans.erase(key);
@@ -1266,7 +1293,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
     best.source = EM_PLAN_TUNED;
     h->batch_plans[key] = best;
     append_batch_plan_cache(h, key, best);
-    if (chosen) *chosen = em_batch_plan_t{best.mask, best.arm, best.source};
+    if (chosen) *chosen = em_batch_plan_t{best.mask, best.arm, best.check, best.source};
     return EM_OK;
 }
 
@@ -1276,7 +1303,7 @@ extern "C" em_status_t em_batch_plan_get(em_handle_t h, int32_t solver, int32_t 
     if (solver != EM_SOLVER_ADMM) return fail(h, EM_ERR_INVALID_ARG, "batch plans are for EM_SOLVER_ADMM");
     auto it = h->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, points_f16 ? 1 : 0});
     const BatchPlan b = (it != h->batch_plans.end()) ? it->second : BatchPlan{};
-    *plan = em_batch_plan_t{b.mask, b.arm, b.source};
+    *plan = em_batch_plan_t{b.mask, b.arm, b.check, b.source};
     return EM_OK;
 }
 
@@ -1291,8 +1318,9 @@ extern "C" em_status_t em_batch_plan_set(em_handle_t h, int32_t solver, int32_t 
     }
     if ((plan->generic_classes & ~kAllWideClasses) != 0)
         return fail(h, EM_ERR_INVALID_ARG, "generic_classes: bits above the sliced classes");
-    if (!plan_values_ok(0, -1, plan->arm_factor)) return fail(h, EM_ERR_INVALID_ARG, "arm_factor must be finite and >= 1");
-    h->batch_plans[key] = BatchPlan{plan->generic_classes, plan->arm_factor, EM_PLAN_SET};
+    if (!plan_values_ok(0, -1, plan->arm_factor, plan->check_every))
+        return fail(h, EM_ERR_INVALID_ARG, "arm_factor must be finite and >= 1, check_every 1, 2, 4 or 8");
+    h->batch_plans[key] = BatchPlan{plan->generic_classes, plan->arm_factor, plan->check_every, EM_PLAN_SET};
     return EM_OK;
 }
 

@@ -19,10 +19,12 @@ constexpr int kWideMinWC = 2, kWideMaxWC = 5;
 constexpr int kNumWideClasses = (kWideMaxWC - kWideMinWC + 1) * kWideMaxM;
 
 // The batch plan applied to one call (em_batch_plan_t without its source):
-// sliced classes routed to the generic kernels, and the arm factor.
+// sliced classes routed to the generic kernels, the arm factor and the
+// residual-check interval.
 struct BatchPlanView {
     uint64_t generic_mask;
     float arm;
+    int check;   // residual-check interval (1, 2, 4 or 8)
 };
 constexpr int kSideStreams = 3;   // with the caller's stream: four concurrent class launches
 
@@ -47,6 +49,7 @@ struct NlemLaunch {
     float lo, hi;
     float tau;       // tol * (hi - lo); 0 = fixed iteration count
     float tau_arm;   // primal residual evaluated after an iteration with r_dual <= tau_arm
+    int32_t check_mask;     // ... and only on iterations t with (t & check_mask) == 0 (or the last one)
     int32_t init_nlm;       // 1: start from the NLM patch instead of the noisy patch
     float eps;              // IRLS surrogate parameter
     unsigned int *counter;  // work-queue head, zeroed before the launch

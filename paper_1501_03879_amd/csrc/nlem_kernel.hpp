@@ -513,7 +513,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             // dual residual of iteration t-1 (all waves hold identical sums),
             // which arms the primal residual of this iteration
             if (t > 1) rd2 = rd_all * inv_d;
-            const bool armed = uniform((t == max_iter) || (tau2 > 0.0f && t > 1 && rd2 <= arm2));
+            const bool armed = uniform((t == max_iter) ||
+                                       (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
 
             // ---- a8 (armed iterations only): lane sums of ||x_k - c||^2 with
             // x_k = v_k - e_k = a_k + (1 - s) delta, read-only on the state

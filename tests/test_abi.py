@@ -51,8 +51,8 @@ def test_struct_sizes_match_the_header():
     assert C.sizeof(emx.NlemImage) == 8 * 3 + 4 * 6          # nlem_image_t
     assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
     assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8 + 8 + 8 * 2 + 8   # em_options_t
-    assert C.sizeof(emx.NlemPlan) == 4 * 5                   # nlem_plan_t
-    assert C.sizeof(emx.BatchPlan) == 8 + 4 + 4              # em_batch_plan_t
+    assert C.sizeof(emx.NlemPlan) == 4 * 6                   # nlem_plan_t
+    assert C.sizeof(emx.BatchPlan) == 8 + 4 * 3 + 4          # em_batch_plan_t (padded to 8)
 
 
 def test_null_handle_is_rejected_without_device_work():
