@@ -483,10 +483,10 @@ def main():
     # fastest plan of its search (both untimed for the line); the timed steps
     # run the plan in force
     plan = {"nlem_builtin": hd.nlem_plan_get(pr, wr)}
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
     if args.tune:
-        for _ in range(3):
-            step()
-        torch.cuda.synchronize()
         plan["nlem_builtin_ms_per_step"] = _events_ms(step, 20)
         t_tune = time.perf_counter()
         hd.nlem_autotune(dict(img=img, out=out, stats=stats, patch_radius=pr, window_radius=wr, h=im.h),
@@ -497,7 +497,7 @@ def main():
     plan["nlem_same_as_builtin"] = all(plan["nlem"][k] == plan["nlem_builtin"][k]
                                        for k in ("waves", "chunk", "order", "arm_factor", "check_every"))
     waves = plan["nlem"]["waves"]
-    for _ in range(args.warmup):
+    for _ in range(3 if args.tune else 0):   # (the warm-up ran before the tuning)
         step()
     torch.cuda.synchronize()
     # the library brackets each NLEM solve launch with HIP events on the same
@@ -709,6 +709,8 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_i
     torch.cuda.synchronize()
     plan = {"batch_builtin": hd.em_batch_plan_get()}
     if tune:
+        for _ in range(3):
+            hd.em_solve_batch(a, w, it, z, st, **kw)
         plan["batch_builtin_ms"] = _events_ms(lambda: hd.em_solve_batch(a, w, it, z, st, **kw), reps)
         t_tune = time.perf_counter()
         hd.em_batch_autotune(a, w, it, z, st, lo=wl.lo, hi=wl.hi, rho=wl.mu, max_iter=wl.max_iter,

@@ -467,7 +467,8 @@ typedef struct {
  * the best count, queue chunks 1, 2, 4 and 8, then (tolerance mode) the
  * queue order off and on, then (tolerance mode, EM-ADMM) arm factors 1.5, 2
  * and 3 and residual-check intervals 2, 4 and 8; a candidate after the wave
- * count replaces the plan only when it is more than 1% faster.  nlem_denoise, nlem_denoise_ex and nlem_denoise_multi
+ * count replaces the plan only when it is more than 1% faster than the plan
+ * kept so far, timed again right before it.  nlem_denoise, nlem_denoise_ex and nlem_denoise_multi
  * use the plan from then on (for a launch of several images, the plan of its
  * shape with FP16 storage when every image in it is FP16); the environment
  * variables EMX_NLEM_WC, EMX_NLEM_CHUNK and EMX_NLEM_ORDER still override.
@@ -527,7 +528,8 @@ typedef struct {
  * storage (opt->points_f16): after the built-in plan, each sliced class that
  * holds instances of the batch (largest first) is tried in the generic
  * classes, then arm factors 1.5, 2 and 3 and check intervals 2, 4 and 8
- * (tolerance mode); a change is kept when more than 1% faster.  `repeats` timed calls per candidate after one
+ * (tolerance mode); a change is kept when more than 1% faster than the plan
+ * kept so far, timed again right before it.  `repeats` timed calls per candidate after one
  * warm-up, synchronously on `stream`; z and stats hold the last candidate's
  * results.  The plan is appended to the EMX_AUTOTUNE_CACHE file as for
  * nlem_autotune.  chosen: NULL or receives the plan.

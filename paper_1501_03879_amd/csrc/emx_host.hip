@@ -895,7 +895,9 @@ static em_status_t time_calls(em_context *h, hipStream_t s, int repeats, F fn, f
 }
 
 // A candidate after the first stage replaces the best plan only when it is
-// faster by more than this fraction (run-to-run noise is ~0.5% here).
+// faster by more than this fraction (run-to-run noise is ~0.5% here) than
+// the best plan timed again right before it: paired timings, so that the
+// clock ramping up during the search does not favour later candidates.
 static constexpr float kTuneMargin = 0.01f;
 
 extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_image_t *image,
@@ -918,10 +920,18 @@ extern "C" em_status_t nlem_autotune(em_handle_t h, void *stream, const nlem_ima
     auto run = [&]() { return nlem_run(h, s, 1, image, *opt); };
     NlemPlan best;
     float best_ms = 0.0f;
+    // margin 0: keep the fastest (first stage); otherwise time the best plan
+    // again, then the candidate, and keep the candidate when faster by margin
     auto trial = [&](const NlemPlan &p, float margin) -> em_status_t {
+        em_status_t r = EM_OK;
+        if (margin > 0.0f) {
+            h->plans[key] = best;
+            r = time_calls(h, s, repeats, run, &best_ms);
+            if (r != EM_OK) return r;
+        }
         h->plans[key] = p;
         float ms = 0.0f;
-        const em_status_t r = time_calls(h, s, repeats, run, &ms);
+        r = time_calls(h, s, repeats, run, &ms);
         if (r == EM_OK && (best.wc == 0 || ms < (1.0f - margin) * best_ms)) {
             best = p;
             best_ms = ms;
@@ -1249,9 +1259,15 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
     float best_ms = 0.0f;
     bool have = false;
     auto trial = [&](const BatchPlan &p, float margin) -> em_status_t {
+        em_status_t r = EM_OK;
+        if (margin > 0.0f && have) {   // paired timing, as in nlem_autotune
+            h->batch_plans[key] = best;
+            r = time_calls(h, s, repeats, run, &best_ms);
+            if (r != EM_OK) return r;
+        }
         h->batch_plans[key] = p;
         float ms = 0.0f;
-        const em_status_t r = time_calls(h, s, repeats, run, &ms);
+        r = time_calls(h, s, repeats, run, &ms);
         if (r == EM_OK && (!have || ms < (1.0f - margin) * best_ms)) {
             best = p;
             best_ms = ms;
