@@ -3,8 +3,11 @@ that the oracle recomputes one by one at the GPU's iteration counts.
 
 * 512 x 512 mixed-noise image (Gaussian sigma 30 + 10% impulses), d = 49,
   n <= 441, FP32 and FP16 image storage (per-pixel error of the FP16 run
-  against the FP32-image oracle, and of both against their own inputs);
-* 16 images of uneven size and radii in one nlem_denoise_multi graph;
+  against the FP32-image oracle, and of both against their own inputs),
+  ~6,000 pixels stratified over impulses, the border band and the image;
+* 16 images of uneven size and radii in one nlem_denoise_multi graph, per
+  image 1,024 random pixels, 128 from the band of truncated windows and the
+  four corners;
 * 1,048,576 uneven point sets (drawn on the device), 10,240 sampled
   instances (2,048 per d); the same batch with IRLS and with the
   weighted-penalty ADMM from the weighted-mean start, 1,280 sampled.
@@ -36,7 +39,7 @@ def test_512_mixed_noise_fp32_and_fp16():
     wl = synth.nlem_512_mixed()
     im = wl.images[0]
     rng = np.random.default_rng(1)
-    pix = _strata(im.noisy, rng, 700)
+    pix = _strata(im.noisy, rng, 2048)
     got32, st32 = run_nlem(im.noisy, 3, 10, im.h, wl.mu, wl.max_iter, wl.tol)
     got16, st16 = run_nlem(im.noisy, 3, 10, im.h, wl.mu, wl.max_iter, wl.tol, fp16=True)
     ref32 = oracle.nlem(im.noisy, 3, 10, im.h, 0, 255, wl.mu, wl.max_iter, 0.0, pix=pix,
@@ -81,14 +84,17 @@ def test_multi_image_workload():
     for k, (im, it) in enumerate(zip(wl.images, items)):
         H, W = im.noisy.shape
         iters = emx.stats_view(it["stats"])[0].cpu().numpy()
-        pix = np.unique(np.concatenate([[0, W - 1, H * W - 1], rng.choice(H * W, 64, replace=False)]))
+        yy, xx = np.divmod(np.arange(H * W), W)
+        border = np.flatnonzero(np.minimum.reduce([yy, xx, H - 1 - yy, W - 1 - xx]) < im.window_radius)
+        pix = np.unique(np.concatenate([[0, W - 1, H * W - W, H * W - 1], rng.choice(H * W, 1024, replace=False),
+                                        rng.choice(border, 128, replace=False)]))
         ref = oracle.nlem(im.noisy, im.patch_radius, im.window_radius, im.h, 0, 255, wl.mu,
                           wl.max_iter, 0.0, pix=pix, max_iter_each=iters[pix])
         got = it["out"].cpu().numpy().reshape(-1).astype(np.float64)
         e, r = rel_errors(got[pix], ref["out"], 255.0)
         worst = max(worst, e)
         print(f"[parity] multi image {k}: {H}x{W} r={im.patch_radius} R={im.window_radius} "
-              f"max_rel={e:.2e} mean iters {iters.mean():.1f}", flush=True)
+              f"{pix.size} px max_rel={e:.2e} rms_rel={r:.2e} mean iters {iters.mean():.1f}", flush=True)
     assert worst <= 1e-4
 
 
