@@ -719,7 +719,7 @@ def batch_interior_rate(im, wl, dev, hd, out_nlem, reps=5, plain=False, oracle_i
         plan["tune_s"] = time.perf_counter() - t_tune
     plan["batch"] = hd.em_batch_plan_get()
     plan["batch_same_as_builtin"] = all(plan["batch"][k] == plan["batch_builtin"][k]
-                                        for k in ("generic_classes", "arm_factor", "check_every"))
+                                        for k in ("generic_classes", "arm_factor", "check_every", "host_counts"))
     ms = _events_ms(lambda: hd.em_solve_batch(a, w, it, z, st, **kw), reps)
     iters, flags = emx.stats_view(st)[0].cpu().numpy(), emx.stats_view(st)[1].cpu().numpy()
     centre = z.reshape(B, d)[:, (d - 1) // 2]

@@ -31,8 +31,10 @@
  *    stream capture after an earlier call of the same sizes on the same
  *    handle has sized its workspace: they then only
  *    launch kernels (work-queue heads are cleared by a kernel, not a memset)
- *    and neither allocate nor synchronise.  nlem_autotune synchronises and
- *    cannot be captured.
+ *    and neither allocate nor synchronise.  nlem_autotune and
+ *    em_batch_autotune synchronise and cannot be captured; a batch plan with
+ *    host_counts makes em_solve_batch(_ex) wait for its classification
+ *    outside capture (em_batch_plan_t).
  *  - Argument errors are detected on the host before anything is queued and
  *    return EM_ERR_INVALID_ARG (nothing is written).  Problems inside one
  *    instance (no points, a bad weight or point) are reported per instance in
@@ -518,6 +520,12 @@ typedef struct {
     uint64_t generic_classes;  /* bit k set: sliced class k is routed to the generic classes */
     float arm_factor;          /* >= 1, 1 = built-in */
     int32_t check_every;       /* 1, 2, 4 or 8; 1 = built-in */
+    int32_t host_counts;       /* 1: the call reads the class counts back after classifying the
+                                  batch (it then waits for the stream up to that point, so it is
+                                  no longer asynchronous) and launches only the populated classes,
+                                  largest work first over its streams, each grid no larger than
+                                  its count; ignored while the stream is being captured; 0 =
+                                  built-in (every class launched, nothing waited for) */
     int32_t source;            /* em_plan_source_t; ignored by em_batch_plan_set */
 } em_batch_plan_t;
 
@@ -528,8 +536,8 @@ typedef struct {
  * storage (opt->points_f16): after the built-in plan, each sliced class that
  * holds instances of the batch (largest first) is tried in the generic
  * classes, then arm factors 1.5, 2 and 3 and check intervals 2, 4 and 8
- * (tolerance mode); a change is kept when more than 1% faster than the plan
- * kept so far, timed again right before it.  `repeats` timed calls per candidate after one
+ * (tolerance mode), then host_counts; a change is kept when more than 1%
+ * faster than the plan kept so far, timed again right before it.  `repeats` timed calls per candidate after one
  * warm-up, synchronously on `stream`; z and stats hold the last candidate's
  * results.  The plan is appended to the EMX_AUTOTUNE_CACHE file as for
  * nlem_autotune.  chosen: NULL or receives the plan.
@@ -541,8 +549,8 @@ em_status_t em_batch_autotune(em_handle_t handle, void *stream, int64_t B, const
                               float *z, em_stats_t *stats, int32_t repeats, em_batch_plan_t *chosen);
 
 /* The batch plan for point storage points_f16 (the handle's, else the
- * built-in: no class routed, arm_factor 1, check_every 1).  solver must be
- * EM_SOLVER_ADMM.
+ * built-in: no class routed, arm_factor 1, check_every 1, host_counts 0).
+ * solver must be EM_SOLVER_ADMM.
  * Errors: INVALID_ARG. */
 em_status_t em_batch_plan_get(em_handle_t handle, int32_t solver, int32_t points_f16,
                               em_batch_plan_t *plan);
@@ -550,7 +558,7 @@ em_status_t em_batch_plan_get(em_handle_t handle, int32_t solver, int32_t points
 /* Set the batch plan for point storage points_f16 (source EM_PLAN_SET), or
  * with plan = NULL return to the built-in one.  Errors: INVALID_ARG (solver
  * other than EM_SOLVER_ADMM, bits above the 28 classes, arm_factor not finite
- * or below 1, check_every not 1, 2, 4 or 8). */
+ * or below 1, check_every not 1, 2, 4 or 8, host_counts not 0 or 1). */
 em_status_t em_batch_plan_set(em_handle_t handle, int32_t solver, int32_t points_f16,
                               const em_batch_plan_t *plan);
 

@@ -66,11 +66,12 @@ class NlemPlan(C.Structure):
 class BatchPlan(C.Structure):
     """em_batch_plan_t: sliced classes routed to the generic kernels, arm factor."""
     _fields_ = [("generic_classes", C.c_uint64), ("arm_factor", C.c_float), ("check_every", C.c_int32),
-                ("source", C.c_int32)]
+                ("host_counts", C.c_int32), ("source", C.c_int32)]
 
     def as_dict(self):
         return dict(generic_classes=int(self.generic_classes), arm_factor=float(self.arm_factor),
-                    check_every=self.check_every, source=PLAN_SOURCES[self.source])
+                    check_every=self.check_every, host_counts=self.host_counts,
+                    source=PLAN_SOURCES[self.source])
 
 
 class EmOptions(C.Structure):
@@ -362,10 +363,12 @@ class Handle:
 
     def em_batch_plan_set(self, plan=None, f16=False, solver=SOLVER_ADMM):
         """Set the batch plan (dict with generic_classes, arm_factor,
-        check_every) or, with plan=None, return to the built-in one."""
+        check_every, host_counts) or, with plan=None, return to the built-in
+        one."""
         p = None if plan is None else BatchPlan(int(plan.get("generic_classes", 0)),
                                                 float(plan.get("arm_factor", 1.0)),
-                                                int(plan.get("check_every", 1)), 0)
+                                                int(plan.get("check_every", 1)),
+                                                int(plan.get("host_counts", 0)), 0)
         self._check(self.lib.em_batch_plan_set(self.h, int(solver), 1 if f16 else 0,
                                                None if p is None else C.byref(p)), "em_batch_plan_set")
 

@@ -24,6 +24,7 @@ void *ctx_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st);
 em_status_t ctx_side_streams(em_context *ctx, hipStream_t **side, hipEvent_t *fork, hipEvent_t **join);
 BatchPlanView ctx_batch_plan(em_context *ctx, const em_options_t &o);
+unsigned int *ctx_host_counts(em_context *ctx, int n);
 
 // Classify: counts per class; empty / malformed instances finished here.
 // Counts go through a per-block LDS histogram (one global atomic per block
@@ -223,6 +224,27 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     if (st != EM_OK) return st;
     const unsigned nb = (unsigned)((B + 255) / 256);
     hipLaunchKernelGGL(batch_classify_count, dim3(nb), dim3(256), 0, s, inst, B, z, stats, counts, mode, gmask);
+    hipStream_t *side;
+    hipEvent_t fork, *join;
+    st = ctx_side_streams(ctx, &side, &fork, &join);
+    if (st != EM_OK) return st;
+    // a plan with host_counts: the class counts come back to the host (the
+    // call waits for the stream up to here), so that only populated classes
+    // are launched; not while the stream is being captured
+    const unsigned int *hc = nullptr;
+    if (plan.host_counts) {
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        hipError_t ce = hipStreamIsCapturing(s, &cst);
+        if (ce != hipSuccess) return ctx_hip_error(ctx, ce, "hipStreamIsCapturing");
+        unsigned int *hbuf = (cst == hipStreamCaptureStatusNone) ? ctx_host_counts(ctx, K) : nullptr;
+        if (hbuf) {
+            ce = hipMemcpyAsync(hbuf, counts, K * sizeof(unsigned int), hipMemcpyDeviceToHost, s);
+            if (ce == hipSuccess) ce = hipEventRecord(fork, s);
+            if (ce == hipSuccess) ce = hipEventSynchronize(fork);
+            if (ce != hipSuccess) return ctx_hip_error(ctx, ce, "class counts to the host");
+            hc = hbuf;
+        }
+    }
     hipLaunchKernelGGL(batch_classify_scan, dim3(1), dim3(64), 0, s, counts, offsets);
     hipLaunchKernelGGL(batch_classify_scatter, dim3(nb), dim3(256), 0, s, inst, B, offsets, fill, list, mode,
                        gmask);
@@ -232,20 +254,29 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     // The classes run concurrently on the caller's stream and the handle's
     // side streams (fork after the classification, join before returning), so
     // one class's tail overlaps the others' work.  The launched classes go to
-    // the four streams in turn, largest shapes first.
-    hipStream_t *side;
-    hipEvent_t fork, *join;
-    st = ctx_side_streams(ctx, &side, &fork, &join);
-    if (st != EM_OK) return st;
+    // the four streams in turn, largest shapes first; with the counts on the
+    // host, only the populated ones, each to the stream with the least work
+    // so far (largest estimated work first: instances x the class's largest
+    // n d), with at most one workgroup per instance.
     e = hipEventRecord(fork, s);
     for (int i = 0; i < kSideStreams && e == hipSuccess; ++i) e = hipStreamWaitEvent(side[i], fork, 0);
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the class streams");
     const ClassKernel *wtab = batch_wide_table();
     const ClassKernel *ftab = batch_fast_table();
     const int *order = class_launch_order();
+    int hc_order[K];
+    if (hc) {
+        for (int c = 0; c < K; ++c) hc_order[c] = c;
+        std::stable_sort(hc_order, hc_order + K, [&](int x, int y) {
+            return (double)hc[x] * (double)class_capacity(x) > (double)hc[y] * (double)class_capacity(y);
+        });
+        order = hc_order;
+    }
+    double load[kSideStreams + 1] = {};
     int launched = 0;
     for (int oi = 0; oi < K; ++oi) {
         const int c = order[oi];
+        if (hc && hc[c] == 0) continue;
         // (with sliced classes routed back by a plan, every generic class may receive instances)
         const bool skip = fast ? c < kFirstFastClass
                                : (c >= kFirstFastClass ||
@@ -255,7 +286,13 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
         const ClassKernel &ck = (c >= kFirstFastClass) ? ftab[c - kFirstFastClass]
                                 : (c >= kNumClasses)  ? wtab[c - kNumClasses]
                                                       : tab[c];
-        const int si = launched++ % (kSideStreams + 1);
+        int si = launched++ % (kSideStreams + 1);
+        if (hc) {
+            si = 0;
+            for (int i = 1; i <= kSideStreams; ++i)
+                if (load[i] < load[si]) si = i;
+            load[si] += (double)hc[c] * (double)class_capacity(c);
+        }
         hipStream_t cs = (si == 0) ? s : side[si - 1];
         ClassLaunch L = class_launch(a, w, inst, o, z, stats, c);
         L.arm = plan.arm;
@@ -269,7 +306,7 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
             L.defer_q = defer_q;
         }
         const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, ck.fn, ck.threads);
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(hc ? (int64_t)hc[c] : B, cap));
         void *args[] = {&L};
         e = hipLaunchKernel(ck.fn, dim3(grid), dim3(ck.threads), args, 0, cs);
         if (e != hipSuccess) return ctx_hip_error(ctx, e, "batch class launch");
@@ -281,7 +318,11 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
     if (e != hipSuccess) return ctx_hip_error(ctx, e, "join of the class streams");
     if (defer) {
         // the deferred far-outlier instances, after every class kernel (an empty
-        // list costs one launch whose workgroups exit at once)
+        // list costs one launch whose workgroups exit at once); the two lists
+        // run concurrently, the second on a side stream joined back
+        e = hipEventRecord(fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side[0], fork, 0);
+        if (e != hipSuccess) return ctx_hip_error(ctx, e, "fork of the deferred lists");
         const ClassKernel *dtab = batch_deferred_table();
         for (int k = 0; k < kDeferLists; ++k) {
             ClassLaunch L = class_launch(a, w, inst, o, z, stats, 0);
@@ -293,9 +334,12 @@ em_status_t batch_solve(em_context *ctx, hipStream_t s, int64_t B, const float *
             const int64_t cap = (int64_t)ctx_num_cus(ctx) * blocks_per_cu(ctx, dtab[k].fn, dtab[k].threads);
             const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(B, cap));
             void *args[] = {&L};
-            e = hipLaunchKernel(dtab[k].fn, dim3(grid), dim3(dtab[k].threads), args, 0, s);
+            e = hipLaunchKernel(dtab[k].fn, dim3(grid), dim3(dtab[k].threads), args, 0, k == 0 ? s : side[0]);
             if (e != hipSuccess) return ctx_hip_error(ctx, e, "deferred launch");
         }
+        e = hipEventRecord(join[0], side[0]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, join[0], 0);
+        if (e != hipSuccess) return ctx_hip_error(ctx, e, "join of the deferred lists");
     }
     return EM_OK;
 }

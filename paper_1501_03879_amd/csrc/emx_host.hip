@@ -62,6 +62,7 @@ struct BatchPlan {
     uint64_t mask = 0;
     float arm = 1.0f;
     int check = 1;
+    int host_counts = 0;
     int source = EM_PLAN_BUILTIN;
 };
 
@@ -83,6 +84,8 @@ struct em_context {
     // plain-path workspace
     void *plain_ws = nullptr;
     size_t plain_ws_bytes = 0;
+    // class counts read back under a plan with host_counts (pinned, on first use)
+    unsigned int *host_counts = nullptr;
     // side streams for concurrent shape-class launches (created on first use)
     hipStream_t side[kSideStreams] = {};
     hipEvent_t fork = nullptr;
@@ -152,14 +155,26 @@ em_status_t ctx_error(em_context *ctx, em_status_t st, const char *msg) { return
 
 em_status_t ctx_hip_error(em_context *ctx, hipError_t e, const char *what) { return hip_fail(ctx, e, what); }
 
+// Pinned host buffer of n class counts (allocated on first use).
+unsigned int *ctx_host_counts(em_context *ctx, int n) {
+    (void)n;   // kNumAllClasses + a few, well under the fixed size below
+    if (!ctx->host_counts &&
+        hipHostMalloc(reinterpret_cast<void **>(&ctx->host_counts), 256 * sizeof(unsigned int),
+                      hipHostMallocDefault) != hipSuccess) {
+        ctx->host_counts = nullptr;
+    }
+    return ctx->host_counts;
+}
+
 // The batch plan of a call: the handle's plan for the fixed-penalty EM-ADMM
 // over a box and its point storage, else the built-in one.
 BatchPlanView ctx_batch_plan(em_context *ctx, const em_options_t &o) {
     if (o.solver == EM_SOLVER_ADMM && o.set == EM_SET_BOX) {
         auto it = ctx->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, o.points_f16 ? 1 : 0});
-        if (it != ctx->batch_plans.end()) return BatchPlanView{it->second.mask, it->second.arm, it->second.check};
+        if (it != ctx->batch_plans.end())
+            return BatchPlanView{it->second.mask, it->second.arm, it->second.check, it->second.host_counts};
     }
-    return BatchPlanView{0, 1.0f, 1};
+    return BatchPlanView{0, 1.0f, 1, 0};
 }
 
 // Work-queue heads: a fixed pool owned by the handle.
@@ -220,8 +235,8 @@ void *ctx_plain_workspace(em_context *ctx, size_t bytes, em_status_t *st) {
 // ---------------------------------------------------------------------------
 // autotune cache: text lines in the file named by EMX_AUTOTUNE_CACHE,
 //   nlem2 <arch> <patch radius> <points per lane> <solver> <fp16> <waves> <chunk> <order> <arm> <check>
-//   batch <arch> <solver> <fp16> <routed classes, hex> <arm> <check>
-// (a missing check field reads as 1)
+//   batch <arch> <solver> <fp16> <routed classes, hex> <arm> <check> <host counts>
+// (a missing check field reads as 1, a missing host-counts field as 0)
 // and, from before the queue and arm fields existed,
 //   nlem <arch> <patch radius> <points per lane> <solver> <waves>
 // (both storages, built-in queue rules).  Later lines win; lines for another
@@ -244,7 +259,7 @@ static void load_plan_cache(em_context *ctx) {
     char line[256];
     while (fgets(line, sizeof(line), f)) {
         char kind[16], arch[64];
-        int pr, m, solver, f16, wc, chunk, order, check = 1;
+        int pr, m, solver, f16, wc, chunk, order, check = 1, hc = 0;
         float arm;
         unsigned long long mask;
         if (sscanf(line, "%15s %63s", kind, arch) != 2 || ctx->arch != arch) continue;
@@ -260,10 +275,11 @@ static void load_plan_cache(em_context *ctx) {
                 for (int x = 0; x < 2; ++x)
                     ctx->plans[PlanKey{pr, m, solver, x}] = NlemPlan{wc, 0, -1, 1.0f, 1, EM_PLAN_CACHE};
         } else if (strcmp(kind, "batch") == 0 &&
-                   sscanf(line, "%*s %*s %d %d %llx %f %d", &solver, &f16, &mask, &arm, &check) >= 4) {
+                   sscanf(line, "%*s %*s %d %d %llx %f %d %d", &solver, &f16, &mask, &arm, &check, &hc) >= 4) {
             if (solver == EM_SOLVER_ADMM && (f16 == 0 || f16 == 1) && (mask & ~kAllWideClasses) == 0 &&
-                plan_values_ok(0, -1, arm, check))
-                ctx->batch_plans[BatchPlanKey{solver, f16}] = BatchPlan{(uint64_t)mask, arm, check, EM_PLAN_CACHE};
+                plan_values_ok(0, -1, arm, check) && (hc == 0 || hc == 1))
+                ctx->batch_plans[BatchPlanKey{solver, f16}] =
+                    BatchPlan{(uint64_t)mask, arm, check, hc, EM_PLAN_CACHE};
         }
     }
     fclose(f);
@@ -288,8 +304,8 @@ static void append_plan_cache(const em_context *ctx, const PlanKey &k, const Nle
 
 static void append_batch_plan_cache(const em_context *ctx, const BatchPlanKey &k, const BatchPlan &p) {
     char line[256];
-    snprintf(line, sizeof(line), "batch %s %d %d %llx %.9g %d\n", ctx->arch.c_str(), k.first, k.second,
-             (unsigned long long)p.mask, (double)p.arm, p.check);
+    snprintf(line, sizeof(line), "batch %s %d %d %llx %.9g %d %d\n", ctx->arch.c_str(), k.first, k.second,
+             (unsigned long long)p.mask, (double)p.arm, p.check, p.host_counts);
     append_cache_line(line);
 }
 
@@ -386,6 +402,7 @@ extern "C" em_status_t em_destroy(em_handle_t h) {
     if (h->counters) (void)hipFree(h->counters);
     if (h->ws) (void)hipFree(h->ws);
     if (h->plain_ws) (void)hipFree(h->plain_ws);
+    if (h->host_counts) (void)hipHostFree(h->host_counts);
     for (int i = 0; i < kSideStreams; ++i) {
         if (h->side[i]) (void)hipStreamDestroy(h->side[i]);
         if (h->join[i]) (void)hipEventDestroy(h->join[i]);
@@ -1248,7 +1265,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
     em_status_t st = em_solve_batch_ex(h, stream, B, a, w, inst, opt, z, stats);
     if (st != EM_OK || B == 0) {
         if (had) h->batch_plans[key] = old;
-        if (st == EM_OK && chosen) *chosen = em_batch_plan_t{old.mask, old.arm, old.check, old.source};
+        if (st == EM_OK && chosen) *chosen = em_batch_plan_t{old.mask, old.arm, old.check, old.host_counts, old.source};
         return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1275,7 +1292,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
         }
         return r;
     };
-    if (st == EM_OK) st = trial(BatchPlan{0, 1.0f, 1, EM_PLAN_TUNED}, 0.0f);
+    if (st == EM_OK) st = trial(BatchPlan{0, 1.0f, 1, 0, EM_PLAN_TUNED}, 0.0f);
     // each populated sliced class in the generic classes, largest first
     int order[kNumWideClasses];
     int npop = 0;
@@ -1301,6 +1318,11 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
         p.check = c;
         st = trial(p, kTuneMargin);
     }
+    if (st == EM_OK) {   // the dispatch: class counts read back, populated classes only
+        BatchPlan p = best;
+        p.host_counts = 1;
+        st = trial(p, kTuneMargin);
+    }
     if (st != EM_OK || !have) {
         if (had) h->batch_plans[key] = old;
         else h->batch_plans.erase(key);
@@ -1309,7 +1331,7 @@ extern "C" em_status_t em_batch_autotune(em_handle_t h, void *stream, int64_t B,
     best.source = EM_PLAN_TUNED;
     h->batch_plans[key] = best;
     append_batch_plan_cache(h, key, best);
-    if (chosen) *chosen = em_batch_plan_t{best.mask, best.arm, best.check, best.source};
+    if (chosen) *chosen = em_batch_plan_t{best.mask, best.arm, best.check, best.host_counts, best.source};
     return EM_OK;
 }
 
@@ -1319,7 +1341,7 @@ extern "C" em_status_t em_batch_plan_get(em_handle_t h, int32_t solver, int32_t 
     if (solver != EM_SOLVER_ADMM) return fail(h, EM_ERR_INVALID_ARG, "batch plans are for EM_SOLVER_ADMM");
     auto it = h->batch_plans.find(BatchPlanKey{EM_SOLVER_ADMM, points_f16 ? 1 : 0});
     const BatchPlan b = (it != h->batch_plans.end()) ? it->second : BatchPlan{};
-    *plan = em_batch_plan_t{b.mask, b.arm, b.check, b.source};
+    *plan = em_batch_plan_t{b.mask, b.arm, b.check, b.host_counts, b.source};
     return EM_OK;
 }
 
@@ -1334,9 +1356,12 @@ extern "C" em_status_t em_batch_plan_set(em_handle_t h, int32_t solver, int32_t 
     }
     if ((plan->generic_classes & ~kAllWideClasses) != 0)
         return fail(h, EM_ERR_INVALID_ARG, "generic_classes: bits above the sliced classes");
-    if (!plan_values_ok(0, -1, plan->arm_factor, plan->check_every))
-        return fail(h, EM_ERR_INVALID_ARG, "arm_factor must be finite and >= 1, check_every 1, 2, 4 or 8");
-    h->batch_plans[key] = BatchPlan{plan->generic_classes, plan->arm_factor, plan->check_every, EM_PLAN_SET};
+    if (!plan_values_ok(0, -1, plan->arm_factor, plan->check_every) ||
+        (plan->host_counts != 0 && plan->host_counts != 1))
+        return fail(h, EM_ERR_INVALID_ARG,
+                    "arm_factor must be finite and >= 1, check_every 1, 2, 4 or 8, host_counts 0 or 1");
+    h->batch_plans[key] =
+        BatchPlan{plan->generic_classes, plan->arm_factor, plan->check_every, plan->host_counts, EM_PLAN_SET};
     return EM_OK;
 }
 

@@ -24,7 +24,8 @@ constexpr int kNumWideClasses = (kWideMaxWC - kWideMinWC + 1) * kWideMaxM;
 struct BatchPlanView {
     uint64_t generic_mask;
     float arm;
-    int check;   // residual-check interval (1, 2, 4 or 8)
+    int check;        // residual-check interval (1, 2, 4 or 8)
+    int host_counts;  // read the class counts back and launch only populated classes
 };
 constexpr int kSideStreams = 3;   // with the caller's stream: four concurrent class launches
 

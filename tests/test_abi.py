@@ -52,7 +52,7 @@ def test_struct_sizes_match_the_header():
     assert C.sizeof(emx.NlemOptions) == 4 * 8                # nlem_options_t
     assert C.sizeof(emx.EmOptions) == 4 * 4 + 8 * 2 + 4 * 8 + 8 + 8 * 2 + 8   # em_options_t
     assert C.sizeof(emx.NlemPlan) == 4 * 6                   # nlem_plan_t
-    assert C.sizeof(emx.BatchPlan) == 8 + 4 * 3 + 4          # em_batch_plan_t (padded to 8)
+    assert C.sizeof(emx.BatchPlan) == 8 + 4 * 4              # em_batch_plan_t
 
 
 def test_null_handle_is_rejected_without_device_work():

@@ -253,8 +253,16 @@ def test_batch_plans_autotune_variants_and_cache(tmp_path, monkeypatch):
     cache = tmp_path / "plans.txt"
     hd = _new_handle(monkeypatch, cache)
     b = _sliced_batch(41, 600)
-    assert hd.em_batch_plan_get() == dict(generic_classes=0, arm_factor=1.0, check_every=1, source="builtin")
-    _, it0, (a, w, inst, z, st) = _batch_parity(hd, b, "batch built-in plan")
+    assert hd.em_batch_plan_get() == dict(generic_classes=0, arm_factor=1.0, check_every=1, host_counts=0,
+                                          source="builtin")
+    z0, it0, (a, w, inst, z, st) = _batch_parity(hd, b, "batch built-in plan")
+    # the host-counts dispatch changes only which classes are launched where:
+    # bitwise the built-in results
+    hd.em_batch_plan_set(dict(host_counts=1))
+    zh, ith, _ = _batch_parity(hd, b, "batch plan host_counts=1")
+    np.testing.assert_array_equal(zh, z0)
+    np.testing.assert_array_equal(ith, it0)
+    hd.em_batch_plan_set(None)
     p = hd.em_batch_autotune(a, w, inst, z, st, lo=b.lo, hi=b.hi, rho=0.5, max_iter=2000, tol=1e-4, repeats=2)
     print(f"[autotune] batch plan {p}", flush=True)
     assert p["source"] == "tuned" and p["arm_factor"] in (1.0, 1.5, 2.0, 3.0) and p["check_every"] in (1, 2, 4, 8)
@@ -288,7 +296,7 @@ def test_batch_plans_autotune_variants_and_cache(tmp_path, monkeypatch):
     np.testing.assert_array_equal(zp.cpu().numpy()[near], got.astype(np.float32)[near])
     hd.em_batch_plan_set(None)
     assert hd.em_batch_plan_get()["source"] == "builtin"
-    for bad in (dict(generic_classes=1 << 28), dict(arm_factor=0.9), dict(check_every=16)):
+    for bad in (dict(generic_classes=1 << 28), dict(arm_factor=0.9), dict(check_every=16), dict(host_counts=2)):
         with pytest.raises(emx.EmxError):
             hd.em_batch_plan_set(bad)
     hd.close()
