@@ -418,7 +418,8 @@ def pointsets_config(hd, dev, reps, per_d, rng):
     res = _rate_record(ms, flops, solves_per_s=B / (ms * 1e-3), instances=B, mean_iters=float(iters.mean()),
                        converged_fraction=float(np.mean(flags == 1)),
                        maxiter_instances=int(np.sum(flags == 2)), reps=reps,
-                       oracle_error={"instances": int(sample.size), **_err(got, ref["z"], 6.0)})
+                       oracle_error={"instances": int(sample.size), **_err(got, ref["z"], 6.0)},
+                       plan=hd.em_batch_plan_get())
     del a, w, z, st, it
     torch.cuda.empty_cache()
     return res

@@ -37,6 +37,7 @@
 #include <hip/hip_fp16.h>
 
 #include "em_device.hpp"
+#include "batch_plan.hpp"
 #include "emx_internal.hpp"
 
 namespace emx {
@@ -67,7 +68,7 @@ __host__ __device__ inline int class_of(int n, int d) {
 }
 
 // Classes of the sliced EM-ADMM kernel (batch_wide.hpp; fixed penalty over a
-// box; shapes in emx_internal.hpp, where a batch plan numbers them too): d in
+// box; shapes in batch_plan.hpp, where a batch plan numbers them too): d in
 // (16, 64] and n <= 448 go to 13-coordinate slices over WC = ceil(d / 13) in
 // [2, 5] waves with M = ceil(n / 64) in [1, 7] points per lane.  Their ids
 // follow the kNumClasses classes above.

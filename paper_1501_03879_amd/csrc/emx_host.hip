@@ -14,6 +14,7 @@
 #include <utility>
 #include <vector>
 
+#include "batch_plan.hpp"
 #include "emx_internal.hpp"
 #include "nlem_group.hpp"
 #include "nlem_table.hpp"
