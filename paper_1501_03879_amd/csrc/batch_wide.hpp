@@ -44,9 +44,9 @@ struct WideShape {
 // each 64-point chunk, one value per lane, coalesced), the loads of up to LA
 // chunks in flight at once (all of them for WC >= 4), the next chunk issued
 // as soon as one has been read back; chunk by chunk the rows go through LDS
-// and every lane keeps its slice of its point as -a.  Loads past the instance
-// read its element 0 (no branches, so nothing waits early); those rows are
-// staged but never read back.
+// and every lane keeps its slice of its point as -a.  Rows past the instance
+// read 0 (no branches, so nothing waits early); they are staged but never
+// read back.
 template <int NJ, int M, int WC, typename T>
 __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, int lane, int j0, float *stage,
                                              float (&na)[M][NJ], float &amax, bool &bad) {
@@ -88,15 +88,23 @@ __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, i
     constexpr int RK = (64 + WC - 1) / WC;                 // rows per wave and chunk
     constexpr int LA0 = 112 / RK;                          // ~112 VGPRs of loads in flight
     constexpr int LA = LA0 < 1 ? 1 : (LA0 > M ? M : LA0);
-    const int step = WC * d;
+    // One buffer load per row, range-checked against the instance: a row
+    // costs one vector add for its offset, rows past the instance (and the
+    // lanes past d of its last row) read 0, and lanes past d of the other
+    // rows read values of the next row, which are not staged.
+    constexpr int TB = (int)sizeof(T);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(A), (short)0, n * d * TB, 0x00020000);
+    const int voff = lane * TB;
     T raw[LA][RK];
     auto issue = [&](int q) {
-        const int off0 = (q * 64 + cw) * d + lane;
 #pragma unroll
         for (int k = 0; k < RK; ++k) {
-            const int r = cw + WC * k;
-            const bool v = r < 64 && q * 64 + r < n && lane < d;
-            raw[q % LA][k] = A[v ? off0 + k * step : 0];
+            const int off = voff + (q * 64 + cw + WC * k) * d * TB;
+            if constexpr (TB == 4)
+                raw[q % LA][k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+            else
+                raw[q % LA][k] = __ushort_as_half(__builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0));
         }
     };
 #pragma unroll
