@@ -225,39 +225,91 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
         float *Z = L.z + e.z_off;
         const int pitch = d | 1;
 
-        // ---- stage points into registers (coalesced via LDS), check them
+        // ---- stage points into registers (coalesced via LDS), check them.
+        // A chunk of 64 points is copied flat, at most KS values per thread,
+        // by range-checked buffer loads (values past the instance read 0),
+        // all of a chunk's loads in flight together; the weights of the
+        // lane's points are loaded before the points.
+        constexpr int NCH = M * WP;               // chunks, in the order (q, pc)
+        constexpr int KS = (DS + WP - 1) / WP;    // 64 d <= 64 DS WC = KS x THREADS values
+        const bool h16 = L.a16 != 0;
+        const int tb = h16 ? 2 : 4;
+        // (the descriptor is read into vector registers: its offset is made
+        // uniform so that the buffer resources are scalar)
+        const int64_t aoff = ((int64_t)uniform_int((int)(e.a_off >> 32)) << 32) |
+                             (int64_t)(unsigned int)uniform_int((int)(e.a_off & 0xffffffff));
+        const char *abase = h16 ? (const char *)(reinterpret_cast<const __half *>(L.a) + aoff)
+                                : (const char *)(L.a + aoff);
+        const float inv_d = 1.0f / (float)d;
+        // (the thread index passed through an opaque move per instance: the
+        // positions derived from it would otherwise be hoisted out of the
+        // instance loop and hold KS registers each for the whole kernel)
+        int tid;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
+        unsigned int raw[KS];
+        // the chunk's values from its first one on: a resource per chunk (its
+        // base and the rest of the instance as the range), the thread's
+        // position as the vector offset, k x THREADS as the immediate one
+        auto issue = [&](int c) {
+            const int first = ((c % WP) * M + c / WP) * 64 * d;
+            const int rest = max(0, n * d - first);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<char *>(abase) + (int64_t)min(first, n * d) * tb, (short)0, rest * tb, 0x00020000);
+            if (h16) {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    raw[k] = __builtin_amdgcn_raw_buffer_load_b16(rs, tid * 2 + S::THREADS * 2 * k, 0, 0);
+            } else {
+#pragma unroll
+                for (int k = 0; k < KS; ++k)
+                    raw[k] = __builtin_amdgcn_raw_buffer_load_b32(rs, tid * 4 + S::THREADS * 4 * k, 0, 0);
+            }
+        };
         float na[M][DS];
         float lam[M];
+        float wraw[M];
+#pragma unroll
+        for (int q = 0; q < M; ++q) wraw[q] = Wt[min(pw * M * 64 + q * 64 + lane, n - 1)];
         bool bad_l = false;
         float amax = 0.0f;
 #pragma unroll
-        for (int q = 0; q < M; ++q) {
+        for (int c = 0; c < NCH; ++c) {
+            const int q = c / WP, pc = c % WP;
+            const int p0 = (pc * M + q) * 64;  // first point of this chunk
+            const int cnt = max(0, min(64, n - p0)) * d;
+            issue(c);
+            __syncthreads();   // the previous chunk has been read back
 #pragma unroll
-            for (int pc = 0; pc < WP; ++pc) {
-                const int p0 = (pc * M + q) * 64;  // first point of this chunk
-                const int cnt = max(0, min(64, n - p0));
-                __syncthreads();
-                for (int i = threadIdx.x; i < cnt * d; i += S::THREADS) {
-                    const int pp = i / d, jj = i - (i / d) * d;
-                    stage[pp * pitch + jj] = aval((int64_t)p0 * d + i);
-                }
-                __syncthreads();
-                if (pc == pw) {
-                    const int p = p0 + lane;
-                    const bool vp = p < n;
-#pragma unroll
-                    for (int jj = 0; jj < DS; ++jj) {
-                        const int j = cw * DS + jj;
-                        const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
-                        bad_l |= !(fabsf(v) <= FLT_MAX);
-                        amax = fmaxf(amax, fabsf(v));
-                        na[q][jj] = -v;
-                    }
-                    const float wv = vp ? Wt[p] : 0.0f;
-                    bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
-                    lam[q] = vp ? wv : -1.0f;  // weight for now (-1: no point); lambda below
+            for (int k = 0; k < KS; ++k) {
+                if (tid < cnt - S::THREADS * k) {
+                    const int i = tid + S::THREADS * k;
+                    // row i / d by a float reciprocal: exact for i < 2^22
+                    const int pp = (int)(((float)i + 0.5f) * inv_d);
+                    const unsigned int bits = raw[k];
+                    stage[pp * pitch + (i - pp * d)] =
+                        h16 ? __half2float(__ushort_as_half((unsigned short)bits)) : __uint_as_float(bits);
                 }
             }
+            __syncthreads();
+            if (pc == pw) {
+                const int p = p0 + lane;
+                const bool vp = p < n;
+#pragma unroll
+                for (int jj = 0; jj < DS; ++jj) {
+                    const int j = cw * DS + jj;
+                    const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
+                    bad_l |= !(fabsf(v) <= FLT_MAX);
+                    amax = fmaxf(amax, fabsf(v));
+                    na[q][jj] = -v;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            const int p = pw * M * 64 + q * 64 + lane;
+            const float wv = (p < n) ? wraw[q] : 0.0f;
+            bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
+            lam[q] = (p < n) ? wv : -1.0f;  // weight for now (-1: no point); lambda below
         }
         const float wamax = wave_max(amax);
         if (__any(bad_l) && lane == 0) flag_s[0] = 1;
