@@ -159,18 +159,32 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
         // one column per lane (TW <= 64); the columns a last partial run
         // reaches past the window are staged too (finite values of masked
         // slots).
+        // All of a wave's row loads are issued before the first is waited
+        // on (reflected positions are always inside the image, so the loads
+        // need no guard; rows past the tile re-read its last row).
         {
+            constexpr int RPW = (S::TW + WC - 1) / WC;   // rows per wave, at most
             const int gx = reflect_idx(ix - R - PR + lane, W);
-            for (int ty = SW; ty < TWr; ty += WC) {
-                const int64_t gy = reflect_idx(iy - R - PR + ty, H);
-                if (lane < TWs) {
-                    float v;
-                    if (I.is_f16)
-                        v = __half2float(reinterpret_cast<const __half *>(I.img)[gy * W + gx]);
-                    else
-                        v = reinterpret_cast<const float *>(I.img)[gy * W + gx];
-                    tile[ty * S::P + lane] = v;
+            float v[RPW];
+            if (I.is_f16) {
+                const __half *img = reinterpret_cast<const __half *>(I.img);
+#pragma unroll
+                for (int k = 0; k < RPW; ++k) {
+                    const int64_t gy = reflect_idx(iy - R - PR + min(SW + WC * k, TWr - 1), H);
+                    v[k] = __half2float(img[gy * W + gx]);
                 }
+            } else {
+                const float *img = reinterpret_cast<const float *>(I.img);
+#pragma unroll
+                for (int k = 0; k < RPW; ++k) {
+                    const int64_t gy = reflect_idx(iy - R - PR + min(SW + WC * k, TWr - 1), H);
+                    v[k] = img[gy * W + gx];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RPW; ++k) {
+                const int ty = SW + WC * k;
+                if (ty < TWr && lane < TWs) tile[ty * S::P + lane] = v[k];
             }
         }
         __syncthreads();
