@@ -230,3 +230,43 @@ def test_far_outliers_reach_the_tolerance():
     report("far-outlier instances tol-mode (oracle at GPU iterations)", emax, erms)
     assert emax <= 1e-4
     assert np.all(ref["r_pri"][st["flags"] == 1] <= 1.05e-4 * 6.0)
+
+
+@pytest.mark.parametrize("f16", [False, True])
+@pytest.mark.parametrize("n,d", [(441, 49), (65, 40), (449, 64), (500, 16), (300, 3), (1, 17)])
+def test_last_instance_at_the_end_of_the_points(n, d, f16):
+    """The staging reads a chunk of 64 rows at a time: rows past an instance
+    and, in the last row, the lanes past d are outside it.  Those reads are
+    range-checked against the instance (they return 0 and are never used),
+    so an instance that ends exactly where the points tensor ends, with a
+    partial last chunk, is solved like any other: sliced (d > 16, n <= 448)
+    and generic classes, FP32 and FP16 storage, against the oracle on the
+    (FP16-rounded) points."""
+    import torch
+    import paper_1501_03879_amd as emx
+    from helpers import gpu, handle
+    rng = np.random.default_rng(1000 * n + d)
+    pts, ws = [], []
+    for nb, db in ((37, d), (n + 5 if n + 5 <= 512 else n - 5, d), (n, d)):   # the tested one last
+        a = rng.standard_normal((nb, db)) * 3.0
+        pts.append(a.astype(np.float32))
+        ws.append(rng.exponential(size=nb).astype(np.float32))
+    b = synth.pointsets.pack_instances(pts, ws, -3.0, 3.0)
+    if f16:
+        b.a = b.a.astype(np.float16).astype(np.float32)
+    dev = gpu()
+    a = torch.from_numpy(b.a.astype(np.float16) if f16 else b.a).to(dev)
+    assert a.numel() == int(b.inst["a_off"][-1]) + n * d   # the last instance ends the tensor
+    w = torch.from_numpy(b.w).to(dev)
+    inst = emx.instances_tensor(b.inst, dev)
+    z = torch.zeros(b.z_size, dtype=torch.float32, device=dev)
+    st = torch.zeros((b.B, 4), dtype=torch.int32, device=dev)
+    hd = handle()
+    hd.em_solve_batch_ex(a, w, inst, z, st, solver=0, init=oracle.INIT_MAXW, lo=b.lo, hi=b.hi, rho=0.5,
+                         max_iter=25, tol=0.0)
+    hd.sync()
+    ref = oracle.em_batch(b, 0.5, 25, 0.0, init=oracle.INIT_MAXW)
+    emax, erms = rel_errors(z.cpu().numpy().astype(np.float64), ref["z"], 6.0)
+    report(f"last instance n={n} d={d} f16={f16}", emax, erms)
+    assert emax <= 1e-4
+    assert np.all(emx.stats_view(st)[1].cpu().numpy() == 2)   # EM_MAXITER at the fixed count
