@@ -275,13 +275,13 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
             const int q = c / WP, pc = c % WP;
-            const int p0 = (pc * M + q) * 64;  // first point of this chunk
-            const int cnt = max(0, min(64, n - p0)) * d;
             issue(c);
             __syncthreads();   // the previous chunk has been read back
+            // the whole chunk is staged: values past the instance read 0, so
+            // the rows of absent points hold zeros
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
-                if (tid < cnt - S::THREADS * k) {
+                if (tid < 64 * d - S::THREADS * k) {
                     const int i = tid + S::THREADS * k;
                     // row i / d by a float reciprocal: exact for i < 2^22
                     const int pp = (int)(((float)i + 0.5f) * inv_d);
@@ -292,15 +292,17 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             }
             __syncthreads();
             if (pc == pw) {
-                const int p = p0 + lane;
-                const bool vp = p < n;
+                // (a NaN is caught by unordered compares of pairs, an
+                // infinity by the running maximum, checked below)
 #pragma unroll
-                for (int jj = 0; jj < DS; ++jj) {
+                for (int jj = 0; jj < DS; jj += 2) {
                     const int j = cw * DS + jj;
-                    const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
-                    bad_l |= !(fabsf(v) <= FLT_MAX);
-                    amax = fmaxf(amax, fabsf(v));
-                    na[q][jj] = -v;
+                    const float v0 = (j < d) ? stage[lane * pitch + j] : 0.0f;
+                    const float v1 = (jj + 1 < DS && j + 1 < d) ? stage[lane * pitch + j + 1] : 0.0f;
+                    bad_l |= __builtin_isunordered(v0, v1);
+                    amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
+                    na[q][jj] = -v0;
+                    if (jj + 1 < DS) na[q][jj + 1] = -v1;
                 }
             }
         }
@@ -311,6 +313,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             bad_l |= !(wv >= 0.0f && wv <= FLT_MAX);
             lam[q] = (p < n) ? wv : -1.0f;  // weight for now (-1: no point); lambda below
         }
+        bad_l |= !(amax <= FLT_MAX);   // an infinite point (NaN ones are flagged already)
         const float wamax = wave_max(amax);
         if (__any(bad_l) && lane == 0) flag_s[0] = 1;
         if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));  // non-negative floats order as ints

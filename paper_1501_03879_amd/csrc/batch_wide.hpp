@@ -119,14 +119,18 @@ __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, i
         }
         if (q + LA < M) issue(q + LA);
         __syncthreads();
-        const bool vp = q * 64 + lane < n;
+        // (rows past the instance were staged as 0, so only coordinates past
+        // d are masked; a NaN is caught by unordered compares of pairs, an
+        // infinity by the running maximum, checked by the caller)
 #pragma unroll
-        for (int jj = 0; jj < NJ; ++jj) {
+        for (int jj = 0; jj < NJ; jj += 2) {
             const int j = j0 + jj;
-            const float v = (vp && j < d) ? stage[lane * pitch + j] : 0.0f;
-            bad |= !(fabsf(v) <= FLT_MAX);
-            amax = fmaxf(amax, fabsf(v));
-            na[q][jj] = -v;
+            const float v0 = (j < d) ? stage[lane * pitch + j] : 0.0f;
+            const float v1 = (jj + 1 < NJ && j + 1 < d) ? stage[lane * pitch + j + 1] : 0.0f;
+            bad |= __builtin_isunordered(v0, v1);
+            amax = fmaxf(amax, fmaxf(fabsf(v0), fabsf(v1)));
+            na[q][jj] = -v0;
+            if (jj + 1 < NJ) na[q][jj + 1] = -v1;
         }
     }
 }
@@ -200,6 +204,7 @@ __device__ __forceinline__ WideStart wide_start(const ClassLaunch &L, const em_i
         stage_points<NJ, M, WC>(A16, n, d, cw, lane, j0, stage, na, amax, bad_l);
     else
         stage_points<NJ, M, WC>(A, n, d, cw, lane, j0, stage, na, amax, bad_l);
+    bad_l |= !(amax <= FLT_MAX);   // an infinite point (NaN ones are flagged already)
     const float wamax = wave_max(amax);
     if (__any(bad_l) && lane == 0) flag_s[0] = 1;
     if (lane == 0) atomicMax(&flag_s[1], __float_as_int(wamax));   // non-negative floats order as ints
