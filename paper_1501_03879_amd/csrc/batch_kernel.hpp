@@ -42,6 +42,12 @@
 
 namespace emx {
 
+// Last word of the buffer resources the staging builds (base, stride 0, a
+// byte range): the gfx9 data-format field set to 32 bits, the other fields
+// zero.  Raw buffer loads take their width from the instruction; the range
+// makes a load past it return 0.
+constexpr int kBufferRsrcWord3 = 0x00020000;
+
 struct ClassShape {
     int ds, m, wc, wp;
 };
@@ -254,7 +260,7 @@ __global__ __launch_bounds__(64 * WC * WP, 2) void batch_solve_kernel(ClassLaunc
             const int first = ((c % WP) * M + c / WP) * 64 * d;
             const int rest = max(0, n * d - first);
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-                const_cast<char *>(abase) + (int64_t)min(first, n * d) * tb, (short)0, rest * tb, 0x00020000);
+                const_cast<char *>(abase) + (int64_t)min(first, n * d) * tb, (short)0, rest * tb, kBufferRsrcWord3);
             if (h16) {
 #pragma unroll
                 for (int k = 0; k < KS; ++k)

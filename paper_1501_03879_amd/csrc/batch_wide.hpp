@@ -94,7 +94,7 @@ __device__ __forceinline__ void stage_points(const T *A, int n, int d, int cw, i
     // rows read values of the next row, which are not staged.
     constexpr int TB = (int)sizeof(T);
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(A), (short)0, n * d * TB, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(A), (short)0, n * d * TB, kBufferRsrcWord3);
     const int voff = lane * TB;
     T raw[LA][RK];
     auto issue = [&](int q) {
