@@ -98,6 +98,7 @@ struct NlemShape {
     // [w QS, min((w + 1) QS, M))
     static constexpr int QS = (M + WC - 1) / WC;
     static_assert(TW <= 64, "tile rows are staged one column per lane");
+    static_assert(D <= 64, "one lane per patch coordinate sums the squared z steps");
 };
 
 template <int PR, int M, int WC, int SW, int SOLVER>
@@ -118,6 +119,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
     // per-wave c = 2 z^t - z^{t-1} of the slice, [0, NJ); lanes that own no
     // coordinate write to a private slot in [64, 128) instead
     float *cv = cvec + SW * 128;
+    // squared z steps of the owned coordinates, by iteration parity (WC > 1)
+    float *dz2s = xs + 3 * WC * 4;
     const int cidx = myv ? myc : 64 + lane;
     // points stay in registers when they fit (the compiler hoists the tile
     // reads); IRLS never changes g = -a, so it always keeps them
@@ -466,12 +469,17 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 float *SV = xn + 2 * WC * M * 64;
 #pragma unroll
                 for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = nrm[q];
-                if (lane == 0) XS[SW * 4] = rd_w;
                 __syncthreads();
-                rd_all = XS[0];
-#pragma unroll
-                for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
-                rd_all = readfirstlane(rd_all);
+                // the dual residual of iteration t-1: the last wave sums the
+                // squared steps the coordinate owners left in LDS (coordinate
+                // order) and hands the total over with the shrink factors
+                if constexpr (SW == WC - 1) {
+                    if (t > 1) {
+                        const float q2 = (lane < S::D) ? dz2s[((t - 1) & 1) * 64 + lane] : 0.0f;
+                        const float tot = wave_sum(q2);
+                        if (lane == 0) XS[SW * 4 + 3] = tot;
+                    }
+                }
                 float ns[QN > 0 ? QN : 1];
 #pragma unroll
                 for (int qq = 0; qq < QN; ++qq) {
@@ -509,6 +517,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 }
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = SV[q * 64 + lane];
+                if (t > 1) rd_all = readfirstlane(XS[(WC - 1) * 4 + 3]);
             } else {
                 // ---- a2 (one wave holds whole points): the weights from the
                 // first iteration's distances, unless the pre-pass made them
@@ -591,7 +600,14 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             const float zn = clampf(fmaf(-Ev, inv_n, zr), L.lo, L.hi);
             const float dz = zn - zr;
             cv[cidx] = zn + dz;
-            rd_w = readfirstlane(wave_sum(dz * dz));
+            if constexpr (WC > 1) {
+                // (summed by the last wave after the next exchange; armed
+                // iterations sum their own below)
+                if (myv) dz2s[(t & 1) * 64 + J0 + myc] = dz * dz;
+                if (armed) rd_w = readfirstlane(wave_sum(dz * dz));
+            } else {
+                rd_w = readfirstlane(wave_sum(dz * dz));
+            }
             const float cz = (2.0f * zr - zp) - zn;
             zp = zr;
             zr = zn;
@@ -703,7 +719,7 @@ __global__ __launch_bounds__(64 * WC, EMX_NLEM_MIN_WAVES) void nlem_solve_kernel
     using S = NlemShape<PR, M, WC>;
     __shared__ float tile[S::TILE];
     __shared__ float xn[S::XN];
-    __shared__ float xs[3 * WC * 4];
+    __shared__ float xs[3 * WC * 4 + 128];   // residual partials; then the squared steps, two buffers
     __shared__ float cvec[WC * 128];
     __shared__ unsigned int item_s;
     const int wave = uniform_int(threadIdx.x >> 6);
