@@ -273,7 +273,11 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
     using RSx = RSF<NJ>;
     __shared__ float stage[S::STAGE];
     __shared__ float xn[S::XN];
-    __shared__ float xs[3 * WC * 4];   // per-wave residual partials: two buffers + the armed test
+    __shared__ float sv[M * 64];       // shrink factors of the points, from the wave that took them
+    // per-wave residual partials (two buffers + the armed test), then the
+    // squared z steps of the owned coordinates by iteration parity
+    __shared__ float xs[3 * WC * 4 + 128];
+    float *dz2s = xs + 3 * WC * 4;
     __shared__ float cvec[WC * 128];   // per wave: c of the slice [0, NJ); private slots [64, 128)
     __shared__ unsigned int item_s;
     __shared__ int flag_s[4];
@@ -341,6 +345,17 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
             const float inv_mu = 1.0f / L.mu;
 #pragma unroll
             for (int q = 0; q < M; ++q) lam[q] = (lam[q] >= 0.0f) ? lam[q] * inv_mu : 0.0f;
+            // wave cw takes the shrink factors of the lane's points [cw QS,
+            // min((cw + 1) QS, M)): their lambdas, picked once per instance
+            constexpr int QS = (M + WC - 1) / WC;
+            float lq[QS];
+#pragma unroll
+            for (int qq = 0; qq < QS; ++qq) {
+                float v = 0.0f;
+#pragma unroll
+                for (int q = 0; q < M; ++q) v = (q == cw * QS + qq) ? lam[q] : v;
+                lq[qq] = v;
+            }
             float g[M][NJ];
 #pragma unroll
             for (int q = 0; q < M; ++q)
@@ -383,31 +398,41 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                 // ---- the slices' partials summed (in wave order, identical in
                 // every wave), with the dual residual of iteration t-1
                 float rd_all = rd_w;
-                if constexpr (WC > 1) {
+                float s[M];
+                {
+                    // wave cw adds up the partials of its share of the points
+                    // (in wave order, as every wave would), takes their
+                    // shrink factors and hands them to the other waves
+                    // through LDS; the last wave also sums the squared z steps
+                    // of iteration t-1 the coordinate owners left there
                     float *X = xn + (t & 1) * WC * M * 64;
                     float *XS = xs + (t & 1) * WC * 4;
 #pragma unroll
                     for (int q = 0; q < M; ++q) X[(cw * M + q) * 64 + lane] = nrm[q];
-                    if (lane == 0) XS[cw * 4] = rd_w;
+                    __syncthreads();
+                    if (cw == WC - 1 && t > 1) {
+                        const float q2 = (lane < d) ? dz2s[((t - 1) & 1) * 64 + lane] : 0.0f;
+                        const float tot = wave_sum(q2);
+                        if (lane == 0) XS[cw * 4 + 3] = tot;
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < QS; ++qq) {
+                        const int q = cw * QS + qq;
+                        if (q < M) {
+                            float sum = X[q * 64 + lane];
+#pragma unroll
+                            for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
+                            sv[q * 64 + lane] = shrink(sum, lq[qq]);
+                        }
+                    }
                     __syncthreads();
 #pragma unroll
-                    for (int q = 0; q < M; ++q) {
-                        float sum = X[q * 64 + lane];
-#pragma unroll
-                        for (int w = 1; w < WC; ++w) sum += X[(w * M + q) * 64 + lane];
-                        nrm[q] = sum;
-                    }
-                    rd_all = XS[0];
-#pragma unroll
-                    for (int w = 1; w < WC; ++w) rd_all += XS[w * 4];
-                    rd_all = readfirstlane(rd_all);
+                    for (int q = 0; q < M; ++q) s[q] = sv[q * 64 + lane];
+                    if (t > 1) rd_all = readfirstlane(XS[(WC - 1) * 4 + 3]);
                 }
                 if (t > 1) rd2 = rd_all * inv_d;
                 const bool armed = uniform((t == max_iter) ||
                                            (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
-                float s[M];
-#pragma unroll
-                for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
                 // ---- armed iterations: lane sums of ||x_k - c||^2 with
                 // x_k = a_k + (1 - s) delta (absent points and padded
                 // coordinates give exactly 0)
@@ -489,7 +514,10 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                 const float zn = own ? clampf(fmaf(-Ev, inv_n, zr), blo, bhi) : 0.0f;
                 const float dz = zn - zr;
                 cv[cidx] = zn + dz;
-                rd_w = readfirstlane(wave_sum(dz * dz));
+                // (summed by the last wave after the next exchange; armed
+                // iterations sum their own below)
+                if (own) dz2s[(t & 1) * 64 + cj] = dz * dz;
+                if (armed) rd_w = readfirstlane(wave_sum(dz * dz));
                 const float cz = (2.0f * zr - zp) - zn;   // c - z' (0 on lanes without a coordinate)
                 zp = zr;
                 zr = zn;
