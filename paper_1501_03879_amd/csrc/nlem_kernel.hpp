@@ -101,6 +101,13 @@ struct NlemShape {
     static_assert(D <= 64, "one lane per patch coordinate sums the squared z steps");
 };
 
+// Totals of two per-lane values over the 64 lanes in one reduction (the
+// stages of one wave sum): the first on lanes 0-31, the second on 32-63.
+__device__ __forceinline__ float wave_sum2(float a, float b) {
+    const float x = swap32_sum(a, b);   // lanes 0-31: a[l] + a[l + 32]; lanes 32-63: b
+    return row_sum16(swap16_sum(x, x));
+}
+
 template <int PR, int M, int WC, int SW, int SOLVER>
 __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, float *xn, float *xs,
                                           float *cvec, unsigned int *item_s) {
@@ -489,7 +496,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 }
                 // (a branch of its own: folded into the iteration, the
                 // exponentials would run on every iteration)
-                const bool first = uniform(t == 1 && !pre);
+                const bool first = t == 1 && !pre;   // (uniform already: t and pre are)
                 if (__builtin_expect(first, 0)) {
                     // ---- a2: NLM weights from the first iteration's
                     // distances (the noisy start: delta = P_i - P_j)
@@ -604,7 +611,6 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 // (summed by the last wave after the next exchange; armed
                 // iterations sum their own below)
                 if (myv) dz2s[(t & 1) * 64 + J0 + myc] = dz * dz;
-                if (armed) rd_w = readfirstlane(wave_sum(dz * dz));
             } else {
                 rd_w = readfirstlane(wave_sum(dz * dz));
             }
@@ -616,7 +622,14 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 // x_k - z' = (x_k - c) + (c - z') and sum_k (x_k - c) = E^t - E^{t+1};
                 // the stop test is taken right away (one barrier for WC > 1)
                 const float rpx = cz * fmaf(fn, cz, 2.0f * (Ep - Ev));
-                rp_w = readfirstlane(wave_sum(rp_lane + rpx));
+                if constexpr (WC > 1) {
+                    // this iteration's dual and primal lane sums in one reduction
+                    const float t2 = wave_sum2(dz * dz, rp_lane + rpx);
+                    rd_w = readfirstlane(t2);
+                    rp_w = readlane(t2, 32);
+                } else {
+                    rp_w = readfirstlane(wave_sum(rp_lane + rpx));
+                }
                 float rd_all = rd_w, rp_all = rp_w;
                 if constexpr (WC > 1) {
                     float *XS = xs + 2 * WC * 4;   // its own slot: armed iterations only
