@@ -517,7 +517,6 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                 // (summed by the last wave after the next exchange; armed
                 // iterations sum their own below)
                 if (own) dz2s[(t & 1) * 64 + cj] = dz * dz;
-                if (armed) rd_w = readfirstlane(wave_sum(dz * dz));
                 const float cz = (2.0f * zr - zp) - zn;   // c - z' (0 on lanes without a coordinate)
                 zp = zr;
                 zr = zn;
@@ -525,7 +524,13 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                     // sum_k ||x_k - z'||^2 = sum_k ||x_k - c||^2 + 2 (c - z') . sum_k (x_k - c)
                     // + n ||c - z'||^2, with sum_k (x_k - c) = E^t - E^{t+1}
                     const float rpx = own ? cz * fmaf(fn, cz, 2.0f * (Ep - Ev)) : 0.0f;
-                    rp_w = readfirstlane(wave_sum(rp_lane + rpx));
+                    // this iteration's dual and primal lane sums in one
+                    // reduction (the stages of one wave sum; the first total
+                    // on lanes 0-31, the second on 32-63)
+                    const float x2 = swap32_sum(dz * dz, rp_lane + rpx);
+                    const float t2 = row_sum16(swap16_sum(x2, x2));
+                    rd_w = readfirstlane(t2);
+                    rp_w = readlane(t2, 32);
                     float rd_t = rd_w, rp_t = rp_w;
                     if constexpr (WC > 1) {
                         float *XS = xs + 2 * WC * 4;   // its own slot: armed iterations only
