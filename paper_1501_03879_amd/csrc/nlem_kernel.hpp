@@ -461,6 +461,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             }
             float s[M];
             float rd_all = rd_w;
+            bool arm_ok = false;   // WC > 1: iteration t-1's dual residual within the arm level
             if constexpr (WC > 1) {
                 // The waves hold partial sums of ||delta||^2 over their
                 // coordinate slices.  Wave SW adds up the partials of its
@@ -484,7 +485,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                     if (t > 1) {
                         const float q2 = (lane < S::D) ? dz2s[((t - 1) & 1) * 64 + lane] : 0.0f;
                         const float tot = wave_sum(q2);
-                        if (lane == 0) XS[SW * 4 + 3] = tot;
+                        // (only the arming test needs it: the flag goes over)
+                        if (lane == 0) reinterpret_cast<int *>(XS)[SW * 4 + 3] = (tot * inv_d <= arm2) ? 1 : 0;
                     }
                 }
                 float ns[QN > 0 ? QN : 1];
@@ -524,7 +526,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 }
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = SV[q * 64 + lane];
-                if (t > 1) rd_all = readfirstlane(XS[(WC - 1) * 4 + 3]);
+                if (t > 1) arm_ok = uniform_int(reinterpret_cast<const int *>(XS)[(WC - 1) * 4 + 3]) != 0;
             } else {
                 // ---- a2 (one wave holds whole points): the weights from the
                 // first iteration's distances, unless the pre-pass made them
@@ -540,11 +542,16 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int q = 0; q < M; ++q) s[q] = shrink(nrm[q], lam[q]);
             }
-            // dual residual of iteration t-1 (all waves hold identical sums),
-            // which arms the primal residual of this iteration
-            if (t > 1) rd2 = rd_all * inv_d;
-            const bool armed = uniform((t == max_iter) ||
-                                       (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
+            // the dual residual of iteration t-1 arms the primal residual of
+            // this iteration (WC > 1: the last wave took the test)
+            bool armed;
+            if constexpr (WC > 1) {
+                armed = (t == max_iter) || (tau2 > 0.0f && t > 1 && arm_ok && (t & L.check_mask) == 0);
+            } else {
+                if (t > 1) rd2 = rd_all * inv_d;
+                armed = uniform((t == max_iter) ||
+                                (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
+            }
 
             // ---- a8 (armed iterations only): lane sums of ||x_k - c||^2 with
             // x_k = v_k - e_k = a_k + (1 - s) delta, read-only on the state
