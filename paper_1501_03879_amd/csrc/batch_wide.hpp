@@ -397,7 +397,7 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                 }
                 // ---- the slices' partials summed (in wave order, identical in
                 // every wave), with the dual residual of iteration t-1
-                float rd_all = rd_w;
+                bool arm_ok = false;
                 float s[M];
                 {
                     // wave cw adds up the partials of its share of the points
@@ -413,7 +413,8 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                     if (cw == WC - 1 && t > 1) {
                         const float q2 = (lane < d) ? dz2s[((t - 1) & 1) * 64 + lane] : 0.0f;
                         const float tot = wave_sum(q2);
-                        if (lane == 0) XS[cw * 4 + 3] = tot;
+                        // (only the arming test needs it: the flag goes over)
+                        if (lane == 0) reinterpret_cast<int *>(XS)[cw * 4 + 3] = (tot * inv_d <= arm2) ? 1 : 0;
                     }
 #pragma unroll
                     for (int qq = 0; qq < QS; ++qq) {
@@ -428,11 +429,11 @@ __global__ __launch_bounds__(64 * WC, WAVES_PER_SIMD) void batch_wide_kernel(Cla
                     __syncthreads();
 #pragma unroll
                     for (int q = 0; q < M; ++q) s[q] = sv[q * 64 + lane];
-                    if (t > 1) rd_all = readfirstlane(XS[(WC - 1) * 4 + 3]);
+                    if (t > 1) arm_ok = uniform_int(reinterpret_cast<const int *>(XS)[(WC - 1) * 4 + 3]) != 0;
                 }
-                if (t > 1) rd2 = rd_all * inv_d;
-                const bool armed = uniform((t == max_iter) ||
-                                           (tau2 > 0.0f && t > 1 && rd2 <= arm2 && (t & L.check_mask) == 0));
+                // the dual residual of iteration t-1 (tested by the last
+                // wave) arms the primal residual of this iteration
+                const bool armed = (t == max_iter) || (tau2 > 0.0f && t > 1 && arm_ok && (t & L.check_mask) == 0);
                 // ---- armed iterations: lane sums of ||x_k - c||^2 with
                 // x_k = a_k + (1 - s) delta (absent points and padded
                 // coordinates give exactly 0)
