@@ -480,7 +480,8 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
                 __syncthreads();
                 // the dual residual of iteration t-1: the last wave sums the
                 // squared steps the coordinate owners left in LDS (coordinate
-                // order) and hands the total over with the shrink factors
+                // order), takes the arming test and hands its outcome over
+                // with the shrink factors
                 if constexpr (SW == WC - 1) {
                     if (t > 1) {
                         const float q2 = (lane < S::D) ? dz2s[((t - 1) & 1) * 64 + lane] : 0.0f;
