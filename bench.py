@@ -568,7 +568,7 @@ def main():
                                "HIP events the library records around each NLEM launch on the "
                                "launch stream over the timed steps (em_kernel_timing); "
                                "achieved_per_step and ms_per_step: events around whole steps "
-                               "(one nlem_denoise call: a queue-head reset, the three queue-order "
+                               "(one nlem_denoise call: the three queue-order "
                                "kernels and one NLEM kernel launch)"},
     }
 

@@ -719,14 +719,14 @@ static em_status_t timing_pair(em_context *h, hipStream_t s, std::pair<hipEvent_
 }
 
 // Queue one persistent launch per (patch radius, points per lane) group of
-// the images, each after a reset of its work-queue head (and the kernels
-// that put its pixels in longest-first order).
+// the images, each after the kernels that put its pixels in longest-first
+// order (the first of them zeroes the work-queue head) or, without the
+// order, a reset of the head.
 static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const nlem_image_t *images,
                             const nlem_options_t &o) {
     auto groups = group_images(count, images);
     if ((int)groups.size() > h->num_counters) return fail(h, EM_ERR_UNSUPPORTED, "too many shape groups");
-    em_status_t st = ctx_reset_counters(h, s, h->counters, (int)groups.size());
-    if (st != EM_OK) return st;
+    em_status_t st = EM_OK;
     const bool ord = order_enabled(o);
     char *ws = nullptr;
     if (ord) {
@@ -752,6 +752,9 @@ static em_status_t nlem_run(em_context *h, hipStream_t s, int32_t count, const n
             st = queue_order(h, s, A);
             if (st != EM_OK) return st;
             L.order = A.order;
+        } else {
+            st = ctx_reset_counters(h, s, L.counter, 1);
+            if (st != EM_OK) return st;
         }
         if (ord) ws += nlem_order_bytes(total);
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
@@ -842,17 +845,18 @@ extern "C" em_status_t nlem_denoise_noalloc(em_handle_t h, void *stream, const v
     L.prefix[0] = 0;
     L.prefix[1] = total;
     L.counter = counter;
-    st = ctx_reset_counters(h, s, counter, 1);
-    if (st != EM_OK) return st;
     const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads, /*cache=*/false);
     L.chunk = queue_chunk(g, total, cap, sc.chunk);
     if (use_order(order_enabled(o), g.pr, total, cap, sc.order)) {
         if (kScratchHeadBytes + nlem_order_bytes(total) > kScratchBytes)
             return fail(h, EM_ERR_UNSUPPORTED, "nlem_denoise_noalloc: order scratch too small");
         const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, scr + kScratchHeadBytes);
-        st = queue_order(h, s, A);   // its first kernel clears the bucket counters
+        st = queue_order(h, s, A);   // its first kernel clears the bucket counters and the head
         if (st != EM_OK) return st;
         L.order = A.order;
+    } else {
+        st = ctx_reset_counters(h, s, counter, 1);
+        if (st != EM_OK) return st;
     }
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, cap));
     void *args[] = {&L};
@@ -1103,7 +1107,7 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
         char *ws = static_cast<char *>(h->multi.ws);
         hipGraph_t graph;
         EMX_HIP(h, hipGraphCreate(&graph, 0));
-        // one chain per group: reset head -> [order: clear, count, scan, scatter] -> NLEM
+        // one chain per group: [order: clear (and the head), count, scatter] or a reset of the head -> NLEM
         auto add = [&](hipGraphNode_t *node, const hipGraphNode_t *dep, const void *fn, dim3 grid, dim3 block,
                        void **args, const char *what) -> em_status_t {
             hipKernelNodeParams p{};
@@ -1134,26 +1138,30 @@ extern "C" em_status_t nlem_denoise_multi(em_handle_t h, void *stream, int32_t c
             L.tau_arm = sc.arm * L.tau;
             L.check_mask = sc.check - 1;
             hipGraphNode_t prev;
-            int one = 1;
-            void *rargs[] = {&counter, &one};
-            st = add(&prev, nullptr, reinterpret_cast<const void *>(&reset_counters_kernel), dim3(1), dim3(64),
-                     rargs, "hipGraphAddKernelNode(reset)");
-            if (st != EM_OK) return st;
             const int64_t total = L.prefix[L.count];
             const int64_t cap = (int64_t)h->num_cus * blocks_per_cu(h, k.fn, k.threads);
             L.chunk = queue_chunk(g, total, cap, sc.chunk);
             if (use_order(ord, g.pr, total, cap, sc.order)) {
+                // the first order kernel also zeroes the work-queue head
                 const NlemOrderArgs A = nlem_order_args(L, g.pr, o.lo, o.hi, ws);
                 OrderKernel ok[kOrderKernels];
                 nlem_order_kernels(A, h->num_cus, ok);
-                for (const OrderKernel &x : ok) {
+                for (int i = 0; i < kOrderKernels; ++i) {
+                    const OrderKernel &x = ok[i];
                     void *oargs[] = {const_cast<NlemOrderArgs *>(&A)};
                     hipGraphNode_t nn;
-                    st = add(&nn, &prev, x.fn, dim3(x.grid), dim3(x.block), oargs, "hipGraphAddKernelNode(order)");
+                    st = add(&nn, i ? &prev : nullptr, x.fn, dim3(x.grid), dim3(x.block), oargs,
+                             "hipGraphAddKernelNode(order)");
                     if (st != EM_OK) return st;
                     prev = nn;
                 }
                 L.order = A.order;
+            } else {
+                int one = 1;
+                void *rargs[] = {&counter, &one};
+                st = add(&prev, nullptr, reinterpret_cast<const void *>(&reset_counters_kernel), dim3(1), dim3(64),
+                         rargs, "hipGraphAddKernelNode(reset)");
+                if (st != EM_OK) return st;
             }
             if (ord) ws += nlem_order_bytes(total);
             void *kargs[] = {&L};

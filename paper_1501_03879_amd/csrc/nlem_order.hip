@@ -24,19 +24,54 @@ static constexpr int kCnt = 3 * kOrderBuckets + 1;
 // largest patch radius (the host rejects larger ones before any launch)
 static constexpr int kOrderMaxPr = EM_MAX_PATCH_RADIUS;
 
+// Zeroes the bucket counters and the NLEM launch's work-queue head (the
+// launch that follows on the same stream needs no reset of its own).
 __global__ void nlem_order_clear(NlemOrderArgs A) {
     for (int i = threadIdx.x; i < kCnt; i += blockDim.x) A.cnt[i] = 0u;
+    if (threadIdx.x == 0) *A.L.counter = 0u;
+}
+
+// Sums of the values and of their squares over the PS x PS patch of pixel
+// (iy, ix), reflected at the borders.  The loads are unrolled and all go out
+// before the first is used; the sums run in row-major order.
+template <int PS>
+__device__ __forceinline__ void patch_sums(const NlemImageDesc &I, int iy, int ix, float &s1, float &s2) {
+    constexpr int PR = PS / 2;
+    int64_t ro[PS];
+    int co[PS];
+#pragma unroll
+    for (int k = 0; k < PS; ++k) {
+        ro[k] = (int64_t)reflect_idx(iy - PR + k, I.H) * I.W;
+        co[k] = reflect_idx(ix - PR + k, I.W);
+    }
+    float v[PS * PS];
+    if (I.is_f16) {
+        const __half *f16 = static_cast<const __half *>(I.img);
+#pragma unroll
+        for (int k = 0; k < PS * PS; ++k) v[k] = __half2float(f16[ro[k / PS] + co[k % PS]]);
+    } else {
+        const float *f32 = static_cast<const float *>(I.img);
+#pragma unroll
+        for (int k = 0; k < PS * PS; ++k) v[k] = f32[ro[k / PS] + co[k % PS]];
+    }
+    s1 = 0.0f;
+    s2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PS * PS; ++k) {
+        s1 += v[k];
+        s2 = fmaf(v[k], v[k], s2);
+    }
 }
 
 // Bucket of every pixel (stored) and the per-bucket counts.
-__global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
+template <int PS>
+__device__ __forceinline__ void order_count(const NlemOrderArgs &A) {
     __shared__ unsigned int hist[kOrderBuckets];
     for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) hist[i] = 0u;
     __syncthreads();
     const NlemLaunch &L = A.L;
     const int64_t total = L.prefix[L.count];
-    const int P = 2 * A.pr + 1;
-    const float inv_d = 1.0f / (float)(P * P);
+    const float inv_d = 1.0f / (float)(PS * PS);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
          q += (int64_t)gridDim.x * blockDim.x) {
         int b = 0;
@@ -44,25 +79,10 @@ __global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
         const NlemImageDesc &I = L.img[b];
         const int pix = (int)(q - L.prefix[b]);
         const int iy = pix / I.W, ix = pix - (pix / I.W) * I.W;
-        const float *f32 = static_cast<const float *>(I.img);
-        const __half *f16 = static_cast<const __half *>(I.img);
-        // reflected rows and columns of the patch, once per pixel
-        int64_t ro[2 * kOrderMaxPr + 1];
-        int co[2 * kOrderMaxPr + 1];
-        for (int k = 0; k < P; ++k) {
-            ro[k] = (int64_t)reflect_idx(iy - A.pr + k, I.H) * I.W;
-            co[k] = reflect_idx(ix - A.pr + k, I.W);
-        }
         // one pass: the key only orders the queue, so the rounding of
         // E[v^2] - E[v]^2 in FP32 does not matter
-        float s1 = 0.0f, s2 = 0.0f;
-        for (int ky = 0; ky < P; ++ky)
-            for (int kx = 0; kx < P; ++kx) {
-                const int64_t o = ro[ky] + co[kx];
-                const float v = I.is_f16 ? __half2float(f16[o]) : f32[o];
-                s1 += v;
-                s2 = fmaf(v, v, s2);
-            }
+        float s1, s2;
+        patch_sums<PS>(I, iy, ix, s1, s2);
         const float m = s1 * inv_d;
         const float var = fmaxf(fmaf(-m, m, s2 * inv_d), 0.0f);
         const float key = sqrtf(var) * A.scale;   // std / (hi - lo) * 2K, in [0, K]
@@ -73,6 +93,16 @@ __global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
     __syncthreads();
     for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x)
         if (hist[i]) atomicAdd(&A.cnt[i], hist[i]);
+}
+
+__global__ __launch_bounds__(256) void nlem_order_count(NlemOrderArgs A) {
+    static_assert(kOrderMaxPr == 3, "one case per patch radius");
+    switch (A.pr) {
+        case 0: order_count<1>(A); break;
+        case 1: order_count<3>(A); break;
+        case 2: order_count<5>(A); break;
+        default: order_count<7>(A); break;
+    }
 }
 
 // Every block first turns the bucket counts into offsets with the largest
