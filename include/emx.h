@@ -566,8 +566,8 @@ em_status_t em_batch_plan_set(em_handle_t handle, int32_t solver, int32_t points
  * em_kernel_timing - for measurement tools: while enabled (enable != 0),
  * every NLEM solve launch of nlem_denoise, nlem_denoise_ex and nlm_denoise
  * (and of nlem_autotune's trials) is bracketed by two HIP events on its stream, so the solve kernel's own duration can be
- * read without the small kernels that precede it (queue reset and queue
- * order).  Not recorded: launches into a stream that is being captured, and
+ * read without the small kernels that precede it (the queue-order kernels,
+ * or a reset of the queue head where the order is not used).  Not recorded: launches into a stream that is being captured, and
  * the multi-image graph.  Enabling or disabling discards unread timings.
  * em_kernel_timing_read - waits for the recorded events and returns the sum
  * of their durations (ms) and the number of launches, then clears them;
