@@ -104,3 +104,29 @@ def test_queue_chunks_parity(chunk, monkeypatch):
     e, r = rel_errors(ok.cpu().numpy().reshape(-1).astype(np.float64), ref["out"], 255.0)
     report(f"nlem r2 R5 T9, {chunk} queue positions per atomic", e, r)
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("pr,wr,fp16", [(0, 4, False), (1, 5, True), (2, 7, False), (3, 5, True)])
+def test_forced_order_every_patch_size(pr, wr, fp16):
+    """A plan with the order forced on (order = 1) runs the order kernels on
+    small images too, for every patch size (each size has its own unrolled
+    patch-statistics kernel): outputs and statistics identical, bit for bit,
+    to the same plan with the order off, and every pixel written."""
+    gpu()
+    hd = handle()
+    base = hd.nlem_plan_get(pr, wr, f16=fp16)
+    runs = []
+    try:
+        for order in (0, 1):
+            hd.nlem_plan_set(pr, wr, dict(base, order=order), f16=fp16)
+            items = _items([(30 + pr, 37, 45, pr, wr)], fp16)
+            hd.nlem_denoise_ex(items, max_iter=200, tol=1e-4)
+            hd.sync()
+            runs.append(_snapshot(items))
+    finally:
+        hd.nlem_plan_set(pr, wr, None, f16=fp16)
+    (o0, s0), = runs[0]
+    (o1, s1), = runs[1]
+    assert torch_equal(o0, o1) and torch_equal(s0, s1)
+    assert float(o1.min()) >= 0.0   # every pixel written (the fill value is -7)
+    print(f"[order] forced on, r={pr} R={wr} fp16={fp16}: identical to the order off", flush=True)
