@@ -442,6 +442,15 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             }
         } else
         for (; t <= max_iter && !bad; ++t) {
+            // Wave priority (several coordinate waves): a wave runs the first
+            // half of an iteration (its own points: delta and the norm
+            // partials) at the lowest priority and the rest, from the first
+            // barrier on, at a higher one.  The SIMDs are shared by three
+            // workgroups; favouring the waves past the barrier lets a
+            // workgroup reach its next barrier sooner while the first halves
+            // of the others fill the issue slots (2.375 -> 2.254 ms on the
+            // 256x256 image with 7x7 patches and 21x21 windows).
+            if constexpr (WC > 1) __builtin_amdgcn_s_setprio(0);
             // Large slices read the points from the LDS tile every iteration;
             // without this the compiler hoists the loop-invariant tile reads
             // and keeps all M*NJ points live in registers.
@@ -478,6 +487,7 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
 #pragma unroll
                 for (int q = 0; q < M; ++q) X[(SW * M + q) * 64 + lane] = nrm[q];
                 __syncthreads();
+                __builtin_amdgcn_s_setprio(1);
                 // the dual residual of iteration t-1: the last wave sums the
                 // squared steps the coordinate owners left in LDS (coordinate
                 // order), takes the arming test and hands its outcome over
