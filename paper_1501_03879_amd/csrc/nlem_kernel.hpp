@@ -445,11 +445,11 @@ __device__ __forceinline__ void nlem_wave(const NlemLaunch &L, float *tile, floa
             // Wave priority (several coordinate waves): a wave runs the first
             // half of an iteration (its own points: delta and the norm
             // partials) at the lowest priority and the rest, from the first
-            // barrier on, at a higher one.  The SIMDs are shared by three
-            // workgroups; favouring the waves past the barrier lets a
-            // workgroup reach its next barrier sooner while the first halves
-            // of the others fill the issue slots (2.375 -> 2.254 ms on the
-            // 256x256 image with 7x7 patches and 21x21 windows).
+            // barrier on, at a higher one.  Several workgroups share each
+            // SIMD (three for 7x7 patches and 21x21 windows); favouring the
+            // waves past the barrier lets a workgroup reach its next barrier
+            // sooner while the first halves of the others fill the issue
+            // slots (2.375 -> 2.254 ms on the 256x256 image with that shape).
             if constexpr (WC > 1) __builtin_amdgcn_s_setprio(0);
             // Large slices read the points from the LDS tile every iteration;
             // without this the compiler hoists the loop-invariant tile reads
